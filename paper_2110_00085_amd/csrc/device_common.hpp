@@ -1,0 +1,223 @@
+// Device-side building blocks shared by the gfx950 kernels: scene/camera
+// parameter blocks, Philox4x32-10, phase functions, the orthonormal basis,
+// and the incremental 3-D DDA voxel walkers (Amanatides & Woo style).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace prt {
+
+constexpr int kWave = 64;
+constexpr int kMaxCams = 24;
+constexpr int kMaxOrder = 64;
+constexpr double kPi = 3.14159265358979323846;
+
+// Scene constants in the units the kernels use (grid units for lengths).
+struct DevScene {
+    int nx, ny, nz, max_order;
+    double vk;              // voxel edge [km]
+    double beta_air;        // 1/km
+    double w_c, w_a;        // single-scattering albedos
+    double g;               // HG asymmetry
+    double hg_num;          // (1 - g^2) / (4 pi)
+    double sun[3];          // propagation direction of the sun's rays
+    double a_top, a_x, a_y; // projected areas of the lit faces [km^2]
+    double w0;              // source weight F0 * projected box area
+    double x_face, y_face;  // grid coordinate of the lit x / y face
+};
+
+// Cameras with positions converted to grid units.
+struct DevCams {
+    int n, W, H, pad;
+    double pos[kMaxCams][3];
+    double rot[kMaxCams][9];
+    double f[kMaxCams];
+};
+
+// ------------------------------------------------------------ Philox4x32-10
+
+__device__ __forceinline__ void philox4x32_10(uint32_t k0, uint32_t k1, uint32_t& x0, uint32_t& x1,
+                                              uint32_t& x2, uint32_t& x3)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
+        const uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
+        const uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+    }
+}
+
+// Four uniforms in (0,1) for (path, event): (x + 1/2) 2^-32, exact in FP64.
+__device__ __forceinline__ void uniforms4(uint64_t seed, uint64_t path, uint32_t event, double u[4])
+{
+    uint32_t x0 = (uint32_t)path, x1 = (uint32_t)(path >> 32), x2 = event, x3 = 0u;
+    philox4x32_10((uint32_t)seed, (uint32_t)(seed >> 32), x0, x1, x2, x3);
+    u[0] = ((double)x0 + 0.5) * 0x1p-32;
+    u[1] = ((double)x1 + 0.5) * 0x1p-32;
+    u[2] = ((double)x2 + 0.5) * 0x1p-32;
+    u[3] = ((double)x3 + 0.5) * 0x1p-32;
+}
+
+// ---------------------------------------------------------- phase functions
+
+__device__ __forceinline__ double phase_hg(const DevScene& s, double mu)
+{
+    const double d = 1.0 + s.g * s.g - 2.0 * s.g * mu;
+    return s.hg_num / (d * sqrt(d));
+}
+
+__device__ __forceinline__ double phase_rayleigh(double mu)
+{
+    return (3.0 / (16.0 * kPi)) * (1.0 + mu * mu);
+}
+
+__device__ __forceinline__ double sample_hg(double u, double g)
+{
+    double mu;
+    if (fabs(g) < 1e-6) {
+        mu = 2.0 * u - 1.0;
+    } else {
+        const double s = (1.0 - g * g) / (1.0 - g + 2.0 * g * u);
+        mu = (1.0 + g * g - s * s) / (2.0 * g);
+    }
+    return fmin(1.0, fmax(-1.0, mu));
+}
+
+// Rayleigh: the cubic mu^3 + 3 mu + 4 - 8u = 0 has the single real root s - 1/s,
+// s = cbrt(q + sqrt(q^2 + 1)), q = 4u - 2.
+__device__ __forceinline__ double sample_rayleigh(double u)
+{
+    const double q = 4.0 * u - 2.0;
+    const double s = cbrt(q + sqrt(q * q + 1.0));
+    return fmin(1.0, fmax(-1.0, s - 1.0 / s));
+}
+
+// New direction at cosine mu, azimuth phi about n, in the branchless
+// orthonormal basis of Duff et al. (JCGT 2017); renormalised.
+__device__ __forceinline__ void scatter_direction(const double n[3], double mu, double phi, double out[3])
+{
+    const double sgn = n[2] >= 0.0 ? 1.0 : -1.0;
+    const double a = -1.0 / (sgn + n[2]);
+    const double b = n[0] * n[1] * a;
+    const double e1x = 1.0 + sgn * n[0] * n[0] * a, e1y = sgn * b, e1z = -sgn * n[0];
+    const double e2x = b, e2y = sgn + n[1] * n[1] * a, e2z = -n[1];
+    const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    const double wx = mu * n[0] + st * (cp * e1x + sp * e2x);
+    const double wy = mu * n[1] + st * (cp * e1y + sp * e2y);
+    const double wz = mu * n[2] + st * (cp * e1z + sp * e2z);
+    const double inv = 1.0 / sqrt(wx * wx + wy * wy + wz * wz);
+    out[0] = wx * inv;
+    out[1] = wy * inv;
+    out[2] = wz * inv;
+}
+
+// Scattering "directional function" f_s = w_c beta_c f_HG + w_a beta_a f_R.
+__device__ __forceinline__ double fs_mix(const DevScene& s, double beta_c, double hg, double ray)
+{
+    return s.w_c * beta_c * hg + s.w_a * s.beta_air * ray;
+}
+
+// -------------------------------------------------------------- projection
+
+// FP64 pinhole projection of a grid-unit point; returns pixel or -1.
+__device__ __forceinline__ int project(const DevCams& c, int d, double x, double y, double z, double vk)
+{
+    const double* R = c.rot[d];
+    const double qx = (x - c.pos[d][0]) * vk, qy = (y - c.pos[d][1]) * vk, qz = (z - c.pos[d][2]) * vk;
+    const double px = R[0] * qx + R[1] * qy + R[2] * qz;
+    const double py = R[3] * qx + R[4] * qy + R[5] * qz;
+    const double pz = R[6] * qx + R[7] * qy + R[8] * qz;
+    if (!(pz > 0.0)) return -1;
+    const double iz = 1.0 / pz;
+    const double u = c.f[d] * px * iz + 0.5 * c.W;
+    const double v = c.f[d] * py * iz + 0.5 * c.H;
+    if (!(u >= 0.0 && u < c.W && v >= 0.0 && v < c.H)) return -1;
+    const int col = min((int)floor(u), c.W - 1);
+    const int row = min((int)floor(v), c.H - 1);
+    return row * c.W + col;
+}
+
+// ------------------------------------------------------------- DDA walker
+
+// Incremental voxel walk along p + t w from voxel (ix,iy,iz) over t in
+// [0, tmax] (grid units), clipped by the box.  The functor is called as
+// f(voxel, t_start, length) for every piece of nonzero length, in order; it
+// returns false to stop the walk.  Returns the parameter t reached (the box
+// exit, tmax, or where the functor stopped).  Every iteration advances one
+// index toward the box boundary, and the loop is capped at nx+ny+nz+3
+// iterations, so the walk terminates for any input (including non-finite
+// directions).
+template <typename Real, typename F>
+__device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy,
+                                         int iz, Real wx, Real wy, Real wz, Real tmax, F&& f)
+{
+    const Real inf = (Real)INFINITY;
+    const int sx = wx > (Real)0 ? 1 : (wx < (Real)0 ? -1 : 0);
+    const int sy = wy > (Real)0 ? 1 : (wy < (Real)0 ? -1 : 0);
+    const int sz = wz > (Real)0 ? 1 : (wz < (Real)0 ? -1 : 0);
+    if (sx == 0 && sy == 0 && sz == 0) return (Real)0;
+    const Real ivx = sx ? (Real)1 / wx : (Real)0;
+    const Real ivy = sy ? (Real)1 / wy : (Real)0;
+    const Real ivz = sz ? (Real)1 / wz : (Real)0;
+    Real tnx = sx > 0 ? ((Real)(ix + 1) - px) * ivx : (sx < 0 ? ((Real)ix - px) * ivx : inf);
+    Real tny = sy > 0 ? ((Real)(iy + 1) - py) * ivy : (sy < 0 ? ((Real)iy - py) * ivy : inf);
+    Real tnz = sz > 0 ? ((Real)(iz + 1) - pz) * ivz : (sz < 0 ? ((Real)iz - pz) * ivz : inf);
+    const Real dtx = sx ? (Real)sx * ivx : inf;
+    const Real dty = sy ? (Real)sy * ivy : inf;
+    const Real dtz = sz ? (Real)sz * ivz : inf;
+    const int stop_x = sx > 0 ? nx : -1, stop_y = sy > 0 ? ny : -1, stop_z = sz > 0 ? nz : -1;
+    const int sy_v = sy * nx, sz_v = sz * nx * ny;
+    int v = ix + nx * (iy + ny * iz);
+    Real t = (Real)0;
+    const int maxit = nx + ny + nz + 3;
+    for (int it = 0; it < maxit; ++it) {
+        const Real tn = fmin(tnx, fmin(tny, tnz));
+        const Real te = fmin(tn, tmax);
+        if (te > t) {
+            if (!f(v, t, te - t)) return t;
+            t = te;
+        }
+        if (!(tn < tmax)) return t;
+        if (tnx <= tny && tnx <= tnz) {
+            ix += sx;
+            if (ix == stop_x) return t;
+            v += sx;
+            tnx += dtx;
+        } else if (tny <= tnz) {
+            iy += sy;
+            if (iy == stop_y) return t;
+            v += sy_v;
+            tny += dty;
+        } else {
+            iz += sz;
+            if (iz == stop_z) return t;
+            v += sz_v;
+            tnz += dtz;
+        }
+    }
+    return t;
+}
+
+// Voxel index components of a linear voxel id.
+__device__ __forceinline__ void voxel_ijk(int v, int nx, int ny, int& ix, int& iy, int& iz)
+{
+    ix = v % nx;
+    const int r = v / nx;
+    iy = r % ny;
+    iz = r / ny;
+}
+
+__device__ __forceinline__ int vox_of(const float4& r) { return __float_as_int(r.w); }
+
+}  // namespace prt

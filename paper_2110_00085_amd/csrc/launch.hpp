@@ -1,0 +1,81 @@
+// Kernel argument blocks and launcher entry points shared by the host API
+// (prt_api.cpp) and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+
+namespace prt {
+
+// Device view of a path store in wavefront-batch layout: sorted slot i
+// belongs to batch i/64, lane i%64; vertex k of that slot is the float4
+// record vtx[batch_off[i/64] + 64*k + i%64] = (x, y, z, voxel bits), grid units.
+struct StoreView {
+    const float4* vtx;
+    const int64_t* batch_off;
+    const uint8_t* B;       // scatters per sorted slot
+    const uint8_t* nv;      // stored vertices per sorted slot (0 for padding)
+    int64_t n_slots;        // 64 * n_batches
+    int64_t first_slot;     // first slot with B > 0 (sorted order)
+    const float* beta_ref;  // reference cloud field
+};
+
+struct SampleArgs {
+    DevScene s;
+    const float* beta_c;   // cloud field the paths are drawn from
+    const void* grid_tot;  // Real[N_u]: beta_c + beta_air
+    uint64_t seed;
+    int64_t n;
+    float4* tmp;           // [n][max_order+2] records
+    uint8_t* tB;
+    uint8_t* tnv;
+};
+
+struct TraceArgs {
+    DevScene s;
+    StoreView st;
+    const float* bc_t;        // current cloud field
+    const void* grid_tot;     // Real[N_u]: beta_t + beta_air
+    const void* grid_dlt;     // Real[N_u]: beta_t - beta_ref
+    double* img;              // render: raw tallies [n][H][W]
+    const double* rho;        // grad: residual / (N Omega_p) [n][H][W]
+    double* grad;             // grad: [N_u]
+    double* partial;          // reweight: per-block (sum r, sum r^2)
+    int32_t brender;
+    unsigned long long* counters;  // [0] voxel segs, [1] local estimates, [3] overhead segs
+};
+
+// ---- sampling, sorting, packing (sample.hip)
+hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const float* bc_r, double beta_air,
+                             int64_t nu, void* grid_tot, void* grid_dlt);
+hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a);
+hipError_t launch_sort_by_size(hipStream_t st, const uint8_t* key, int64_t n, int nbins, uint32_t* blockhist,
+                               int32_t* perm);
+int64_t sort_scratch_words(int64_t n, int nbins);
+hipError_t launch_gather_sizes(hipStream_t st, const int32_t* perm, const uint8_t* tB, const uint8_t* tnv,
+                               int64_t n, int64_t n_slots, uint8_t* B, uint8_t* nv);
+hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, int64_t* batch_off);
+hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, const int64_t* tmp_off,
+                       int64_t tmp_stride, const uint8_t* nv, const int64_t* batch_off, int64_t n,
+                       int64_t n_slots, float4* vtx);
+hipError_t launch_first_nonzero(hipStream_t st, const uint8_t* B, int64_t n, int64_t* out);
+
+// ---- hot path (trace.hip)
+hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c);
+hipError_t launch_render_finalize(hipStream_t st, double* img, const DevCams& c, double scale);
+hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho, const DevCams& c, double scale);
+hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c);
+hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int64_t* n_blocks);
+
+// ---- loop glue (loop.hip)
+hipError_t launch_fill(hipStream_t st, double* p, int64_t n, double v);
+hipError_t launch_loss(hipStream_t st, int64_t n, const double* img, const double* tgt, double* res,
+                       double* partial, double* loss);
+int64_t loss_blocks(int64_t n);
+hipError_t launch_sum_pairs(hipStream_t st, const double* partial, int64_t n_blocks, double* out2);
+hipError_t launch_adam(hipStream_t st, int64_t n, double* beta, float* beta_f32, const double* grad, double* m,
+                       double* v, double lr, double b1, double b2, double eps, double bc1, double bc2);
+
+}  // namespace prt

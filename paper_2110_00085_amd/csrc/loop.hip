@@ -1,0 +1,124 @@
+// Loop glue of the optimisation (Alg. 2): appearance loss and residual
+// (Eq. appearance_loss), the Adam step with projection onto beta >= 0, and
+// fixed-order FP64 reductions.
+#include "launch.hpp"
+
+namespace prt {
+
+__global__ void __launch_bounds__(256) fill_kernel(double* __restrict__ p, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(hipStream_t st, double* p, int64_t n, double v)
+{
+    if (n <= 0) return hipSuccess;
+    fill_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+constexpr int kLossItems = 4096;  // elements per block
+
+int64_t loss_blocks(int64_t n) { return (n + kLossItems - 1) / kLossItems; }
+
+// residual = images - target; per-block sums of residual^2 into partial[2*b]
+__global__ void __launch_bounds__(256) loss_kernel(int64_t n, const double* __restrict__ img,
+                                                   const double* __restrict__ tgt, double* __restrict__ res,
+                                                   double* __restrict__ partial)
+{
+    __shared__ double red[256];
+    const int64_t base = (int64_t)blockIdx.x * kLossItems;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < kLossItems; j += blockDim.x) {
+        const int64_t i = base + j;
+        if (i < n) {
+            const double r = img[i] - tgt[i];
+            res[i] = r;
+            s += r * r;
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = red[0];
+        partial[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+// out2[0..1] = column sums of the (n_blocks x 2) partials, in a fixed order.
+__global__ void __launch_bounds__(256) sum_pairs_kernel(const double* __restrict__ partial, int64_t nb,
+                                                        double* __restrict__ out2, double scale0)
+{
+    __shared__ double red[2][256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) {
+        a += partial[2 * i];
+        b += partial[2 * i + 1];
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + o];
+            red[1][threadIdx.x] += red[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out2[0] = red[0][0] * scale0;
+        if (scale0 == 1.0) out2[1] = red[1][0];
+    }
+}
+
+hipError_t launch_loss(hipStream_t st, int64_t n, const double* img, const double* tgt, double* res,
+                       double* partial, double* loss)
+{
+    const int64_t nb = loss_blocks(n);
+    loss_kernel<<<dim3((unsigned)nb), dim3(256), 0, st>>>(n, img, tgt, res, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sum_pairs_kernel<<<dim3(1), dim3(256), 0, st>>>(partial, nb, loss, 0.5);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_pairs(hipStream_t st, const double* partial, int64_t n_blocks, double* out2)
+{
+    sum_pairs_kernel<<<dim3(1), dim3(256), 0, st>>>(partial, n_blocks, out2, 1.0);
+    return hipGetLastError();
+}
+
+// Adam (Kingma & Ba) with bias corrections bc1 = 1 - b1^t, bc2 = 1 - b2^t,
+// then projection onto beta >= 0 and the FP32 copy used by the kernels.
+__global__ void __launch_bounds__(256) adam_kernel(int64_t n, double* __restrict__ beta, float* __restrict__ bf,
+                                                   const double* __restrict__ g, double* __restrict__ m,
+                                                   double* __restrict__ v, double lr, double b1, double b2,
+                                                   double eps, double bc1, double bc2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double gi = g[i];
+    const double mi = b1 * m[i] + (1.0 - b1) * gi;
+    const double vi = b2 * v[i] + (1.0 - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const double step = lr * (mi / bc1) / (sqrt(vi / bc2) + eps);
+    const double nb = fmax(beta[i] - step, 0.0);
+    beta[i] = nb;
+    bf[i] = (float)nb;
+}
+
+hipError_t launch_adam(hipStream_t st, int64_t n, double* beta, float* beta_f32, const double* grad, double* m,
+                       double* v, double lr, double b1, double b2, double eps, double bc1, double bc2)
+{
+    adam_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, beta, beta_f32, grad, m, v, lr, b1, b2,
+                                                                        eps, bc1, bc2);
+    return hipGetLastError();
+}
+
+}  // namespace prt

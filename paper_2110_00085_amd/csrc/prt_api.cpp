@@ -1,0 +1,842 @@
+// Host side of the C ABI declared in include/prt.h: argument validation,
+// contexts, path-store lifecycle, kernel launches and telemetry.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/prt.h"
+#include "launch.hpp"
+
+using namespace prt;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess) return fail(PRT_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+enum KernelId { K_SAMPLE = 0, K_SORT, K_PACK, K_PREP, K_RENDER, K_FINALIZE, K_GRAD, K_REWEIGHT, K_LOSS, K_ADAM, K_COUNT };
+const char* kKernelNames[K_COUNT] = {"sample", "sort", "pack", "prep", "render", "render_finalize",
+                                     "grad", "reweight", "loss", "adam"};
+
+struct Timed {
+    int id;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct prt_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int fp64 = 0;
+    void* grid_tot = nullptr;
+    void* grid_dlt = nullptr;
+    size_t grid_bytes = 0;
+    double* pix = nullptr;      // rho scratch
+    size_t pix_n = 0;
+    double* part = nullptr;     // reduction partials
+    size_t part_n = 0;
+    double* out2 = nullptr;     // two doubles of reduction output
+    unsigned long long* counters = nullptr;  // 4
+    uint64_t paths_done = 0;
+    bool timing = false;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[K_COUNT] = {};
+    int64_t launches[K_COUNT] = {};
+};
+
+struct prt_paths_s {
+    prt_ctx ctx = nullptr;
+    int device = 0;
+    uint64_t n = 0;
+    int64_t nb = 0, n_slots = 0, first_slot = 0;
+    int32_t max_order = 0, nx = 0, ny = 0, nz = 0;
+    uint64_t seed = 0;
+    float4* vtx = nullptr;
+    int64_t n_records = 0;
+    int64_t* batch_off = nullptr;
+    uint8_t* B = nullptr;
+    uint8_t* nv = nullptr;
+    int32_t* perm = nullptr;
+    float* beta_ref = nullptr;
+    uint64_t bytes = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+hipEvent_t take_event(prt_ctx c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records an event pair around the launches made while it is alive.
+struct TimedScope {
+    prt_ctx c;
+    Timed t{};
+    bool on;
+    TimedScope(prt_ctx ctx, int id) : c(ctx), on(ctx->timing)
+    {
+        if (!on) return;
+        t.id = id;
+        t.a = take_event(c);
+        t.b = take_event(c);
+        if (!t.a || !t.b) {
+            on = false;
+            return;
+        }
+        (void)hipEventRecord(t.a, c->stream);
+    }
+    ~TimedScope()
+    {
+        if (!on) return;
+        (void)hipEventRecord(t.b, c->stream);
+        c->pending.push_back(t);
+    }
+};
+
+bool finite_all(std::initializer_list<double> v)
+{
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+int check_scene(const prt_scene* s)
+{
+    if (!s) return fail(PRT_E_INVALID, "scene is NULL");
+    if (s->nx < 1 || s->ny < 1 || s->nz < 1) return fail(PRT_E_INVALID, "grid dims must be >= 1");
+    if ((int64_t)s->nx * s->ny * s->nz >= (int64_t)1 << 31)
+        return fail(PRT_E_CAPACITY, "grid has more than 2^31 - 1 voxels");
+    if (s->max_order < 1 || s->max_order > PRT_MAX_ORDER)
+        return fail(PRT_E_CAPACITY, "max_order %d outside [1, %d]", s->max_order, PRT_MAX_ORDER);
+    if (!finite_all({s->voxel_km, s->beta_air, s->albedo_cloud, s->albedo_air, s->g, s->sun_zenith_deg,
+                     s->sun_azimuth_deg, s->sun_flux}))
+        return fail(PRT_E_INVALID, "non-finite scene parameter");
+    if (!(s->voxel_km > 0)) return fail(PRT_E_INVALID, "voxel_km must be > 0");
+    if (!(s->beta_air >= 0)) return fail(PRT_E_INVALID, "beta_air must be >= 0");
+    if (!(s->albedo_cloud > 0 && s->albedo_cloud <= 1) || !(s->albedo_air > 0 && s->albedo_air <= 1))
+        return fail(PRT_E_INVALID, "albedos must lie in (0, 1]");
+    if (!(std::fabs(s->g) < 1)) return fail(PRT_E_INVALID, "|g| must be < 1");
+    if (!(s->sun_zenith_deg >= 0 && s->sun_zenith_deg < 90)) return fail(PRT_E_INVALID, "sun zenith must be in [0, 90)");
+    if (!(s->sun_flux > 0)) return fail(PRT_E_INVALID, "sun_flux must be > 0");
+    if (!s->beta_cloud) return fail(PRT_E_INVALID, "beta_cloud is NULL");
+    return PRT_OK;
+}
+
+DevScene make_dev_scene(const prt_scene* s)
+{
+    DevScene d{};
+    d.nx = s->nx;
+    d.ny = s->ny;
+    d.nz = s->nz;
+    d.max_order = s->max_order;
+    d.vk = s->voxel_km;
+    d.beta_air = s->beta_air;
+    d.w_c = s->albedo_cloud;
+    d.w_a = s->albedo_air;
+    d.g = s->g;
+    d.hg_num = (1.0 - s->g * s->g) / (4.0 * kPi);
+    const double th = s->sun_zenith_deg * kPi / 180.0, ph = s->sun_azimuth_deg * kPi / 180.0;
+    d.sun[0] = std::sin(th) * std::cos(ph);
+    d.sun[1] = std::sin(th) * std::sin(ph);
+    d.sun[2] = -std::cos(th);
+    const double Lx = s->nx * s->voxel_km, Ly = s->ny * s->voxel_km, Lz = s->nz * s->voxel_km;
+    d.a_top = Lx * Ly * std::fabs(d.sun[2]);
+    d.a_x = Ly * Lz * std::fabs(d.sun[0]);
+    d.a_y = Lx * Lz * std::fabs(d.sun[1]);
+    d.w0 = s->sun_flux * (d.a_top + d.a_x + d.a_y);
+    d.x_face = d.sun[0] > 0 ? 0.0 : (double)s->nx;
+    d.y_face = d.sun[1] > 0 ? 0.0 : (double)s->ny;
+    return d;
+}
+
+int make_dev_cams(const prt_cameras* c, double vk, DevCams* out)
+{
+    if (!c) return fail(PRT_E_INVALID, "cameras is NULL");
+    if (c->n < 1 || c->n > PRT_MAX_CAMERAS) return fail(PRT_E_CAPACITY, "camera count %d outside [1, %d]", c->n, PRT_MAX_CAMERAS);
+    if (c->width < 1 || c->height < 1 || c->width > 16384 || c->height > 16384)
+        return fail(PRT_E_INVALID, "image size must be in [1, 16384]");
+    if (!c->pos || !c->rot || !c->f_px) return fail(PRT_E_INVALID, "camera arrays must be non-NULL");
+    std::memset(out, 0, sizeof *out);
+    out->n = c->n;
+    out->W = c->width;
+    out->H = c->height;
+    for (int d = 0; d < c->n; ++d) {
+        for (int k = 0; k < 3; ++k) {
+            if (!std::isfinite(c->pos[3 * d + k])) return fail(PRT_E_INVALID, "non-finite camera position");
+            out->pos[d][k] = c->pos[3 * d + k] / vk;
+        }
+        for (int k = 0; k < 9; ++k) {
+            if (!std::isfinite(c->rot[9 * d + k])) return fail(PRT_E_INVALID, "non-finite camera rotation");
+            out->rot[d][k] = c->rot[9 * d + k];
+        }
+        if (!(c->f_px[d] > 0) || !std::isfinite(c->f_px[d])) return fail(PRT_E_INVALID, "focal length must be > 0");
+        out->f[d] = c->f_px[d];
+    }
+    return PRT_OK;
+}
+
+int check_match(const prt_scene* s, prt_paths p)
+{
+    if (!p) return fail(PRT_E_INVALID, "paths is NULL");
+    if (s->nx != p->nx || s->ny != p->ny || s->nz != p->nz || s->max_order != p->max_order)
+        return fail(PRT_E_MISMATCH, "scene grid %dx%dx%d/order %d differs from the store's %dx%dx%d/order %d", s->nx,
+                    s->ny, s->nz, s->max_order, p->nx, p->ny, p->nz, p->max_order);
+    return PRT_OK;
+}
+
+template <typename T>
+int dalloc(T** p, size_t count, uint64_t* bytes = nullptr)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(PRT_E_NOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+    }
+    if (bytes) *bytes += count * sizeof(T);
+    return PRT_OK;
+}
+
+int ensure_grids(prt_ctx c, int64_t nu)
+{
+    const size_t need = (size_t)nu * (c->fp64 ? 8 : 4);
+    if (c->grid_bytes >= need) return PRT_OK;
+    (void)hipFree(c->grid_tot);
+    (void)hipFree(c->grid_dlt);
+    c->grid_tot = c->grid_dlt = nullptr;
+    c->grid_bytes = 0;
+    if (hipMalloc(&c->grid_tot, need) != hipSuccess || hipMalloc(&c->grid_dlt, need) != hipSuccess)
+        return fail(PRT_E_NOMEM, "grid scratch allocation failed");
+    c->grid_bytes = need;
+    return PRT_OK;
+}
+
+int ensure_pix(prt_ctx c, size_t n)
+{
+    if (c->pix_n >= n) return PRT_OK;
+    (void)hipFree(c->pix);
+    c->pix = nullptr;
+    c->pix_n = 0;
+    int rc = dalloc(&c->pix, n);
+    if (rc) return rc;
+    c->pix_n = n;
+    return PRT_OK;
+}
+
+int ensure_part(prt_ctx c, size_t n)
+{
+    if (c->part_n >= n) return PRT_OK;
+    (void)hipFree(c->part);
+    c->part = nullptr;
+    c->part_n = 0;
+    int rc = dalloc(&c->part, n);
+    if (rc) return rc;
+    c->part_n = n;
+    return PRT_OK;
+}
+
+void free_store(prt_paths p)
+{
+    if (!p) return;
+    DeviceGuard g(p->device);
+    (void)hipFree(p->vtx);
+    (void)hipFree(p->batch_off);
+    (void)hipFree(p->B);
+    (void)hipFree(p->nv);
+    (void)hipFree(p->perm);
+    (void)hipFree(p->beta_ref);
+    delete p;
+}
+
+// Shared tail of sample and import: sort the temp paths by size, lay them out
+// in wavefront batches and fill the store.  tmp rows are addressed by tmp_off
+// (CSR) or by id * tmp_stride.
+int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_off, int64_t tmp_stride,
+                const uint8_t* tB, const uint8_t* tnv)
+{
+    const int64_t n = (int64_t)p->n;
+    p->nb = (n + kWave - 1) / kWave;
+    p->n_slots = p->nb * kWave;
+    const int nbins = p->max_order + 1;
+    int rc;
+    uint32_t* hist = nullptr;
+    if ((rc = dalloc(&p->perm, n, &p->bytes))) return rc;
+    if ((rc = dalloc(&p->B, p->n_slots, &p->bytes))) return rc;
+    if ((rc = dalloc(&p->nv, p->n_slots, &p->bytes))) return rc;
+    if ((rc = dalloc(&p->batch_off, p->nb + 1, &p->bytes))) return rc;
+    if ((rc = dalloc(&hist, sort_scratch_words(n, nbins)))) return rc;
+    {
+        TimedScope ts(c, K_SORT);
+        hipError_t e = launch_sort_by_size(c->stream, tB, n, nbins, hist, p->perm);
+        if (e == hipSuccess) e = launch_gather_sizes(c->stream, p->perm, tB, tnv, n, p->n_slots, p->B, p->nv);
+        if (e == hipSuccess) e = launch_batch_offsets(c->stream, p->nv, p->nb, p->batch_off);
+        if (e != hipSuccess) {
+            (void)hipFree(hist);
+            return fail(PRT_E_HIP, "sort launch failed: %s", hipGetErrorString(e));
+        }
+    }
+    int64_t* d_first = nullptr;
+    if ((rc = dalloc(&d_first, 1))) {
+        (void)hipFree(hist);
+        return rc;
+    }
+    HIPCHK(launch_first_nonzero(c->stream, p->B, n, d_first));
+    int64_t host2[2] = {0, 0};
+    hipError_t e1 = hipMemcpyAsync(&host2[0], p->batch_off + p->nb, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
+    hipError_t e2 = hipMemcpyAsync(&host2[1], d_first, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
+    hipError_t e3 = hipStreamSynchronize(c->stream);
+    (void)hipFree(hist);
+    (void)hipFree(d_first);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        return fail(PRT_E_HIP, "store size readback failed: %s",
+                    hipGetErrorString(e3 != hipSuccess ? e3 : (e1 != hipSuccess ? e1 : e2)));
+    p->n_records = host2[0];
+    p->first_slot = host2[1];
+    if ((rc = dalloc(&p->vtx, p->n_records, &p->bytes))) return rc;
+    {
+        TimedScope ts(c, K_PACK);
+        HIPCHK(launch_pack(c->stream, p->perm, tmp, tmp_off, tmp_stride, p->nv, p->batch_off, n, p->n_slots, p->vtx));
+    }
+    return PRT_OK;
+}
+
+prt_paths new_store(prt_ctx c, const prt_scene* s, uint64_t n, uint64_t seed)
+{
+    prt_paths p = new prt_paths_s();
+    p->ctx = c;
+    p->device = c->device;
+    p->n = n;
+    p->seed = seed;
+    p->max_order = s->max_order;
+    p->nx = s->nx;
+    p->ny = s->ny;
+    p->nz = s->nz;
+    return p;
+}
+
+StoreView view_of(prt_paths p)
+{
+    StoreView v;
+    v.vtx = p->vtx;
+    v.batch_off = p->batch_off;
+    v.B = p->B;
+    v.nv = p->nv;
+    v.n_slots = p->n_slots;
+    v.first_slot = p->first_slot;
+    v.beta_ref = p->beta_ref;
+    return v;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char* prt_last_error(void) { return g_err.c_str(); }
+
+int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
+{
+    if (!out) return fail(PRT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (precision != PRT_TRAVERSAL_FP32 && precision != PRT_ALL_FP64) return fail(PRT_E_INVALID, "unknown precision %d", precision);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PRT_E_HIP, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(PRT_E_INVALID, "device %d out of range (have %d)", device, ndev);
+    DeviceGuard g(device);
+    prt_ctx c = new prt_ctx_s();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->fp64 = precision == PRT_ALL_FP64;
+    if (hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void**)&c->out2, 2 * sizeof(double)) != hipSuccess) {
+        (void)hipFree(c->counters);
+        delete c;
+        return fail(PRT_E_NOMEM, "context allocation failed");
+    }
+    if (hipMemset(c->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipFree(c->counters);
+        (void)hipFree(c->out2);
+        delete c;
+        return fail(PRT_E_HIP, "context init failed");
+    }
+    *out = c;
+    return PRT_OK;
+}
+
+void prt_destroy(prt_ctx c)
+{
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& t : c->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    (void)hipFree(c->grid_tot);
+    (void)hipFree(c->grid_dlt);
+    (void)hipFree(c->pix);
+    (void)hipFree(c->part);
+    (void)hipFree(c->out2);
+    (void)hipFree(c->counters);
+    delete c;
+}
+
+int prt_set_stream(prt_ctx c, void* hip_stream)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    c->stream = (hipStream_t)hip_stream;
+    return PRT_OK;
+}
+
+int prt_sample(prt_ctx c, const prt_scene* s, uint64_t seed, uint64_t n_paths, prt_paths* out)
+{
+    if (!c || !out) return fail(PRT_E_INVALID, "ctx/out is NULL");
+    *out = nullptr;
+    int rc = check_scene(s);
+    if (rc) return rc;
+    if (n_paths < 1 || n_paths > ((uint64_t)1 << 31) - 64) return fail(PRT_E_CAPACITY, "n_paths must be in [1, 2^31-64]");
+    DeviceGuard g(c->device);
+    const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
+    const int64_t n = (int64_t)n_paths;
+    const int64_t stride = s->max_order + 2;
+    if ((rc = ensure_grids(c, nu))) return rc;
+    prt_paths p = new_store(c, s, n_paths, seed);
+    float4* tmp = nullptr;
+    uint8_t *tB = nullptr, *tnv = nullptr;
+    auto cleanup = [&](int code) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        (void)hipFree(tB);
+        (void)hipFree(tnv);
+        if (code != PRT_OK) free_store(p);
+        return code;
+    };
+    if ((rc = dalloc(&p->beta_ref, nu, &p->bytes))) return cleanup(rc);
+    if ((rc = dalloc(&tmp, (size_t)n * stride))) return cleanup(rc);
+    if ((rc = dalloc(&tB, n))) return cleanup(rc);
+    if ((rc = dalloc(&tnv, n))) return cleanup(rc);
+    hipError_t e = hipMemcpyAsync(p->beta_ref, s->beta_cloud, nu * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return cleanup(fail(PRT_E_HIP, "beta_ref snapshot: %s", hipGetErrorString(e)));
+    {
+        TimedScope ts(c, K_PREP);
+        e = launch_prep_grids(c->stream, c->fp64, p->beta_ref, nullptr, s->beta_air, nu, c->grid_tot, nullptr);
+    }
+    if (e != hipSuccess) return cleanup(fail(PRT_E_HIP, "prep launch: %s", hipGetErrorString(e)));
+    SampleArgs a;
+    a.s = make_dev_scene(s);
+    a.beta_c = p->beta_ref;
+    a.grid_tot = c->grid_tot;
+    a.seed = seed;
+    a.n = n;
+    a.tmp = tmp;
+    a.tB = tB;
+    a.tnv = tnv;
+    {
+        TimedScope ts(c, K_SAMPLE);
+        e = launch_sample(c->stream, c->fp64, a);
+    }
+    if (e != hipSuccess) return cleanup(fail(PRT_E_HIP, "sample launch: %s", hipGetErrorString(e)));
+    if ((rc = build_store(c, p, tmp, nullptr, stride, tB, tnv))) return cleanup(rc);
+    rc = cleanup(PRT_OK);
+    if (rc == PRT_OK) *out = p;
+    return rc;
+}
+
+int prt_paths_import(prt_ctx c, const prt_scene* s, uint64_t n_paths, const int64_t* off, const float* xyz,
+                     const int32_t* vox, const int32_t* B, const float* beta_ref, uint64_t seed, prt_paths* out)
+{
+    if (!c || !out) return fail(PRT_E_INVALID, "ctx/out is NULL");
+    *out = nullptr;
+    int rc = check_scene(s);
+    if (rc) return rc;
+    if (!off || !xyz || !vox || !B || !beta_ref) return fail(PRT_E_INVALID, "import arrays must be non-NULL");
+    if (n_paths < 1 || n_paths > ((uint64_t)1 << 31) - 64) return fail(PRT_E_CAPACITY, "n_paths must be in [1, 2^31-64]");
+    const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
+    const int64_t n = (int64_t)n_paths;
+    if (off[0] != 0) return fail(PRT_E_INVALID, "off[0] must be 0");
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t cnt = off[i + 1] - off[i];
+        const int b = B[i];
+        if (b < 0 || b > s->max_order) return fail(PRT_E_INVALID, "path %lld: B=%d outside [0, max_order]", (long long)i, b);
+        const int64_t want = b == s->max_order ? b + 1 : b + 2;
+        if (cnt != want)
+            return fail(PRT_E_INVALID, "path %lld: %lld vertices for B=%d", (long long)i, (long long)cnt, b);
+        for (int64_t k = 0; k < cnt; ++k) {
+            const int32_t v = vox[off[i] + k];
+            const bool exit_vertex = (k == cnt - 1) && (cnt == b + 2);
+            if (exit_vertex ? v != -1 : (v < 0 || v >= nu))
+                return fail(PRT_E_INVALID, "path %lld vertex %lld: voxel %d invalid", (long long)i, (long long)k, v);
+            for (int a = 0; a < 3; ++a)
+                if (!std::isfinite(xyz[3 * (off[i] + k) + a])) return fail(PRT_E_INVALID, "non-finite vertex");
+        }
+    }
+    DeviceGuard g(c->device);
+    const int64_t nrec = off[n];
+    std::vector<float4> h(nrec);
+    for (int64_t r = 0; r < nrec; ++r) {
+        float4 q;
+        q.x = xyz[3 * r];
+        q.y = xyz[3 * r + 1];
+        q.z = xyz[3 * r + 2];
+        std::memcpy(&q.w, &vox[r], 4);
+        h[r] = q;
+    }
+    std::vector<uint8_t> hB(n), hnv(n);
+    for (int64_t i = 0; i < n; ++i) {
+        hB[i] = (uint8_t)B[i];
+        hnv[i] = (uint8_t)(off[i + 1] - off[i]);
+    }
+    prt_paths p = new_store(c, s, n_paths, seed);
+    float4* tmp = nullptr;
+    int64_t* toff = nullptr;
+    uint8_t *tB = nullptr, *tnv = nullptr;
+    auto cleanup = [&](int code) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        (void)hipFree(toff);
+        (void)hipFree(tB);
+        (void)hipFree(tnv);
+        if (code != PRT_OK) free_store(p);
+        return code;
+    };
+    if ((rc = dalloc(&p->beta_ref, nu, &p->bytes))) return cleanup(rc);
+    if ((rc = dalloc(&tmp, nrec))) return cleanup(rc);
+    if ((rc = dalloc(&toff, n + 1))) return cleanup(rc);
+    if ((rc = dalloc(&tB, n))) return cleanup(rc);
+    if ((rc = dalloc(&tnv, n))) return cleanup(rc);
+    hipError_t e = hipMemcpy(tmp, h.data(), nrec * sizeof(float4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(toff, off, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(tB, hB.data(), n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(tnv, hnv.data(), n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->beta_ref, beta_ref, nu * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(fail(PRT_E_HIP, "import upload: %s", hipGetErrorString(e)));
+    if ((rc = build_store(c, p, tmp, toff, 0, tB, tnv))) return cleanup(rc);
+    rc = cleanup(PRT_OK);
+    if (rc == PRT_OK) *out = p;
+    return rc;
+}
+
+int prt_paths_export(prt_ctx c, prt_paths p, int64_t* off, float* xyz, int32_t* vox, int32_t* B, float* beta_ref)
+{
+    if (!c || !p || !off || !B) return fail(PRT_E_INVALID, "ctx/paths/off/B must be non-NULL");
+    DeviceGuard g(p->device);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t n = (int64_t)p->n;
+    std::vector<int32_t> perm(n);
+    std::vector<uint8_t> hB(p->n_slots), hnv(p->n_slots);
+    std::vector<int64_t> boff(p->nb + 1);
+    HIPCHK(hipMemcpy(perm.data(), p->perm, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hB.data(), p->B, p->n_slots, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hnv.data(), p->nv, p->n_slots, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(boff.data(), p->batch_off, (p->nb + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<int64_t> slot_of(n);
+    for (int64_t i = 0; i < n; ++i) slot_of[perm[i]] = i;
+    off[0] = 0;
+    for (int64_t id = 0; id < n; ++id) {
+        off[id + 1] = off[id] + hnv[slot_of[id]];
+        B[id] = hB[slot_of[id]];
+    }
+    if (xyz || vox) {
+        std::vector<float4> hv(p->n_records);
+        HIPCHK(hipMemcpy(hv.data(), p->vtx, p->n_records * sizeof(float4), hipMemcpyDeviceToHost));
+        for (int64_t id = 0; id < n; ++id) {
+            const int64_t i = slot_of[id];
+            const int64_t base = boff[i / kWave] + i % kWave;
+            for (int k = 0; k < hnv[i]; ++k) {
+                const float4 q = hv[base + (int64_t)k * kWave];
+                const int64_t r = off[id] + k;
+                if (xyz) {
+                    xyz[3 * r] = q.x;
+                    xyz[3 * r + 1] = q.y;
+                    xyz[3 * r + 2] = q.z;
+                }
+                if (vox) std::memcpy(&vox[r], &q.w, 4);
+            }
+        }
+    }
+    if (beta_ref)
+        HIPCHK(hipMemcpy(beta_ref, p->beta_ref, (size_t)p->nx * p->ny * p->nz * sizeof(float), hipMemcpyDeviceToHost));
+    return PRT_OK;
+}
+
+int prt_paths_permutation(prt_ctx c, prt_paths p, int32_t* perm)
+{
+    if (!c || !p || !perm) return fail(PRT_E_INVALID, "ctx/paths/perm must be non-NULL");
+    DeviceGuard g(p->device);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(perm, p->perm, p->n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return PRT_OK;
+}
+
+int prt_paths_info(prt_paths p, prt_paths_info_t* info)
+{
+    if (!p || !info) return fail(PRT_E_INVALID, "paths/info is NULL");
+    info->n_paths = p->n;
+    info->n_vertices = (uint64_t)p->n_records;
+    info->n_batches = (uint64_t)p->nb;
+    info->seed = p->seed;
+    info->bytes = p->bytes;
+    info->max_order = p->max_order;
+    info->nx = p->nx;
+    info->ny = p->ny;
+    info->nz = p->nz;
+    return PRT_OK;
+}
+
+void prt_paths_destroy(prt_paths p)
+{
+    if (!p) return;
+    if (p->ctx) {
+        DeviceGuard g(p->device);
+        (void)hipStreamSynchronize(p->ctx->stream);
+    }
+    free_store(p);
+}
+
+int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p, int32_t max_order_render,
+               double* images)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    int rc = check_scene(s);
+    if (rc) return rc;
+    if ((rc = check_match(s, p))) return rc;
+    if (!images) return fail(PRT_E_INVALID, "images is NULL");
+    if (max_order_render < 0) return fail(PRT_E_INVALID, "max_order_render must be >= 0");
+    TraceArgs a{};
+    DevCams dc;
+    if ((rc = make_dev_cams(cams, s->voxel_km, &dc))) return rc;
+    DeviceGuard g(c->device);
+    const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
+    if ((rc = ensure_grids(c, nu))) return rc;
+    const int64_t npx = (int64_t)dc.n * dc.W * dc.H;
+    {
+        TimedScope ts(c, K_PREP);
+        HIPCHK(launch_fill(c->stream, images, npx, 0.0));
+        HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
+                                 c->grid_dlt));
+    }
+    a.s = make_dev_scene(s);
+    a.st = view_of(p);
+    a.bc_t = s->beta_cloud;
+    a.grid_tot = c->grid_tot;
+    a.grid_dlt = c->grid_dlt;
+    a.img = images;
+    a.brender = std::min(max_order_render, s->max_order);
+    a.counters = c->counters;
+    {
+        TimedScope ts(c, K_RENDER);
+        HIPCHK(launch_render(c->stream, c->fp64, a, dc));
+    }
+    {
+        TimedScope ts(c, K_FINALIZE);
+        HIPCHK(launch_render_finalize(c->stream, images, dc, 1.0 / (double)p->n));
+    }
+    c->paths_done += p->n;
+    return PRT_OK;
+}
+
+int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p, const double* residual, double* grad)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    int rc = check_scene(s);
+    if (rc) return rc;
+    if ((rc = check_match(s, p))) return rc;
+    if (!residual || !grad) return fail(PRT_E_INVALID, "residual/grad is NULL");
+    DevCams dc;
+    if ((rc = make_dev_cams(cams, s->voxel_km, &dc))) return rc;
+    DeviceGuard g(c->device);
+    const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
+    if ((rc = ensure_grids(c, nu))) return rc;
+    const int64_t npx = (int64_t)dc.n * dc.W * dc.H;
+    if ((rc = ensure_pix(c, npx))) return rc;
+    {
+        TimedScope ts(c, K_PREP);
+        HIPCHK(launch_fill(c->stream, grad, nu, 0.0));
+        HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
+                                 c->grid_dlt));
+        HIPCHK(launch_grad_prep(c->stream, residual, c->pix, dc, 1.0 / (double)p->n));
+    }
+    TraceArgs a{};
+    a.s = make_dev_scene(s);
+    a.st = view_of(p);
+    a.bc_t = s->beta_cloud;
+    a.grid_tot = c->grid_tot;
+    a.grid_dlt = c->grid_dlt;
+    a.rho = c->pix;
+    a.grad = grad;
+    a.brender = s->max_order;
+    a.counters = c->counters;
+    {
+        TimedScope ts(c, K_GRAD);
+        HIPCHK(launch_grad(c->stream, c->fp64, a, dc));
+    }
+    return PRT_OK;
+}
+
+int prt_reweight(prt_ctx c, const prt_scene* s, prt_paths p, double* mean_r, double* ess)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    int rc = check_scene(s);
+    if (rc) return rc;
+    if ((rc = check_match(s, p))) return rc;
+    if (!mean_r || !ess) return fail(PRT_E_INVALID, "mean_r/ess is NULL");
+    DeviceGuard g(c->device);
+    const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
+    if ((rc = ensure_grids(c, nu))) return rc;
+    const int64_t nblk = (p->n_slots + 255) / 256;
+    if ((rc = ensure_part(c, 2 * nblk))) return rc;
+    {
+        TimedScope ts(c, K_PREP);
+        HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
+                                 c->grid_dlt));
+    }
+    TraceArgs a{};
+    a.s = make_dev_scene(s);
+    a.st = view_of(p);
+    a.bc_t = s->beta_cloud;
+    a.grid_tot = c->grid_tot;
+    a.grid_dlt = c->grid_dlt;
+    a.partial = c->part;
+    a.counters = c->counters;
+    int64_t nb = 0;
+    {
+        TimedScope ts(c, K_REWEIGHT);
+        HIPCHK(launch_reweight(c->stream, c->fp64, a, &nb));
+        HIPCHK(launch_sum_pairs(c->stream, c->part, nb, c->out2));
+    }
+    double h[2];
+    HIPCHK(hipMemcpyAsync(h, c->out2, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *mean_r = h[0] / (double)p->n;
+    *ess = h[1] > 0 ? h[0] * h[0] / h[1] : 0.0;
+    return PRT_OK;
+}
+
+int prt_loss(prt_ctx c, int64_t n, const double* images, const double* target, double* residual, double* loss)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    if (n < 1 || !images || !target || !residual || !loss) return fail(PRT_E_INVALID, "bad loss arguments");
+    DeviceGuard g(c->device);
+    int rc = ensure_part(c, 2 * loss_blocks(n));
+    if (rc) return rc;
+    TimedScope ts(c, K_LOSS);
+    HIPCHK(launch_loss(c->stream, n, images, target, residual, c->part, loss));
+    return PRT_OK;
+}
+
+int prt_adam(prt_ctx c, int64_t n, double* beta, float* beta_f32, const double* grad, double* m, double* v, int32_t t,
+             double lr, double b1, double b2, double eps)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    if (n < 1 || !beta || !beta_f32 || !grad || !m || !v) return fail(PRT_E_INVALID, "bad adam arguments");
+    if (t < 1 || !finite_all({lr, b1, b2, eps}) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+        return fail(PRT_E_INVALID, "bad adam hyper-parameters");
+    DeviceGuard g(c->device);
+    TimedScope ts(c, K_ADAM);
+    HIPCHK(launch_adam(c->stream, n, beta, beta_f32, grad, m, v, lr, b1, b2, eps, 1.0 - std::pow(b1, t),
+                       1.0 - std::pow(b2, t)));
+    return PRT_OK;
+}
+
+int prt_counters(prt_ctx c, prt_counters_t* out, int reset)
+{
+    if (!c || !out) return fail(PRT_E_INVALID, "ctx/out is NULL");
+    DeviceGuard g(c->device);
+    unsigned long long h[4];
+    HIPCHK(hipMemcpyAsync(h, c->counters, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    out->voxel_segments = h[0];
+    out->local_estimates = h[1];
+    out->paths = c->paths_done;
+    out->overhead_segments = h[3];
+    if (reset) {
+        c->paths_done = 0;
+        HIPCHK(hipMemsetAsync(c->counters, 0, sizeof h, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return PRT_OK;
+}
+
+int prt_enable_timing(prt_ctx c, int enable)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    c->timing = enable != 0;
+    return PRT_OK;
+}
+
+int prt_kernel_times(prt_ctx c, double* total_ms, int64_t* launches, int n, int reset)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    DeviceGuard g(c->device);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (auto& t : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            c->total_ms[t.id] += ms;
+            c->launches[t.id] += 1;
+        }
+        c->pool.push_back(t.a);
+        c->pool.push_back(t.b);
+    }
+    c->pending.clear();
+    for (int i = 0; i < n && i < K_COUNT; ++i) {
+        if (total_ms) total_ms[i] = c->total_ms[i];
+        if (launches) launches[i] = c->launches[i];
+    }
+    if (reset)
+        for (int i = 0; i < K_COUNT; ++i) {
+            c->total_ms[i] = 0;
+            c->launches[i] = 0;
+        }
+    return K_COUNT;
+}
+
+const char* prt_kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "unknown"; }
+
+}  // extern "C"

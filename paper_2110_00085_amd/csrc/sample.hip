@@ -1,0 +1,339 @@
+// Path sampling (Sec. 3.4), the stable counting sort by path size (Sec. 5.3)
+// and the packing of the sorted paths into wavefront batches.
+#include "launch.hpp"
+
+namespace prt {
+
+// ------------------------------------------------------------- field prep
+
+template <typename Real>
+__global__ void __launch_bounds__(256) prep_grids_kernel(const float* __restrict__ bc_t,
+                                                         const float* __restrict__ bc_r, double beta_air,
+                                                         int64_t nu, Real* __restrict__ tot,
+                                                         Real* __restrict__ dlt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nu) return;
+    const double t = (double)bc_t[i];
+    tot[i] = (Real)(t + beta_air);
+    if (dlt) dlt[i] = (Real)(t - (double)bc_r[i]);
+}
+
+hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const float* bc_r, double beta_air,
+                             int64_t nu, void* grid_tot, void* grid_dlt)
+{
+    const int64_t blocks = (nu + 255) / 256;
+    if (fp64)
+        prep_grids_kernel<double><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(
+            bc_t, bc_r, beta_air, nu, (double*)grid_tot, (double*)grid_dlt);
+    else
+        prep_grids_kernel<float><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(
+            bc_t, bc_r, beta_air, nu, (float*)grid_tot, (float*)grid_dlt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- sampler
+
+__device__ __forceinline__ float4 vrec(double x, double y, double z, int v)
+{
+    return make_float4((float)x, (float)y, (float)z, __int_as_float(v));
+}
+
+// One thread per path id.  Entry point uniform over the projected box area;
+// free flights by the DDA until the optical depth passes tau = -ln u; at a
+// scatter the particle type is drawn with probability beta_s^(j)/beta_s and a
+// direction from its phase function; the path ends when it leaves the box or
+// after max_order scatters.  Vertices go to row id of tmp (stride max_order+2).
+template <typename Real>
+__global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= a.n) return;
+    const DevScene& s = a.s;
+    const Real* __restrict__ gt = (const Real*)a.grid_tot;
+    const int stride = s.max_order + 2;
+    float4* __restrict__ out = a.tmp + id * stride;
+
+    double u[4];
+    uniforms4(a.seed, (uint64_t)id, 0u, u);
+    const double A = s.a_top + s.a_x + s.a_y;
+    double x, y, z;
+    if (u[0] * A < s.a_top) {
+        x = u[1] * s.nx; y = u[2] * s.ny; z = (double)s.nz;
+    } else if (u[0] * A < s.a_top + s.a_x) {
+        x = s.x_face; y = u[1] * s.ny; z = u[2] * s.nz;
+    } else {
+        x = u[1] * s.nx; y = s.y_face; z = u[2] * s.nz;
+    }
+    int ix = min(max((int)floor(x), 0), s.nx - 1);
+    int iy = min(max((int)floor(y), 0), s.ny - 1);
+    int iz = min(max((int)floor(z), 0), s.nz - 1);
+    int v = ix + s.nx * (iy + s.ny * iz);
+    int nv = 0;
+    out[nv++] = vrec(x, y, z, v);
+    double w[3] = {s.sun[0], s.sun[1], s.sun[2]};
+    // optical depth target in units of (1/km * grid length)
+    double tau = -log(u[3]) / s.vk;
+    int b = 0;
+    for (;;) {
+        const Real taur = (Real)tau;
+        Real acc = (Real)0, thit = (Real)0;
+        int hit = -1;
+        const Real tend = dda_walk<Real>(
+            s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy, iz, (Real)w[0], (Real)w[1], (Real)w[2],
+            (Real)INFINITY, [&](int vv, Real t0, Real l) {
+                const Real bt = gt[vv];
+                const Real dt = bt * l;
+                if (taur < acc + dt) {
+                    hit = vv;
+                    thit = t0 + (taur - acc) / bt;
+                    return false;
+                }
+                acc += dt;
+                return true;
+            });
+        if (hit < 0) {
+            const double te = (double)tend;
+            out[nv++] = vrec(x + te * w[0], y + te * w[1], z + te * w[2], -1);
+            break;
+        }
+        if (sizeof(Real) == 8) {
+            const double th = (double)thit;
+            x = x + th * w[0]; y = y + th * w[1]; z = z + th * w[2];
+        } else {
+            const float th = (float)thit;
+            x = (double)((float)x + th * (float)w[0]);
+            y = (double)((float)y + th * (float)w[1]);
+            z = (double)((float)z + th * (float)w[2]);
+        }
+        ++b;
+        out[nv++] = vrec(x, y, z, hit);
+        if (b >= s.max_order) break;
+        voxel_ijk(hit, s.nx, s.ny, ix, iy, iz);
+        uniforms4(a.seed, (uint64_t)id, (uint32_t)b, u);
+        const double bsc = s.w_c * (double)a.beta_c[hit];
+        const double bs = bsc + s.w_a * s.beta_air;
+        const double mu = (u[0] * bs < bsc) ? sample_hg(u[1], s.g) : sample_rayleigh(u[1]);
+        double wn[3];
+        scatter_direction(w, mu, 2.0 * kPi * u[2], wn);
+        w[0] = wn[0]; w[1] = wn[1]; w[2] = wn[2];
+        tau = -log(u[3]) / s.vk;
+    }
+    a.tB[id] = (uint8_t)b;
+    a.tnv[id] = (uint8_t)nv;
+}
+
+hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a)
+{
+    const int64_t blocks = (a.n + 255) / 256;
+    if (fp64)
+        sample_kernel<double><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
+    else
+        sample_kernel<float><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------- stable counting sort
+
+// Keys (path sizes) are processed in tiles of kSortTile; tile t's count of
+// key k lives at hist[k * n_tiles + t], so an exclusive scan of hist in that
+// order gives every (key, tile) its first output position.
+constexpr int kSortTile = 1024;
+constexpr int kMaxBins = kMaxOrder + 1;
+
+__global__ void __launch_bounds__(256) sort_hist_kernel(const uint8_t* __restrict__ key, int64_t n, int nbins,
+                                                        int64_t n_tiles, uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t h[kMaxBins];
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int j = threadIdx.x; j < kSortTile; j += blockDim.x) {
+        const int64_t i = base + j;
+        if (i < n) atomicAdd(&h[min((int)key[i], nbins - 1)], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nbins; k += blockDim.x) hist[(int64_t)k * n_tiles + blockIdx.x] = h[k];
+}
+
+// Single-workgroup exclusive scan (in place) of m uint32 values: each thread
+// sums a contiguous chunk, the chunk sums are scanned in LDS, then each
+// thread rewrites its chunk.
+__global__ void __launch_bounds__(1024) scan_u32_kernel(uint32_t* __restrict__ a, int64_t m)
+{
+    __shared__ uint32_t sums[1024];
+    const int64_t chunk = (m + 1023) / 1024;
+    const int64_t lo = min((int64_t)threadIdx.x * chunk, m), hi = min(lo + chunk, m);
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += a[i];
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t add = threadIdx.x >= (unsigned)off ? sums[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sums[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? sums[threadIdx.x - 1] : 0u;
+    for (int64_t i = lo; i < hi; ++i) {
+        const uint32_t c = a[i];
+        a[i] = run;
+        run += c;
+    }
+}
+
+// Thread k of a tile owns key k: it walks the tile in id order and assigns
+// consecutive output positions to the ids with that key (stable).
+__global__ void __launch_bounds__(128) sort_scatter_kernel(const uint8_t* __restrict__ key, int64_t n, int nbins,
+                                                           int64_t n_tiles, const uint32_t* __restrict__ off,
+                                                           int32_t* __restrict__ perm)
+{
+    __shared__ uint8_t kt[kSortTile];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int j = threadIdx.x; j < kSortTile; j += blockDim.x) {
+        const int64_t i = base + j;
+        kt[j] = i < n ? (uint8_t)min((int)key[i], nbins - 1) : (uint8_t)0xFF;
+    }
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k >= nbins) return;
+    uint32_t pos = off[(int64_t)k * n_tiles + blockIdx.x];
+    const int cnt = (int)min((int64_t)kSortTile, n - base);
+    for (int j = 0; j < cnt; ++j)
+        if (kt[j] == k) perm[pos++] = (int32_t)(base + j);
+}
+
+int64_t sort_scratch_words(int64_t n, int nbins)
+{
+    return ((n + kSortTile - 1) / kSortTile) * (int64_t)nbins;
+}
+
+hipError_t launch_sort_by_size(hipStream_t st, const uint8_t* key, int64_t n, int nbins, uint32_t* blockhist,
+                               int32_t* perm)
+{
+    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    sort_hist_kernel<<<dim3((unsigned)n_tiles), dim3(256), 0, st>>>(key, n, nbins, n_tiles, blockhist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    scan_u32_kernel<<<dim3(1), dim3(1024), 0, st>>>(blockhist, n_tiles * nbins);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sort_scatter_kernel<<<dim3((unsigned)n_tiles), dim3(128), 0, st>>>(key, n, nbins, n_tiles, blockhist, perm);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- packing
+
+__global__ void __launch_bounds__(256) gather_sizes_kernel(const int32_t* __restrict__ perm,
+                                                           const uint8_t* __restrict__ tB,
+                                                           const uint8_t* __restrict__ tnv, int64_t n,
+                                                           int64_t n_slots, uint8_t* __restrict__ B,
+                                                           uint8_t* __restrict__ nv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_slots) return;
+    if (i < n) {
+        const int32_t id = perm[i];
+        B[i] = tB[id];
+        nv[i] = tnv[id];
+    } else {
+        B[i] = 0;
+        nv[i] = 0;
+    }
+}
+
+hipError_t launch_gather_sizes(hipStream_t st, const int32_t* perm, const uint8_t* tB, const uint8_t* tnv,
+                               int64_t n, int64_t n_slots, uint8_t* B, uint8_t* nv)
+{
+    gather_sizes_kernel<<<dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, st>>>(perm, tB, tnv, n, n_slots,
+                                                                                      B, nv);
+    return hipGetLastError();
+}
+
+// batch_off[b] = 64 * sum_{b' < b} rows(b'), rows(b) = max stored vertices
+// over the batch; batch_off[nb] is the total record count.
+__global__ void __launch_bounds__(1024) batch_offsets_kernel(const uint8_t* __restrict__ nv, int64_t nb,
+                                                             int64_t* __restrict__ off)
+{
+    __shared__ int64_t sums[1024];
+    const int64_t chunk = (nb + 1023) / 1024;
+    const int64_t lo = min((int64_t)threadIdx.x * chunk, nb), hi = min(lo + chunk, nb);
+    auto rows = [&](int64_t b) {
+        int r = 0;
+        for (int l = 0; l < kWave; ++l) r = max(r, (int)nv[b * kWave + l]);
+        return (int64_t)r * kWave;
+    };
+    int64_t s = 0;
+    for (int64_t b = lo; b < hi; ++b) s += rows(b);
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t add = threadIdx.x >= (unsigned)o ? sums[threadIdx.x - o] : 0;
+        __syncthreads();
+        sums[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x ? sums[threadIdx.x - 1] : 0;
+    for (int64_t b = lo; b < hi; ++b) {
+        off[b] = run;
+        run += rows(b);
+    }
+    if (threadIdx.x == 1023) off[nb] = sums[1023];
+}
+
+hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, int64_t* batch_off)
+{
+    batch_offsets_kernel<<<dim3(1), dim3(1024), 0, st>>>(nv, nb, batch_off);
+    return hipGetLastError();
+}
+
+// One thread per sorted slot: copy the path's records into its lane of the
+// batch (rows beyond its own vertex count are zero-filled).
+__global__ void __launch_bounds__(256) pack_kernel(const int32_t* __restrict__ perm, const float4* __restrict__ tmp,
+                                                   const int64_t* __restrict__ tmp_off, int64_t tmp_stride,
+                                                   const uint8_t* __restrict__ nv,
+                                                   const int64_t* __restrict__ batch_off, int64_t n,
+                                                   int64_t n_slots, float4* __restrict__ vtx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_slots) return;
+    const int64_t b = i / kWave, lane = i % kWave;
+    const int64_t rows = (batch_off[b + 1] - batch_off[b]) / kWave;
+    float4* dst = vtx + batch_off[b] + lane;
+    const int cnt = i < n ? (int)nv[i] : 0;
+    const float4* src = nullptr;
+    if (i < n) {
+        const int64_t id = perm[i];
+        src = tmp + (tmp_off ? tmp_off[id] : id * tmp_stride);
+    }
+    for (int64_t k = 0; k < rows; ++k) dst[k * kWave] = k < cnt ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, const int64_t* tmp_off,
+                       int64_t tmp_stride, const uint8_t* nv, const int64_t* batch_off, int64_t n, int64_t n_slots,
+                       float4* vtx)
+{
+    pack_kernel<<<dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, st>>>(perm, tmp, tmp_off, tmp_stride, nv,
+                                                                              batch_off, n, n_slots, vtx);
+    return hipGetLastError();
+}
+
+// Index of the first sorted slot with B > 0 (n if none); slots are sorted by B.
+__global__ void first_nonzero_kernel(const uint8_t* __restrict__ B, int64_t n, int64_t* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (B[mid] > 0) hi = mid; else lo = mid + 1;
+    }
+    *out = lo;
+}
+
+hipError_t launch_first_nonzero(hipStream_t st, const uint8_t* B, int64_t n, int64_t* out)
+{
+    first_nonzero_kernel<<<dim3(1), dim3(64), 0, st>>>(B, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace prt

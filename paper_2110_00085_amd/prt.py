@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libprt.so (include/prt.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Device
+buffers are torch tensors (their data pointers are passed through); host
+arrays are numpy arrays.  A nonzero status raises PrtError with the
+library's message.  The binding refuses to run without the built HIP
+library: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprt.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "prt.h")
+
+PRT_OK, PRT_E_INVALID, PRT_E_NOMEM, PRT_E_CAPACITY, PRT_E_MISMATCH, PRT_E_HIP = 0, -1, -2, -3, -4, -5
+PRT_TRAVERSAL_FP32, PRT_ALL_FP64 = 0, 1
+PRT_MAX_CAMERAS, PRT_MAX_ORDER = 24, 64
+
+
+class PrtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"prt error {code}: {msg}")
+        self.code = code
+
+
+class prt_scene(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("max_order", C.c_int32),
+                ("voxel_km", C.c_double), ("beta_air", C.c_double), ("albedo_cloud", C.c_double),
+                ("albedo_air", C.c_double), ("g", C.c_double), ("sun_zenith_deg", C.c_double),
+                ("sun_azimuth_deg", C.c_double), ("sun_flux", C.c_double), ("beta_cloud", C.c_void_p)]
+
+
+class prt_cameras(C.Structure):
+    _fields_ = [("n", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("pad", C.c_int32),
+                ("pos", C.c_void_p), ("rot", C.c_void_p), ("f_px", C.c_void_p)]
+
+
+class prt_counters_t(C.Structure):
+    _fields_ = [("voxel_segments", C.c_uint64), ("local_estimates", C.c_uint64), ("paths", C.c_uint64),
+                ("overhead_segments", C.c_uint64)]
+
+
+class prt_paths_info_t(C.Structure):
+    _fields_ = [("n_paths", C.c_uint64), ("n_vertices", C.c_uint64), ("n_batches", C.c_uint64),
+                ("seed", C.c_uint64), ("bytes", C.c_uint64), ("max_order", C.c_int32), ("nx", C.c_int32),
+                ("ny", C.c_int32), ("nz", C.c_int32)]
+
+
+_lib = None
+_V, _I32, _I64, _U64, _D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+
+
+def lib():
+    """Load libprt.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "prt_create": ([C.c_int, _V, C.c_int, C.POINTER(_V)], C.c_int),
+            "prt_destroy": ([_V], None),
+            "prt_set_stream": ([_V, _V], C.c_int),
+            "prt_last_error": ([], C.c_char_p),
+            "prt_sample": ([_V, C.POINTER(prt_scene), _U64, _U64, C.POINTER(_V)], C.c_int),
+            "prt_paths_import": ([_V, C.POINTER(prt_scene), _U64, _V, _V, _V, _V, _V, _U64, C.POINTER(_V)], C.c_int),
+            "prt_paths_export": ([_V, _V, _V, _V, _V, _V, _V], C.c_int),
+            "prt_paths_permutation": ([_V, _V, _V], C.c_int),
+            "prt_paths_info": ([_V, C.POINTER(prt_paths_info_t)], C.c_int),
+            "prt_paths_destroy": ([_V], None),
+            "prt_render": ([_V, C.POINTER(prt_scene), C.POINTER(prt_cameras), _V, _I32, _V], C.c_int),
+            "prt_grad": ([_V, C.POINTER(prt_scene), C.POINTER(prt_cameras), _V, _V, _V], C.c_int),
+            "prt_reweight": ([_V, C.POINTER(prt_scene), _V, C.POINTER(_D), C.POINTER(_D)], C.c_int),
+            "prt_loss": ([_V, _I64, _V, _V, _V, _V], C.c_int),
+            "prt_adam": ([_V, _I64, _V, _V, _V, _V, _V, _I32, _D, _D, _D, _D], C.c_int),
+            "prt_counters": ([_V, C.POINTER(prt_counters_t), C.c_int], C.c_int),
+            "prt_enable_timing": ([_V, C.c_int], C.c_int),
+            "prt_kernel_times": ([_V, _V, _V, C.c_int, C.c_int], C.c_int),
+            "prt_kernel_name": ([C.c_int], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PRT_OK:
+        raise PrtError(rc, lib().prt_last_error().decode())
+
+
+def _dptr(t) -> int:
+    """Device pointer of a contiguous torch tensor."""
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _hptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ------------------------------------------------------------ marshalling
+
+def make_scene(params, beta_cloud) -> prt_scene:
+    """prt_scene from an object with the scene attributes and a device
+    float32 tensor beta_cloud [nz][ny][nx]."""
+    import torch
+    if beta_cloud.dtype != torch.float32 or not beta_cloud.is_cuda:
+        raise ValueError("beta_cloud must be a float32 device tensor")
+    if beta_cloud.numel() != params.nx * params.ny * params.nz:
+        raise ValueError("beta_cloud size does not match the grid")
+    return prt_scene(params.nx, params.ny, params.nz, params.max_order, params.voxel_km, params.beta_air,
+                     params.albedo_cloud, params.albedo_air, params.g, params.sun_zenith_deg,
+                     params.sun_azimuth_deg, params.sun_flux, _dptr(beta_cloud))
+
+
+class CamerasHost:
+    """prt_cameras with its host arrays kept alive."""
+
+    def __init__(self, cams):
+        self.pos = np.ascontiguousarray(cams.pos, dtype=np.float64)
+        self.rot = np.ascontiguousarray(cams.rot, dtype=np.float64)
+        self.f = np.ascontiguousarray(cams.f_px, dtype=np.float64)
+        self.n, self.width, self.height = int(cams.n), int(cams.width), int(cams.height)
+        self.s = prt_cameras(self.n, self.width, self.height, 0, _hptr(self.pos).value, _hptr(self.rot).value,
+                             _hptr(self.f).value)
+
+    @property
+    def image_shape(self):
+        return (self.n, self.height, self.width)
+
+
+# ---------------------------------------------------------- entry points
+
+def prt_create(device: int = 0, stream: int | None = None, precision: int = PRT_TRAVERSAL_FP32):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device).cuda_stream
+    h = _V()
+    _check(lib().prt_create(device, stream, precision, C.byref(h)))
+    return h
+
+
+def prt_destroy(ctx):
+    lib().prt_destroy(ctx)
+
+
+def prt_set_stream(ctx, stream: int):
+    _check(lib().prt_set_stream(ctx, stream))
+
+
+def prt_sample(ctx, scene: prt_scene, seed: int, n_paths: int):
+    h = _V()
+    _check(lib().prt_sample(ctx, C.byref(scene), seed, n_paths, C.byref(h)))
+    return h
+
+
+def prt_paths_import(ctx, scene: prt_scene, off, xyz, vox, B, beta_ref, seed: int = 0):
+    off = np.ascontiguousarray(off, np.int64)
+    xyz = np.ascontiguousarray(xyz, np.float32)
+    vox = np.ascontiguousarray(vox, np.int32)
+    B = np.ascontiguousarray(B, np.int32)
+    br = np.ascontiguousarray(beta_ref, np.float32).ravel()
+    h = _V()
+    _check(lib().prt_paths_import(ctx, C.byref(scene), len(B), _hptr(off), _hptr(xyz), _hptr(vox), _hptr(B),
+                                  _hptr(br), seed, C.byref(h)))
+    return h
+
+
+def prt_paths_info(paths) -> prt_paths_info_t:
+    info = prt_paths_info_t()
+    _check(lib().prt_paths_info(paths, C.byref(info)))
+    return info
+
+
+def prt_paths_export(ctx, paths, vertices: bool = True):
+    """(off, xyz, vox, B, beta_ref) as numpy arrays in path-id order."""
+    info = prt_paths_info(paths)
+    n = int(info.n_paths)
+    off = np.zeros(n + 1, np.int64)
+    B = np.zeros(n, np.int32)
+    _check(lib().prt_paths_export(ctx, paths, _hptr(off), None, None, _hptr(B), None))
+    if not vertices:
+        return off, None, None, B, None
+    nv = int(off[-1])
+    xyz = np.zeros((nv, 3), np.float32)
+    vox = np.zeros(nv, np.int32)
+    br = np.zeros(info.nx * info.ny * info.nz, np.float32)
+    _check(lib().prt_paths_export(ctx, paths, _hptr(off), _hptr(xyz), _hptr(vox), _hptr(B), _hptr(br)))
+    return off, xyz, vox, B, br.reshape(info.nz, info.ny, info.nx)
+
+
+def prt_paths_permutation(ctx, paths) -> np.ndarray:
+    n = int(prt_paths_info(paths).n_paths)
+    perm = np.zeros(n, np.int32)
+    _check(lib().prt_paths_permutation(ctx, paths, _hptr(perm)))
+    return perm
+
+
+def prt_paths_destroy(paths):
+    lib().prt_paths_destroy(paths)
+
+
+def prt_render(ctx, scene: prt_scene, cams: CamerasHost, paths, max_order_render: int, images):
+    _check(lib().prt_render(ctx, C.byref(scene), C.byref(cams.s), paths, int(max_order_render), _dptr(images)))
+
+
+def prt_grad(ctx, scene: prt_scene, cams: CamerasHost, paths, residual, grad):
+    _check(lib().prt_grad(ctx, C.byref(scene), C.byref(cams.s), paths, _dptr(residual), _dptr(grad)))
+
+
+def prt_reweight(ctx, scene: prt_scene, paths):
+    m, e = _D(), _D()
+    _check(lib().prt_reweight(ctx, C.byref(scene), paths, C.byref(m), C.byref(e)))
+    return m.value, e.value
+
+
+def prt_loss(ctx, images, target, residual, loss):
+    _check(lib().prt_loss(ctx, images.numel(), _dptr(images), _dptr(target), _dptr(residual), _dptr(loss)))
+
+
+def prt_adam(ctx, beta, beta_f32, grad, m, v, t: int, lr: float, b1: float = 0.9, b2: float = 0.999,
+             eps: float = 1e-8):
+    _check(lib().prt_adam(ctx, beta.numel(), _dptr(beta), _dptr(beta_f32), _dptr(grad), _dptr(m), _dptr(v),
+                          int(t), lr, b1, b2, eps))
+
+
+def prt_counters(ctx, reset: bool = False) -> dict:
+    c = prt_counters_t()
+    _check(lib().prt_counters(ctx, C.byref(c), int(reset)))
+    return {"voxel_segments": c.voxel_segments, "local_estimates": c.local_estimates, "paths": c.paths,
+            "overhead_segments": c.overhead_segments}
+
+
+def prt_enable_timing(ctx, enable: bool = True):
+    _check(lib().prt_enable_timing(ctx, int(enable)))
+
+
+def prt_kernel_times(ctx, reset: bool = False) -> dict:
+    ms = np.zeros(32, np.float64)
+    cnt = np.zeros(32, np.int64)
+    k = lib().prt_kernel_times(ctx, _hptr(ms), _hptr(cnt), 32, int(reset))
+    if k < 0:
+        _check(k)
+    return {lib().prt_kernel_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
+
+
+def prt_kernel_name(i: int) -> str:
+    return lib().prt_kernel_name(i).decode()
+
+
+def header_entry_points() -> list[str]:
+    """Names of the functions declared in include/prt.h."""
+    import re
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(prt_\w+)\s*\(", src, re.M)))
+
+
+def prt_last_error() -> str:
+    return lib().prt_last_error().decode()

@@ -1,0 +1,321 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs and, for render/grad/reweight, on identical stored paths
+drawn by the oracle and imported into the library.
+
+Tolerances: FP32 traversal mode -- images 1e-5, gradients 1e-4 relative (L2),
+correction-factor statistics 1e-5; all-FP64 mode -- 1e-9 (only the
+summation order of the FP64 atomics and libm ulps differ)."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": {"img": 1e-5, "grad": 1e-4, "rw": 1e-5}, "fp64": {"img": 1e-9, "grad": 1e-9, "rw": 1e-10}}
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2110_00085_amd import api, prt
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    prt.lib()  # fails loudly when the HIP library is missing
+    return torch, prt, api
+
+
+def _prec(P, name):
+    return P.PRT_ALL_FP64 if name == "fp64" else P.PRT_TRAVERSAL_FP32
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _perturbed(scene, seed=5, amp=0.15):
+    rng = np.random.default_rng(seed)
+    return (scene.beta_cloud * (1 + amp * rng.uniform(-1, 1, scene.beta_cloud.shape))).astype(np.float32)
+
+
+def _store(api, ctx, torch, scene, paths):
+    return api.PathStore.from_host(ctx, scene, _dev(torch, scene.beta_cloud), paths.off, paths.xyz, paths.vox,
+                                   paths.B, paths.beta_ref, paths.seed)
+
+
+def _workload(name):
+    if name == "cloud8":
+        s = inputs.cloud8()
+        return s, inputs.cloud8_cameras(s), 10_000, 1001
+    if name == "cloud32mid":
+        s = inputs.cloud32()
+        return s, inputs.cloud32_cameras(s), (1 << 15) + 37, 1002
+    raise KeyError(name)
+
+
+# ---------------------------------------------------------------- sampling
+
+def test_sample_fp64_matches_oracle(env):
+    torch, P, api = env
+    scene, _, n, seed = _workload("cloud8")
+    say(f"sample fp64 cloud8 n={n}")
+    ctx = api.Context(0, P.PRT_ALL_FP64)
+    st = api.PathStore.sample(ctx, scene, _dev(torch, scene.beta_cloud), seed, n)
+    off, xyz, vox, B, br = st.export()
+    ref = oracle.sample(scene, seed, n)
+    assert np.array_equal(br, scene.beta_cloud)
+    same = B == ref.B
+    assert same.mean() >= 0.9995, same.mean()
+    for i in np.nonzero(same)[0][::7]:
+        a, b = xyz[off[i]:off[i + 1]], ref.xyz[ref.off[i]:ref.off[i + 1]]
+        assert a.shape == b.shape
+        assert np.abs(a.astype(float) - b).max() <= 2e-6 * 8, i
+        assert np.array_equal(vox[off[i]:off[i + 1]], ref.vox[ref.off[i]:ref.off[i + 1]])
+    perm = P.prt_paths_permutation(ctx.handle, st.handle)
+    assert np.array_equal(perm, oracle.sort_permutation(B))
+
+
+@pytest.mark.parametrize("name", ["cloud8", "cloud32mid"])
+def test_sample_fp32_close_to_oracle(env, name):
+    torch, P, api = env
+    scene, _, n, seed = _workload(name)
+    say(f"sample fp32 {name} n={n}")
+    ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
+    st = api.PathStore.sample(ctx, scene, _dev(torch, scene.beta_cloud), seed, n)
+    off, xyz, vox, B, _ = st.export()
+    ref = oracle.sample(scene, seed, n)
+    same = B == ref.B
+    assert same.mean() >= 0.995, same.mean()
+    dev = []
+    for i in np.nonzero(same & (B > 0))[0][:3000]:
+        a, b = xyz[off[i]:off[i + 1]].astype(float), ref.xyz[ref.off[i]:ref.off[i + 1]].astype(float)
+        dev.append(np.abs(a - b).max())
+    assert np.median(dev) < 1e-4, np.median(dev)
+    perm = P.prt_paths_permutation(ctx.handle, st.handle)
+    assert np.array_equal(perm, oracle.sort_permutation(B))
+
+
+# ---------------------------------------------- render / grad / reweight
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["cloud8", "cloud32mid"])
+def test_render_grad_reweight_match_oracle(env, prec, name):
+    torch, P, api = env
+    scene, cams, n, seed = _workload(name)
+    say(f"render/grad/reweight {prec} {name} n={n}")
+    paths = oracle.sample(scene, seed, n)
+    beta_t = _perturbed(scene)
+    ctx = api.Context(0, _prec(P, prec))
+    st = _store(api, ctx, torch, scene, paths)
+    ch = P.CamerasHost(cams)
+    bt = _dev(torch, beta_t)
+    tol = TOL[prec]
+    for br in (scene.max_order, 1, 3):
+        img = api.render(ctx, scene, bt, ch, st, br).cpu().numpy()
+        ref = oracle.render(scene, cams, paths, beta_t=beta_t, max_order_render=br)
+        assert np.abs(ref).max() > 0
+        assert _rel(img, ref) <= tol["img"], (br, _rel(img, ref))
+    rng = np.random.default_rng(3)
+    res = rng.standard_normal(ref.shape) * np.abs(ref).mean()
+    g = api.grad(ctx, scene, bt, ch, st, torch.as_tensor(res).cuda()).cpu().numpy()
+    gref = oracle.grad(scene, cams, paths, res, beta_t=beta_t)
+    assert np.abs(gref).max() > 0
+    assert _rel(g, gref) <= tol["grad"], _rel(g, gref)
+    mr, ess = P.prt_reweight(ctx.handle, P.make_scene(scene, bt), st.handle)
+    mr_ref, ess_ref = oracle.reweight(scene, paths, beta_t=beta_t)
+    assert abs(mr - mr_ref) <= tol["rw"] * abs(mr_ref), (mr, mr_ref)
+    assert abs(ess - ess_ref) <= tol["rw"] * abs(ess_ref), (ess, ess_ref)
+
+
+def test_counters_match_oracle(env):
+    torch, P, api = env
+    scene, cams, n, seed = _workload("cloud8")
+    say("counters fp64 cloud8")
+    paths = oracle.sample(scene, seed, n)
+    ctx = api.Context(0, P.PRT_ALL_FP64)
+    st = _store(api, ctx, torch, scene, paths)
+    P.prt_counters(ctx.handle, reset=True)
+    api.render(ctx, scene, _dev(torch, scene.beta_cloud), P.CamerasHost(cams), st)
+    c = P.prt_counters(ctx.handle, reset=True)
+    _, cref = oracle.render(scene, cams, paths, return_counters=True)
+    assert c["local_estimates"] == cref[1]
+    assert abs(c["voxel_segments"] - cref[0]) <= 1e-4 * cref[0], (c, cref)
+    assert c["paths"] == n
+
+
+def test_full_size_cloud32(env):
+    """The benchmark workload (32^3, 9 x 64^2 cameras, 2^22 paths, 20 orders)
+    in the launch configuration the bench times (FP32 traversal)."""
+    torch, P, api = env
+    scene, cams = inputs.cloud32(), None
+    cams = inputs.cloud32_cameras(scene)
+    n, seed = 1 << 22, 1002
+    say(f"full size cloud32 n={n}: oracle sampling")
+    paths = oracle.sample(scene, seed, n)
+    beta_t = _perturbed(scene, seed=7, amp=0.1)
+    ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
+    st = _store(api, ctx, torch, scene, paths)
+    ch = P.CamerasHost(cams)
+    bt = _dev(torch, beta_t)
+    say("full size: gpu render")
+    img = api.render(ctx, scene, bt, ch, st).cpu().numpy()
+    say("full size: oracle render")
+    ref = oracle.render(scene, cams, paths, beta_t=beta_t)
+    assert _rel(img, ref) <= TOL["fp32"]["img"], _rel(img, ref)
+    res = np.random.default_rng(4).standard_normal(ref.shape) * np.abs(ref).mean()
+    say("full size: gpu grad")
+    g = api.grad(ctx, scene, bt, ch, st, torch.as_tensor(res).cuda()).cpu().numpy()
+    say("full size: oracle grad")
+    gref = oracle.grad(scene, cams, paths, res, beta_t=beta_t)
+    assert _rel(g, gref) <= TOL["fp32"]["grad"], _rel(g, gref)
+    mr, ess = P.prt_reweight(ctx.handle, P.make_scene(scene, bt), st.handle)
+    mr_ref, ess_ref = oracle.reweight(scene, paths, beta_t=beta_t)
+    assert abs(mr - mr_ref) <= 1e-5 * mr_ref and abs(ess - ess_ref) <= 1e-5 * ess_ref
+
+
+# ------------------------------------------------------------- loop glue
+
+def test_loss_and_adam_match_oracle(env):
+    torch, P, api = env
+    say("loss + adam")
+    ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
+    rng = np.random.default_rng(8)
+    n = 100_003
+    img, tgt = rng.standard_normal(n), rng.standard_normal(n)
+    res = torch.empty(n, dtype=torch.float64, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    P.prt_loss(ctx.handle, torch.as_tensor(img).cuda(), torch.as_tensor(tgt).cuda(), res, loss)
+    L, r = oracle.loss_and_residual(img, tgt)
+    assert np.array_equal(res.cpu().numpy(), r)
+    assert abs(loss.item() - L) <= 1e-12 * L
+    beta = rng.uniform(0, 1, 5000)
+    b = torch.as_tensor(beta.copy()).cuda()
+    b32 = torch.empty(5000, dtype=torch.float32, device="cuda")
+    m = torch.zeros(5000, dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(m)
+    mo, vo = np.zeros(5000), np.zeros(5000)
+    for t in range(1, 4):
+        g = rng.standard_normal(5000)
+        P.prt_adam(ctx.handle, b, b32, torch.as_tensor(g).cuda(), m, v, t, 0.1)
+        beta, mo, vo = oracle.adam_step(beta, g, mo, vo, t, 0.1)
+    assert np.allclose(b.cpu().numpy(), beta, rtol=1e-13, atol=1e-15)
+    assert np.array_equal(b32.cpu().numpy(), beta.astype(np.float32))
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_edge_cases(env):
+    torch, P, api = env
+    say("edge cases")
+    ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
+    scene, cams, _, _ = _workload("cloud8")
+    ch = P.CamerasHost(cams)
+    # a single path
+    paths = oracle.sample(scene, 1001, 1, ids=[37])
+    st = _store(api, ctx, torch, scene, paths)
+    bt = _dev(torch, scene.beta_cloud)
+    img = api.render(ctx, scene, bt, ch, st).cpu().numpy()
+    assert _rel(img, oracle.render(scene, cams, paths)) <= 1e-5 or np.abs(img).max() == 0
+    # an empty medium: no path scatters, images and gradient vanish, r = 1
+    empty = scene.with_beta(np.zeros_like(scene.beta_cloud))
+    empty.beta_air = 0.0
+    z = _dev(torch, empty.beta_cloud)
+    st0 = api.PathStore.sample(ctx, empty, z, 5, 777)
+    _, _, _, B, _ = st0.export(vertices=False)
+    assert (B == 0).all()
+    assert np.abs(api.render(ctx, empty, z, ch, st0).cpu().numpy()).max() == 0.0
+    res = torch.ones(ch.image_shape, dtype=torch.float64, device="cuda")
+    assert np.abs(api.grad(ctx, empty, z, ch, st0, res).cpu().numpy()).max() == 0.0
+    mr, ess = P.prt_reweight(ctx.handle, P.make_scene(empty, z), st0.handle)
+    assert mr == 1.0 and abs(ess - 777) < 1e-9
+    # one scattering order only; capped paths
+    s1 = inputs.cloud8()
+    s1.max_order = 1
+    p1 = oracle.sample(s1, 9, 3000)
+    assert (p1.B <= 1).all() and (p1.B == 1).any()
+    st1 = _store(api, ctx, torch, s1, p1)
+    img1 = api.render(ctx, s1, _dev(torch, s1.beta_cloud), ch, st1).cpu().numpy()
+    assert _rel(img1, oracle.render(s1, cams, p1)) <= 1e-5
+    # cameras that see nothing
+    far = inputs.cameras_at([[100.0, 100.0, 100.0]], [[200.0, 200.0, 200.0]], 8, 8, 10.0)
+    assert np.abs(api.render(ctx, scene, bt, P.CamerasHost(far), st1).cpu().numpy()).max() == 0.0
+    # repeated renders agree to rounding of the atomic summation order
+    st2 = _store(api, ctx, torch, scene, oracle.sample(scene, 1001, 10_000))
+    a = api.render(ctx, scene, bt, ch, st2).cpu().numpy()
+    b = api.render(ctx, scene, bt, ch, st2).cpu().numpy()
+    assert _rel(a, b) <= 1e-13
+
+
+def test_argument_errors(env):
+    torch, P, api = env
+    say("argument errors")
+    ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
+    scene, cams, _, _ = _workload("cloud8")
+    bt = _dev(torch, scene.beta_cloud)
+    st = api.PathStore.sample(ctx, scene, bt, 1, 1000)
+    ch = P.CamerasHost(cams)
+    img = torch.empty(ch.image_shape, dtype=torch.float64, device="cuda")
+    other = inputs.random_field((4, 4, 4))
+    with pytest.raises(P.PrtError) as e:
+        P.prt_render(ctx.handle, P.make_scene(other, _dev(torch, other.beta_cloud)), ch, st.handle, 10, img)
+    assert e.value.code == P.PRT_E_MISMATCH
+    bad = inputs.cloud8()
+    bad.albedo_cloud = 1.5
+    with pytest.raises(P.PrtError) as e:
+        P.prt_render(ctx.handle, P.make_scene(bad, bt), ch, st.handle, 10, img)
+    assert e.value.code == P.PRT_E_INVALID
+    many = inputs.arc_cameras(scene, np.linspace(-60, 60, 25), 4, 4)
+    with pytest.raises(P.PrtError) as e:
+        P.prt_render(ctx.handle, P.make_scene(scene, bt), P.CamerasHost(many), st.handle, 10, img)
+    assert e.value.code == P.PRT_E_CAPACITY
+    bad2 = inputs.cloud8()
+    bad2.max_order = 0
+    with pytest.raises(P.PrtError) as e:
+        P.prt_sample(ctx.handle, P.make_scene(bad2, bt), 1, 10)
+    assert e.value.code == P.PRT_E_CAPACITY
+
+
+# -------------------------------------------------------------- autograd
+
+def test_autograd_function_and_finite_differences(env):
+    """RenderFn.backward equals prt_grad, and (all-FP64) matches central finite
+    differences of the rendered loss at fixed paths."""
+    torch, P, api = env
+    say("autograd + finite differences")
+    sc = inputs.random_field((4, 4, 4), voxel_km=0.1, lo=0.5, hi=8.0, seed=21, albedo_cloud=0.9, g=0.85,
+                             max_order=12)
+    cams = inputs.arc_cameras(sc, [-40.0, 0.0, 35.0], 8, 8)
+    ctx = api.Context(0, P.PRT_ALL_FP64)
+    st = api.PathStore.sample(ctx, sc, _dev(torch, sc.beta_cloud), 404, 3000)
+    ch = P.CamerasHost(cams)
+    beta = torch.as_tensor(_perturbed(sc, 3, 0.2).astype(np.float64)).cuda().requires_grad_(True)
+    tgt = torch.as_tensor(np.random.default_rng(2).uniform(0, 1, ch.image_shape)).cuda()
+    img = api.RenderFn.apply(beta, ctx, sc, ch, st)
+    loss = 0.5 * ((img - tgt) ** 2).sum()
+    loss.backward()
+    g = beta.grad.detach().cpu().numpy()
+    g2 = api.grad(ctx, sc, beta.detach().float(), ch, st, (img - tgt).detach().contiguous()).cpu().numpy()
+    assert np.allclose(g, g2, rtol=1e-12, atol=1e-14 * np.abs(g).max())
+
+    def L(b64):
+        with torch.no_grad():
+            im = api.render(ctx, sc, b64.float().contiguous(), ch, st)
+            return float(0.5 * ((im - tgt) ** 2).sum())
+
+    b0 = beta.detach().float().double()
+    h = 2.0 ** -8
+    for v in [0, 13, 27, 42, 63]:
+        e = torch.zeros_like(b0).view(-1)
+        e[v] = h
+        e = e.view_as(b0)
+        fd = (L(b0 + e) - L(b0 - e)) / (2 * h)
+        assert abs(fd - g.ravel()[v]) <= 1e-5 * np.abs(g).max() + 1e-9 * abs(fd), (v, fd, g.ravel()[v])
