@@ -1,0 +1,226 @@
+"""Throughput of the path-recycling tomography hot path on one MI355X.
+
+One step = one pass over every row of the hot path on the same batch of
+synthetic input: resample (Philox path sampling, counting sort by size,
+wavefront packing, reference snapshot), recycled render with local
+estimation, appearance loss, path-reuse gradient, Adam step with
+projection, and the correction-factor statistics at the updated field.
+The reported value is paths per second of that full step (forward +
+backward), N / (step time).  The recycled step (the same without the
+resample, which path recycling skips on most iterations) is reported
+alongside.
+
+Workload (default): 32^3 smoothed random cloud, 20 m voxels, 0-60 1/km,
+w_c 0.99, g 0.85, air 0.01 1/km Rayleigh, sun at 30 deg; 9 cameras of
+64x64 px from -60 to +60 deg; 2^22 paths, at most 20 scatters; FP32
+traversal with FP64 weights and tallies.  Target images come from a second
+seeded field rendered with fresh paths.
+
+Roofline: the dominant kernel's launches are timed with HIP events on the
+library's stream; its algorithmic work (voxel-segments and local estimates
+counted by the kernels) is converted to VALU lane-operations with fixed
+per-unit costs and compared with the chip's VALU lane-op peak.
+The CPU baseline is the FP64 oracle doing one full step on a bounded sample
+of the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# VALU peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-operations/s
+# (one FP32 or FP64 FMA per lane per clock without packed math).
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+# algorithmic VALU lane-ops per unit of work ("Roofline")
+OPS = {
+    "render": {"voxel_segment": 6, "local_estimate": 40},
+    "grad": {"voxel_segment": 8, "local_estimate": 50},
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cloud32")
+    ap.add_argument("--paths", type=int, default=0, help="override the number of paths")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--cpu-paths", type=int, default=1 << 22, help="paths in the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on a single GPU; --gpus must be 1 (multi-GPU path sharding is "
+              "described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2110_00085_amd import api, prt as P
+
+    make_scene, make_cams, n_paths, seed = inputs.WORKLOADS[args.workload]
+    if args.paths:
+        n_paths = args.paths
+    scene = make_scene()
+    cams = make_cams(scene)
+    ch = P.CamerasHost(cams)
+    prec = P.PRT_ALL_FP64 if args.precision == "fp64" else P.PRT_TRAVERSAL_FP32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(0)
+    ctx = api.Context(0, prec)
+    h = ctx.handle
+    print(f"[bench] workload {args.workload}: grid {scene.nx}x{scene.ny}x{scene.nz}, {cams.n} cams "
+          f"{cams.width}x{cams.height}, {n_paths} paths, {scene.max_order} orders, {args.precision}", flush=True)
+
+    # target images from a second seeded field with fresh paths (untimed)
+    tgt_scene = scene.with_beta(inputs.gaussian_field_cloud(scene.nx, 3)) if args.workload == "cloud32" else \
+        scene.with_beta(scene.beta_cloud * 1.1)
+    tb = torch.as_tensor(tgt_scene.beta_cloud).to(dev)
+    st_t = api.PathStore.sample(ctx, tgt_scene, tb, seed + 1000, n_paths)
+    target = api.render(ctx, tgt_scene, tb, ch, st_t)
+    st_t.close()
+
+    beta32 = torch.as_tensor(scene.beta_cloud).to(dev).contiguous()
+    beta64 = beta32.double()
+    m = torch.zeros_like(beta64)
+    v = torch.zeros_like(beta64)
+    img = torch.empty(ch.image_shape, dtype=torch.float64, device=dev)
+    res = torch.empty_like(img)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty((scene.nz, scene.ny, scene.nx), dtype=torch.float64, device=dev)
+    sc = P.make_scene(scene, beta32)
+    state = {"t": 0, "store": None}
+
+    def resample():
+        if state["store"] is not None:
+            state["store"].close()
+        state["store"] = api.PathStore.sample(ctx, scene, beta32, seed + state["t"], n_paths)
+
+    def iterate():
+        st = state["store"].handle
+        state["t"] += 1
+        P.prt_render(h, sc, ch, st, scene.max_order, img)
+        P.prt_loss(h, img, target, res, loss)
+        P.prt_grad(h, sc, ch, st, res, grad)
+        P.prt_adam(h, beta64, beta32, grad, m, v, state["t"], 0.1)
+        return P.prt_reweight(h, sc, st)
+
+    def full_step():
+        resample()
+        return iterate()
+
+    for _ in range(args.warmup):
+        full_step()
+    torch.cuda.synchronize()
+
+    # algorithmic work of one render and one grad on the current store
+    P.prt_counters(h, reset=True)
+    P.prt_render(h, sc, ch, state["store"].handle, scene.max_order, img)
+    c_r = P.prt_counters(h, reset=True)
+
+    # timed region: K full steps
+    P.prt_enable_timing(h, True)
+    P.prt_kernel_times(h, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rw = None
+    for _ in range(args.steps):
+        rw = full_step()
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    ktimes = P.prt_kernel_times(h, reset=True)
+    P.prt_enable_timing(h, False)
+
+    # recycled steps (no resample) for reference
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        iterate()
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+
+    ms_step = 1e3 * t_full / args.steps
+    value = n_paths / (t_full / args.steps)
+    # dominant kernel and its roofline
+    dom = max(ktimes, key=lambda k: ktimes[k][0])
+    dom_ms = ktimes[dom][0] / max(ktimes[dom][1], 1)
+    units = {"voxel_segment": c_r["voxel_segments"], "local_estimate": c_r["local_estimates"]}
+    per = OPS.get(dom)
+    if per is not None:
+        ops = sum(per[k] * units[k] for k in per)
+        achieved = ops / (dom_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": VALU_LANE_OPS_PEAK / 1e12,
+                    "unit": "TOP/s", "frac": achieved * 1e12 / VALU_LANE_OPS_PEAK, "traffic": None,
+                    "avg_launch_ms": dom_ms, "work_per_launch": units}
+    else:
+        roofline = {"bound": "alu", "kernel": dom, "achieved": None, "peak": VALU_LANE_OPS_PEAK / 1e12,
+                    "unit": "TOP/s", "frac": None, "traffic": None, "avg_launch_ms": dom_ms}
+
+    out = {
+        "metric": "paths/s (forward+backward)",
+        "value": value,
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 traversal, f64 weights/tallies" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {scene.nx}x{scene.ny}x{scene.nz} grid "
+                               f"{scene.voxel_km * 1000:g} m voxels, {cams.n} cameras {cams.width}x{cams.height}, "
+                               f"{n_paths} paths, {scene.max_order} orders, step = resample+render+loss+grad"
+                               f"+adam+reweight",
+                   "paths": n_paths, "precision": args.precision},
+        "recycled_ms_per_step": 1e3 * t_rec / args.steps,
+        "recycled_paths_per_s": n_paths / (t_rec / args.steps),
+        "voxel_segments_per_s_render": units["voxel_segment"] / (ktimes["render"][0] / max(ktimes["render"][1], 1) * 1e-3),
+        "kernel_ms_per_step": {k: ktimes[k][0] / args.steps for k in ktimes if ktimes[k][1]},
+        "mean_r_last": rw[0] if rw else None,
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene, cams, target.cpu().numpy(), seed, min(args.cpu_paths, n_paths),
+                                           n_paths)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(scene, cams, target, seed, n_cpu, n_total):
+    """The FP64 oracle doing one full step (sample, render, loss, grad, Adam,
+    reweight) on the first n_cpu paths of the same stream."""
+    import numpy as np
+
+    import oracle
+    if not os.path.exists(os.path.join(ROOT, "oracle", "libprt_oracle.so")):
+        oracle.build()
+    t0 = time.perf_counter()
+    paths = oracle.sample(scene, seed, n_cpu)
+    img = oracle.render(scene, cams, paths)
+    L, res = oracle.loss_and_residual(img, target)
+    g = oracle.grad(scene, cams, paths, res)
+    beta = scene.beta_cloud.astype(np.float64)
+    beta, _, _ = oracle.adam_step(beta, g, np.zeros_like(beta), np.zeros_like(beta), 1, 0.1)
+    oracle.reweight(scene, paths, beta_t=beta.astype(np.float32))
+    dt = time.perf_counter() - t0
+    return {"value": n_cpu / dt, "unit": "paths/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one full step on the first {n_cpu} of the {n_total} paths (same seeds), FP64, "
+                      f"{dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -120,6 +120,8 @@ typedef struct {
    borrowed, may be NULL for the null stream) and a precision mode.  The
    context owns its scratch memory. */
 int prt_create(int device, void* hip_stream, int precision, prt_ctx* out);
+/* Destroy a context after waiting for all work on its device.  Stores built
+   with it stay valid. */
 void prt_destroy(prt_ctx ctx);
 int prt_set_stream(prt_ctx ctx, void* hip_stream);
 /* Thread-local text of the last error (never NULL). */
@@ -163,6 +165,8 @@ int prt_paths_export(prt_ctx ctx, prt_paths paths, int64_t* off, float* xyz, int
 int prt_paths_permutation(prt_ctx ctx, prt_paths paths, int32_t* perm);
 
 int prt_paths_info(prt_paths paths, prt_paths_info_t* info);
+/* Free a store.  Independent of the context that built it (which may be
+   destroyed first); waits for all work on the store's device. */
 void prt_paths_destroy(prt_paths paths);
 
 /* ------------------------------------------------------------ hot path */

@@ -7,9 +7,25 @@ gradient kernel (Eq. loss_gradient generalised to dL/dI from autograd).
 """
 from __future__ import annotations
 
+import atexit
+import weakref
+
 import torch
 
 from . import prt as P
+
+_live_stores: "weakref.WeakSet[PathStore]" = weakref.WeakSet()
+_live_contexts: "weakref.WeakSet[Context]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Release library handles while the HIP runtime is still up: stores
+    first, then contexts (finalizer order at interpreter exit is arbitrary)."""
+    for s in list(_live_stores):
+        s.close()
+    for c in list(_live_contexts):
+        c.close()
 
 
 class Context:
@@ -19,6 +35,7 @@ class Context:
         self.device = device
         self.precision = precision
         self.handle = P.prt_create(device, torch.cuda.current_stream(device).cuda_stream, precision)
+        _live_contexts.add(self)
 
     def close(self):
         if self.handle is not None:
@@ -38,6 +55,7 @@ class PathStore:
     def __init__(self, ctx: Context, handle):
         self.ctx = ctx
         self.handle = handle
+        _live_stores.add(self)
 
     @classmethod
     def sample(cls, ctx: Context, params, beta_cloud, seed: int, n_paths: int) -> "PathStore":

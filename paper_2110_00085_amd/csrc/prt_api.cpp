@@ -68,7 +68,6 @@ struct prt_ctx_s {
 };
 
 struct prt_paths_s {
-    prt_ctx ctx = nullptr;
     int device = 0;
     uint64_t n = 0;
     int64_t nb = 0, n_slots = 0, first_slot = 0;
@@ -279,10 +278,13 @@ int ensure_part(prt_ctx c, size_t n)
     return PRT_OK;
 }
 
+// Frees a store.  It does not touch the context it was built with (the
+// context may already be gone); it waits for all work on the store's device.
 void free_store(prt_paths p)
 {
     if (!p) return;
     DeviceGuard g(p->device);
+    (void)hipDeviceSynchronize();
     (void)hipFree(p->vtx);
     (void)hipFree(p->batch_off);
     (void)hipFree(p->B);
@@ -347,7 +349,6 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
 prt_paths new_store(prt_ctx c, const prt_scene* s, uint64_t n, uint64_t seed)
 {
     prt_paths p = new prt_paths_s();
-    p->ctx = c;
     p->device = c->device;
     p->n = n;
     p->seed = seed;
@@ -412,7 +413,7 @@ void prt_destroy(prt_ctx c)
 {
     if (!c) return;
     DeviceGuard g(c->device);
-    (void)hipStreamSynchronize(c->stream);
+    (void)hipDeviceSynchronize();
     for (auto& t : c->pending) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -629,15 +630,7 @@ int prt_paths_info(prt_paths p, prt_paths_info_t* info)
     return PRT_OK;
 }
 
-void prt_paths_destroy(prt_paths p)
-{
-    if (!p) return;
-    if (p->ctx) {
-        DeviceGuard g(p->device);
-        (void)hipStreamSynchronize(p->ctx->stream);
-    }
-    free_store(p);
-}
+void prt_paths_destroy(prt_paths p) { free_store(p); }
 
 int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p, int32_t max_order_render,
                double* images)

@@ -247,7 +247,7 @@ def test_edge_cases(env):
     assert _rel(img1, oracle.render(s1, cams, p1)) <= 1e-5
     # cameras that see nothing
     far = inputs.cameras_at([[100.0, 100.0, 100.0]], [[200.0, 200.0, 200.0]], 8, 8, 10.0)
-    assert np.abs(api.render(ctx, scene, bt, P.CamerasHost(far), st1).cpu().numpy()).max() == 0.0
+    assert np.abs(api.render(ctx, s1, _dev(torch, s1.beta_cloud), P.CamerasHost(far), st1).cpu().numpy()).max() == 0.0
     # repeated renders agree to rounding of the atomic summation order
     st2 = _store(api, ctx, torch, scene, oracle.sample(scene, 1001, 10_000))
     a = api.render(ctx, scene, bt, ch, st2).cpu().numpy()
