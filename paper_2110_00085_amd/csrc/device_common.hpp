@@ -152,12 +152,17 @@ __device__ __forceinline__ int project(const DevCams& c, int d, double x, double
 
 // Incremental voxel walk along p + t w from voxel (ix,iy,iz) over t in
 // [0, tmax] (grid units), clipped by the box.  The functor is called as
-// f(voxel, t_start, length) for every piece of nonzero length, in order; it
+// f(voxel, t_start, length) for every piece in order, with length >= 0
+// (zero for a degenerate piece, e.g. when p sits on a voxel face); it
 // returns false to stop the walk.  Returns the parameter t reached (the box
-// exit, tmax, or where the functor stopped).  Every iteration advances one
-// index toward the box boundary, and the loop is capped at nx+ny+nz+3
-// iterations, so the walk terminates for any input (including non-finite
-// directions).
+// exit, tmax, or where the functor stopped).
+//
+// The step is branchless: the axis of the nearest face is chosen with
+// selects, and each axis carries the number of faces left before the box
+// boundary, so leaving the box needs no index bound checks.  Every
+// iteration either advances one axis or returns, and the loop is capped at
+// nx+ny+nz+3 iterations, so it terminates for any input (including
+// non-finite directions, whose components are treated as zero).
 template <typename Real, typename F>
 __device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy,
                                          int iz, Real wx, Real wy, Real wz, Real tmax, F&& f)
@@ -173,38 +178,32 @@ __device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real p
     Real tnx = sx > 0 ? ((Real)(ix + 1) - px) * ivx : (sx < 0 ? ((Real)ix - px) * ivx : inf);
     Real tny = sy > 0 ? ((Real)(iy + 1) - py) * ivy : (sy < 0 ? ((Real)iy - py) * ivy : inf);
     Real tnz = sz > 0 ? ((Real)(iz + 1) - pz) * ivz : (sz < 0 ? ((Real)iz - pz) * ivz : inf);
-    const Real dtx = sx ? (Real)sx * ivx : inf;
-    const Real dty = sy ? (Real)sy * ivy : inf;
-    const Real dtz = sz ? (Real)sz * ivz : inf;
-    const int stop_x = sx > 0 ? nx : -1, stop_y = sy > 0 ? ny : -1, stop_z = sz > 0 ? nz : -1;
-    const int sy_v = sy * nx, sz_v = sz * nx * ny;
+    const Real dtx = (Real)sx * ivx, dty = (Real)sy * ivy, dtz = (Real)sz * ivz;
+    // faces left before the boundary along each axis
+    int rx = sx > 0 ? nx - 1 - ix : ix;
+    int ry = sy > 0 ? ny - 1 - iy : iy;
+    int rz = sz > 0 ? nz - 1 - iz : iz;
+    const int dvx = sx, dvy = sy * nx, dvz = sz * nx * ny;
     int v = ix + nx * (iy + ny * iz);
     Real t = (Real)0;
     const int maxit = nx + ny + nz + 3;
     for (int it = 0; it < maxit; ++it) {
         const Real tn = fmin(tnx, fmin(tny, tnz));
         const Real te = fmin(tn, tmax);
-        if (te > t) {
-            if (!f(v, t, te - t)) return t;
-            t = te;
-        }
+        if (!f(v, t, fmax(te - t, (Real)0))) return t;
+        t = fmax(t, te);
         if (!(tn < tmax)) return t;
-        if (tnx <= tny && tnx <= tnz) {
-            ix += sx;
-            if (ix == stop_x) return t;
-            v += sx;
-            tnx += dtx;
-        } else if (tny <= tnz) {
-            iy += sy;
-            if (iy == stop_y) return t;
-            v += sy_v;
-            tny += dty;
-        } else {
-            iz += sz;
-            if (iz == stop_z) return t;
-            v += sz_v;
-            tnz += dtz;
-        }
+        const bool bx = tnx == tn;
+        const bool by = !bx && tny == tn;
+        const int r = bx ? rx : (by ? ry : rz);
+        if (r <= 0) return t;
+        rx -= bx ? 1 : 0;
+        ry -= by ? 1 : 0;
+        rz -= (!bx && !by) ? 1 : 0;
+        v += bx ? dvx : (by ? dvy : dvz);
+        tnx = bx ? tnx + dtx : tnx;
+        tny = by ? tny + dty : tny;
+        tnz = (!bx && !by) ? tnz + dtz : tnz;
     }
     return t;
 }

@@ -63,10 +63,28 @@ hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, c
 hipError_t launch_first_nonzero(hipStream_t st, const uint8_t* B, int64_t n, int64_t* out);
 
 // ---- hot path (trace.hip)
-hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c);
+// Where render tallies and reads: FP32 LDS image partials (reduced by a
+// second kernel) and/or the extinction grid cached in LDS, when they fit.
+struct RenderPlan {
+    bool img_lds = false, grid_lds = false;
+    int n_wg = 1;
+    size_t partial_bytes = 0;
+};
+RenderPlan plan_render(int fp64, int64_t nu, int64_t nimg, int64_t n_slots, int64_t first_slot, int n_cu);
+hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
+                         float* partial);
 hipError_t launch_render_finalize(hipStream_t st, double* img, const DevCams& c, double scale);
 hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho, const DevCams& c, double scale);
-hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c);
+// How the gradient is tallied: per-workgroup LDS partials (reduced by a
+// second kernel) when the grid fits the LDS budget, else FP64 atomics.
+struct GradPlan {
+    bool lds = false;
+    int n_wg = 1;
+    size_t partial_bytes = 0;
+};
+GradPlan plan_grad(int fp64, int64_t nu, int64_t n_slots, int64_t first_slot, int n_cu);
+hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p,
+                       void* partial);
 hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int64_t* n_blocks);
 
 // ---- loop glue (loop.hip)

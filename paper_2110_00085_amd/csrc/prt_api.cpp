@@ -50,6 +50,11 @@ struct prt_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
     int fp64 = 0;
+    int n_cu = 1;               // compute units on the device (persistent launches)
+    void* gpart = nullptr;      // per-workgroup gradient partials
+    size_t gpart_bytes = 0;
+    void* rpart = nullptr;      // per-workgroup image partials
+    size_t rpart_bytes = 0;
     void* grid_tot = nullptr;
     void* grid_dlt = nullptr;
     size_t grid_bytes = 0;
@@ -254,6 +259,22 @@ int ensure_grids(prt_ctx c, int64_t nu)
     return PRT_OK;
 }
 
+// Grows a context scratch buffer to at least `bytes`.
+int ensure_scratch(void** buf, size_t* have, size_t bytes)
+{
+    if (bytes <= *have) return PRT_OK;
+    (void)hipFree(*buf);
+    *buf = nullptr;
+    *have = 0;
+    if (hipMalloc(buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *buf = nullptr;
+        return fail(PRT_E_NOMEM, "scratch allocation of %zu bytes failed", bytes);
+    }
+    *have = bytes;
+    return PRT_OK;
+}
+
 int ensure_pix(prt_ctx c, size_t n)
 {
     if (c->pix_n >= n) return PRT_OK;
@@ -393,6 +414,8 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     c->fp64 = precision == PRT_ALL_FP64;
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
+        c->n_cu = 1;
     if (hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&c->out2, 2 * sizeof(double)) != hipSuccess) {
         (void)hipFree(c->counters);
@@ -422,6 +445,8 @@ void prt_destroy(prt_ctx c)
     (void)hipFree(c->grid_tot);
     (void)hipFree(c->grid_dlt);
     (void)hipFree(c->pix);
+    (void)hipFree(c->gpart);
+    (void)hipFree(c->rpart);
     (void)hipFree(c->part);
     (void)hipFree(c->out2);
     (void)hipFree(c->counters);
@@ -662,9 +687,11 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     a.img = images;
     a.brender = std::min(max_order_render, s->max_order);
     a.counters = c->counters;
+    const RenderPlan plan = plan_render(c->fp64, nu, npx, p->n_slots, p->first_slot, c->n_cu);
+    if ((rc = ensure_scratch(&c->rpart, &c->rpart_bytes, plan.partial_bytes))) return rc;
     {
         TimedScope ts(c, K_RENDER);
-        HIPCHK(launch_render(c->stream, c->fp64, a, dc));
+        HIPCHK(launch_render(c->stream, c->fp64, a, dc, plan, (float*)c->rpart));
     }
     {
         TimedScope ts(c, K_FINALIZE);
@@ -705,9 +732,11 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
     a.grad = grad;
     a.brender = s->max_order;
     a.counters = c->counters;
+    const GradPlan plan = plan_grad(c->fp64, nu, p->n_slots, p->first_slot, c->n_cu);
+    if ((rc = ensure_scratch(&c->gpart, &c->gpart_bytes, plan.partial_bytes))) return rc;
     {
         TimedScope ts(c, K_GRAD);
-        HIPCHK(launch_grad(c->stream, c->fp64, a, dc));
+        HIPCHK(launch_grad(c->stream, c->fp64, a, dc, plan, c->gpart));
     }
     return PRT_OK;
 }

@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
             s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy, iz, (Real)w[0], (Real)w[1], (Real)w[2],
             (Real)INFINITY, [&](int vv, Real t0, Real l) {
                 const Real bt = gt[vv];
-                const Real dt = bt * l;
+                const Real dt = bt * l;  // zero for an empty voxel or a zero-length piece
                 if (taur < acc + dt) {
                     hit = vv;
                     thit = t0 + (taur - acc) / bt;

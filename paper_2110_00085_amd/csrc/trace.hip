@@ -6,6 +6,8 @@
 // (nearly) equal size B thanks to the sort, so lanes leave the scatter loop
 // together.  The voxel walk runs in Real (float or double); projection,
 // phase functions, path weights and all tallies are FP64.
+#include <algorithm>
+
 #include "launch.hpp"
 
 namespace prt {
@@ -37,37 +39,43 @@ __device__ __forceinline__ double seg_dir(const Vtx& a, const Vtx& b, double w[3
 
 __device__ __forceinline__ int clamp_vox(int v, int nu) { return min(max(v, 0), nu - 1); }
 
-// Sum of grid[v] * length over the walk from vertex p (voxel p.v) along w for
-// length tmax; returns the sum (grid units) and adds the pieces to *count.
-template <typename Real>
-__device__ __forceinline__ Real walk_sum(const DevScene& s, const Real* __restrict__ grid, const Vtx& p,
-                                         const double w[3], double tmax, uint64_t& count)
+// Sum of beta(v) * length over the walk from vertex p (voxel p.v) along w
+// for length tmax (grid units); adds the nonzero pieces to count.
+template <typename Real, typename G>
+__device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx& p, const double w[3], double tmax,
+                                         uint64_t& count)
 {
     int ix, iy, iz;
     voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
     Real acc = (Real)0;
+    uint32_t n = 0;
     dda_walk<Real>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
                    (Real)w[2], (Real)tmax, [&](int v, Real, Real l) {
-                       acc += grid[v] * l;
-                       ++count;
+                       acc += beta(v) * l;
+                       n += l > (Real)0 ? 1u : 0u;
                        return true;
                    });
+    count += n;
     return acc;
 }
 
-// Adds scale * length (km) to grad[v] for every piece of the walk.
-template <typename Real>
-__device__ __forceinline__ void walk_scatter(const DevScene& s, double* __restrict__ grad, const Vtx& p,
-                                             const double w[3], double tmax, double scale, uint64_t& count)
+// Calls add(v, scale * length) for every nonzero piece of the walk.
+template <typename Real, typename A>
+__device__ __forceinline__ void walk_scatter(const DevScene& s, A&& add, const Vtx& p, const double w[3], double tmax,
+                                             double scale, uint64_t& count)
 {
     int ix, iy, iz;
     voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
+    uint32_t n = 0;
     dda_walk<Real>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
                    (Real)w[2], (Real)tmax, [&](int v, Real, Real l) {
-                       unsafeAtomicAdd(&grad[v], scale * (double)l);
-                       ++count;
+                       if (l > (Real)0) {
+                           add(v, scale * (double)l);
+                           ++n;
+                       }
                        return true;
                    });
+    count += n;
 }
 
 // Factor of scatter vertex k (1 <= k < b) in the recycled contribution:
@@ -91,72 +99,161 @@ __device__ __forceinline__ void flush_counts(unsigned long long* c, uint64_t seg
 
 // ------------------------------------------------------------------ render
 
-template <typename Real>
-__global__ void __launch_bounds__(256) render_kernel(TraceArgs a, DevCams cams)
+// Persistent launch: each workgroup of kBlock threads caches the extinction
+// grid in LDS when it fits, then its wavefronts walk batches
+// first_batch + wave, + total_waves, ...  (the batches are sorted by path
+// size, so the stride gives every wave a similar mix of sizes).
+constexpr int kBlock = 1024;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr size_t kLdsBudget = 128 * 1024;       // grids
+constexpr size_t kLdsImageBudget = 152 * 1024;  // image tallies (+ grid if both fit)
+
+// kGridLds: the total-extinction grid is cached in LDS.  kImgLds: the
+// workgroup tallies its contributions in an FP32 LDS image and writes it to
+// partial[blockIdx.x]; render_reduce_kernel adds the partials in FP64 in
+// workgroup order.  Otherwise every contribution is an FP64 atomic on the
+// output image.
+template <typename Real, bool kGridLds, bool kImgLds>
+__global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cams, float* __restrict__ partial)
 {
-    const int64_t slot = a.st.first_slot + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= a.st.n_slots) return;
-    const int Br = min((int)a.st.B[slot], a.brender);
-    if (Br <= 0) return;
+    extern __shared__ unsigned char smem[];
     const DevScene& s = a.s;
-    const Real* __restrict__ gt = (const Real*)a.grid_tot;
-    const Real* __restrict__ gd = (const Real*)a.grid_dlt;
-    const float4* __restrict__ V = a.st.vtx + a.st.batch_off[slot / kWave] + (slot % kWave);
     const int nu = s.nx * s.ny * s.nz;
     const int npix = cams.W * cams.H;
+    const int nimg = npix * cams.n;
+    float* __restrict__ simg = reinterpret_cast<float*>(smem);
+    Real* __restrict__ sgrid = reinterpret_cast<Real*>(smem + (kImgLds ? (size_t)nimg * sizeof(float) : 0));
+    const Real* __restrict__ gtot = (const Real*)a.grid_tot;
+    const Real* __restrict__ gd = (const Real*)a.grid_dlt;
+    if (kGridLds)
+        for (int i = threadIdx.x; i < nu; i += kBlock) sgrid[i] = gtot[i];
+    if (kImgLds)
+        for (int i = threadIdx.x; i < nimg; i += kBlock) simg[i] = 0.f;
+    if (kGridLds || kImgLds) __syncthreads();
+    auto beta_tot = [&](int v) -> Real { return kGridLds ? sgrid[v] : gtot[v]; };
     const double r2scale = 1.0 / (s.vk * s.vk);
+    const int lane = threadIdx.x % kWave;
+    const int64_t nb = a.st.n_slots / kWave;
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
     uint64_t nseg = 0, nle = 0;
-
-    Vtx p0 = load_vtx(V, 0);
-    double P = s.w0;           // running f/mu of the prefix (without the last vertex)
-    double wprev[3] = {0.0, 0.0, 0.0};
-    for (int b = 1; b <= Br; ++b) {
-        const Vtx p1 = load_vtx(V, b);
-        double w[3];
-        const double L = seg_dir(p0, p1, w);
-        // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
-        const Real dt = walk_sum<Real>(s, gd, p0, w, L, nseg);
-        P *= exp(-(double)dt * s.vk);
-        if (b >= 2) {
-            const int v = clamp_vox(p0.v, nu);
-            P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
-                              wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
+    for (int64_t bt = a.st.first_slot / kWave + (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; bt < nb;
+         bt += stride) {
+        const int64_t slot = bt * kWave + lane;
+        const int Br = min((int)a.st.B[slot], a.brender);
+        if (Br <= 0) continue;
+        const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+        Vtx p0 = load_vtx(V, 0);
+        double P = s.w0;  // running f/mu of the prefix (without the last vertex)
+        double wprev[3] = {0.0, 0.0, 0.0};
+        for (int b = 1; b <= Br; ++b) {
+            const Vtx p1 = load_vtx(V, b);
+            double w[3];
+            const double L = seg_dir(p0, p1, w);
+            // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
+            const Real dt = walk_sum<Real>(s, [&](int v) { return gd[v]; }, p0, w, L, nseg);
+            P *= exp(-(double)dt * s.vk);
+            if (b >= 2) {
+                const int v = clamp_vox(p0.v, nu);
+                P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
+                                  wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
+            }
+            // local estimates from x_b to every camera
+            const int v1 = clamp_vox(p1.v, nu);
+            const double bct = (double)a.bc_t[v1];
+            const double base = P / ((double)a.st.beta_ref[v1] + s.beta_air);
+            for (int d = 0; d < cams.n; ++d) {
+                const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
+                if (pix < 0) continue;
+                const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
+                const double dist2 = ex * ex + ey * ey + ez * ez;
+                const double dist = sqrt(dist2);
+                const double id = 1.0 / dist;
+                const double u[3] = {ex * id, ey * id, ez * id};
+                const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
+                const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
+                const Real tc = walk_sum<Real>(s, beta_tot, p1, u, dist, nseg);
+                const double c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
+                if (kImgLds) atomicAdd(&simg[d * npix + pix], (float)c);
+                else unsafeAtomicAdd(&a.img[(int64_t)d * npix + pix], c);
+                ++nle;
+            }
+            wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
+            p0 = p1;
         }
-        // local estimates from x_b to every camera
-        const int v1 = clamp_vox(p1.v, nu);
-        const double bct = (double)a.bc_t[v1];
-        const double base = P / ((double)a.st.beta_ref[v1] + s.beta_air);
-        for (int d = 0; d < cams.n; ++d) {
-            const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
-            if (pix < 0) continue;
-            const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
-            const double dist2 = ex * ex + ey * ey + ez * ez;
-            const double dist = sqrt(dist2);
-            const double id = 1.0 / dist;
-            const double u[3] = {ex * id, ey * id, ez * id};
-            const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
-            const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
-            const Real tc = walk_sum<Real>(s, gt, p1, u, dist, nseg);
-            const double c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
-            unsafeAtomicAdd(&a.img[(int64_t)d * npix + pix], c);
-            ++nle;
-        }
-        wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
-        p0 = p1;
     }
     flush_counts(a.counters, nseg, nle, 0);
+    if (kImgLds) {
+        __syncthreads();
+        float* __restrict__ out = partial + (int64_t)blockIdx.x * nimg;
+        for (int i = threadIdx.x; i < nimg; i += kBlock) out[i] = simg[i];
+    }
 }
 
-hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c)
+// img[i] = sum over workgroups of partial[w][i] (FP64, workgroup order).
+__global__ void __launch_bounds__(256) render_reduce_kernel(const float* __restrict__ partial, int n_wg, int64_t n,
+                                                            double* __restrict__ img)
 {
-    const int64_t n = a.st.n_slots - a.st.first_slot;
-    if (n <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    if (fp64)
-        render_kernel<double><<<dim3(blocks), dim3(256), 0, st>>>(a, c);
-    else
-        render_kernel<float><<<dim3(blocks), dim3(256), 0, st>>>(a, c);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int w = 0; w < n_wg; ++w) acc += (double)partial[(int64_t)w * n + i];
+    img[i] = acc;
+}
+
+template <typename Real, bool kGridLds, bool kImgLds>
+static hipError_t launch_render_t(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, float* partial)
+{
+    const size_t nu = (size_t)a.s.nx * a.s.ny * a.s.nz;
+    const size_t nimg = (size_t)c.W * c.H * c.n;
+    const size_t lds = (kGridLds ? nu * sizeof(Real) : 0) + (kImgLds ? nimg * sizeof(float) : 0);
+    if (lds) {
+        hipError_t e = hipFuncSetAttribute((const void*)render_kernel<Real, kGridLds, kImgLds>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    render_kernel<Real, kGridLds, kImgLds><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !kImgLds) return e;
+    render_reduce_kernel<<<dim3((unsigned)((nimg + 255) / 256)), dim3(256), 0, st>>>(partial, n_wg, (int64_t)nimg,
+                                                                                   a.img);
     return hipGetLastError();
+}
+
+// Workgroups for a persistent launch over the batches that hold scattered paths.
+static int persistent_groups(int64_t n_slots, int64_t first_slot, int n_cu, int per_cu)
+{
+    const int64_t batches = (n_slots - first_slot + kWave - 1) / kWave;
+    const int64_t need = (batches + kWavesPerBlock - 1) / kWavesPerBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)n_cu * per_cu));
+}
+
+RenderPlan plan_render(int fp64, int64_t nu, int64_t nimg, int64_t n_slots, int64_t first_slot, int n_cu)
+{
+    RenderPlan p;
+    const int64_t img_bytes = nimg * 4, grid_bytes = nu * (fp64 ? 8 : 4);
+    // FP32 image partials only in FP32 traversal mode (the all-FP64 mode keeps FP64 tallies)
+    p.img_lds = !fp64 && img_bytes <= (int64_t)kLdsImageBudget;
+    p.grid_lds = grid_bytes + (p.img_lds ? img_bytes : 0) <= (int64_t)kLdsImageBudget &&
+                 grid_bytes <= (int64_t)kLdsBudget;
+    p.n_wg = persistent_groups(n_slots, first_slot, n_cu, (p.img_lds || p.grid_lds) ? 1 : 2);
+    p.partial_bytes = p.img_lds ? (size_t)p.n_wg * nimg * sizeof(float) : 0;
+    return p;
+}
+
+hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
+                         float* partial)
+{
+    if (a.st.n_slots - a.st.first_slot <= 0) return hipSuccess;
+    if (fp64) {
+        if (p.grid_lds) return launch_render_t<double, true, false>(st, a, c, p.n_wg, nullptr);
+        return launch_render_t<double, false, false>(st, a, c, p.n_wg, nullptr);
+    }
+    if (p.img_lds) {
+        if (p.grid_lds) return launch_render_t<float, true, true>(st, a, c, p.n_wg, partial);
+        return launch_render_t<float, false, true>(st, a, c, p.n_wg, partial);
+    }
+    if (p.grid_lds) return launch_render_t<float, true, false>(st, a, c, p.n_wg, nullptr);
+    return launch_render_t<float, false, false>(st, a, c, p.n_wg, nullptr);
 }
 
 // Exact pixel solid angle: F(x,y) = atan(xy / (f sqrt(x^2+y^2+f^2))) is the
@@ -212,103 +309,169 @@ hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho,
 // A_k = sum_{b>k} R_b, adding -A_k l along segment k and A_k times the
 // vertex term at x_k.  Together this is sum_{b,d} w_{b,d} S(b,d) with S the
 // tomography PSF of the local-estimate sub-path.
-template <typename Real>
-__global__ void __launch_bounds__(256) grad_kernel(TraceArgs a, DevCams cams)
+//
+// Tally: with kLds the workgroup accumulates the gradient in LDS (type T)
+// and writes its partial sums to partial[blockIdx.x][v]; a second kernel
+// adds the partials in FP64 in a fixed order.  Without kLds every update is
+// an FP64 atomic on the output.
+template <typename Real, typename T, bool kLds>
+__global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams, T* __restrict__ partial)
 {
-    const int64_t slot = a.st.first_slot + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= a.st.n_slots) return;
-    const int Bn = (int)a.st.B[slot];
-    if (Bn <= 0) return;
+    extern __shared__ unsigned char smem[];
+    T* __restrict__ sg = reinterpret_cast<T*>(smem);
     const DevScene& s = a.s;
-    const Real* __restrict__ gt = (const Real*)a.grid_tot;
-    const Real* __restrict__ gd = (const Real*)a.grid_dlt;
-    const float4* __restrict__ V = a.st.vtx + a.st.batch_off[slot / kWave] + (slot % kWave);
     const int nu = s.nx * s.ny * s.nz;
+    if (kLds) {
+        for (int i = threadIdx.x; i < nu; i += kBlock) sg[i] = (T)0;
+        __syncthreads();
+    }
+    double* __restrict__ gout = a.grad;
+    auto add = [&](int v, double x) {
+        if (kLds) atomicAdd(&sg[v], (T)x);
+        else unsafeAtomicAdd(&gout[v], x);
+    };
+    const Real* __restrict__ gtot = (const Real*)a.grid_tot;
+    const Real* __restrict__ gd = (const Real*)a.grid_dlt;
     const int npix = cams.W * cams.H;
     const double r2scale = 1.0 / (s.vk * s.vk);
-    double* __restrict__ grad = a.grad;
+    const int lane = threadIdx.x % kWave;
+    const int64_t nb = a.st.n_slots / kWave;
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
     uint64_t nseg = 0, novh = 0;
     double R[kMaxOrder + 1];
-
-    Vtx p0 = load_vtx(V, 0);
-    double P = s.w0;
-    double wprev[3] = {0.0, 0.0, 0.0};
-    for (int b = 1; b <= Bn; ++b) {
-        const Vtx p1 = load_vtx(V, b);
-        double w[3];
-        const double L = seg_dir(p0, p1, w);
-        const Real dt = walk_sum<Real>(s, gd, p0, w, L, novh);
-        P *= exp(-(double)dt * s.vk);
-        if (b >= 2) {
-            const int v = clamp_vox(p0.v, nu);
-            P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
-                              wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
-        }
-        const int v1 = clamp_vox(p1.v, nu);
-        const double bct = (double)a.bc_t[v1];
-        const double base = P / ((double)a.st.beta_ref[v1] + s.beta_air);
-        double Rb = 0.0, vert = 0.0;
-        for (int d = 0; d < cams.n; ++d) {
-            const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
-            if (pix < 0) continue;
-            const double rho = a.rho[(int64_t)d * npix + pix];
-            if (rho == 0.0) continue;
-            const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
-            const double dist2 = ex * ex + ey * ey + ez * ez;
-            const double dist = sqrt(dist2);
-            const double id = 1.0 / dist;
-            const double u[3] = {ex * id, ey * id, ez * id};
-            const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
-            const double hg = phase_hg(s, mu);
-            const double fst = fs_mix(s, bct, hg, phase_rayleigh(mu));
-            const Real tc = walk_sum<Real>(s, gt, p1, u, dist, nseg);
-            const double wgt = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2) * rho;
-            Rb += wgt;
-            // vertex term at x_b: w * w_c f_HG / f_s,t (written as c/f_s times w_c f_HG)
-            if (fst > 0.0) vert += wgt * (s.w_c * hg / fst);
-            walk_scatter<Real>(s, grad, p1, u, dist, -wgt * s.vk, novh);
-        }
-        if (vert != 0.0) unsafeAtomicAdd(&grad[v1], vert);
-        R[b] = Rb;
-        wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
-        p0 = p1;
-    }
-    // pass 2: segments k = Bn-1 .. 0 with suffix weights
-    double A = 0.0;
-    Vtx pk1 = load_vtx(V, Bn);
-    for (int k = Bn - 1; k >= 0; --k) {
-        A += R[k + 1];
-        const Vtx pk = load_vtx(V, k);
-        double w[3];
-        const double L = seg_dir(pk, pk1, w);
-        if (A != 0.0) {
-            walk_scatter<Real>(s, grad, pk, w, L, -A * s.vk, nseg);
-            if (k >= 1) {
-                const Vtx pm = load_vtx(V, k - 1);
-                double wm[3];
-                seg_dir(pm, pk, wm);
-                const double mu = wm[0] * w[0] + wm[1] * w[1] + wm[2] * w[2];
-                const int v = clamp_vox(pk.v, nu);
-                const double hg = phase_hg(s, mu);
-                const double fst = fs_mix(s, (double)a.bc_t[v], hg, phase_rayleigh(mu));
-                if (fst > 0.0) unsafeAtomicAdd(&grad[v], A * (s.w_c * hg / fst));
+    for (int64_t bt = a.st.first_slot / kWave + (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; bt < nb;
+         bt += stride) {
+        const int64_t slot = bt * kWave + lane;
+        const int Bn = (int)a.st.B[slot];
+        if (Bn <= 0) continue;
+        const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+        Vtx p0 = load_vtx(V, 0);
+        double P = s.w0;
+        double wprev[3] = {0.0, 0.0, 0.0};
+        for (int b = 1; b <= Bn; ++b) {
+            const Vtx p1 = load_vtx(V, b);
+            double w[3];
+            const double L = seg_dir(p0, p1, w);
+            const Real dt = walk_sum<Real>(s, [&](int v) { return gd[v]; }, p0, w, L, novh);
+            P *= exp(-(double)dt * s.vk);
+            if (b >= 2) {
+                const int v = clamp_vox(p0.v, nu);
+                P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
+                                  wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
             }
+            const int v1 = clamp_vox(p1.v, nu);
+            const double bct = (double)a.bc_t[v1];
+            const double base = P / ((double)a.st.beta_ref[v1] + s.beta_air);
+            double Rb = 0.0, vert = 0.0;
+            for (int d = 0; d < cams.n; ++d) {
+                const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
+                if (pix < 0) continue;
+                const double rho = a.rho[(int64_t)d * npix + pix];
+                if (rho == 0.0) continue;
+                const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
+                const double dist2 = ex * ex + ey * ey + ez * ez;
+                const double dist = sqrt(dist2);
+                const double id = 1.0 / dist;
+                const double u[3] = {ex * id, ey * id, ez * id};
+                const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
+                const double hg = phase_hg(s, mu);
+                const double fst = fs_mix(s, bct, hg, phase_rayleigh(mu));
+                const Real tc = walk_sum<Real>(s, [&](int v) { return gtot[v]; }, p1, u, dist, nseg);
+                const double wgt = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2) * rho;
+                Rb += wgt;
+                // vertex term at x_b: w * w_c f_HG / f_s,t
+                if (fst > 0.0) vert += wgt * (s.w_c * hg / fst);
+                walk_scatter<Real>(s, add, p1, u, dist, -wgt * s.vk, novh);
+            }
+            if (vert != 0.0) add(v1, vert);
+            R[b] = Rb;
+            wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
+            p0 = p1;
         }
-        pk1 = pk;
+        // pass 2: segments k = Bn-1 .. 0 with suffix weights
+        double A = 0.0;
+        Vtx pk1 = load_vtx(V, Bn);
+        for (int k = Bn - 1; k >= 0; --k) {
+            A += R[k + 1];
+            const Vtx pk = load_vtx(V, k);
+            double w[3];
+            const double L = seg_dir(pk, pk1, w);
+            if (A != 0.0) {
+                walk_scatter<Real>(s, add, pk, w, L, -A * s.vk, nseg);
+                if (k >= 1) {
+                    const Vtx pm = load_vtx(V, k - 1);
+                    double wm[3];
+                    seg_dir(pm, pk, wm);
+                    const double mu = wm[0] * w[0] + wm[1] * w[1] + wm[2] * w[2];
+                    const int v = clamp_vox(pk.v, nu);
+                    const double hg = phase_hg(s, mu);
+                    const double fst = fs_mix(s, (double)a.bc_t[v], hg, phase_rayleigh(mu));
+                    if (fst > 0.0) add(v, A * (s.w_c * hg / fst));
+                }
+            }
+            pk1 = pk;
+        }
     }
     flush_counts(a.counters, nseg, 0, novh);
+    if (kLds) {
+        __syncthreads();
+        T* __restrict__ out = partial + (int64_t)blockIdx.x * nu;
+        for (int i = threadIdx.x; i < nu; i += kBlock) out[i] = sg[i];
+    }
 }
 
-hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c)
+// grad[v] = sum over workgroups of partial[w][v], in FP64, in workgroup order.
+template <typename T>
+__global__ void __launch_bounds__(256) grad_reduce_kernel(const T* __restrict__ partial, int n_wg, int64_t nu,
+                                                          double* __restrict__ grad)
 {
-    const int64_t n = a.st.n_slots - a.st.first_slot;
-    if (n <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    if (fp64)
-        grad_kernel<double><<<dim3(blocks), dim3(256), 0, st>>>(a, c);
-    else
-        grad_kernel<float><<<dim3(blocks), dim3(256), 0, st>>>(a, c);
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nu) return;
+    double acc = 0.0;
+    for (int w = 0; w < n_wg; ++w) acc += (double)partial[(int64_t)w * nu + v];
+    grad[v] = acc;
+}
+
+template <typename Real, typename T, bool kLds>
+static hipError_t launch_grad_t(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, void* partial)
+{
+    const int64_t nu = (int64_t)a.s.nx * a.s.ny * a.s.nz;
+    const size_t lds = kLds ? (size_t)nu * sizeof(T) : 0;
+    if (kLds) {
+        hipError_t e = hipFuncSetAttribute((const void*)grad_kernel<Real, T, kLds>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    grad_kernel<Real, T, kLds><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, (T*)partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !kLds) return e;
+    grad_reduce_kernel<T><<<dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, st>>>((const T*)partial, n_wg, nu,
+                                                                                  a.grad);
     return hipGetLastError();
+}
+
+GradPlan plan_grad(int fp64, int64_t nu, int64_t n_slots, int64_t first_slot, int n_cu)
+{
+    GradPlan p;
+    const int64_t tally = fp64 ? 8 : 4;
+    p.lds = nu * tally <= (int64_t)kLdsBudget;
+    const int64_t batches = (n_slots - first_slot + kWave - 1) / kWave;
+    const int64_t need = std::max<int64_t>(1, (batches + kWavesPerBlock - 1) / kWavesPerBlock);
+    p.n_wg = (int)std::min<int64_t>(need, (int64_t)n_cu * (p.lds ? 1 : 2));
+    p.partial_bytes = p.lds ? (size_t)p.n_wg * nu * tally : 0;
+    return p;
+}
+
+hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p,
+                       void* partial)
+{
+    if (a.st.n_slots - a.st.first_slot <= 0) return hipSuccess;
+    if (fp64) {
+        if (p.lds) return launch_grad_t<double, double, true>(st, a, c, p.n_wg, partial);
+        return launch_grad_t<double, double, false>(st, a, c, p.n_wg, nullptr);
+    }
+    if (p.lds) return launch_grad_t<float, float, true>(st, a, c, p.n_wg, partial);
+    return launch_grad_t<float, double, false>(st, a, c, p.n_wg, nullptr);
 }
 
 // ---------------------------------------------------------------- reweight
@@ -340,7 +503,7 @@ __global__ void __launch_bounds__(256) reweight_kernel(TraceArgs a)
                 const Vtx p1 = load_vtx(V, k + 1);
                 double w[3];
                 const double L = seg_dir(p0, p1, w);
-                lr -= (double)walk_sum<Real>(s, gd, p0, w, L, cnt) * s.vk;
+                lr -= (double)walk_sum<Real>(s, [&](int v) { return gd[v]; }, p0, w, L, cnt) * s.vk;
                 if (k >= 1) {
                     const int v = clamp_vox(p0.v, nu);
                     const double bct = (double)a.bc_t[v], bcr = (double)a.st.beta_ref[v];
