@@ -45,6 +45,12 @@ struct TraceArgs {
     double* partial;          // reweight: per-block (sum r, sum r^2)
     int32_t brender;
     unsigned long long* counters;  // [0] voxel segs, [1] local estimates, [3] overhead segs
+    // Transmittance tape: render records every in-image contribution c_{b,d}
+    // (FP32) at tape[(batch_off[batch] - tape_base) * n_cams + (b*n_cams + d)*64 + lane];
+    // grad reuses it when *tape_flag is 1 (same beta_t, cameras and scene).
+    float* tape;
+    int64_t tape_base;
+    const int* tape_flag;
 };
 
 // ---- sampling, sorting, packing (sample.hip)
@@ -86,6 +92,8 @@ GradPlan plan_grad(int fp64, int64_t nu, int64_t n_slots, int64_t first_slot, in
 hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p,
                        void* partial);
 hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int64_t* n_blocks);
+// flag = 1 if a[i] == b[i] bitwise for all i < n, else 0.
+hipError_t launch_equal_flag(hipStream_t st, const float* a, const float* b, int64_t n, int* flag);
 
 // ---- loop glue (loop.hip)
 hipError_t launch_fill(hipStream_t st, double* p, int64_t n, double v);

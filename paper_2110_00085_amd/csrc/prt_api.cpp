@@ -64,6 +64,7 @@ struct prt_ctx_s {
     size_t part_n = 0;
     double* out2 = nullptr;     // two doubles of reduction output
     unsigned long long* counters = nullptr;  // 4
+    int* flag = nullptr;        // device flag: the tape matches beta_t
     uint64_t paths_done = 0;
     bool timing = false;
     std::vector<Timed> pending;
@@ -86,6 +87,15 @@ struct prt_paths_s {
     int32_t* perm = nullptr;
     float* beta_ref = nullptr;
     uint64_t bytes = 0;
+    int64_t tape_base = 0;      // batch_off of the first batch with scattering paths
+    // Transmittance tape written by prt_render (FP32 traversal mode), reused by
+    // prt_grad when beta_t, the cameras and the scene constants are unchanged.
+    float* tape = nullptr;
+    size_t tape_cap = 0;        // entries
+    float* tape_beta = nullptr; // beta_t of the render that wrote the tape
+    bool tape_valid = false;
+    DevCams tape_cams{};
+    DevScene tape_scene{};
 };
 
 namespace {
@@ -312,6 +322,8 @@ void free_store(prt_paths p)
     (void)hipFree(p->nv);
     (void)hipFree(p->perm);
     (void)hipFree(p->beta_ref);
+    (void)hipFree(p->tape);
+    (void)hipFree(p->tape_beta);
     delete p;
 }
 
@@ -359,11 +371,40 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
                     hipGetErrorString(e3 != hipSuccess ? e3 : (e1 != hipSuccess ? e1 : e2)));
     p->n_records = host2[0];
     p->first_slot = host2[1];
+    p->tape_base = p->n_records;
+    if (p->first_slot < n) HIPCHK(hipMemcpy(&p->tape_base, p->batch_off + p->first_slot / kWave, sizeof(int64_t),
+                                            hipMemcpyDeviceToHost));
     if ((rc = dalloc(&p->vtx, p->n_records, &p->bytes))) return rc;
     {
         TimedScope ts(c, K_PACK);
         HIPCHK(launch_pack(c->stream, p->perm, tmp, tmp_off, tmp_stride, p->nv, p->batch_off, n, p->n_slots, p->vtx));
     }
+    return PRT_OK;
+}
+
+// Tape capacity: one FP32 entry per (vertex record, camera) from the first
+// scattering batch on; capped so that large workloads recompute instead.
+constexpr size_t kMaxTapeBytes = (size_t)16 << 30;
+
+int ensure_tape(prt_paths p, size_t n_cams, int64_t nu)
+{
+    const size_t need = (size_t)(p->n_records - p->tape_base) * n_cams;
+    if (need * sizeof(float) > kMaxTapeBytes) return PRT_E_CAPACITY;
+    if (!p->tape_beta && hipMalloc((void**)&p->tape_beta, (size_t)nu * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        p->tape_beta = nullptr;
+        return PRT_E_NOMEM;
+    }
+    if (need <= p->tape_cap && p->tape) return PRT_OK;
+    (void)hipFree(p->tape);
+    p->tape = nullptr;
+    p->tape_cap = 0;
+    if (hipMalloc((void**)&p->tape, std::max<size_t>(need, 1) * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        p->tape = nullptr;
+        return PRT_E_NOMEM;
+    }
+    p->tape_cap = need;
     return PRT_OK;
 }
 
@@ -417,8 +458,10 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
     if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
         c->n_cu = 1;
     if (hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc((void**)&c->out2, 2 * sizeof(double)) != hipSuccess) {
+        hipMalloc((void**)&c->out2, 2 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&c->flag, sizeof(int)) != hipSuccess) {
         (void)hipFree(c->counters);
+        (void)hipFree(c->out2);
         delete c;
         return fail(PRT_E_NOMEM, "context allocation failed");
     }
@@ -449,6 +492,7 @@ void prt_destroy(prt_ctx c)
     (void)hipFree(c->rpart);
     (void)hipFree(c->part);
     (void)hipFree(c->out2);
+    (void)hipFree(c->flag);
     (void)hipFree(c->counters);
     delete c;
 }
@@ -687,6 +731,16 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     a.img = images;
     a.brender = std::min(max_order_render, s->max_order);
     a.counters = c->counters;
+    // record the transmittance tape when the render covers every order (FP32 mode)
+    p->tape_valid = false;
+    if (!c->fp64 && a.brender >= s->max_order && (rc = ensure_tape(p, (size_t)dc.n, nu)) == PRT_OK) {
+        a.tape = p->tape;
+        a.tape_base = p->tape_base;
+        HIPCHK(hipMemcpyAsync(p->tape_beta, s->beta_cloud, nu * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        p->tape_valid = true;
+        p->tape_cams = dc;
+        p->tape_scene = a.s;
+    }
     const RenderPlan plan = plan_render(c->fp64, nu, npx, p->n_slots, p->first_slot, c->n_cu);
     if ((rc = ensure_scratch(&c->rpart, &c->rpart_bytes, plan.partial_bytes))) return rc;
     {
@@ -732,6 +786,14 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
     a.grad = grad;
     a.brender = s->max_order;
     a.counters = c->counters;
+    if (p->tape_valid && !c->fp64 && std::memcmp(&p->tape_cams, &dc, sizeof dc) == 0 &&
+        std::memcmp(&p->tape_scene, &a.s, sizeof a.s) == 0) {
+        // the tape is used only if beta_t equals the field it was recorded with
+        HIPCHK(launch_equal_flag(c->stream, s->beta_cloud, p->tape_beta, nu, c->flag));
+        a.tape = p->tape;
+        a.tape_base = p->tape_base;
+        a.tape_flag = c->flag;
+    }
     const GradPlan plan = plan_grad(c->fp64, nu, p->n_slots, p->first_slot, c->n_cu);
     if ((rc = ensure_scratch(&c->gpart, &c->gpart_bytes, plan.partial_bytes))) return rc;
     {

@@ -113,7 +113,7 @@ constexpr size_t kLdsImageBudget = 152 * 1024;  // image tallies (+ grid if both
 // partial[blockIdx.x]; render_reduce_kernel adds the partials in FP64 in
 // workgroup order.  Otherwise every contribution is an FP64 atomic on the
 // output image.
-template <typename Real, bool kGridLds, bool kImgLds>
+template <typename Real, bool kGridLds, bool kImgLds, bool kTape>
 __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cams, float* __restrict__ partial)
 {
     extern __shared__ unsigned char smem[];
@@ -142,6 +142,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
         const int Br = min((int)a.st.B[slot], a.brender);
         if (Br <= 0) continue;
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+        float* __restrict__ T = kTape ? a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane : nullptr;
         Vtx p0 = load_vtx(V, 0);
         double P = s.w0;  // running f/mu of the prefix (without the last vertex)
         double wprev[3] = {0.0, 0.0, 0.0};
@@ -173,6 +174,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                 const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
                 const Real tc = walk_sum<Real>(s, beta_tot, p1, u, dist, nseg);
                 const double c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
+                if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = (float)c;
                 if (kImgLds) atomicAdd(&simg[d * npix + pix], (float)c);
                 else unsafeAtomicAdd(&a.img[(int64_t)d * npix + pix], c);
                 ++nle;
@@ -200,18 +202,18 @@ __global__ void __launch_bounds__(256) render_reduce_kernel(const float* __restr
     img[i] = acc;
 }
 
-template <typename Real, bool kGridLds, bool kImgLds>
+template <typename Real, bool kGridLds, bool kImgLds, bool kTape>
 static hipError_t launch_render_t(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, float* partial)
 {
     const size_t nu = (size_t)a.s.nx * a.s.ny * a.s.nz;
     const size_t nimg = (size_t)c.W * c.H * c.n;
     const size_t lds = (kGridLds ? nu * sizeof(Real) : 0) + (kImgLds ? nimg * sizeof(float) : 0);
     if (lds) {
-        hipError_t e = hipFuncSetAttribute((const void*)render_kernel<Real, kGridLds, kImgLds>,
+        hipError_t e = hipFuncSetAttribute((const void*)render_kernel<Real, kGridLds, kImgLds, kTape>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    render_kernel<Real, kGridLds, kImgLds><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, partial);
+    render_kernel<Real, kGridLds, kImgLds, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !kImgLds) return e;
     render_reduce_kernel<<<dim3((unsigned)((nimg + 255) / 256)), dim3(256), 0, st>>>(partial, n_wg, (int64_t)nimg,
@@ -244,16 +246,23 @@ hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const Dev
                          float* partial)
 {
     if (a.st.n_slots - a.st.first_slot <= 0) return hipSuccess;
-    if (fp64) {
-        if (p.grid_lds) return launch_render_t<double, true, false>(st, a, c, p.n_wg, nullptr);
-        return launch_render_t<double, false, false>(st, a, c, p.n_wg, nullptr);
+    if (fp64) {  // the all-FP64 mode records no FP32 tape
+        if (p.grid_lds) return launch_render_t<double, true, false, false>(st, a, c, p.n_wg, nullptr);
+        return launch_render_t<double, false, false, false>(st, a, c, p.n_wg, nullptr);
     }
+    const bool tape = a.tape != nullptr;
     if (p.img_lds) {
-        if (p.grid_lds) return launch_render_t<float, true, true>(st, a, c, p.n_wg, partial);
-        return launch_render_t<float, false, true>(st, a, c, p.n_wg, partial);
+        if (p.grid_lds)
+            return tape ? launch_render_t<float, true, true, true>(st, a, c, p.n_wg, partial)
+                        : launch_render_t<float, true, true, false>(st, a, c, p.n_wg, partial);
+        return tape ? launch_render_t<float, false, true, true>(st, a, c, p.n_wg, partial)
+                    : launch_render_t<float, false, true, false>(st, a, c, p.n_wg, partial);
     }
-    if (p.grid_lds) return launch_render_t<float, true, false>(st, a, c, p.n_wg, nullptr);
-    return launch_render_t<float, false, false>(st, a, c, p.n_wg, nullptr);
+    if (p.grid_lds)
+        return tape ? launch_render_t<float, true, false, true>(st, a, c, p.n_wg, nullptr)
+                    : launch_render_t<float, true, false, false>(st, a, c, p.n_wg, nullptr);
+    return tape ? launch_render_t<float, false, false, true>(st, a, c, p.n_wg, nullptr)
+                : launch_render_t<float, false, false, false>(st, a, c, p.n_wg, nullptr);
 }
 
 // Exact pixel solid angle: F(x,y) = atan(xy / (f sqrt(x^2+y^2+f^2))) is the
@@ -314,9 +323,12 @@ hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho,
 // and writes its partial sums to partial[blockIdx.x][v]; a second kernel
 // adds the partials in FP64 in a fixed order.  Without kLds every update is
 // an FP64 atomic on the output.
-template <typename Real, typename T, bool kLds>
+template <typename Real, typename T, bool kLds, bool kTape>
 __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams, T* __restrict__ partial)
 {
+    // With a tape flag, the tape variant runs only when the tape is valid and
+    // the recomputing variant only when it is not (uniform early exit).
+    if (a.tape_flag && ((*a.tape_flag != 0) != kTape)) return;
     extern __shared__ unsigned char smem[];
     T* __restrict__ sg = reinterpret_cast<T*>(smem);
     const DevScene& s = a.s;
@@ -345,6 +357,7 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
         const int Bn = (int)a.st.B[slot];
         if (Bn <= 0) continue;
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+        const float* __restrict__ Tp = kTape ? a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane : nullptr;
         Vtx p0 = load_vtx(V, 0);
         double P = s.w0;
         double wprev[3] = {0.0, 0.0, 0.0};
@@ -352,12 +365,14 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
             const Vtx p1 = load_vtx(V, b);
             double w[3];
             const double L = seg_dir(p0, p1, w);
-            const Real dt = walk_sum<Real>(s, [&](int v) { return gd[v]; }, p0, w, L, novh);
-            P *= exp(-(double)dt * s.vk);
-            if (b >= 2) {
-                const int v = clamp_vox(p0.v, nu);
-                P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
-                                  wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
+            if (!kTape) {
+                const Real dt = walk_sum<Real>(s, [&](int v) { return gd[v]; }, p0, w, L, novh);
+                P *= exp(-(double)dt * s.vk);
+                if (b >= 2) {
+                    const int v = clamp_vox(p0.v, nu);
+                    P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
+                                      wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
+                }
             }
             const int v1 = clamp_vox(p1.v, nu);
             const double bct = (double)a.bc_t[v1];
@@ -376,8 +391,14 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
                 const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
                 const double hg = phase_hg(s, mu);
                 const double fst = fs_mix(s, bct, hg, phase_rayleigh(mu));
-                const Real tc = walk_sum<Real>(s, [&](int v) { return gtot[v]; }, p1, u, dist, nseg);
-                const double wgt = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2) * rho;
+                double c;
+                if (kTape) {
+                    c = (double)Tp[(int64_t)(b * cams.n + d) * kWave];
+                } else {
+                    const Real tc = walk_sum<Real>(s, [&](int v) { return gtot[v]; }, p1, u, dist, nseg);
+                    c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
+                }
+                const double wgt = c * rho;
                 Rb += wgt;
                 // vertex term at x_b: w * w_c f_HG / f_s,t
                 if (fst > 0.0) vert += wgt * (s.w_c * hg / fst);
@@ -432,18 +453,30 @@ __global__ void __launch_bounds__(256) grad_reduce_kernel(const T* __restrict__ 
     grad[v] = acc;
 }
 
-template <typename Real, typename T, bool kLds>
-static hipError_t launch_grad_t(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, void* partial)
+template <typename Real, typename T, bool kLds, bool kTape>
+static hipError_t launch_grad_one(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, void* partial)
 {
     const int64_t nu = (int64_t)a.s.nx * a.s.ny * a.s.nz;
     const size_t lds = kLds ? (size_t)nu * sizeof(T) : 0;
     if (kLds) {
-        hipError_t e = hipFuncSetAttribute((const void*)grad_kernel<Real, T, kLds>,
+        hipError_t e = hipFuncSetAttribute((const void*)grad_kernel<Real, T, kLds, kTape>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    grad_kernel<Real, T, kLds><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, (T*)partial);
-    hipError_t e = hipGetLastError();
+    grad_kernel<Real, T, kLds, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, (T*)partial);
+    return hipGetLastError();
+}
+
+// Launches the tape variant (when a tape flag is given) and the recomputing
+// variant; exactly one of them does work.  Then reduces LDS partials.
+template <typename Real, typename T, bool kLds>
+static hipError_t launch_grad_t(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, void* partial)
+{
+    const int64_t nu = (int64_t)a.s.nx * a.s.ny * a.s.nz;
+    hipError_t e = hipSuccess;
+    if (a.tape_flag && a.tape) e = launch_grad_one<Real, T, kLds, true>(st, a, c, n_wg, partial);
+    if (e != hipSuccess) return e;
+    e = launch_grad_one<Real, T, kLds, false>(st, a, c, n_wg, partial);
     if (e != hipSuccess || !kLds) return e;
     grad_reduce_kernel<T><<<dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, st>>>((const T*)partial, n_wg, nu,
                                                                                   a.grad);
@@ -472,6 +505,25 @@ hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCa
     }
     if (p.lds) return launch_grad_t<float, float, true>(st, a, c, p.n_wg, partial);
     return launch_grad_t<float, double, false>(st, a, c, p.n_wg, nullptr);
+}
+
+// flag = 1 when two fields are bitwise equal (the tape's beta and beta_t).
+__global__ void __launch_bounds__(256) equal_flag_kernel(const float* __restrict__ x, const float* __restrict__ y,
+                                                         int64_t n, int* __restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && __float_as_int(x[i]) != __float_as_int(y[i])) *flag = 0;
+}
+
+__global__ void set_flag_kernel(int* flag, int v) { *flag = v; }
+
+hipError_t launch_equal_flag(hipStream_t st, const float* x, const float* y, int64_t n, int* flag)
+{
+    set_flag_kernel<<<dim3(1), dim3(1), 0, st>>>(flag, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    equal_flag_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(x, y, n, flag);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- reweight

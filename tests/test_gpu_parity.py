@@ -126,10 +126,26 @@ def test_render_grad_reweight_match_oracle(env, prec, name):
         assert _rel(img, ref) <= tol["img"], (br, _rel(img, ref))
     rng = np.random.default_rng(3)
     res = rng.standard_normal(ref.shape) * np.abs(ref).mean()
-    g = api.grad(ctx, scene, bt, ch, st, torch.as_tensor(res).cuda()).cpu().numpy()
     gref = oracle.grad(scene, cams, paths, res, beta_t=beta_t)
     assert np.abs(gref).max() > 0
+    res_d = torch.as_tensor(res).cuda()
+    # grad right after a render of all orders (reuses the render's transmittances)
+    img = api.render(ctx, scene, bt, ch, st).cpu().numpy()
+    say(f"  image rel err {_rel(img, oracle.render(scene, cams, paths, beta_t=beta_t)):.2e}")
+    g = api.grad(ctx, scene, bt, ch, st, res_d).cpu().numpy()
+    say(f"  grad rel err (after full render) {_rel(g, gref):.2e}")
     assert _rel(g, gref) <= tol["grad"], _rel(g, gref)
+    # grad after a partial-order render recomputes everything
+    api.render(ctx, scene, bt, ch, st, 2)
+    g = api.grad(ctx, scene, bt, ch, st, res_d).cpu().numpy()
+    say(f"  grad rel err (recomputed) {_rel(g, gref):.2e}")
+    assert _rel(g, gref) <= tol["grad"], _rel(g, gref)
+    # grad at a field other than the last render's recomputes everything
+    beta_u = _perturbed(scene, seed=11, amp=0.2)
+    api.render(ctx, scene, bt, ch, st)
+    g = api.grad(ctx, scene, _dev(torch, beta_u), ch, st, res_d).cpu().numpy()
+    gref_u = oracle.grad(scene, cams, paths, res, beta_t=beta_u)
+    assert _rel(g, gref_u) <= tol["grad"], _rel(g, gref_u)
     mr, ess = P.prt_reweight(ctx.handle, P.make_scene(scene, bt), st.handle)
     mr_ref, ess_ref = oracle.reweight(scene, paths, beta_t=beta_t)
     assert abs(mr - mr_ref) <= tol["rw"] * abs(mr_ref), (mr, mr_ref)
@@ -172,10 +188,11 @@ def test_full_size_cloud32(env):
     ref = oracle.render(scene, cams, paths, beta_t=beta_t)
     assert _rel(img, ref) <= TOL["fp32"]["img"], _rel(img, ref)
     res = np.random.default_rng(4).standard_normal(ref.shape) * np.abs(ref).mean()
-    say("full size: gpu grad")
+    say(f"full size: image rel err {_rel(img, ref):.2e}; gpu grad")
     g = api.grad(ctx, scene, bt, ch, st, torch.as_tensor(res).cuda()).cpu().numpy()
     say("full size: oracle grad")
     gref = oracle.grad(scene, cams, paths, res, beta_t=beta_t)
+    say(f"full size: grad rel err {_rel(g, gref):.2e}")
     assert _rel(g, gref) <= TOL["fp32"]["grad"], _rel(g, gref)
     mr, ess = P.prt_reweight(ctx.handle, P.make_scene(scene, bt), st.handle)
     mr_ref, ess_ref = oracle.reweight(scene, paths, beta_t=beta_t)
