@@ -55,11 +55,29 @@ def parse():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--cpu-paths", type=int, default=1 << 22, help="paths in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (to scale FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain 1 GiB device-to-device copy (torch's copy kernel), 3 times:
+    FETCH_SIZE and WRITE_SIZE of these dispatches should each read 1 GiB."""
+    import torch
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "dispatches": 3}), flush=True)
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on a single GPU; --gpus must be 1 (multi-GPU path sharding is "
               "described in DESIGN.md but not built)", file=sys.stderr)
@@ -104,9 +122,10 @@ def main():
     state = {"t": 0, "store": None}
 
     def resample():
-        if state["store"] is not None:
-            state["store"].close()
-        state["store"] = api.PathStore.sample(ctx, scene, beta32, seed + state["t"], n_paths)
+        if state["store"] is None:
+            state["store"] = api.PathStore.sample(ctx, scene, beta32, seed + state["t"], n_paths)
+        else:
+            state["store"].resample(scene, beta32, seed + state["t"], n_paths)
 
     def iterate():
         st = state["store"].handle

@@ -141,6 +141,12 @@ const char* prt_last_error(void);
    n_paths in [1, 2^31 - 64]. */
 int prt_sample(prt_ctx ctx, const prt_scene* scene, uint64_t seed, uint64_t n_paths, prt_paths* out);
 
+/* Resample into an existing store (Alg. 2 after the first iteration): the
+   same operation as prt_sample, reusing the store's device buffers when they
+   are large enough (the store may change grid or size).  On failure the store
+   is left valid and empty.  Synchronises. */
+int prt_resample(prt_ctx ctx, const prt_scene* scene, uint64_t seed, uint64_t n_paths, prt_paths paths);
+
 /* Build a store from host paths in CSR form: vertex k of path i is
    xyz[3*(off[i]+k)..] (grid units, float) with voxel vox[off[i]+k]; B[i]
    scatters; vertices 1..B[i] are scatter points with voxel ids in range,

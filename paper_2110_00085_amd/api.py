@@ -66,6 +66,10 @@ class PathStore:
         return cls(ctx, P.prt_paths_import(ctx.handle, P.make_scene(params, beta_cloud), off, xyz, vox, B,
                                            beta_ref, seed))
 
+    def resample(self, params, beta_cloud, seed: int, n_paths: int) -> "PathStore":
+        P.prt_resample(self.ctx.handle, P.make_scene(params, beta_cloud), seed, n_paths, self.handle)
+        return self
+
     def info(self):
         return P.prt_paths_info(self.handle)
 

@@ -51,6 +51,11 @@ struct TraceArgs {
     float* tape;
     int64_t tape_base;
     const int* tape_flag;
+    // Dynamic schedule: wavefronts take tasks from *work (reset to 0 before the
+    // launch); task t covers batch n_batches-1-t/groups (heaviest first, the
+    // batches being sorted by size) and camera group t%groups.
+    unsigned int* work;
+    int groups;
 };
 
 // ---- sampling, sorting, packing (sample.hip)
@@ -66,7 +71,10 @@ hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, i
 hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, const int64_t* tmp_off,
                        int64_t tmp_stride, const uint8_t* nv, const int64_t* batch_off, int64_t n,
                        int64_t n_slots, float4* vtx);
-hipError_t launch_first_nonzero(hipStream_t st, const uint8_t* B, int64_t n, int64_t* out);
+// meta[0] = batch_off[nb] (records), meta[1] = first slot with B > 0 (n if
+// none), meta[2] = batch_off of that slot's batch (records of B = 0 batches).
+hipError_t launch_store_meta(hipStream_t st, const uint8_t* B, int64_t n, const int64_t* batch_off, int64_t nb,
+                             int64_t* meta);
 
 // ---- hot path (trace.hip)
 // Where render tallies and reads: FP32 LDS image partials (reduced by a

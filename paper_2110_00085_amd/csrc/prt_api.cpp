@@ -55,6 +55,16 @@ struct prt_ctx_s {
     size_t gpart_bytes = 0;
     void* rpart = nullptr;      // per-workgroup image partials
     size_t rpart_bytes = 0;
+    // sampling / sorting temporaries (grow-only)
+    void* s_tmp = nullptr;
+    size_t s_tmp_bytes = 0;
+    void* s_keys = nullptr;     // tB and tnv
+    size_t s_keys_bytes = 0;
+    void* s_hist = nullptr;
+    size_t s_hist_bytes = 0;
+    void* s_off = nullptr;      // import offsets
+    size_t s_off_bytes = 0;
+    int64_t* meta = nullptr;    // 3 int64 read back after packing
     void* grid_tot = nullptr;
     void* grid_dlt = nullptr;
     size_t grid_bytes = 0;
@@ -65,6 +75,7 @@ struct prt_ctx_s {
     double* out2 = nullptr;     // two doubles of reduction output
     unsigned long long* counters = nullptr;  // 4
     int* flag = nullptr;        // device flag: the tape matches beta_t
+    unsigned int* work = nullptr;  // task counter of the persistent kernels
     uint64_t paths_done = 0;
     bool timing = false;
     std::vector<Timed> pending;
@@ -75,6 +86,9 @@ struct prt_ctx_s {
 
 struct prt_paths_s {
     int device = 0;
+    // allocated element counts of each buffer (a refill reuses a buffer when
+    // it is large enough)
+    int64_t cap_perm = 0, cap_slots = 0, cap_nv = 0, cap_boff = 0, cap_records = 0, cap_nu = 0;
     uint64_t n = 0;
     int64_t nb = 0, n_slots = 0, first_slot = 0;
     int32_t max_order = 0, nx = 0, ny = 0, nz = 0;
@@ -232,6 +246,11 @@ int make_dev_cams(const prt_cameras* c, double vk, DevCams* out)
     return PRT_OK;
 }
 
+// Camera groups per path task: three groups balance the persistent waves
+// (a task is at most a third of a path's local estimates) at the cost of
+// walking each free-flight segment once per group.
+int camera_groups(int n_cams) { return n_cams < 3 ? n_cams : 3; }
+
 int check_match(const prt_scene* s, prt_paths p)
 {
     if (!p) return fail(PRT_E_INVALID, "paths is NULL");
@@ -327,9 +346,43 @@ void free_store(prt_paths p)
     delete p;
 }
 
-// Shared tail of sample and import: sort the temp paths by size, lay them out
-// in wavefront batches and fill the store.  tmp rows are addressed by tmp_off
-// (CSR) or by id * tmp_stride.
+// Grows one buffer to hold `count` elements (contents not kept); *cap is
+// the element count currently allocated for exactly this buffer.
+template <typename T>
+int grow(T** buf, int64_t* cap, int64_t count)
+{
+    count = std::max<int64_t>(count, 1);
+    if (*buf && count <= *cap) return PRT_OK;
+    (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    int rc = dalloc(buf, (size_t)count);
+    if (rc == PRT_OK) *cap = count;
+    return rc;
+}
+
+// Per-path arrays of a store for n paths (perm, sizes, batch offsets).
+int reserve_paths(prt_paths p, int64_t n)
+{
+    const int64_t nb = (n + kWave - 1) / kWave;
+    int rc;
+    if ((rc = grow(&p->perm, &p->cap_perm, n))) return rc;
+    if ((rc = grow(&p->B, &p->cap_slots, nb * kWave))) return rc;
+    if ((rc = grow(&p->nv, &p->cap_nv, nb * kWave))) return rc;
+    return grow(&p->batch_off, &p->cap_boff, nb + 1);
+}
+
+uint64_t store_bytes(const prt_paths_s* p)
+{
+    return (uint64_t)p->cap_perm * 4 + (uint64_t)p->cap_slots + (uint64_t)p->cap_nv + (uint64_t)p->cap_boff * 8 +
+           (uint64_t)p->cap_records * 16 + (uint64_t)p->cap_nu * 4 + (uint64_t)p->tape_cap * 4 +
+           (p->tape_beta ? (uint64_t)p->cap_nu * 4 : 0);
+}
+
+// Shared tail of sample, resample and import: sort the temporary paths by
+// size, lay them out in wavefront batches and fill the store.  tmp rows are
+// addressed by tmp_off (CSR) or by id * tmp_stride.  Reads back the store
+// size once (one synchronisation).
 int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_off, int64_t tmp_stride,
                 const uint8_t* tB, const uint8_t* tnv)
 {
@@ -338,48 +391,69 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
     p->n_slots = p->nb * kWave;
     const int nbins = p->max_order + 1;
     int rc;
-    uint32_t* hist = nullptr;
-    if ((rc = dalloc(&p->perm, n, &p->bytes))) return rc;
-    if ((rc = dalloc(&p->B, p->n_slots, &p->bytes))) return rc;
-    if ((rc = dalloc(&p->nv, p->n_slots, &p->bytes))) return rc;
-    if ((rc = dalloc(&p->batch_off, p->nb + 1, &p->bytes))) return rc;
-    if ((rc = dalloc(&hist, sort_scratch_words(n, nbins)))) return rc;
+    if ((rc = reserve_paths(p, n))) return rc;
+    if ((rc = ensure_scratch(&c->s_hist, &c->s_hist_bytes, sort_scratch_words(n, nbins) * sizeof(uint32_t)))) return rc;
     {
         TimedScope ts(c, K_SORT);
-        hipError_t e = launch_sort_by_size(c->stream, tB, n, nbins, hist, p->perm);
-        if (e == hipSuccess) e = launch_gather_sizes(c->stream, p->perm, tB, tnv, n, p->n_slots, p->B, p->nv);
-        if (e == hipSuccess) e = launch_batch_offsets(c->stream, p->nv, p->nb, p->batch_off);
-        if (e != hipSuccess) {
-            (void)hipFree(hist);
-            return fail(PRT_E_HIP, "sort launch failed: %s", hipGetErrorString(e));
-        }
+        HIPCHK(launch_sort_by_size(c->stream, tB, n, nbins, (uint32_t*)c->s_hist, p->perm));
+        HIPCHK(launch_gather_sizes(c->stream, p->perm, tB, tnv, n, p->n_slots, p->B, p->nv));
+        HIPCHK(launch_batch_offsets(c->stream, p->nv, p->nb, p->batch_off));
+        HIPCHK(launch_store_meta(c->stream, p->B, n, p->batch_off, p->nb, c->meta));
     }
-    int64_t* d_first = nullptr;
-    if ((rc = dalloc(&d_first, 1))) {
-        (void)hipFree(hist);
-        return rc;
-    }
-    HIPCHK(launch_first_nonzero(c->stream, p->B, n, d_first));
-    int64_t host2[2] = {0, 0};
-    hipError_t e1 = hipMemcpyAsync(&host2[0], p->batch_off + p->nb, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
-    hipError_t e2 = hipMemcpyAsync(&host2[1], d_first, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
-    hipError_t e3 = hipStreamSynchronize(c->stream);
-    (void)hipFree(hist);
-    (void)hipFree(d_first);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
-        return fail(PRT_E_HIP, "store size readback failed: %s",
-                    hipGetErrorString(e3 != hipSuccess ? e3 : (e1 != hipSuccess ? e1 : e2)));
-    p->n_records = host2[0];
-    p->first_slot = host2[1];
-    p->tape_base = p->n_records;
-    if (p->first_slot < n) HIPCHK(hipMemcpy(&p->tape_base, p->batch_off + p->first_slot / kWave, sizeof(int64_t),
-                                            hipMemcpyDeviceToHost));
-    if ((rc = dalloc(&p->vtx, p->n_records, &p->bytes))) return rc;
+    int64_t meta[3] = {0, 0, 0};
+    HIPCHK(hipMemcpyAsync(meta, c->meta, sizeof meta, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    p->n_records = meta[0];
+    p->first_slot = meta[1];
+    p->tape_base = meta[2];
+    if ((rc = grow(&p->vtx, &p->cap_records, p->n_records))) return rc;
     {
         TimedScope ts(c, K_PACK);
         HIPCHK(launch_pack(c->stream, p->perm, tmp, tmp_off, tmp_stride, p->nv, p->batch_off, n, p->n_slots, p->vtx));
     }
     return PRT_OK;
+}
+
+// Samples n paths into p (allocated or reused) under scene->beta_cloud.
+int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_paths p)
+{
+    const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
+    const int64_t stride = s->max_order + 2;
+    int rc;
+    // earlier work may still read the store's or the context's buffers
+    HIPCHK(hipDeviceSynchronize());
+    if ((rc = ensure_grids(c, nu))) return rc;
+    if ((rc = grow(&p->beta_ref, &p->cap_nu, nu))) return rc;
+    if ((rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes, (size_t)n * stride * sizeof(float4)))) return rc;
+    if ((rc = ensure_scratch(&c->s_keys, &c->s_keys_bytes, 2 * (size_t)n))) return rc;
+    p->n = (uint64_t)n;
+    p->seed = seed;
+    p->max_order = s->max_order;
+    p->nx = s->nx;
+    p->ny = s->ny;
+    p->nz = s->nz;
+    p->tape_valid = false;
+    uint8_t* tB = (uint8_t*)c->s_keys;
+    uint8_t* tnv = tB + n;
+    HIPCHK(hipMemcpyAsync(p->beta_ref, s->beta_cloud, nu * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    {
+        TimedScope ts(c, K_PREP);
+        HIPCHK(launch_prep_grids(c->stream, c->fp64, p->beta_ref, nullptr, s->beta_air, nu, c->grid_tot, nullptr));
+    }
+    SampleArgs a;
+    a.s = make_dev_scene(s);
+    a.beta_c = p->beta_ref;
+    a.grid_tot = c->grid_tot;
+    a.seed = seed;
+    a.n = n;
+    a.tmp = (float4*)c->s_tmp;
+    a.tB = tB;
+    a.tnv = tnv;
+    {
+        TimedScope ts(c, K_SAMPLE);
+        HIPCHK(launch_sample(c->stream, c->fp64, a));
+    }
+    return build_store(c, p, (const float4*)c->s_tmp, nullptr, stride, tB, tnv);
 }
 
 // Tape capacity: one FP32 entry per (vertex record, camera) from the first
@@ -459,7 +533,11 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
         c->n_cu = 1;
     if (hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&c->out2, 2 * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&c->flag, sizeof(int)) != hipSuccess) {
+        hipMalloc((void**)&c->flag, sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&c->work, sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void**)&c->meta, 3 * sizeof(int64_t)) != hipSuccess) {
+        (void)hipFree(c->work);
+        (void)hipFree(c->flag);
         (void)hipFree(c->counters);
         (void)hipFree(c->out2);
         delete c;
@@ -490,9 +568,15 @@ void prt_destroy(prt_ctx c)
     (void)hipFree(c->pix);
     (void)hipFree(c->gpart);
     (void)hipFree(c->rpart);
+    (void)hipFree(c->s_tmp);
+    (void)hipFree(c->s_keys);
+    (void)hipFree(c->s_hist);
+    (void)hipFree(c->s_off);
+    (void)hipFree(c->meta);
     (void)hipFree(c->part);
     (void)hipFree(c->out2);
     (void)hipFree(c->flag);
+    (void)hipFree(c->work);
     (void)hipFree(c->counters);
     delete c;
 }
@@ -512,50 +596,32 @@ int prt_sample(prt_ctx c, const prt_scene* s, uint64_t seed, uint64_t n_paths, p
     if (rc) return rc;
     if (n_paths < 1 || n_paths > ((uint64_t)1 << 31) - 64) return fail(PRT_E_CAPACITY, "n_paths must be in [1, 2^31-64]");
     DeviceGuard g(c->device);
-    const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
-    const int64_t n = (int64_t)n_paths;
-    const int64_t stride = s->max_order + 2;
-    if ((rc = ensure_grids(c, nu))) return rc;
     prt_paths p = new_store(c, s, n_paths, seed);
-    float4* tmp = nullptr;
-    uint8_t *tB = nullptr, *tnv = nullptr;
-    auto cleanup = [&](int code) {
+    if ((rc = fill_sampled(c, s, seed, (int64_t)n_paths, p))) {
         (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(tmp);
-        (void)hipFree(tB);
-        (void)hipFree(tnv);
-        if (code != PRT_OK) free_store(p);
-        return code;
-    };
-    if ((rc = dalloc(&p->beta_ref, nu, &p->bytes))) return cleanup(rc);
-    if ((rc = dalloc(&tmp, (size_t)n * stride))) return cleanup(rc);
-    if ((rc = dalloc(&tB, n))) return cleanup(rc);
-    if ((rc = dalloc(&tnv, n))) return cleanup(rc);
-    hipError_t e = hipMemcpyAsync(p->beta_ref, s->beta_cloud, nu * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return cleanup(fail(PRT_E_HIP, "beta_ref snapshot: %s", hipGetErrorString(e)));
-    {
-        TimedScope ts(c, K_PREP);
-        e = launch_prep_grids(c->stream, c->fp64, p->beta_ref, nullptr, s->beta_air, nu, c->grid_tot, nullptr);
+        free_store(p);
+        return rc;
     }
-    if (e != hipSuccess) return cleanup(fail(PRT_E_HIP, "prep launch: %s", hipGetErrorString(e)));
-    SampleArgs a;
-    a.s = make_dev_scene(s);
-    a.beta_c = p->beta_ref;
-    a.grid_tot = c->grid_tot;
-    a.seed = seed;
-    a.n = n;
-    a.tmp = tmp;
-    a.tB = tB;
-    a.tnv = tnv;
-    {
-        TimedScope ts(c, K_SAMPLE);
-        e = launch_sample(c->stream, c->fp64, a);
+    *out = p;
+    return PRT_OK;
+}
+
+int prt_resample(prt_ctx c, const prt_scene* s, uint64_t seed, uint64_t n_paths, prt_paths p)
+{
+    if (!c || !p) return fail(PRT_E_INVALID, "ctx/paths is NULL");
+    int rc = check_scene(s);
+    if (rc) return rc;
+    if (n_paths < 1 || n_paths > ((uint64_t)1 << 31) - 64) return fail(PRT_E_CAPACITY, "n_paths must be in [1, 2^31-64]");
+    if (p->device != c->device) return fail(PRT_E_INVALID, "store lives on device %d, context on %d", p->device, c->device);
+    DeviceGuard g(c->device);
+    if ((rc = fill_sampled(c, s, seed, (int64_t)n_paths, p))) {
+        // the store is left empty but valid
+        p->n = 0;
+        p->nb = p->n_slots = p->first_slot = p->n_records = 0;
+        p->tape_valid = false;
+        return rc;
     }
-    if (e != hipSuccess) return cleanup(fail(PRT_E_HIP, "sample launch: %s", hipGetErrorString(e)));
-    if ((rc = build_store(c, p, tmp, nullptr, stride, tB, tnv))) return cleanup(rc);
-    rc = cleanup(PRT_OK);
-    if (rc == PRT_OK) *out = p;
-    return rc;
+    return PRT_OK;
 }
 
 int prt_paths_import(prt_ctx c, const prt_scene* s, uint64_t n_paths, const int64_t* off, const float* xyz,
@@ -603,33 +669,28 @@ int prt_paths_import(prt_ctx c, const prt_scene* s, uint64_t n_paths, const int6
         hnv[i] = (uint8_t)(off[i + 1] - off[i]);
     }
     prt_paths p = new_store(c, s, n_paths, seed);
-    float4* tmp = nullptr;
-    int64_t* toff = nullptr;
-    uint8_t *tB = nullptr, *tnv = nullptr;
-    auto cleanup = [&](int code) {
+    auto bail = [&](int code) {
         (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(tmp);
-        (void)hipFree(toff);
-        (void)hipFree(tB);
-        (void)hipFree(tnv);
-        if (code != PRT_OK) free_store(p);
+        free_store(p);
         return code;
     };
-    if ((rc = dalloc(&p->beta_ref, nu, &p->bytes))) return cleanup(rc);
-    if ((rc = dalloc(&tmp, nrec))) return cleanup(rc);
-    if ((rc = dalloc(&toff, n + 1))) return cleanup(rc);
-    if ((rc = dalloc(&tB, n))) return cleanup(rc);
-    if ((rc = dalloc(&tnv, n))) return cleanup(rc);
+    if ((rc = grow(&p->beta_ref, &p->cap_nu, nu))) return bail(rc);
+    if ((rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes, (size_t)nrec * sizeof(float4)))) return bail(rc);
+    if ((rc = ensure_scratch(&c->s_off, &c->s_off_bytes, (size_t)(n + 1) * sizeof(int64_t)))) return bail(rc);
+    if ((rc = ensure_scratch(&c->s_keys, &c->s_keys_bytes, 2 * (size_t)n))) return bail(rc);
+    float4* tmp = (float4*)c->s_tmp;
+    int64_t* toff = (int64_t*)c->s_off;
+    uint8_t* tB = (uint8_t*)c->s_keys;
+    uint8_t* tnv = tB + n;
     hipError_t e = hipMemcpy(tmp, h.data(), nrec * sizeof(float4), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(toff, off, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tB, hB.data(), n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tnv, hnv.data(), n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->beta_ref, beta_ref, nu * sizeof(float), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return cleanup(fail(PRT_E_HIP, "import upload: %s", hipGetErrorString(e)));
-    if ((rc = build_store(c, p, tmp, toff, 0, tB, tnv))) return cleanup(rc);
-    rc = cleanup(PRT_OK);
-    if (rc == PRT_OK) *out = p;
-    return rc;
+    if (e != hipSuccess) return bail(fail(PRT_E_HIP, "import upload: %s", hipGetErrorString(e)));
+    if ((rc = build_store(c, p, tmp, toff, 0, tB, tnv))) return bail(rc);
+    *out = p;
+    return PRT_OK;
 }
 
 int prt_paths_export(prt_ctx c, prt_paths p, int64_t* off, float* xyz, int32_t* vox, int32_t* B, float* beta_ref)
@@ -691,7 +752,7 @@ int prt_paths_info(prt_paths p, prt_paths_info_t* info)
     info->n_vertices = (uint64_t)p->n_records;
     info->n_batches = (uint64_t)p->nb;
     info->seed = p->seed;
-    info->bytes = p->bytes;
+    info->bytes = store_bytes(p);
     info->max_order = p->max_order;
     info->nx = p->nx;
     info->ny = p->ny;
@@ -731,6 +792,8 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     a.img = images;
     a.brender = std::min(max_order_render, s->max_order);
     a.counters = c->counters;
+    a.work = c->work;
+    a.groups = camera_groups(dc.n);
     // record the transmittance tape when the render covers every order (FP32 mode)
     p->tape_valid = false;
     if (!c->fp64 && a.brender >= s->max_order && (rc = ensure_tape(p, (size_t)dc.n, nu)) == PRT_OK) {
@@ -786,6 +849,8 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
     a.grad = grad;
     a.brender = s->max_order;
     a.counters = c->counters;
+    a.work = c->work;
+    a.groups = camera_groups(dc.n);
     if (p->tape_valid && !c->fp64 && std::memcmp(&p->tape_cams, &dc, sizeof dc) == 0 &&
         std::memcmp(&p->tape_scene, &a.s, sizeof a.s) == 0) {
         // the tape is used only if beta_t equals the field it was recorded with

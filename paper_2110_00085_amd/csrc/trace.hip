@@ -88,6 +88,14 @@ __device__ __forceinline__ double vertex_ratio(const DevScene& s, double bct, do
     return (bsr / btr) * (fst / fsr);
 }
 
+// Next task for this wavefront (lane 0 takes it from the counter).
+__device__ __forceinline__ unsigned int next_task(unsigned int* work)
+{
+    unsigned int t = 0;
+    if (threadIdx.x % kWave == 0) t = atomicAdd(work, 1u);
+    return __shfl(t, 0);
+}
+
 __device__ __forceinline__ void flush_counts(unsigned long long* c, uint64_t seg, uint64_t le, uint64_t ovh)
 {
     if (seg) atomicAdd(&c[0], (unsigned long long)seg);
@@ -99,10 +107,11 @@ __device__ __forceinline__ void flush_counts(unsigned long long* c, uint64_t seg
 
 // ------------------------------------------------------------------ render
 
-// Persistent launch: each workgroup of kBlock threads caches the extinction
-// grid in LDS when it fits, then its wavefronts walk batches
-// first_batch + wave, + total_waves, ...  (the batches are sorted by path
-// size, so the stride gives every wave a similar mix of sizes).
+__global__ void reset_u32_kernel(unsigned int* p) { *p = 0u; }
+
+// Persistent launch: each workgroup of kBlock threads sets up its LDS (image
+// tallies, extinction grid), then its wavefronts take (batch, camera group)
+// tasks from a device counter, heaviest batches first.
 constexpr int kBlock = 1024;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr size_t kLdsBudget = 128 * 1024;       // grids
@@ -134,13 +143,17 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
     const double r2scale = 1.0 / (s.vk * s.vk);
     const int lane = threadIdx.x % kWave;
     const int64_t nb = a.st.n_slots / kWave;
-    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-    uint64_t nseg = 0, nle = 0;
-    for (int64_t bt = a.st.first_slot / kWave + (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; bt < nb;
-         bt += stride) {
+    const int G = a.groups, cpg = (cams.n + G - 1) / G;
+    const unsigned int n_tasks = (unsigned int)(nb - a.st.first_slot / kWave) * (unsigned int)G;
+    uint64_t nseg = 0, nle = 0, novh = 0;
+    for (unsigned int task = next_task(a.work); task < n_tasks; task = next_task(a.work)) {
+        const int64_t bt = nb - 1 - (int64_t)(task / G);
+        const int g = (int)(task % G);
+        const int d_lo = g * cpg, d_hi = min(cams.n, d_lo + cpg);
         const int64_t slot = bt * kWave + lane;
         const int Br = min((int)a.st.B[slot], a.brender);
         if (Br <= 0) continue;
+        uint64_t& segc = g == 0 ? nseg : novh;  // segments are walked once per camera group
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
         float* __restrict__ T = kTape ? a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane : nullptr;
         Vtx p0 = load_vtx(V, 0);
@@ -151,7 +164,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
             double w[3];
             const double L = seg_dir(p0, p1, w);
             // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
-            const Real dt = walk_sum<Real>(s, [&](int v) { return gd[v]; }, p0, w, L, nseg);
+            const Real dt = walk_sum<Real>(s, [&](int v) { return gd[v]; }, p0, w, L, segc);
             P *= exp(-(double)dt * s.vk);
             if (b >= 2) {
                 const int v = clamp_vox(p0.v, nu);
@@ -162,7 +175,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
             const int v1 = clamp_vox(p1.v, nu);
             const double bct = (double)a.bc_t[v1];
             const double base = P / ((double)a.st.beta_ref[v1] + s.beta_air);
-            for (int d = 0; d < cams.n; ++d) {
+            for (int d = d_lo; d < d_hi; ++d) {
                 const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
                 if (pix < 0) continue;
                 const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
@@ -183,7 +196,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
             p0 = p1;
         }
     }
-    flush_counts(a.counters, nseg, nle, 0);
+    flush_counts(a.counters, nseg, nle, novh);
     if (kImgLds) {
         __syncthreads();
         float* __restrict__ out = partial + (int64_t)blockIdx.x * nimg;
@@ -213,6 +226,7 @@ static hipError_t launch_render_t(hipStream_t st, const TraceArgs& a, const DevC
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
+    reset_u32_kernel<<<dim3(1), dim3(1), 0, st>>>(a.work);
     render_kernel<Real, kGridLds, kImgLds, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !kImgLds) return e;
@@ -348,14 +362,20 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
     const double r2scale = 1.0 / (s.vk * s.vk);
     const int lane = threadIdx.x % kWave;
     const int64_t nb = a.st.n_slots / kWave;
-    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    const int G = a.groups, cpg = (cams.n + G - 1) / G;
+    const unsigned int n_tasks = (unsigned int)(nb - a.st.first_slot / kWave) * (unsigned int)G;
     uint64_t nseg = 0, novh = 0;
     double R[kMaxOrder + 1];
-    for (int64_t bt = a.st.first_slot / kWave + (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; bt < nb;
-         bt += stride) {
+    // Camera groups split a path's local estimates; pass 2 is linear in R_b, so
+    // each group runs it with its own partial sums and the totals add up.
+    for (unsigned int task = next_task(a.work); task < n_tasks; task = next_task(a.work)) {
+        const int64_t bt = nb - 1 - (int64_t)(task / G);
+        const int g = (int)(task % G);
+        const int d_lo = g * cpg, d_hi = min(cams.n, d_lo + cpg);
         const int64_t slot = bt * kWave + lane;
         const int Bn = (int)a.st.B[slot];
         if (Bn <= 0) continue;
+        uint64_t& segc = g == 0 ? nseg : novh;
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
         const float* __restrict__ Tp = kTape ? a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane : nullptr;
         Vtx p0 = load_vtx(V, 0);
@@ -378,7 +398,7 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
             const double bct = (double)a.bc_t[v1];
             const double base = P / ((double)a.st.beta_ref[v1] + s.beta_air);
             double Rb = 0.0, vert = 0.0;
-            for (int d = 0; d < cams.n; ++d) {
+            for (int d = d_lo; d < d_hi; ++d) {
                 const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
                 if (pix < 0) continue;
                 const double rho = a.rho[(int64_t)d * npix + pix];
@@ -418,7 +438,7 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
             double w[3];
             const double L = seg_dir(pk, pk1, w);
             if (A != 0.0) {
-                walk_scatter<Real>(s, add, pk, w, L, -A * s.vk, nseg);
+                walk_scatter<Real>(s, add, pk, w, L, -A * s.vk, segc);
                 if (k >= 1) {
                     const Vtx pm = load_vtx(V, k - 1);
                     double wm[3];
@@ -463,6 +483,7 @@ static hipError_t launch_grad_one(hipStream_t st, const TraceArgs& a, const DevC
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
+    reset_u32_kernel<<<dim3(1), dim3(1), 0, st>>>(a.work);
     grad_kernel<Real, T, kLds, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, (T*)partial);
     return hipGetLastError();
 }

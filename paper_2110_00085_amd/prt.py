@@ -68,6 +68,7 @@ def lib():
             "prt_set_stream": ([_V, _V], C.c_int),
             "prt_last_error": ([], C.c_char_p),
             "prt_sample": ([_V, C.POINTER(prt_scene), _U64, _U64, C.POINTER(_V)], C.c_int),
+            "prt_resample": ([_V, C.POINTER(prt_scene), _U64, _U64, _V], C.c_int),
             "prt_paths_import": ([_V, C.POINTER(prt_scene), _U64, _V, _V, _V, _V, _V, _U64, C.POINTER(_V)], C.c_int),
             "prt_paths_export": ([_V, _V, _V, _V, _V, _V, _V], C.c_int),
             "prt_paths_permutation": ([_V, _V, _V], C.c_int),
@@ -161,6 +162,10 @@ def prt_sample(ctx, scene: prt_scene, seed: int, n_paths: int):
     h = _V()
     _check(lib().prt_sample(ctx, C.byref(scene), seed, n_paths, C.byref(h)))
     return h
+
+
+def prt_resample(ctx, scene: prt_scene, seed: int, n_paths: int, paths):
+    _check(lib().prt_resample(ctx, C.byref(scene), seed, n_paths, paths))
 
 
 def prt_paths_import(ctx, scene: prt_scene, off, xyz, vox, B, beta_ref, seed: int = 0):

@@ -84,6 +84,26 @@ def test_sample_fp64_matches_oracle(env):
     assert np.array_equal(perm, oracle.sort_permutation(B))
 
 
+def test_resample_reuses_store(env):
+    """prt_resample refills a store (growing and shrinking it) with exactly the
+    paths prt_sample draws for the same seed and size."""
+    torch, P, api = env
+    say("resample grow/shrink")
+    ctx = api.Context(0, P.PRT_ALL_FP64)
+    s8 = inputs.cloud8()
+    b8 = _dev(torch, s8.beta_cloud)
+    st = api.PathStore.sample(ctx, s8, b8, 1001, 500)
+    s32 = inputs.cloud32()
+    b32 = _dev(torch, s32.beta_cloud)
+    for sc, bd, seed, n in ((s8, b8, 7, 20_000), (s32, b32, 9, 3_000), (s8, b8, 1001, 10_000)):
+        st.resample(sc, bd, seed, n)
+        ref = api.PathStore.sample(ctx, sc, bd, seed, n)
+        got, exp = st.export(), ref.export()
+        for x, y in zip(got, exp):
+            assert np.array_equal(x, y)
+        assert st.info().n_paths == n and st.info().nx == sc.nx
+
+
 @pytest.mark.parametrize("name", ["cloud8", "cloud32mid"])
 def test_sample_fp32_close_to_oracle(env, name):
     torch, P, api = env
