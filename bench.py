@@ -38,7 +38,9 @@ if ROOT not in sys.path:
 # VALU peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-operations/s
 # (one FP32 or FP64 FMA per lane per clock without packed math).
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
-# algorithmic VALU lane-ops per unit of work ("Roofline")
+# algorithmic VALU lane-operations per unit of work: the arithmetic of one
+# voxel piece of a walk and of one local estimate (projection, phase
+# functions, weight), as the kernels perform it
 OPS = {
     "render": {"voxel_segment": 6, "local_estimate": 40},
     "grad": {"voxel_segment": 8, "local_estimate": 50},
@@ -79,8 +81,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on a single GPU; --gpus must be 1 (multi-GPU path sharding is "
-              "described in DESIGN.md but not built)", file=sys.stderr)
+        print("bench.py: the hot path runs on one GPU; --gpus must be 1 (sharding paths over GPUs is not "
+              "implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -172,20 +174,23 @@ def main():
 
     ms_step = 1e3 * t_full / args.steps
     value = n_paths / (t_full / args.steps)
-    # dominant kernel and its roofline
+    # dominant kernel (most time per step) and its roofline; a grad call may
+    # launch its kernel once per z slab, so work is spread over its launches
     dom = max(ktimes, key=lambda k: ktimes[k][0])
-    dom_ms = ktimes[dom][0] / max(ktimes[dom][1], 1)
+    launches = max(ktimes[dom][1], 1)
+    dom_ms = ktimes[dom][0] / launches
+    per_call = launches / args.steps
     units = {"voxel_segment": c_r["voxel_segments"], "local_estimate": c_r["local_estimates"]}
     per = OPS.get(dom)
+    roofline = {"bound": "alu", "kernel": dom, "achieved": None, "peak": VALU_LANE_OPS_PEAK / 1e12,
+                "unit": "TOP/s", "frac": None, "traffic": None, "avg_launch_ms": dom_ms,
+                "launches_per_step": per_call}
     if per is not None:
-        ops = sum(per[k] * units[k] for k in per)
+        work = {k: units[k] / per_call for k in per}
+        ops = sum(per[k] * work[k] for k in per)
         achieved = ops / (dom_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                    "unit": "TOP/s", "frac": achieved * 1e12 / VALU_LANE_OPS_PEAK, "traffic": None,
-                    "avg_launch_ms": dom_ms, "work_per_launch": units}
-    else:
-        roofline = {"bound": "alu", "kernel": dom, "achieved": None, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                    "unit": "TOP/s", "frac": None, "traffic": None, "avg_launch_ms": dom_ms}
+        roofline.update({"achieved": achieved, "frac": achieved * 1e12 / VALU_LANE_OPS_PEAK,
+                         "work_per_launch": work, "lane_ops_per_launch": ops})
 
     out = {
         "metric": "paths/s (forward+backward)",

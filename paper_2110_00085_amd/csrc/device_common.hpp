@@ -150,31 +150,29 @@ __device__ __forceinline__ int project(const DevCams& c, int d, double x, double
 
 // ------------------------------------------------------------- DDA walker
 
-// Incremental voxel walk along p + t w from voxel (ix,iy,iz) over t in
-// [0, tmax] (grid units), clipped by the box.  The functor is called as
+// Steps of the incremental voxel walk along p + t w, from voxel (ix,iy,iz)
+// at parameter t (grid units) up to tmax, inside the box [0,nx) x [0,ny) x
+// [z0,z1) (all layers, or a slab of z layers).  The functor is called as
 // f(voxel, t_start, length) for every piece in order, with length >= 0
-// (zero for a degenerate piece, e.g. when p sits on a voxel face); it
-// returns false to stop the walk.  Returns the parameter t reached (the box
-// exit, tmax, or where the functor stopped).
+// (zero for a degenerate piece, e.g. when p sits on a voxel face) and the
+// voxel numbered inside the box (ix + nx*(iy + ny*(iz - z0))); it returns
+// false to stop the walk.  Returns the parameter t reached (the box exit,
+// tmax, or where the functor stopped).
 //
 // The step is branchless: the axis of the nearest face is chosen with
 // selects, and each axis carries the number of faces left before the box
 // boundary, so leaving the box needs no index bound checks.  Every
 // iteration either advances one axis or returns, and the loop is capped at
-// nx+ny+nz+3 iterations, so it terminates for any input (including
-// non-finite directions, whose components are treated as zero).
+// nx+ny+(z1-z0)+3 iterations, so it terminates for any input (including
+// non-finite directions, whose components are treated as zero).  Face
+// parameters are always measured from p, so a walk that starts part way
+// (t > 0) produces the same pieces as one started at p.
 template <typename Real, typename F>
-__device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy,
-                                         int iz, Real wx, Real wy, Real wz, Real tmax, F&& f)
+__device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real px, Real py, Real pz, int ix, int iy,
+                                          int iz, int sx, int sy, int sz, Real ivx, Real ivy, Real ivz, Real t,
+                                          Real tmax, F&& f)
 {
     const Real inf = (Real)INFINITY;
-    const int sx = wx > (Real)0 ? 1 : (wx < (Real)0 ? -1 : 0);
-    const int sy = wy > (Real)0 ? 1 : (wy < (Real)0 ? -1 : 0);
-    const int sz = wz > (Real)0 ? 1 : (wz < (Real)0 ? -1 : 0);
-    if (sx == 0 && sy == 0 && sz == 0) return (Real)0;
-    const Real ivx = sx ? (Real)1 / wx : (Real)0;
-    const Real ivy = sy ? (Real)1 / wy : (Real)0;
-    const Real ivz = sz ? (Real)1 / wz : (Real)0;
     Real tnx = sx > 0 ? ((Real)(ix + 1) - px) * ivx : (sx < 0 ? ((Real)ix - px) * ivx : inf);
     Real tny = sy > 0 ? ((Real)(iy + 1) - py) * ivy : (sy < 0 ? ((Real)iy - py) * ivy : inf);
     Real tnz = sz > 0 ? ((Real)(iz + 1) - pz) * ivz : (sz < 0 ? ((Real)iz - pz) * ivz : inf);
@@ -182,11 +180,10 @@ __device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real p
     // faces left before the boundary along each axis
     int rx = sx > 0 ? nx - 1 - ix : ix;
     int ry = sy > 0 ? ny - 1 - iy : iy;
-    int rz = sz > 0 ? nz - 1 - iz : iz;
+    int rz = sz > 0 ? z1 - 1 - iz : iz - z0;
     const int dvx = sx, dvy = sy * nx, dvz = sz * nx * ny;
-    int v = ix + nx * (iy + ny * iz);
-    Real t = (Real)0;
-    const int maxit = nx + ny + nz + 3;
+    int v = ix + nx * (iy + ny * (iz - z0));
+    const int maxit = nx + ny + (z1 - z0) + 3;
     for (int it = 0; it < maxit; ++it) {
         const Real tn = fmin(tnx, fmin(tny, tnz));
         const Real te = fmin(tn, tmax);
@@ -206,6 +203,61 @@ __device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real p
         tnz = (!bx && !by) ? tnz + dtz : tnz;
     }
     return t;
+}
+
+// Direction signs and inverse components; false when w has no nonzero
+// component.
+template <typename Real>
+__device__ __forceinline__ bool dda_dir(Real wx, Real wy, Real wz, int& sx, int& sy, int& sz, Real& ivx, Real& ivy,
+                                        Real& ivz)
+{
+    sx = wx > (Real)0 ? 1 : (wx < (Real)0 ? -1 : 0);
+    sy = wy > (Real)0 ? 1 : (wy < (Real)0 ? -1 : 0);
+    sz = wz > (Real)0 ? 1 : (wz < (Real)0 ? -1 : 0);
+    ivx = sx ? (Real)1 / wx : (Real)0;
+    ivy = sy ? (Real)1 / wy : (Real)0;
+    ivz = sz ? (Real)1 / wz : (Real)0;
+    return sx != 0 || sy != 0 || sz != 0;
+}
+
+// Walk over the whole grid from p (in voxel (ix,iy,iz)) for t in [0, tmax].
+template <typename Real, typename F>
+__device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy,
+                                         int iz, Real wx, Real wy, Real wz, Real tmax, F&& f)
+{
+    int sx, sy, sz;
+    Real ivx, ivy, ivz;
+    if (!dda_dir(wx, wy, wz, sx, sy, sz, ivx, ivy, ivz)) return (Real)0;
+    return dda_steps<Real>(nx, ny, 0, nz, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, (Real)0, tmax, f);
+}
+
+// The part of that walk inside the slab of z layers [z0, z1): the pieces
+// are those of the whole-grid walk that fall in the slab, with voxels
+// numbered inside the slab.  When p lies outside the slab the walk enters
+// it through the near z face (if the ray reaches that face inside the box
+// before tmax); the entry voxel is taken from the entry point, so a piece
+// next to the entry can differ from the whole-grid walk by rounding only.
+template <typename Real, typename F>
+__device__ __forceinline__ void dda_walk_slab(int nx, int ny, int z0, int z1, Real px, Real py, Real pz, int ix,
+                                              int iy, int iz, Real wx, Real wy, Real wz, Real tmax, F&& f)
+{
+    int sx, sy, sz;
+    Real ivx, ivy, ivz;
+    if (!dda_dir(wx, wy, wz, sx, sy, sz, ivx, ivy, ivz)) return;
+    Real t = (Real)0;
+    if (iz < z0 || iz >= z1) {
+        const bool below = iz < z0;
+        if (below ? sz <= 0 : sz >= 0) return;
+        t = ((Real)(below ? z0 : z1) - pz) * ivz;
+        if (!(t < tmax)) return;
+        const Real x = px + t * wx, y = py + t * wy;
+        if (!(x >= (Real)0 && x <= (Real)nx && y >= (Real)0 && y <= (Real)ny)) return;
+        ix = min((int)x, nx - 1);
+        iy = min((int)y, ny - 1);
+        iz = below ? z0 : z1 - 1;
+        t = fmax(t, (Real)0);
+    }
+    dda_steps<Real>(nx, ny, z0, z1, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, t, tmax, f);
 }
 
 // Voxel index components of a linear voxel id.

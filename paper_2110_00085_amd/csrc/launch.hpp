@@ -85,20 +85,33 @@ struct RenderPlan {
     size_t partial_bytes = 0;
 };
 RenderPlan plan_render(int fp64, int64_t nu, int64_t nimg, int64_t n_slots, int64_t first_slot, int n_cu);
+// The persistent render kernel alone (its task counter a.work[0] must be zero);
+// with img_lds, launch_render_reduce then adds the partials into the images.
 hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
                          float* partial);
+hipError_t launch_render_reduce(hipStream_t st, const DevCams& c, const RenderPlan& p, const float* partial,
+                                double* img);
+// work[0..n) = 0 (n <= 64): task counters of the persistent kernels.
+hipError_t launch_reset_work(hipStream_t st, unsigned int* work, int n);
 hipError_t launch_render_finalize(hipStream_t st, double* img, const DevCams& c, double scale);
 hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho, const DevCams& c, double scale);
-// How the gradient is tallied: per-workgroup LDS partials (reduced by a
-// second kernel) when the grid fits the LDS budget, else FP64 atomics.
+// How the gradient is tallied: per-workgroup FP64 LDS partials of one slab of
+// z layers at a time (reduced by a second kernel), when a layer fits the LDS
+// budget and the grid needs few slabs, else FP64 atomics on the output.
 struct GradPlan {
     bool lds = false;
+    int slab_layers = 1, n_slabs = 1;
     int n_wg = 1;
     size_t partial_bytes = 0;
 };
-GradPlan plan_grad(int fp64, int64_t nu, int64_t n_slots, int64_t first_slot, int n_cu);
-hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p,
+GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu);
+// Gradient terms of slab i (z layers [i*slab_layers, min(nz, (i+1)*slab_layers))):
+// the persistent grad kernels (task counters a.work[0] and a.work[1] must be
+// zero); with lds, launch_grad_reduce then writes the slab's gradient.
+hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p, int slab,
                        void* partial);
+hipError_t launch_grad_reduce(hipStream_t st, const GradPlan& p, int nx, int ny, int nz, int slab,
+                              const void* partial, double* grad);
 hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int64_t* n_blocks);
 // flag = 1 if a[i] == b[i] bitwise for all i < n, else 0.
 hipError_t launch_equal_flag(hipStream_t st, const float* a, const float* b, int64_t n, int* flag);

@@ -35,9 +35,12 @@ int fail(int code, const char* fmt, ...)
         if (e_ != hipSuccess) return fail(PRT_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));       \
     } while (0)
 
-enum KernelId { K_SAMPLE = 0, K_SORT, K_PACK, K_PREP, K_RENDER, K_FINALIZE, K_GRAD, K_REWEIGHT, K_LOSS, K_ADAM, K_COUNT };
-const char* kKernelNames[K_COUNT] = {"sample", "sort", "pack", "prep", "render", "render_finalize",
-                                     "grad", "reweight", "loss", "adam"};
+enum KernelId {
+    K_SAMPLE = 0, K_SORT, K_PACK, K_PREP, K_RENDER, K_FINALIZE, K_GRAD, K_REWEIGHT, K_LOSS, K_ADAM,
+    K_RENDER_REDUCE, K_GRAD_REDUCE, K_COUNT
+};
+const char* kKernelNames[K_COUNT] = {"sample", "sort", "pack",     "prep", "render",        "render_finalize",
+                                     "grad",   "reweight", "loss", "adam", "render_reduce", "grad_reduce"};
 
 struct Timed {
     int id;
@@ -75,7 +78,7 @@ struct prt_ctx_s {
     double* out2 = nullptr;     // two doubles of reduction output
     unsigned long long* counters = nullptr;  // 4
     int* flag = nullptr;        // device flag: the tape matches beta_t
-    unsigned int* work = nullptr;  // task counter of the persistent kernels
+    unsigned int* work = nullptr;  // task counters of the persistent kernels [2]
     uint64_t paths_done = 0;
     bool timing = false;
     std::vector<Timed> pending;
@@ -534,7 +537,7 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
     if (hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&c->out2, 2 * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&c->flag, sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&c->work, sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void**)&c->work, 2 * sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void**)&c->meta, 3 * sizeof(int64_t)) != hipSuccess) {
         (void)hipFree(c->work);
         (void)hipFree(c->flag);
@@ -806,9 +809,14 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     }
     const RenderPlan plan = plan_render(c->fp64, nu, npx, p->n_slots, p->first_slot, c->n_cu);
     if ((rc = ensure_scratch(&c->rpart, &c->rpart_bytes, plan.partial_bytes))) return rc;
+    HIPCHK(launch_reset_work(c->stream, c->work, 1));
     {
         TimedScope ts(c, K_RENDER);
         HIPCHK(launch_render(c->stream, c->fp64, a, dc, plan, (float*)c->rpart));
+    }
+    {
+        TimedScope ts(c, K_RENDER_REDUCE);
+        HIPCHK(launch_render_reduce(c->stream, dc, plan, (const float*)c->rpart, images));
     }
     {
         TimedScope ts(c, K_FINALIZE);
@@ -859,11 +867,16 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
         a.tape_base = p->tape_base;
         a.tape_flag = c->flag;
     }
-    const GradPlan plan = plan_grad(c->fp64, nu, p->n_slots, p->first_slot, c->n_cu);
+    const GradPlan plan = plan_grad(s->nx, s->ny, s->nz, p->n_slots, p->first_slot, c->n_cu);
     if ((rc = ensure_scratch(&c->gpart, &c->gpart_bytes, plan.partial_bytes))) return rc;
-    {
-        TimedScope ts(c, K_GRAD);
-        HIPCHK(launch_grad(c->stream, c->fp64, a, dc, plan, c->gpart));
+    for (int i = 0; i < plan.n_slabs; ++i) {
+        HIPCHK(launch_reset_work(c->stream, c->work, 2));
+        {
+            TimedScope ts(c, K_GRAD);
+            HIPCHK(launch_grad(c->stream, c->fp64, a, dc, plan, i, c->gpart));
+        }
+        TimedScope ts(c, K_GRAD_REDUCE);
+        HIPCHK(launch_grad_reduce(c->stream, plan, s->nx, s->ny, s->nz, i, c->gpart, grad));
     }
     return PRT_OK;
 }

@@ -59,22 +59,23 @@ __device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx&
     return acc;
 }
 
-// Calls add(v, scale * length) for every nonzero piece of the walk.
+// Calls add(v, scale * length) for every nonzero piece of the walk that
+// lies in the slab of z layers [z0, z1), v numbered inside the slab.
 template <typename Real, typename A>
 __device__ __forceinline__ void walk_scatter(const DevScene& s, A&& add, const Vtx& p, const double w[3], double tmax,
-                                             double scale, uint64_t& count)
+                                             double scale, uint64_t& count, int z0, int z1)
 {
     int ix, iy, iz;
     voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
     uint32_t n = 0;
-    dda_walk<Real>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
-                   (Real)w[2], (Real)tmax, [&](int v, Real, Real l) {
-                       if (l > (Real)0) {
-                           add(v, scale * (double)l);
-                           ++n;
-                       }
-                       return true;
-                   });
+    dda_walk_slab<Real>(s.nx, s.ny, z0, z1, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
+                        (Real)w[2], (Real)tmax, [&](int v, Real, Real l) {
+                            if (l > (Real)0) {
+                                add(v, scale * (double)l);
+                                ++n;
+                            }
+                            return true;
+                        });
     count += n;
 }
 
@@ -107,7 +108,10 @@ __device__ __forceinline__ void flush_counts(unsigned long long* c, uint64_t seg
 
 // ------------------------------------------------------------------ render
 
-__global__ void reset_u32_kernel(unsigned int* p) { *p = 0u; }
+__global__ void reset_u32_kernel(unsigned int* p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
 
 // Persistent launch: each workgroup of kBlock threads sets up its LDS (image
 // tallies, extinction grid), then its wavefronts take (batch, camera group)
@@ -116,6 +120,7 @@ constexpr int kBlock = 1024;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr size_t kLdsBudget = 128 * 1024;       // grids
 constexpr size_t kLdsImageBudget = 152 * 1024;  // image tallies (+ grid if both fit)
+constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs per launch sequence
 
 // kGridLds: the total-extinction grid is cached in LDS.  kImgLds: the
 // workgroup tallies its contributions in an FP32 LDS image and writes it to
@@ -226,12 +231,7 @@ static hipError_t launch_render_t(hipStream_t st, const TraceArgs& a, const DevC
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    reset_u32_kernel<<<dim3(1), dim3(1), 0, st>>>(a.work);
     render_kernel<Real, kGridLds, kImgLds, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !kImgLds) return e;
-    render_reduce_kernel<<<dim3((unsigned)((nimg + 255) / 256)), dim3(256), 0, st>>>(partial, n_wg, (int64_t)nimg,
-                                                                                   a.img);
     return hipGetLastError();
 }
 
@@ -277,6 +277,21 @@ hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const Dev
                     : launch_render_t<float, true, false, false>(st, a, c, p.n_wg, nullptr);
     return tape ? launch_render_t<float, false, false, true>(st, a, c, p.n_wg, nullptr)
                 : launch_render_t<float, false, false, false>(st, a, c, p.n_wg, nullptr);
+}
+
+hipError_t launch_render_reduce(hipStream_t st, const DevCams& c, const RenderPlan& p, const float* partial,
+                                double* img)
+{
+    if (!p.img_lds) return hipSuccess;
+    const int64_t nimg = (int64_t)c.W * c.H * c.n;
+    render_reduce_kernel<<<dim3((unsigned)((nimg + 255) / 256)), dim3(256), 0, st>>>(partial, p.n_wg, nimg, img);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_work(hipStream_t st, unsigned int* work, int n)
+{
+    reset_u32_kernel<<<dim3(1), dim3(64), 0, st>>>(work, n);
+    return hipGetLastError();
 }
 
 // Exact pixel solid angle: F(x,y) = atan(xy / (f sqrt(x^2+y^2+f^2))) is the
@@ -333,28 +348,40 @@ hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho,
 // vertex term at x_k.  Together this is sum_{b,d} w_{b,d} S(b,d) with S the
 // tomography PSF of the local-estimate sub-path.
 //
-// Tally: with kLds the workgroup accumulates the gradient in LDS (type T)
-// and writes its partial sums to partial[blockIdx.x][v]; a second kernel
-// adds the partials in FP64 in a fixed order.  Without kLds every update is
-// an FP64 atomic on the output.
-template <typename Real, typename T, bool kLds, bool kTape>
-__global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams, T* __restrict__ partial)
+// Tally: one launch covers the slab of z layers [z0, z1) and adds only the
+// score terms of voxels in it (the walks are clipped to the slab).  With
+// kLds the workgroup accumulates the slab in LDS in FP64 (LDS FP64 adds are
+// several times faster than FP32 ones on this chip) and writes its partial
+// sums to partial[blockIdx.x][v]; a second kernel adds the partials in a
+// fixed order.  Without kLds the launch covers all layers and every update
+// is an FP64 atomic on the output.
+template <typename Real, bool kLds, bool kTape>
+__global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams, int z0, int z1,
+                                                      double* __restrict__ partial)
 {
     // With a tape flag, the tape variant runs only when the tape is valid and
     // the recomputing variant only when it is not (uniform early exit).
     if (a.tape_flag && ((*a.tape_flag != 0) != kTape)) return;
     extern __shared__ unsigned char smem[];
-    T* __restrict__ sg = reinterpret_cast<T*>(smem);
+    double* __restrict__ sg = reinterpret_cast<double*>(smem);
     const DevScene& s = a.s;
     const int nu = s.nx * s.ny * s.nz;
+    const int layer = s.nx * s.ny;
+    const int vlo = z0 * layer, nsv = (z1 - z0) * layer;
     if (kLds) {
-        for (int i = threadIdx.x; i < nu; i += kBlock) sg[i] = (T)0;
+        for (int i = threadIdx.x; i < nsv; i += kBlock) sg[i] = 0.0;
         __syncthreads();
     }
-    double* __restrict__ gout = a.grad;
+    double* __restrict__ gout = a.grad + vlo;
+    // v is numbered inside the slab
     auto add = [&](int v, double x) {
-        if (kLds) atomicAdd(&sg[v], (T)x);
+        if (kLds) atomicAdd(&sg[v], x);
         else unsafeAtomicAdd(&gout[v], x);
+    };
+    // vertex terms: v is a grid voxel, added only when it lies in the slab
+    auto add_vox = [&](int v, double x) {
+        const int u = v - vlo;
+        if ((unsigned)u < (unsigned)nsv) add(u, x);
     };
     const Real* __restrict__ gtot = (const Real*)a.grid_tot;
     const Real* __restrict__ gd = (const Real*)a.grid_dlt;
@@ -364,6 +391,8 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
     const int64_t nb = a.st.n_slots / kWave;
     const int G = a.groups, cpg = (cams.n + G - 1) / G;
     const unsigned int n_tasks = (unsigned int)(nb - a.st.first_slot / kWave) * (unsigned int)G;
+    // algorithmic work is counted once, in the launch of the first slab
+    const bool count = z0 == 0;
     uint64_t nseg = 0, novh = 0;
     double R[kMaxOrder + 1];
     // Camera groups split a path's local estimates; pass 2 is linear in R_b, so
@@ -376,6 +405,7 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
         const int Bn = (int)a.st.B[slot];
         if (Bn <= 0) continue;
         uint64_t& segc = g == 0 ? nseg : novh;
+        uint64_t& cseg = count ? nseg : novh;
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
         const float* __restrict__ Tp = kTape ? a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane : nullptr;
         Vtx p0 = load_vtx(V, 0);
@@ -415,16 +445,16 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
                 if (kTape) {
                     c = (double)Tp[(int64_t)(b * cams.n + d) * kWave];
                 } else {
-                    const Real tc = walk_sum<Real>(s, [&](int v) { return gtot[v]; }, p1, u, dist, nseg);
+                    const Real tc = walk_sum<Real>(s, [&](int v) { return gtot[v]; }, p1, u, dist, cseg);
                     c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
                 }
                 const double wgt = c * rho;
                 Rb += wgt;
                 // vertex term at x_b: w * w_c f_HG / f_s,t
                 if (fst > 0.0) vert += wgt * (s.w_c * hg / fst);
-                walk_scatter<Real>(s, add, p1, u, dist, -wgt * s.vk, novh);
+                walk_scatter<Real>(s, add, p1, u, dist, -wgt * s.vk, novh, z0, z1);
             }
-            if (vert != 0.0) add(v1, vert);
+            if (vert != 0.0) add_vox(v1, vert);
             R[b] = Rb;
             wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
             p0 = p1;
@@ -438,16 +468,16 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
             double w[3];
             const double L = seg_dir(pk, pk1, w);
             if (A != 0.0) {
-                walk_scatter<Real>(s, add, pk, w, L, -A * s.vk, segc);
-                if (k >= 1) {
+                walk_scatter<Real>(s, add, pk, w, L, -A * s.vk, segc, z0, z1);
+                const int v = clamp_vox(pk.v, nu);
+                if (k >= 1 && (unsigned)(v - vlo) < (unsigned)nsv) {
                     const Vtx pm = load_vtx(V, k - 1);
                     double wm[3];
                     seg_dir(pm, pk, wm);
                     const double mu = wm[0] * w[0] + wm[1] * w[1] + wm[2] * w[2];
-                    const int v = clamp_vox(pk.v, nu);
                     const double hg = phase_hg(s, mu);
                     const double fst = fs_mix(s, (double)a.bc_t[v], hg, phase_rayleigh(mu));
-                    if (fst > 0.0) add(v, A * (s.w_c * hg / fst));
+                    if (fst > 0.0) add(v - vlo, A * (s.w_c * hg / fst));
                 }
             }
             pk1 = pk;
@@ -456,76 +486,98 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
     flush_counts(a.counters, nseg, 0, novh);
     if (kLds) {
         __syncthreads();
-        T* __restrict__ out = partial + (int64_t)blockIdx.x * nu;
-        for (int i = threadIdx.x; i < nu; i += kBlock) out[i] = sg[i];
+        double* __restrict__ out = partial + (int64_t)blockIdx.x * nsv;
+        for (int i = threadIdx.x; i < nsv; i += kBlock) out[i] = sg[i];
     }
 }
 
-// grad[v] = sum over workgroups of partial[w][v], in FP64, in workgroup order.
-template <typename T>
-__global__ void __launch_bounds__(256) grad_reduce_kernel(const T* __restrict__ partial, int n_wg, int64_t nu,
+// grad[v] = sum over workgroups of partial[w][v], in workgroup order.
+__global__ void __launch_bounds__(256) grad_reduce_kernel(const double* __restrict__ partial, int n_wg, int64_t nv,
                                                           double* __restrict__ grad)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nu) return;
+    if (v >= nv) return;
     double acc = 0.0;
-    for (int w = 0; w < n_wg; ++w) acc += (double)partial[(int64_t)w * nu + v];
+    for (int w = 0; w < n_wg; ++w) acc += partial[(int64_t)w * nv + v];
     grad[v] = acc;
 }
 
-template <typename Real, typename T, bool kLds, bool kTape>
-static hipError_t launch_grad_one(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, void* partial)
+template <typename Real, bool kLds, bool kTape>
+static hipError_t launch_grad_one(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, int z0, int z1,
+                                  double* partial)
 {
-    const int64_t nu = (int64_t)a.s.nx * a.s.ny * a.s.nz;
-    const size_t lds = kLds ? (size_t)nu * sizeof(T) : 0;
+    const size_t lds = kLds ? (size_t)(z1 - z0) * a.s.nx * a.s.ny * sizeof(double) : 0;
     if (kLds) {
-        hipError_t e = hipFuncSetAttribute((const void*)grad_kernel<Real, T, kLds, kTape>,
+        hipError_t e = hipFuncSetAttribute((const void*)grad_kernel<Real, kLds, kTape>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    reset_u32_kernel<<<dim3(1), dim3(1), 0, st>>>(a.work);
-    grad_kernel<Real, T, kLds, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, (T*)partial);
+    grad_kernel<Real, kLds, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, z0, z1, partial);
     return hipGetLastError();
 }
 
-// Launches the tape variant (when a tape flag is given) and the recomputing
-// variant; exactly one of them does work.  Then reduces LDS partials.
-template <typename Real, typename T, bool kLds>
-static hipError_t launch_grad_t(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, void* partial)
+// The tape variant (when a tape flag is given) and the recomputing variant;
+// exactly one of them does work.  They take tasks from work[0] and work[1].
+template <typename Real, bool kLds>
+static hipError_t launch_grad_t(hipStream_t st, const TraceArgs& a, const DevCams& c, const GradPlan& p, int z0,
+                                int z1, double* partial)
 {
-    const int64_t nu = (int64_t)a.s.nx * a.s.ny * a.s.nz;
     hipError_t e = hipSuccess;
-    if (a.tape_flag && a.tape) e = launch_grad_one<Real, T, kLds, true>(st, a, c, n_wg, partial);
+    if (a.tape_flag && a.tape) e = launch_grad_one<Real, kLds, true>(st, a, c, p.n_wg, z0, z1, partial);
     if (e != hipSuccess) return e;
-    e = launch_grad_one<Real, T, kLds, false>(st, a, c, n_wg, partial);
-    if (e != hipSuccess || !kLds) return e;
-    grad_reduce_kernel<T><<<dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, st>>>((const T*)partial, n_wg, nu,
-                                                                                  a.grad);
-    return hipGetLastError();
+    TraceArgs b = a;
+    b.work = a.work + 1;
+    return launch_grad_one<Real, kLds, false>(st, b, c, p.n_wg, z0, z1, partial);
 }
 
-GradPlan plan_grad(int fp64, int64_t nu, int64_t n_slots, int64_t first_slot, int n_cu)
+GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu)
 {
     GradPlan p;
-    const int64_t tally = fp64 ? 8 : 4;
-    p.lds = nu * tally <= (int64_t)kLdsBudget;
+    const int64_t layer_bytes = (int64_t)nx * ny * (int64_t)sizeof(double);
+    const int64_t layers = std::min<int64_t>(nz, (int64_t)kLdsBudget / layer_bytes);
+    const int64_t slabs = layers > 0 ? (nz + layers - 1) / layers : 0;
+    // Every slab repeats the per-contribution set-up of pass 1, so past a few
+    // slabs FP64 atomics on the output are cheaper.
+    p.lds = layers > 0 && slabs <= kMaxGradSlabs;
+    p.slab_layers = p.lds ? (int)layers : nz;
+    p.n_slabs = p.lds ? (int)slabs : 1;
     const int64_t batches = (n_slots - first_slot + kWave - 1) / kWave;
     const int64_t need = std::max<int64_t>(1, (batches + kWavesPerBlock - 1) / kWavesPerBlock);
     p.n_wg = (int)std::min<int64_t>(need, (int64_t)n_cu * (p.lds ? 1 : 2));
-    p.partial_bytes = p.lds ? (size_t)p.n_wg * nu * tally : 0;
+    p.partial_bytes = p.lds ? (size_t)p.n_wg * (size_t)(p.slab_layers * layer_bytes) : 0;
     return p;
 }
 
-hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p,
+void grad_slab(const GradPlan& p, int nz, int i, int* z0, int* z1)
+{
+    *z0 = i * p.slab_layers;
+    *z1 = std::min(nz, *z0 + p.slab_layers);
+}
+
+hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p, int slab,
                        void* partial)
 {
     if (a.st.n_slots - a.st.first_slot <= 0) return hipSuccess;
+    int z0, z1;
+    grad_slab(p, a.s.nz, slab, &z0, &z1);
     if (fp64) {
-        if (p.lds) return launch_grad_t<double, double, true>(st, a, c, p.n_wg, partial);
-        return launch_grad_t<double, double, false>(st, a, c, p.n_wg, nullptr);
+        if (p.lds) return launch_grad_t<double, true>(st, a, c, p, z0, z1, (double*)partial);
+        return launch_grad_t<double, false>(st, a, c, p, z0, z1, nullptr);
     }
-    if (p.lds) return launch_grad_t<float, float, true>(st, a, c, p.n_wg, partial);
-    return launch_grad_t<float, double, false>(st, a, c, p.n_wg, nullptr);
+    if (p.lds) return launch_grad_t<float, true>(st, a, c, p, z0, z1, (double*)partial);
+    return launch_grad_t<float, false>(st, a, c, p, z0, z1, nullptr);
+}
+
+hipError_t launch_grad_reduce(hipStream_t st, const GradPlan& p, int nx, int ny, int nz, int slab,
+                              const void* partial, double* grad)
+{
+    if (!p.lds) return hipSuccess;
+    int z0, z1;
+    grad_slab(p, nz, slab, &z0, &z1);
+    const int64_t layer = (int64_t)nx * ny, nv = (int64_t)(z1 - z0) * layer;
+    grad_reduce_kernel<<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st>>>((const double*)partial, p.n_wg,
+                                                                                nv, grad + z0 * layer);
+    return hipGetLastError();
 }
 
 // flag = 1 when two fields are bitwise equal (the tape's beta and beta_t).

@@ -59,6 +59,12 @@ def _workload(name):
     if name == "cloud32mid":
         s = inputs.cloud32()
         return s, inputs.cloud32_cameras(s), (1 << 15) + 37, 1002
+    if name == "slabs40":
+        # 40 x 40 x 24 grid: the gradient tally runs in three z slabs of
+        # 10, 10 and 4 layers (FP64 LDS, 12.8 KB per layer)
+        s = inputs.random_field((40, 40, 24), voxel_km=0.02, lo=0.0, hi=30.0, seed=40, albedo_cloud=0.99,
+                                g=0.85, max_order=12)
+        return s, inputs.arc_cameras(s, [-50.0, -20.0, 0.0, 25.0, 55.0], 32, 32), 20_011, 1040
     raise KeyError(name)
 
 
@@ -127,7 +133,7 @@ def test_sample_fp32_close_to_oracle(env, name):
 # ---------------------------------------------- render / grad / reweight
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["cloud8", "cloud32mid"])
+@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "slabs40"])
 def test_render_grad_reweight_match_oracle(env, prec, name):
     torch, P, api = env
     scene, cams, n, seed = _workload(name)
