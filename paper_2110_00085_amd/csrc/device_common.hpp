@@ -157,20 +157,21 @@ __device__ __forceinline__ int project(const DevCams& c, int d, double x, double
 // (zero for a degenerate piece, e.g. when p sits on a voxel face) and the
 // voxel numbered inside the box (ix + nx*(iy + ny*(iz - z0))); it returns
 // false to stop the walk.  Returns the parameter t reached (the box exit,
-// tmax, or where the functor stopped).
+// tmax, or where the functor stopped) and adds the number of pieces visited
+// to *pieces.
 //
 // The step is branchless: the axis of the nearest face is chosen with
 // selects, and each axis carries the number of faces left before the box
 // boundary, so leaving the box needs no index bound checks.  Every
-// iteration either advances one axis or returns, and the loop is capped at
-// nx+ny+(z1-z0)+3 iterations, so it terminates for any input (including
-// non-finite directions, whose components are treated as zero).  Face
+// iteration either leaves the loop or uses up one face of one axis, so the
+// walk ends after at most (faces left) + 1 pieces for any input, including
+// non-finite directions (whose components are treated as zero).  Face
 // parameters are always measured from p, so a walk that starts part way
 // (t > 0) produces the same pieces as one started at p.
 template <typename Real, typename F>
 __device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real px, Real py, Real pz, int ix, int iy,
                                           int iz, int sx, int sy, int sz, Real ivx, Real ivy, Real ivz, Real t,
-                                          Real tmax, F&& f)
+                                          Real tmax, uint32_t& pieces, F&& f)
 {
     const Real inf = (Real)INFINITY;
     Real tnx = sx > 0 ? ((Real)(ix + 1) - px) * ivx : (sx < 0 ? ((Real)ix - px) * ivx : inf);
@@ -181,27 +182,30 @@ __device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real p
     int rx = sx > 0 ? nx - 1 - ix : ix;
     int ry = sy > 0 ? ny - 1 - iy : iy;
     int rz = sz > 0 ? z1 - 1 - iz : iz - z0;
+    const int faces = rx + ry + rz;
     const int dvx = sx, dvy = sy * nx, dvz = sz * nx * ny;
     int v = ix + nx * (iy + ny * (iz - z0));
-    const int maxit = nx + ny + (z1 - z0) + 3;
-    for (int it = 0; it < maxit; ++it) {
+    for (;;) {
         const Real tn = fmin(tnx, fmin(tny, tnz));
-        const Real te = fmin(tn, tmax);
-        if (!f(v, t, fmax(te - t, (Real)0))) return t;
-        t = fmax(t, te);
-        if (!(tn < tmax)) return t;
+        const bool go = tn < tmax;
+        // the face parameters only grow, so te never decreases along the walk
+        const Real te = go ? tn : tmax;
+        if (!f(v, t, fmax(te - t, (Real)0))) break;
+        t = te;
         const bool bx = tnx == tn;
         const bool by = !bx && tny == tn;
+        const bool bz = !bx && !by;
         const int r = bx ? rx : (by ? ry : rz);
-        if (r <= 0) return t;
+        if (!go || r <= 0) break;
         rx -= bx ? 1 : 0;
         ry -= by ? 1 : 0;
-        rz -= (!bx && !by) ? 1 : 0;
+        rz -= bz ? 1 : 0;
         v += bx ? dvx : (by ? dvy : dvz);
-        tnx = bx ? tnx + dtx : tnx;
-        tny = by ? tny + dty : tny;
-        tnz = (!bx && !by) ? tnz + dtz : tnz;
+        tnx += bx ? dtx : (Real)0;
+        tny += by ? dty : (Real)0;
+        tnz += bz ? dtz : (Real)0;
     }
+    pieces += (uint32_t)(faces - rx - ry - rz + 1);
     return t;
 }
 
@@ -228,10 +232,26 @@ __device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real p
     int sx, sy, sz;
     Real ivx, ivy, ivz;
     if (!dda_dir(wx, wy, wz, sx, sy, sz, ivx, ivy, ivz)) return (Real)0;
-    return dda_steps<Real>(nx, ny, 0, nz, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, (Real)0, tmax, f);
+    uint32_t pieces = 0;
+    return dda_steps<Real>(nx, ny, 0, nz, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, (Real)0, tmax, pieces,
+                           f);
 }
 
-// The part of that walk inside the slab of z layers [z0, z1): the pieces
+// As dda_walk, adding the number of pieces visited to *pieces.
+template <typename Real, typename F>
+__device__ __forceinline__ Real dda_walk_counted(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy,
+                                                 int iz, Real wx, Real wy, Real wz, Real tmax, uint32_t& pieces,
+                                                 F&& f)
+{
+    int sx, sy, sz;
+    Real ivx, ivy, ivz;
+    if (!dda_dir(wx, wy, wz, sx, sy, sz, ivx, ivy, ivz)) return (Real)0;
+    return dda_steps<Real>(nx, ny, 0, nz, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, (Real)0, tmax, pieces,
+                           f);
+}
+
+// The part of that walk inside the slab of z layers [z0, z1) (pieces counted
+// as in dda_walk_counted): the pieces
 // are those of the whole-grid walk that fall in the slab, with voxels
 // numbered inside the slab.  When p lies outside the slab the walk enters
 // it through the near z face (if the ray reaches that face inside the box
@@ -239,7 +259,8 @@ __device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real p
 // next to the entry can differ from the whole-grid walk by rounding only.
 template <typename Real, typename F>
 __device__ __forceinline__ void dda_walk_slab(int nx, int ny, int z0, int z1, Real px, Real py, Real pz, int ix,
-                                              int iy, int iz, Real wx, Real wy, Real wz, Real tmax, F&& f)
+                                              int iy, int iz, Real wx, Real wy, Real wz, Real tmax,
+                                              uint32_t& pieces, F&& f)
 {
     int sx, sy, sz;
     Real ivx, ivy, ivz;
@@ -257,7 +278,7 @@ __device__ __forceinline__ void dda_walk_slab(int nx, int ny, int z0, int z1, Re
         iz = below ? z0 : z1 - 1;
         t = fmax(t, (Real)0);
     }
-    dda_steps<Real>(nx, ny, z0, z1, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, t, tmax, f);
+    dda_steps<Real>(nx, ny, z0, z1, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, t, tmax, pieces, f);
 }
 
 // Voxel index components of a linear voxel id.

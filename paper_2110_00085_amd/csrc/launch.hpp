@@ -31,6 +31,7 @@ struct SampleArgs {
     float4* tmp;           // [n][max_order+2] records
     uint8_t* tB;
     uint8_t* tnv;
+    unsigned int* next;    // path-id counter of the persistent sampler (zero at launch)
 };
 
 struct TraceArgs {
@@ -49,8 +50,18 @@ struct TraceArgs {
     // (FP32) at tape[(batch_off[batch] - tape_base) * n_cams + (b*n_cams + d)*64 + lane];
     // grad reuses it when *tape_flag is 1 (same beta_t, cameras and scene).
     float* tape;
-    int64_t tape_base;
+    int64_t tape_base;        // records of the leading batches without scatters
+    // Render prefix: pbase[batch_off[batch] - tape_base + 64*b + lane] =
+    // P_b / (beta_ref(x_b) + beta_air), the recycled weight of the sub-path
+    // x_0..x_b without its last direction factor and connection.
+    double* pbase;
     const int* tape_flag;
+    // Gradient weights (tape case): wtape has the tape's layout and holds
+    // w_{b,d} = c_{b,d} rho_{d,p} (0 outside the image); vaux[batch_off[batch] -
+    // tape_base + 64*b + lane] = (R_b, connection vertex term at x_b,
+    // w_c f_HG / f_s,t of the scatter at x_b, 0).
+    float* wtape;
+    float4* vaux;
     // Dynamic schedule: wavefronts take tasks from *work (reset to 0 before the
     // launch); task t covers batch n_batches-1-t/groups (heaviest first, the
     // batches being sorted by size) and camera group t%groups.
@@ -61,13 +72,14 @@ struct TraceArgs {
 // ---- sampling, sorting, packing (sample.hip)
 hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const float* bc_r, double beta_air,
                              int64_t nu, void* grid_tot, void* grid_dlt);
-hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a);
+hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu);
 hipError_t launch_sort_by_size(hipStream_t st, const uint8_t* key, int64_t n, int nbins, uint32_t* blockhist,
                                int32_t* perm);
 int64_t sort_scratch_words(int64_t n, int nbins);
 hipError_t launch_gather_sizes(hipStream_t st, const int32_t* perm, const uint8_t* tB, const uint8_t* tnv,
                                int64_t n, int64_t n_slots, uint8_t* B, uint8_t* nv);
-hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, int64_t* batch_off);
+// scratch: the sort's scratch (sort_scratch_words(64 * nb, ...) words) may be reused.
+hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, int64_t* batch_off, void* scratch);
 hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, const int64_t* tmp_off,
                        int64_t tmp_stride, const uint8_t* nv, const int64_t* batch_off, int64_t n,
                        int64_t n_slots, float4* vtx);
@@ -85,7 +97,10 @@ struct RenderPlan {
     size_t partial_bytes = 0;
 };
 RenderPlan plan_render(int fp64, int64_t nu, int64_t nimg, int64_t n_slots, int64_t first_slot, int n_cu);
-// The persistent render kernel alone (its task counter a.work[0] must be zero);
+// Per-vertex prefix weights of the render (one lane per path).
+hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a);
+// The persistent render kernel alone (its task counter a.work[0] must be zero,
+// a.pbase filled by launch_render_prefix);
 // with img_lds, launch_render_reduce then adds the partials into the images.
 hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
                          float* partial);
@@ -105,9 +120,13 @@ struct GradPlan {
     size_t partial_bytes = 0;
 };
 GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu);
+// Gradient weights from the tape (runs only when *a.tape_flag is 1).
+hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c);
 // Gradient terms of slab i (z layers [i*slab_layers, min(nz, (i+1)*slab_layers))):
 // the persistent grad kernels (task counters a.work[0] and a.work[1] must be
-// zero); with lds, launch_grad_reduce then writes the slab's gradient.
+// zero): with a tape flag, the walk kernel on the stored weights and the
+// recomputing kernel, exactly one of which does work; with lds,
+// launch_grad_reduce then writes the slab's gradient.
 hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p, int slab,
                        void* partial);
 hipError_t launch_grad_reduce(hipStream_t st, const GradPlan& p, int nx, int ny, int nz, int slab,

@@ -37,10 +37,11 @@ int fail(int code, const char* fmt, ...)
 
 enum KernelId {
     K_SAMPLE = 0, K_SORT, K_PACK, K_PREP, K_RENDER, K_FINALIZE, K_GRAD, K_REWEIGHT, K_LOSS, K_ADAM,
-    K_RENDER_REDUCE, K_GRAD_REDUCE, K_COUNT
+    K_RENDER_REDUCE, K_GRAD_REDUCE, K_GRAD_WEIGHTS, K_RENDER_PREFIX, K_COUNT
 };
-const char* kKernelNames[K_COUNT] = {"sample", "sort", "pack",     "prep", "render",        "render_finalize",
-                                     "grad",   "reweight", "loss", "adam", "render_reduce", "grad_reduce"};
+const char* kKernelNames[K_COUNT] = {"sample", "sort",          "pack",        "prep",         "render",
+                                     "render_finalize", "grad",  "reweight",    "loss",         "adam",
+                                     "render_reduce",   "grad_reduce", "grad_weights", "render_prefix"};
 
 struct Timed {
     int id;
@@ -57,6 +58,10 @@ struct prt_ctx_s {
     void* gpart = nullptr;      // per-workgroup gradient partials
     size_t gpart_bytes = 0;
     void* rpart = nullptr;      // per-workgroup image partials
+    size_t gw_bytes = 0, gaux_bytes = 0, pb_bytes = 0;
+    void* pb = nullptr;         // render prefix weights per vertex record (double)
+    void* gw = nullptr;         // gradient weights per (vertex, camera), tape layout
+    void* gaux = nullptr;       // per-vertex gradient sums (float4)
     size_t rpart_bytes = 0;
     // sampling / sorting temporaries (grow-only)
     void* s_tmp = nullptr;
@@ -78,7 +83,7 @@ struct prt_ctx_s {
     double* out2 = nullptr;     // two doubles of reduction output
     unsigned long long* counters = nullptr;  // 4
     int* flag = nullptr;        // device flag: the tape matches beta_t
-    unsigned int* work = nullptr;  // task counters of the persistent kernels [2]
+    unsigned int* work = nullptr;  // task counters of the persistent kernels [4]: render/grad 0-1, sampler 2
     uint64_t paths_done = 0;
     bool timing = false;
     std::vector<Timed> pending;
@@ -400,7 +405,7 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
         TimedScope ts(c, K_SORT);
         HIPCHK(launch_sort_by_size(c->stream, tB, n, nbins, (uint32_t*)c->s_hist, p->perm));
         HIPCHK(launch_gather_sizes(c->stream, p->perm, tB, tnv, n, p->n_slots, p->B, p->nv));
-        HIPCHK(launch_batch_offsets(c->stream, p->nv, p->nb, p->batch_off));
+        HIPCHK(launch_batch_offsets(c->stream, p->nv, p->nb, p->batch_off, c->s_hist));
         HIPCHK(launch_store_meta(c->stream, p->B, n, p->batch_off, p->nb, c->meta));
     }
     int64_t meta[3] = {0, 0, 0};
@@ -452,9 +457,11 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     a.tmp = (float4*)c->s_tmp;
     a.tB = tB;
     a.tnv = tnv;
+    a.next = c->work + 2;
+    HIPCHK(launch_reset_work(c->stream, a.next, 1));
     {
         TimedScope ts(c, K_SAMPLE);
-        HIPCHK(launch_sample(c->stream, c->fp64, a));
+        HIPCHK(launch_sample(c->stream, c->fp64, a, c->n_cu));
     }
     return build_store(c, p, (const float4*)c->s_tmp, nullptr, stride, tB, tnv);
 }
@@ -537,7 +544,7 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
     if (hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&c->out2, 2 * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&c->flag, sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&c->work, 2 * sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void**)&c->work, 4 * sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void**)&c->meta, 3 * sizeof(int64_t)) != hipSuccess) {
         (void)hipFree(c->work);
         (void)hipFree(c->flag);
@@ -571,6 +578,9 @@ void prt_destroy(prt_ctx c)
     (void)hipFree(c->pix);
     (void)hipFree(c->gpart);
     (void)hipFree(c->rpart);
+    (void)hipFree(c->gw);
+    (void)hipFree(c->gaux);
+    (void)hipFree(c->pb);
     (void)hipFree(c->s_tmp);
     (void)hipFree(c->s_keys);
     (void)hipFree(c->s_hist);
@@ -797,11 +807,14 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     a.counters = c->counters;
     a.work = c->work;
     a.groups = camera_groups(dc.n);
+    a.tape_base = p->tape_base;
+    if ((rc = ensure_scratch(&c->pb, &c->pb_bytes, (size_t)(p->n_records - p->tape_base) * sizeof(double))))
+        return rc;
+    a.pbase = (double*)c->pb;
     // record the transmittance tape when the render covers every order (FP32 mode)
     p->tape_valid = false;
     if (!c->fp64 && a.brender >= s->max_order && (rc = ensure_tape(p, (size_t)dc.n, nu)) == PRT_OK) {
         a.tape = p->tape;
-        a.tape_base = p->tape_base;
         HIPCHK(hipMemcpyAsync(p->tape_beta, s->beta_cloud, nu * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
         p->tape_valid = true;
         p->tape_cams = dc;
@@ -809,6 +822,10 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     }
     const RenderPlan plan = plan_render(c->fp64, nu, npx, p->n_slots, p->first_slot, c->n_cu);
     if ((rc = ensure_scratch(&c->rpart, &c->rpart_bytes, plan.partial_bytes))) return rc;
+    {
+        TimedScope ts(c, K_RENDER_PREFIX);
+        HIPCHK(launch_render_prefix(c->stream, c->fp64, a));
+    }
     HIPCHK(launch_reset_work(c->stream, c->work, 1));
     {
         TimedScope ts(c, K_RENDER);
@@ -859,13 +876,21 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
     a.counters = c->counters;
     a.work = c->work;
     a.groups = camera_groups(dc.n);
-    if (p->tape_valid && !c->fp64 && std::memcmp(&p->tape_cams, &dc, sizeof dc) == 0 &&
+    const size_t recs = (size_t)(p->n_records - p->tape_base);  // records from the first scattering batch on
+    if (recs > 0 && p->tape_valid && !c->fp64 && std::memcmp(&p->tape_cams, &dc, sizeof dc) == 0 &&
         std::memcmp(&p->tape_scene, &a.s, sizeof a.s) == 0) {
         // the tape is used only if beta_t equals the field it was recorded with
         HIPCHK(launch_equal_flag(c->stream, s->beta_cloud, p->tape_beta, nu, c->flag));
         a.tape = p->tape;
         a.tape_base = p->tape_base;
         a.tape_flag = c->flag;
+        // weights and per-vertex sums for the walks on the tape
+        if ((rc = ensure_scratch(&c->gw, &c->gw_bytes, recs * dc.n * sizeof(float)))) return rc;
+        if ((rc = ensure_scratch(&c->gaux, &c->gaux_bytes, recs * sizeof(float4)))) return rc;
+        a.wtape = (float*)c->gw;
+        a.vaux = (float4*)c->gaux;
+        TimedScope ts(c, K_GRAD_WEIGHTS);
+        HIPCHK(launch_grad_weights(c->stream, a, dc));
     }
     const GradPlan plan = plan_grad(s->nx, s->ny, s->nz, p->n_slots, p->first_slot, c->n_cu);
     if ((rc = ensure_scratch(&c->gpart, &c->gpart_bytes, plan.partial_bytes))) return rc;

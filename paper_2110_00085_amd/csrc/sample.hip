@@ -1,5 +1,7 @@
 // Path sampling (Sec. 3.4), the stable counting sort by path size (Sec. 5.3)
 // and the packing of the sorted paths into wavefront batches.
+#include <algorithm>
+
 #include "launch.hpp"
 
 namespace prt {
@@ -34,48 +36,78 @@ hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const 
 
 // ---------------------------------------------------------------- sampler
 
+// Resident 256-thread workgroups per CU for the persistent sampler.
+constexpr int kSampleBlocksPerCU = 8;
+
 __device__ __forceinline__ float4 vrec(double x, double y, double z, int v)
 {
     return make_float4((float)x, (float)y, (float)z, __int_as_float(v));
 }
 
-// One thread per path id.  Entry point uniform over the projected box area;
-// free flights by the DDA until the optical depth passes tau = -ln u; at a
-// scatter the particle type is drawn with probability beta_s^(j)/beta_s and a
-// direction from its phase function; the path ends when it leaves the box or
-// after max_order scatters.  Vertices go to row id of tmp (stride max_order+2).
+// Persistent sampler with path regeneration: a lane whose path has ended
+// takes the next path id from a device counter (one atomic per wavefront),
+// so wavefronts do not wait for their longest path.  Each path is sampled as
+// follows.  Entry point uniform over the projected box area; free flights by
+// the DDA until the optical depth passes tau = -ln u; at a scatter the
+// particle type is drawn with probability beta_s^(j)/beta_s and a direction
+// from its phase function; the path ends when it leaves the box or after
+// max_order scatters.  Vertices go to row id of tmp (stride max_order+2).
+// The uniforms of path id come from its own Philox counters, so the result
+// does not depend on which lane samples it.
 template <typename Real>
 __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
 {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= a.n) return;
     const DevScene& s = a.s;
     const Real* __restrict__ gt = (const Real*)a.grid_tot;
     const int stride = s.max_order + 2;
-    float4* __restrict__ out = a.tmp + id * stride;
-
+    const int lane = threadIdx.x % kWave;
+    const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;  // lanes under this one
+    int64_t id = 0;
+    float4* __restrict__ out = nullptr;
+    double x = 0.0, y = 0.0, z = 0.0, tau = 0.0;
+    double w[3] = {0.0, 0.0, 0.0};
     double u[4];
-    uniforms4(a.seed, (uint64_t)id, 0u, u);
-    const double A = s.a_top + s.a_x + s.a_y;
-    double x, y, z;
-    if (u[0] * A < s.a_top) {
-        x = u[1] * s.nx; y = u[2] * s.ny; z = (double)s.nz;
-    } else if (u[0] * A < s.a_top + s.a_x) {
-        x = s.x_face; y = u[1] * s.ny; z = u[2] * s.nz;
-    } else {
-        x = u[1] * s.nx; y = s.y_face; z = u[2] * s.nz;
-    }
-    int ix = min(max((int)floor(x), 0), s.nx - 1);
-    int iy = min(max((int)floor(y), 0), s.ny - 1);
-    int iz = min(max((int)floor(z), 0), s.nz - 1);
-    int v = ix + s.nx * (iy + s.ny * iz);
-    int nv = 0;
-    out[nv++] = vrec(x, y, z, v);
-    double w[3] = {s.sun[0], s.sun[1], s.sun[2]};
-    // optical depth target in units of (1/km * grid length)
-    double tau = -log(u[3]) / s.vk;
-    int b = 0;
+    int ix = 0, iy = 0, iz = 0, b = 0, nv = 0;
+    bool active = false, exhausted = false;
     for (;;) {
+        if (!exhausted) {
+            const uint64_t need = __ballot(!active);
+            if (need) {
+                const int leader = __ffsll((unsigned long long)need) - 1;
+                unsigned int base = 0;
+                if (lane == leader) base = atomicAdd(a.next, (unsigned int)__popcll(need));
+                base = __shfl(base, leader);
+                if ((int64_t)base + __popcll(need) >= a.n) exhausted = true;
+                const int64_t nid = (int64_t)base + __popcll(need & below);
+                if (!active && nid < a.n) {
+                    // start path nid at the source
+                    id = nid;
+                    out = a.tmp + id * stride;
+                    uniforms4(a.seed, (uint64_t)id, 0u, u);
+                    const double A = s.a_top + s.a_x + s.a_y;
+                    if (u[0] * A < s.a_top) {
+                        x = u[1] * s.nx; y = u[2] * s.ny; z = (double)s.nz;
+                    } else if (u[0] * A < s.a_top + s.a_x) {
+                        x = s.x_face; y = u[1] * s.ny; z = u[2] * s.nz;
+                    } else {
+                        x = u[1] * s.nx; y = s.y_face; z = u[2] * s.nz;
+                    }
+                    ix = min(max((int)floor(x), 0), s.nx - 1);
+                    iy = min(max((int)floor(y), 0), s.ny - 1);
+                    iz = min(max((int)floor(z), 0), s.nz - 1);
+                    nv = 0;
+                    out[nv++] = vrec(x, y, z, ix + s.nx * (iy + s.ny * iz));
+                    w[0] = s.sun[0]; w[1] = s.sun[1]; w[2] = s.sun[2];
+                    // optical depth target in units of (1/km * grid length)
+                    tau = -log(u[3]) / s.vk;
+                    b = 0;
+                    active = true;
+                }
+            }
+        }
+        if (!__any(active)) break;
+        if (!active) continue;
+        // one event: the free flight to the next scatter or out of the box
         const Real taur = (Real)tau;
         Real acc = (Real)0, thit = (Real)0;
         int hit = -1;
@@ -92,40 +124,48 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
                 acc += dt;
                 return true;
             });
+        bool done;
         if (hit < 0) {
             const double te = (double)tend;
             out[nv++] = vrec(x + te * w[0], y + te * w[1], z + te * w[2], -1);
-            break;
-        }
-        if (sizeof(Real) == 8) {
-            const double th = (double)thit;
-            x = x + th * w[0]; y = y + th * w[1]; z = z + th * w[2];
+            done = true;
         } else {
-            const float th = (float)thit;
-            x = (double)((float)x + th * (float)w[0]);
-            y = (double)((float)y + th * (float)w[1]);
-            z = (double)((float)z + th * (float)w[2]);
+            if (sizeof(Real) == 8) {
+                const double th = (double)thit;
+                x = x + th * w[0]; y = y + th * w[1]; z = z + th * w[2];
+            } else {
+                const float th = (float)thit;
+                x = (double)((float)x + th * (float)w[0]);
+                y = (double)((float)y + th * (float)w[1]);
+                z = (double)((float)z + th * (float)w[2]);
+            }
+            ++b;
+            out[nv++] = vrec(x, y, z, hit);
+            done = b >= s.max_order;
+            if (!done) {
+                voxel_ijk(hit, s.nx, s.ny, ix, iy, iz);
+                uniforms4(a.seed, (uint64_t)id, (uint32_t)b, u);
+                const double bsc = s.w_c * (double)a.beta_c[hit];
+                const double bs = bsc + s.w_a * s.beta_air;
+                const double mu = (u[0] * bs < bsc) ? sample_hg(u[1], s.g) : sample_rayleigh(u[1]);
+                double wn[3];
+                scatter_direction(w, mu, 2.0 * kPi * u[2], wn);
+                w[0] = wn[0]; w[1] = wn[1]; w[2] = wn[2];
+                tau = -log(u[3]) / s.vk;
+            }
         }
-        ++b;
-        out[nv++] = vrec(x, y, z, hit);
-        if (b >= s.max_order) break;
-        voxel_ijk(hit, s.nx, s.ny, ix, iy, iz);
-        uniforms4(a.seed, (uint64_t)id, (uint32_t)b, u);
-        const double bsc = s.w_c * (double)a.beta_c[hit];
-        const double bs = bsc + s.w_a * s.beta_air;
-        const double mu = (u[0] * bs < bsc) ? sample_hg(u[1], s.g) : sample_rayleigh(u[1]);
-        double wn[3];
-        scatter_direction(w, mu, 2.0 * kPi * u[2], wn);
-        w[0] = wn[0]; w[1] = wn[1]; w[2] = wn[2];
-        tau = -log(u[3]) / s.vk;
+        if (done) {
+            a.tB[id] = (uint8_t)b;
+            a.tnv[id] = (uint8_t)nv;
+            active = false;
+        }
     }
-    a.tB[id] = (uint8_t)b;
-    a.tnv[id] = (uint8_t)nv;
 }
 
-hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a)
+hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu)
 {
-    const int64_t blocks = (a.n + 255) / 256;
+    if (a.n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((a.n + 255) / 256, (int64_t)n_cu * kSampleBlocksPerCU);
     if (fp64)
         sample_kernel<double><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
     else
@@ -156,30 +196,72 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const uint8_t* __restric
     for (int k = threadIdx.x; k < nbins; k += blockDim.x) hist[(int64_t)k * n_tiles + blockIdx.x] = h[k];
 }
 
-// Single-workgroup exclusive scan (in place) of m uint32 values: each thread
-// sums a contiguous chunk, the chunk sums are scanned in LDS, then each
-// thread rewrites its chunk.
-__global__ void __launch_bounds__(1024) scan_u32_kernel(uint32_t* __restrict__ a, int64_t m)
+// Exclusive prefix sum in place, tiled: each workgroup scans a tile of
+// kScanTile values (4 consecutive values per thread, a Hillis-Steele scan of
+// the 256 thread totals in LDS) and writes the tile total; the tile totals
+// are scanned the same way (recursively) and added back to their tiles.
+constexpr int kScanTile = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(256) scan_tile_kernel(T* __restrict__ a, int64_t n, T* __restrict__ tile_sum)
 {
-    __shared__ uint32_t sums[1024];
-    const int64_t chunk = (m + 1023) / 1024;
-    const int64_t lo = min((int64_t)threadIdx.x * chunk, m), hi = min(lo + chunk, m);
-    uint32_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += a[i];
-    sums[threadIdx.x] = s;
+    __shared__ T s[256];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * kScanTile + 4 * t;
+    T e[4];
+    T run = 0;
+    for (int k = 0; k < 4; ++k) {
+        const T v = i0 + k < n ? a[i0 + k] : (T)0;
+        e[k] = run;
+        run += v;
+    }
+    s[t] = run;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t add = threadIdx.x >= (unsigned)off ? sums[threadIdx.x - off] : 0u;
+    for (int off = 1; off < 256; off <<= 1) {
+        const T add = t >= off ? s[t - off] : (T)0;
         __syncthreads();
-        sums[threadIdx.x] += add;
+        s[t] += add;
         __syncthreads();
     }
-    uint32_t run = threadIdx.x ? sums[threadIdx.x - 1] : 0u;
-    for (int64_t i = lo; i < hi; ++i) {
-        const uint32_t c = a[i];
-        a[i] = run;
-        run += c;
+    const T before = t ? s[t - 1] : (T)0;
+    for (int k = 0; k < 4; ++k)
+        if (i0 + k < n) a[i0 + k] = before + e[k];
+    if (t == 255 && tile_sum) tile_sum[blockIdx.x] = s[255];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) scan_add_kernel(T* __restrict__ a, int64_t n, const T* __restrict__ tile_off)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] += tile_off[i / kScanTile];
+}
+
+// Elements of scratch that scan_exclusive needs for n values.
+static int64_t scan_scratch_elems(int64_t n)
+{
+    int64_t tot = 0;
+    for (int64_t m = n; m > kScanTile;) {
+        m = (m + kScanTile - 1) / kScanTile;
+        tot += m;
     }
+    return tot;
+}
+
+template <typename T>
+static hipError_t scan_exclusive(hipStream_t st, T* a, int64_t n, T* scratch)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles == 1) {
+        scan_tile_kernel<T><<<dim3(1), dim3(256), 0, st>>>(a, n, nullptr);
+        return hipGetLastError();
+    }
+    scan_tile_kernel<T><<<dim3((unsigned)tiles), dim3(256), 0, st>>>(a, n, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = scan_exclusive<T>(st, scratch, tiles, scratch + tiles)) != hipSuccess) return e;
+    scan_add_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(a, n, scratch);
+    return hipGetLastError();
 }
 
 // Thread k of a tile owns key k: it walks the tile in id order and assigns
@@ -205,7 +287,12 @@ __global__ void __launch_bounds__(128) sort_scatter_kernel(const uint8_t* __rest
 
 int64_t sort_scratch_words(int64_t n, int nbins)
 {
-    return ((n + kSortTile - 1) / kSortTile) * (int64_t)nbins;
+    const int64_t hist = ((n + kSortTile - 1) / kSortTile) * (int64_t)nbins;
+    const int64_t sort_words = hist + scan_scratch_elems(hist);
+    // launch_batch_offsets reuses the same scratch for its int64 scan
+    const int64_t nb = (n + kWave - 1) / kWave;
+    const int64_t boff_words = 2 * scan_scratch_elems(nb + 1);
+    return std::max<int64_t>(1, std::max(sort_words, boff_words));
 }
 
 hipError_t launch_sort_by_size(hipStream_t st, const uint8_t* key, int64_t n, int nbins, uint32_t* blockhist,
@@ -215,9 +302,8 @@ hipError_t launch_sort_by_size(hipStream_t st, const uint8_t* key, int64_t n, in
     sort_hist_kernel<<<dim3((unsigned)n_tiles), dim3(256), 0, st>>>(key, n, nbins, n_tiles, blockhist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    scan_u32_kernel<<<dim3(1), dim3(1024), 0, st>>>(blockhist, n_tiles * nbins);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int64_t m = n_tiles * nbins;
+    if ((e = scan_exclusive<uint32_t>(st, blockhist, m, blockhist + m)) != hipSuccess) return e;
     sort_scatter_kernel<<<dim3((unsigned)n_tiles), dim3(128), 0, st>>>(key, n, nbins, n_tiles, blockhist, perm);
     return hipGetLastError();
 }
@@ -251,40 +337,28 @@ hipError_t launch_gather_sizes(hipStream_t st, const int32_t* perm, const uint8_
 }
 
 // batch_off[b] = 64 * sum_{b' < b} rows(b'), rows(b) = max stored vertices
-// over the batch; batch_off[nb] is the total record count.
-__global__ void __launch_bounds__(1024) batch_offsets_kernel(const uint8_t* __restrict__ nv, int64_t nb,
-                                                             int64_t* __restrict__ off)
+// over the batch; batch_off[nb] is the total record count.  One wavefront
+// per batch writes 64 * rows(b) (and batch_off[nb] = 0), then an exclusive
+// scan turns the counts into offsets.
+__global__ void __launch_bounds__(256) batch_rows_kernel(const uint8_t* __restrict__ nv, int64_t nb,
+                                                         int64_t* __restrict__ off)
 {
-    __shared__ int64_t sums[1024];
-    const int64_t chunk = (nb + 1023) / 1024;
-    const int64_t lo = min((int64_t)threadIdx.x * chunk, nb), hi = min(lo + chunk, nb);
-    auto rows = [&](int64_t b) {
-        int r = 0;
-        for (int l = 0; l < kWave; ++l) r = max(r, (int)nv[b * kWave + l]);
-        return (int64_t)r * kWave;
-    };
-    int64_t s = 0;
-    for (int64_t b = lo; b < hi; ++b) s += rows(b);
-    sums[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int64_t add = threadIdx.x >= (unsigned)o ? sums[threadIdx.x - o] : 0;
-        __syncthreads();
-        sums[threadIdx.x] += add;
-        __syncthreads();
-    }
-    int64_t run = threadIdx.x ? sums[threadIdx.x - 1] : 0;
-    for (int64_t b = lo; b < hi; ++b) {
-        off[b] = run;
-        run += rows(b);
-    }
-    if (threadIdx.x == 1023) off[nb] = sums[1023];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = i / kWave;
+    int r = b < nb ? (int)nv[i] : 0;
+    for (int o = kWave / 2; o > 0; o >>= 1) r = max(r, __shfl_xor(r, o));
+    if (i % kWave == 0 && b < nb) off[b] = (int64_t)r * kWave;
+    if (i == 0) off[nb] = 0;
 }
 
-hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, int64_t* batch_off)
+hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, int64_t* batch_off, void* scratch)
 {
-    batch_offsets_kernel<<<dim3(1), dim3(1024), 0, st>>>(nv, nb, batch_off);
-    return hipGetLastError();
+    const int64_t slots = nb * kWave;
+    batch_rows_kernel<<<dim3((unsigned)std::max<int64_t>(1, (slots + 255) / 256)), dim3(256), 0, st>>>(nv, nb,
+                                                                                                     batch_off);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return scan_exclusive<int64_t>(st, batch_off, nb + 1, (int64_t*)scratch);
 }
 
 // One thread per sorted slot: copy the path's records into its lane of the

@@ -40,7 +40,7 @@ __device__ __forceinline__ double seg_dir(const Vtx& a, const Vtx& b, double w[3
 __device__ __forceinline__ int clamp_vox(int v, int nu) { return min(max(v, 0), nu - 1); }
 
 // Sum of beta(v) * length over the walk from vertex p (voxel p.v) along w
-// for length tmax (grid units); adds the nonzero pieces to count.
+// for length tmax (grid units); adds the number of pieces to count.
 template <typename Real, typename G>
 __device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx& p, const double w[3], double tmax,
                                          uint64_t& count)
@@ -49,18 +49,18 @@ __device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx&
     voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
     Real acc = (Real)0;
     uint32_t n = 0;
-    dda_walk<Real>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
-                   (Real)w[2], (Real)tmax, [&](int v, Real, Real l) {
-                       acc += beta(v) * l;
-                       n += l > (Real)0 ? 1u : 0u;
-                       return true;
-                   });
+    dda_walk_counted<Real>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
+                           (Real)w[2], (Real)tmax, n, [&](int v, Real, Real l) {
+                               acc += beta((uint32_t)v) * l;
+                               return true;
+                           });
     count += n;
     return acc;
 }
 
-// Calls add(v, scale * length) for every nonzero piece of the walk that
-// lies in the slab of z layers [z0, z1), v numbered inside the slab.
+// Calls add(v, scale * length) for every piece of the walk that lies in the
+// slab of z layers [z0, z1), v numbered inside the slab (zero-length pieces
+// add zero).
 template <typename Real, typename A>
 __device__ __forceinline__ void walk_scatter(const DevScene& s, A&& add, const Vtx& p, const double w[3], double tmax,
                                              double scale, uint64_t& count, int z0, int z1)
@@ -69,11 +69,8 @@ __device__ __forceinline__ void walk_scatter(const DevScene& s, A&& add, const V
     voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
     uint32_t n = 0;
     dda_walk_slab<Real>(s.nx, s.ny, z0, z1, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
-                        (Real)w[2], (Real)tmax, [&](int v, Real, Real l) {
-                            if (l > (Real)0) {
-                                add(v, scale * (double)l);
-                                ++n;
-                            }
+                        (Real)w[2], (Real)tmax, n, [&](int v, Real, Real l) {
+                            add((uint32_t)v, scale * (double)l);
                             return true;
                         });
     count += n;
@@ -122,11 +119,66 @@ constexpr size_t kLdsBudget = 128 * 1024;       // grids
 constexpr size_t kLdsImageBudget = 152 * 1024;  // image tallies (+ grid if both fit)
 constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs per launch sequence
 
+// Prefix weights, one lane per path: walks the free-flight segments once and
+// stores, for every scatter b <= brender, base_b = P_b / (beta_ref(x_b) +
+// beta_air) with P_b = w0 prod_{k<b} exp(-(tau_t - tau_ref)(segment k))
+// prod_{1<=k<b} albedo_ref f_s,t / f_s,ref (x_k): every local estimate at
+// x_b is base_b f_s,t(x_b, mu_bd) exp(-tau_t(connection)) / r^2.
+template <typename Real>
+__global__ void __launch_bounds__(256) render_prefix_kernel(TraceArgs a)
+{
+    const int64_t slot = a.st.first_slot / kWave * kWave + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= a.st.n_slots) return;
+    const int Br = min((int)a.st.B[slot], a.brender);
+    if (Br <= 0) return;
+    const DevScene& s = a.s;
+    const int nu = s.nx * s.ny * s.nz;
+    const Real* __restrict__ gd = (const Real*)a.grid_dlt;
+    const int64_t bt = slot / kWave, lane = slot % kWave;
+    const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+    double* __restrict__ out = a.pbase + (a.st.batch_off[bt] - a.tape_base) + lane;
+    uint64_t nseg = 0;
+    Vtx p0 = load_vtx(V, 0);
+    double P = s.w0;
+    double wprev[3] = {0.0, 0.0, 0.0};
+    for (int b = 1; b <= Br; ++b) {
+        const Vtx p1 = load_vtx(V, b);
+        double w[3];
+        const double L = seg_dir(p0, p1, w);
+        // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
+        const Real dt = walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, nseg);
+        P *= exp(-(double)dt * s.vk);
+        if (b >= 2) {
+            const int v = clamp_vox(p0.v, nu);
+            P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
+                              wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
+        }
+        out[(int64_t)b * kWave] = P / ((double)a.st.beta_ref[clamp_vox(p1.v, nu)] + s.beta_air);
+        wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
+        p0 = p1;
+    }
+    flush_counts(a.counters, nseg, 0, 0);
+}
+
+hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a)
+{
+    const int64_t slots = a.st.n_slots - a.st.first_slot / kWave * kWave;
+    if (slots <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((slots + 255) / 256)), block(256);
+    if (fp64) render_prefix_kernel<double><<<grid, block, 0, st>>>(a);
+    else render_prefix_kernel<float><<<grid, block, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// Local estimates from the stored paths.  Tasks are (batch, camera group),
+// heaviest batches first; per scatter b the task reads base_b and, for every
+// camera of its group, projects x_b, evaluates f_s,t and walks the
+// connection for its transmittance.
 // kGridLds: the total-extinction grid is cached in LDS.  kImgLds: the
 // workgroup tallies its contributions in an FP32 LDS image and writes it to
 // partial[blockIdx.x]; render_reduce_kernel adds the partials in FP64 in
 // workgroup order.  Otherwise every contribution is an FP64 atomic on the
-// output image.
+// output image.  kTape: every contribution is also recorded on the tape.
 template <typename Real, bool kGridLds, bool kImgLds, bool kTape>
 __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cams, float* __restrict__ partial)
 {
@@ -138,19 +190,18 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
     float* __restrict__ simg = reinterpret_cast<float*>(smem);
     Real* __restrict__ sgrid = reinterpret_cast<Real*>(smem + (kImgLds ? (size_t)nimg * sizeof(float) : 0));
     const Real* __restrict__ gtot = (const Real*)a.grid_tot;
-    const Real* __restrict__ gd = (const Real*)a.grid_dlt;
     if (kGridLds)
         for (int i = threadIdx.x; i < nu; i += kBlock) sgrid[i] = gtot[i];
     if (kImgLds)
         for (int i = threadIdx.x; i < nimg; i += kBlock) simg[i] = 0.f;
     if (kGridLds || kImgLds) __syncthreads();
-    auto beta_tot = [&](int v) -> Real { return kGridLds ? sgrid[v] : gtot[v]; };
+    auto beta_tot = [&](uint32_t v) -> Real { return kGridLds ? sgrid[v] : gtot[v]; };
     const double r2scale = 1.0 / (s.vk * s.vk);
     const int lane = threadIdx.x % kWave;
     const int64_t nb = a.st.n_slots / kWave;
     const int G = a.groups, cpg = (cams.n + G - 1) / G;
     const unsigned int n_tasks = (unsigned int)(nb - a.st.first_slot / kWave) * (unsigned int)G;
-    uint64_t nseg = 0, nle = 0, novh = 0;
+    uint64_t nseg = 0, nle = 0;
     for (unsigned int task = next_task(a.work); task < n_tasks; task = next_task(a.work)) {
         const int64_t bt = nb - 1 - (int64_t)(task / G);
         const int g = (int)(task % G);
@@ -158,28 +209,17 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
         const int64_t slot = bt * kWave + lane;
         const int Br = min((int)a.st.B[slot], a.brender);
         if (Br <= 0) continue;
-        uint64_t& segc = g == 0 ? nseg : novh;  // segments are walked once per camera group
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+        const double* __restrict__ Pb = a.pbase + (a.st.batch_off[bt] - a.tape_base) + lane;
         float* __restrict__ T = kTape ? a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane : nullptr;
         Vtx p0 = load_vtx(V, 0);
-        double P = s.w0;  // running f/mu of the prefix (without the last vertex)
-        double wprev[3] = {0.0, 0.0, 0.0};
         for (int b = 1; b <= Br; ++b) {
             const Vtx p1 = load_vtx(V, b);
             double w[3];
-            const double L = seg_dir(p0, p1, w);
-            // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
-            const Real dt = walk_sum<Real>(s, [&](int v) { return gd[v]; }, p0, w, L, segc);
-            P *= exp(-(double)dt * s.vk);
-            if (b >= 2) {
-                const int v = clamp_vox(p0.v, nu);
-                P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
-                                  wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
-            }
-            // local estimates from x_b to every camera
+            seg_dir(p0, p1, w);
             const int v1 = clamp_vox(p1.v, nu);
             const double bct = (double)a.bc_t[v1];
-            const double base = P / ((double)a.st.beta_ref[v1] + s.beta_air);
+            const double base = Pb[(int64_t)b * kWave];
             for (int d = d_lo; d < d_hi; ++d) {
                 const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
                 if (pix < 0) continue;
@@ -197,11 +237,10 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                 else unsafeAtomicAdd(&a.img[(int64_t)d * npix + pix], c);
                 ++nle;
             }
-            wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
             p0 = p1;
         }
     }
-    flush_counts(a.counters, nseg, nle, novh);
+    flush_counts(a.counters, nseg, nle, 0);
     if (kImgLds) {
         __syncthreads();
         float* __restrict__ out = partial + (int64_t)blockIdx.x * nimg;
@@ -340,13 +379,13 @@ hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho,
 
 // -------------------------------------------------------------------- grad
 
-// Per path: pass 1 recomputes every contribution c_{b,d} and its weight
-// w = c rho_{d,p}; it adds the connection part of the score (-l along the
-// connection, the vertex term at x_b) and keeps R_b = sum_d w_{b,d}.  Pass 2
-// walks the free-flight segments backwards with the suffix sums
-// A_k = sum_{b>k} R_b, adding -A_k l along segment k and A_k times the
-// vertex term at x_k.  Together this is sum_{b,d} w_{b,d} S(b,d) with S the
-// tomography PSF of the local-estimate sub-path.
+// The gradient is sum_{b,d} w_{b,d} S(b,d), with w = c rho_{d,p} and S the
+// tomography PSF of the local-estimate sub-path (Sec. 4.4, App. C): -l in
+// every voxel of the sub-path's segments and connection, plus the vertex
+// terms at its scatters.  Summing over d first gives R_b = sum_d w_{b,d};
+// free-flight segment k is then shared by every estimate at a later vertex,
+// so it takes -A_k l with A_k = sum_{b>k} R_b, and the scatter at x_k takes
+// A_k times its vertex term.
 //
 // Tally: one launch covers the slab of z layers [z0, z1) and adds only the
 // score terms of voxels in it (the walks are clipped to the slab).  With
@@ -355,34 +394,207 @@ hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho,
 // sums to partial[blockIdx.x][v]; a second kernel adds the partials in a
 // fixed order.  Without kLds the launch covers all layers and every update
 // is an FP64 atomic on the output.
-template <typename Real, bool kLds, bool kTape>
+
+// Slab tally: sg in LDS (kLds) or the output gradient, numbered inside the slab.
+template <bool kLds>
+struct SlabTally {
+    double* __restrict__ out;
+    int vlo, nsv;
+    __device__ __forceinline__ void add(uint32_t v, double x) const
+    {
+        if (kLds) atomicAdd(&out[v], x);
+        else unsafeAtomicAdd(&out[v], x);
+    }
+    // v is a grid voxel, added only when it lies in the slab
+    __device__ __forceinline__ void add_vox(int v, double x) const
+    {
+        const int u = v - vlo;
+        if ((unsigned)u < (unsigned)nsv) add((uint32_t)u, x);
+    }
+};
+
+template <bool kLds>
+__device__ __forceinline__ SlabTally<kLds> slab_tally_begin(const TraceArgs& a, int z0, int z1, unsigned char* smem)
+{
+    const int layer = a.s.nx * a.s.ny;
+    SlabTally<kLds> t;
+    t.vlo = z0 * layer;
+    t.nsv = (z1 - z0) * layer;
+    if (kLds) {
+        t.out = reinterpret_cast<double*>(smem);
+        for (int i = threadIdx.x; i < t.nsv; i += kBlock) t.out[i] = 0.0;
+        __syncthreads();
+    } else {
+        t.out = a.grad + t.vlo;
+    }
+    return t;
+}
+
+template <bool kLds>
+__device__ __forceinline__ void slab_tally_end(const SlabTally<kLds>& t, double* __restrict__ partial)
+{
+    if (!kLds) return;
+    __syncthreads();
+    double* __restrict__ out = partial + (int64_t)blockIdx.x * t.nsv;
+    for (int i = threadIdx.x; i < t.nsv; i += kBlock) out[i] = t.out[i];
+}
+
+// Weights from the transmittance tape, one lane per path: for every (b, d)
+// w_{b,d} = c_{b,d} rho_{d,p} (0 when x_b projects outside camera d), and per
+// vertex R_b, the connection vertex term sum_d w_{b,d} w_c f_HG / f_s,t at
+// x_b, and the coefficient w_c f_HG / f_s,t of the scatter at x_b between
+// segments b-1 and b.  Runs only when the tape matches beta_t.
+__global__ void __launch_bounds__(256) grad_weights_kernel(TraceArgs a, DevCams cams)
+{
+    if (*a.tape_flag == 0) return;
+    const int64_t slot = a.st.first_slot / kWave * kWave + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= a.st.n_slots) return;
+    const int Bn = (int)a.st.B[slot];
+    if (Bn <= 0) return;
+    const DevScene& s = a.s;
+    const int nu = s.nx * s.ny * s.nz;
+    const int npix = cams.W * cams.H;
+    const int64_t bt = slot / kWave, lane = slot % kWave;
+    const int64_t rec0 = a.st.batch_off[bt] - a.tape_base;
+    const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+    const float* __restrict__ Tp = a.tape + rec0 * cams.n + lane;
+    float* __restrict__ Wp = a.wtape + rec0 * cams.n + lane;
+    float4* __restrict__ X = a.vaux + rec0 + lane;
+    uint64_t nle = 0;
+    Vtx p0 = load_vtx(V, 0), p1 = load_vtx(V, 1);
+    double w[3];
+    seg_dir(p0, p1, w);
+    for (int b = 1; b <= Bn; ++b) {
+        const int v1 = clamp_vox(p1.v, nu);
+        const double bct = (double)a.bc_t[v1];
+        double Rb = 0.0, vert = 0.0;
+        for (int d = 0; d < cams.n; ++d) {
+            const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
+            float wf = 0.f;
+            if (pix >= 0) {
+                const double wgt = (double)Tp[(int64_t)(b * cams.n + d) * kWave] * a.rho[(int64_t)d * npix + pix];
+                const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
+                const double id = 1.0 / sqrt(ex * ex + ey * ey + ez * ez);
+                const double mu = (w[0] * ex + w[1] * ey + w[2] * ez) * id;
+                const double hg = phase_hg(s, mu);
+                const double fst = fs_mix(s, bct, hg, phase_rayleigh(mu));
+                Rb += wgt;
+                if (fst > 0.0) vert += wgt * (s.w_c * hg / fst);
+                wf = (float)wgt;
+                ++nle;
+            }
+            Wp[(int64_t)(b * cams.n + d) * kWave] = wf;
+        }
+        // the scatter at x_b turns segment b-1 (direction w) into segment b
+        double coef = 0.0, wn[3] = {0.0, 0.0, 0.0};
+        Vtx p2 = p1;
+        if (b < Bn) {
+            p2 = load_vtx(V, b + 1);
+            seg_dir(p1, p2, wn);
+            const double mu = w[0] * wn[0] + w[1] * wn[1] + w[2] * wn[2];
+            const double hg = phase_hg(s, mu);
+            const double fst = fs_mix(s, bct, hg, phase_rayleigh(mu));
+            if (fst > 0.0) coef = s.w_c * hg / fst;
+        }
+        X[(int64_t)b * kWave] = make_float4((float)Rb, (float)vert, (float)coef, 0.f);
+        w[0] = wn[0]; w[1] = wn[1]; w[2] = wn[2];
+        p1 = p2;
+    }
+    flush_counts(a.counters, 0, nle, 0);
+}
+
+hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c)
+{
+    const int64_t slots = a.st.n_slots - a.st.first_slot / kWave * kWave;
+    if (slots <= 0) return hipSuccess;
+    grad_weights_kernel<<<dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st>>>(a, c);
+    return hipGetLastError();
+}
+
+// Walks on the stored weights (tape case).  Tasks are (batch, kind), heaviest
+// batches first: kind g < groups walks the connections of camera group g
+// (kind 0 also adds the connection vertex terms), kind == groups walks the
+// free-flight segments with the suffix sums A_k and adds their vertex terms.
+template <bool kLds>
+__global__ void __launch_bounds__(kBlock) grad_walk_kernel(TraceArgs a, DevCams cams, int z0, int z1,
+                                                           double* __restrict__ partial)
+{
+    if (*a.tape_flag == 0) return;
+    extern __shared__ unsigned char smem[];
+    const SlabTally<kLds> tally = slab_tally_begin<kLds>(a, z0, z1, smem);
+    auto add = [&](uint32_t v, double x) { tally.add(v, x); };
+    const DevScene& s = a.s;
+    const int nu = s.nx * s.ny * s.nz;
+    const int lane = threadIdx.x % kWave;
+    const int64_t nb = a.st.n_slots / kWave;
+    const int G = a.groups, K = G + 1, cpg = (cams.n + G - 1) / G;
+    const unsigned int n_tasks = (unsigned int)(nb - a.st.first_slot / kWave) * (unsigned int)K;
+    uint64_t nseg = 0;
+    for (unsigned int task = next_task(a.work); task < n_tasks; task = next_task(a.work)) {
+        const int64_t bt = nb - 1 - (int64_t)(task / K);
+        const int kind = (int)(task % K);
+        const int64_t slot = bt * kWave + lane;
+        const int Bn = (int)a.st.B[slot];
+        if (Bn <= 0) continue;
+        const int64_t rec0 = a.st.batch_off[bt] - a.tape_base;
+        const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+        const float4* __restrict__ X = a.vaux + rec0 + lane;
+        if (kind < G) {
+            const int d_lo = kind * cpg, d_hi = min(cams.n, d_lo + cpg);
+            const float* __restrict__ Wp = a.wtape + rec0 * cams.n + lane;
+            for (int b = 1; b <= Bn; ++b) {
+                const Vtx p1 = load_vtx(V, b);
+                for (int d = d_lo; d < d_hi; ++d) {
+                    const double wgt = (double)Wp[(int64_t)(b * cams.n + d) * kWave];
+                    if (wgt == 0.0) continue;
+                    const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
+                    const double dist = sqrt(ex * ex + ey * ey + ez * ez);
+                    const double id = 1.0 / dist;
+                    const double u[3] = {ex * id, ey * id, ez * id};
+                    walk_scatter<float>(s, add, p1, u, dist, -wgt * s.vk, nseg, z0, z1);
+                }
+                if (kind == 0) {
+                    const double vert = (double)X[(int64_t)b * kWave].y;
+                    if (vert != 0.0) tally.add_vox(clamp_vox(p1.v, nu), vert);
+                }
+            }
+        } else {
+            double A = 0.0;
+            Vtx pk1 = load_vtx(V, Bn);
+            for (int k = Bn - 1; k >= 0; --k) {
+                A += (double)X[(int64_t)(k + 1) * kWave].x;
+                const Vtx pk = load_vtx(V, k);
+                double w[3];
+                const double L = seg_dir(pk, pk1, w);
+                if (A != 0.0) {
+                    walk_scatter<float>(s, add, pk, w, L, -A * s.vk, nseg, z0, z1);
+                    if (k >= 1) tally.add_vox(clamp_vox(pk.v, nu), A * (double)X[(int64_t)k * kWave].z);
+                }
+                pk1 = pk;
+            }
+        }
+    }
+    flush_counts(a.counters, nseg, 0, 0);
+    slab_tally_end<kLds>(tally, partial);
+}
+
+// Recomputing variant (no valid tape, or all-FP64 mode), per path: pass 1
+// recomputes every contribution c_{b,d} and its weight w, adds the connection
+// part of the score and keeps R_b; pass 2 walks the free-flight segments
+// backwards with the suffix sums A_k.  Camera groups split a path's local
+// estimates; pass 2 is linear in R_b, so each group runs it with its own
+// partial sums and the totals add up.  With a tape flag it runs only when
+// the tape does not match beta_t.
+template <typename Real, bool kLds>
 __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams, int z0, int z1,
                                                       double* __restrict__ partial)
 {
-    // With a tape flag, the tape variant runs only when the tape is valid and
-    // the recomputing variant only when it is not (uniform early exit).
-    if (a.tape_flag && ((*a.tape_flag != 0) != kTape)) return;
+    if (a.tape_flag && *a.tape_flag != 0) return;
     extern __shared__ unsigned char smem[];
-    double* __restrict__ sg = reinterpret_cast<double*>(smem);
+    const SlabTally<kLds> tally = slab_tally_begin<kLds>(a, z0, z1, smem);
+    auto add = [&](uint32_t v, double x) { tally.add(v, x); };
     const DevScene& s = a.s;
     const int nu = s.nx * s.ny * s.nz;
-    const int layer = s.nx * s.ny;
-    const int vlo = z0 * layer, nsv = (z1 - z0) * layer;
-    if (kLds) {
-        for (int i = threadIdx.x; i < nsv; i += kBlock) sg[i] = 0.0;
-        __syncthreads();
-    }
-    double* __restrict__ gout = a.grad + vlo;
-    // v is numbered inside the slab
-    auto add = [&](int v, double x) {
-        if (kLds) atomicAdd(&sg[v], x);
-        else unsafeAtomicAdd(&gout[v], x);
-    };
-    // vertex terms: v is a grid voxel, added only when it lies in the slab
-    auto add_vox = [&](int v, double x) {
-        const int u = v - vlo;
-        if ((unsigned)u < (unsigned)nsv) add(u, x);
-    };
     const Real* __restrict__ gtot = (const Real*)a.grid_tot;
     const Real* __restrict__ gd = (const Real*)a.grid_dlt;
     const int npix = cams.W * cams.H;
@@ -395,8 +607,6 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
     const bool count = z0 == 0;
     uint64_t nseg = 0, novh = 0;
     double R[kMaxOrder + 1];
-    // Camera groups split a path's local estimates; pass 2 is linear in R_b, so
-    // each group runs it with its own partial sums and the totals add up.
     for (unsigned int task = next_task(a.work); task < n_tasks; task = next_task(a.work)) {
         const int64_t bt = nb - 1 - (int64_t)(task / G);
         const int g = (int)(task % G);
@@ -407,7 +617,6 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
         uint64_t& segc = g == 0 ? nseg : novh;
         uint64_t& cseg = count ? nseg : novh;
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
-        const float* __restrict__ Tp = kTape ? a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane : nullptr;
         Vtx p0 = load_vtx(V, 0);
         double P = s.w0;
         double wprev[3] = {0.0, 0.0, 0.0};
@@ -415,14 +624,12 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
             const Vtx p1 = load_vtx(V, b);
             double w[3];
             const double L = seg_dir(p0, p1, w);
-            if (!kTape) {
-                const Real dt = walk_sum<Real>(s, [&](int v) { return gd[v]; }, p0, w, L, novh);
-                P *= exp(-(double)dt * s.vk);
-                if (b >= 2) {
-                    const int v = clamp_vox(p0.v, nu);
-                    P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
-                                      wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
-                }
+            const Real dt = walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, novh);
+            P *= exp(-(double)dt * s.vk);
+            if (b >= 2) {
+                const int v = clamp_vox(p0.v, nu);
+                P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
+                                  wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
             }
             const int v1 = clamp_vox(p1.v, nu);
             const double bct = (double)a.bc_t[v1];
@@ -441,20 +648,15 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
                 const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
                 const double hg = phase_hg(s, mu);
                 const double fst = fs_mix(s, bct, hg, phase_rayleigh(mu));
-                double c;
-                if (kTape) {
-                    c = (double)Tp[(int64_t)(b * cams.n + d) * kWave];
-                } else {
-                    const Real tc = walk_sum<Real>(s, [&](int v) { return gtot[v]; }, p1, u, dist, cseg);
-                    c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
-                }
+                const Real tc = walk_sum<Real>(s, [&](uint32_t v) { return gtot[v]; }, p1, u, dist, cseg);
+                const double c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
                 const double wgt = c * rho;
                 Rb += wgt;
                 // vertex term at x_b: w * w_c f_HG / f_s,t
                 if (fst > 0.0) vert += wgt * (s.w_c * hg / fst);
                 walk_scatter<Real>(s, add, p1, u, dist, -wgt * s.vk, novh, z0, z1);
             }
-            if (vert != 0.0) add_vox(v1, vert);
+            if (vert != 0.0) tally.add_vox(v1, vert);
             R[b] = Rb;
             wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
             p0 = p1;
@@ -470,25 +672,21 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
             if (A != 0.0) {
                 walk_scatter<Real>(s, add, pk, w, L, -A * s.vk, segc, z0, z1);
                 const int v = clamp_vox(pk.v, nu);
-                if (k >= 1 && (unsigned)(v - vlo) < (unsigned)nsv) {
+                if (k >= 1 && (unsigned)(v - tally.vlo) < (unsigned)tally.nsv) {
                     const Vtx pm = load_vtx(V, k - 1);
                     double wm[3];
                     seg_dir(pm, pk, wm);
                     const double mu = wm[0] * w[0] + wm[1] * w[1] + wm[2] * w[2];
                     const double hg = phase_hg(s, mu);
                     const double fst = fs_mix(s, (double)a.bc_t[v], hg, phase_rayleigh(mu));
-                    if (fst > 0.0) add(v - vlo, A * (s.w_c * hg / fst));
+                    if (fst > 0.0) tally.add((uint32_t)(v - tally.vlo), A * (s.w_c * hg / fst));
                 }
             }
             pk1 = pk;
         }
     }
     flush_counts(a.counters, nseg, 0, novh);
-    if (kLds) {
-        __syncthreads();
-        double* __restrict__ out = partial + (int64_t)blockIdx.x * nsv;
-        for (int i = threadIdx.x; i < nsv; i += kBlock) out[i] = sg[i];
-    }
+    slab_tally_end<kLds>(tally, partial);
 }
 
 // grad[v] = sum over workgroups of partial[w][v], in workgroup order.
@@ -502,32 +700,34 @@ __global__ void __launch_bounds__(256) grad_reduce_kernel(const double* __restri
     grad[v] = acc;
 }
 
-template <typename Real, bool kLds, bool kTape>
-static hipError_t launch_grad_one(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, int z0, int z1,
-                                  double* partial)
+template <typename Kern>
+static hipError_t launch_persistent(hipStream_t st, Kern k, int n_wg, size_t lds, const TraceArgs& a,
+                                   const DevCams& c, int z0, int z1, double* partial)
 {
-    const size_t lds = kLds ? (size_t)(z1 - z0) * a.s.nx * a.s.ny * sizeof(double) : 0;
-    if (kLds) {
-        hipError_t e = hipFuncSetAttribute((const void*)grad_kernel<Real, kLds, kTape>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (lds) {
+        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    grad_kernel<Real, kLds, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, z0, z1, partial);
+    k<<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, z0, z1, partial);
     return hipGetLastError();
 }
 
-// The tape variant (when a tape flag is given) and the recomputing variant;
-// exactly one of them does work.  They take tasks from work[0] and work[1].
+// The walk kernel on stored weights (when a tape flag is given; task counter
+// work[0]) and the recomputing kernel (work[1]); exactly one of them does work.
 template <typename Real, bool kLds>
 static hipError_t launch_grad_t(hipStream_t st, const TraceArgs& a, const DevCams& c, const GradPlan& p, int z0,
                                 int z1, double* partial)
 {
+    const size_t lds = kLds ? (size_t)(z1 - z0) * a.s.nx * a.s.ny * sizeof(double) : 0;
     hipError_t e = hipSuccess;
-    if (a.tape_flag && a.tape) e = launch_grad_one<Real, kLds, true>(st, a, c, p.n_wg, z0, z1, partial);
+    const bool walk = sizeof(Real) == 4 && a.tape_flag && a.tape && a.wtape && a.vaux;
+    if (walk) e = launch_persistent(st, grad_walk_kernel<kLds>, p.n_wg, lds, a, c, z0, z1, partial);
     if (e != hipSuccess) return e;
+    // without the walk kernel the recomputing kernel must run whatever the flag says
     TraceArgs b = a;
     b.work = a.work + 1;
-    return launch_grad_one<Real, kLds, false>(st, b, c, p.n_wg, z0, z1, partial);
+    if (!walk) b.tape_flag = nullptr;
+    return launch_persistent(st, grad_kernel<Real, kLds>, p.n_wg, lds, b, c, z0, z1, partial);
 }
 
 GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu)
@@ -621,30 +821,30 @@ __global__ void __launch_bounds__(256) reweight_kernel(TraceArgs a)
             const float4* __restrict__ V = a.st.vtx + a.st.batch_off[slot / kWave] + (slot % kWave);
             const int nu = s.nx * s.ny * s.nz;
             uint64_t cnt = 0;
-            double lr = 0.0;
+            double lr = 0.0, ratio = 1.0;  // log r = lr + log(ratio)
             Vtx p0 = load_vtx(V, 0);
             double wprev[3] = {0.0, 0.0, 0.0};
             for (int k = 0; k + 1 < nv; ++k) {
                 const Vtx p1 = load_vtx(V, k + 1);
                 double w[3];
                 const double L = seg_dir(p0, p1, w);
-                lr -= (double)walk_sum<Real>(s, [&](int v) { return gd[v]; }, p0, w, L, cnt) * s.vk;
+                lr -= (double)walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, cnt) * s.vk;
                 if (k >= 1) {
                     const int v = clamp_vox(p0.v, nu);
                     const double bct = (double)a.bc_t[v], bcr = (double)a.st.beta_ref[v];
                     const double mu = wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2];
                     const double hg = phase_hg(s, mu), ra = phase_rayleigh(mu);
                     const double bst = s.w_c * bct + s.w_a * s.beta_air, bsr = s.w_c * bcr + s.w_a * s.beta_air;
-                    lr += log((fs_mix(s, bct, hg, ra) * bsr) / (fs_mix(s, bcr, hg, ra) * bst));
+                    ratio *= (fs_mix(s, bct, hg, ra) * bsr) / (fs_mix(s, bcr, hg, ra) * bst);
                 }
                 wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
                 p0 = p1;
             }
             for (int k = 1; k <= Bn; ++k) {
                 const int v = clamp_vox(vox_of(V[(int64_t)k * kWave]), nu);
-                lr += log(((double)a.bc_t[v] + s.beta_air) / ((double)a.st.beta_ref[v] + s.beta_air));
+                ratio *= ((double)a.bc_t[v] + s.beta_air) / ((double)a.st.beta_ref[v] + s.beta_air);
             }
-            r = exp(lr);
+            r = exp(lr) * ratio;
         }
     }
     red[0][threadIdx.x] = r;
