@@ -282,6 +282,12 @@ int dalloc(T** p, size_t count, uint64_t* bytes = nullptr)
     return PRT_OK;
 }
 
+// Capacity for a buffer that must hold count elements, with 1/8 headroom:
+// store sizes vary from one resample to the next, and regrowing a buffer
+// (hipFree synchronises the device) on every new maximum would stall the
+// iteration loop.
+int64_t with_headroom(int64_t count) { return count + count / 8; }
+
 int ensure_grids(prt_ctx c, int64_t nu)
 {
     const size_t need = (size_t)nu * (c->fp64 ? 8 : 4);
@@ -303,6 +309,7 @@ int ensure_scratch(void** buf, size_t* have, size_t bytes)
     (void)hipFree(*buf);
     *buf = nullptr;
     *have = 0;
+    bytes = (size_t)with_headroom((int64_t)bytes);
     if (hipMalloc(buf, bytes) != hipSuccess) {
         (void)hipGetLastError();
         *buf = nullptr;
@@ -364,8 +371,9 @@ int grow(T** buf, int64_t* cap, int64_t count)
     (void)hipFree(*buf);
     *buf = nullptr;
     *cap = 0;
-    int rc = dalloc(buf, (size_t)count);
-    if (rc == PRT_OK) *cap = count;
+    const int64_t want = with_headroom(count);
+    int rc = dalloc(buf, (size_t)want);
+    if (rc == PRT_OK) *cap = want;
     return rc;
 }
 
@@ -483,12 +491,13 @@ int ensure_tape(prt_paths p, size_t n_cams, int64_t nu)
     (void)hipFree(p->tape);
     p->tape = nullptr;
     p->tape_cap = 0;
-    if (hipMalloc((void**)&p->tape, std::max<size_t>(need, 1) * sizeof(float)) != hipSuccess) {
+    const size_t want = std::max<size_t>((size_t)with_headroom((int64_t)need), 1);
+    if (hipMalloc((void**)&p->tape, want * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         p->tape = nullptr;
         return PRT_E_NOMEM;
     }
-    p->tape_cap = need;
+    p->tape_cap = want;
     return PRT_OK;
 }
 
@@ -791,9 +800,13 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
     if ((rc = ensure_grids(c, nu))) return rc;
     const int64_t npx = (int64_t)dc.n * dc.W * dc.H;
+    // batches with scattering paths (the kernels have nothing to do without them)
+    const bool work = p->n_slots > p->first_slot;
+    const RenderPlan plan = plan_render(c->fp64, nu, npx, p->n_slots, p->first_slot, c->n_cu);
     {
         TimedScope ts(c, K_PREP);
-        HIPCHK(launch_fill(c->stream, images, npx, 0.0));
+        // the LDS partials' reduction writes every pixel; otherwise tallies add up on zeros
+        if (!work || !plan.img_lds) HIPCHK(launch_fill(c->stream, images, npx, 0.0));
         HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
                                  c->grid_dlt));
     }
@@ -820,18 +833,17 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
         p->tape_cams = dc;
         p->tape_scene = a.s;
     }
-    const RenderPlan plan = plan_render(c->fp64, nu, npx, p->n_slots, p->first_slot, c->n_cu);
     if ((rc = ensure_scratch(&c->rpart, &c->rpart_bytes, plan.partial_bytes))) return rc;
-    {
-        TimedScope ts(c, K_RENDER_PREFIX);
-        HIPCHK(launch_render_prefix(c->stream, c->fp64, a));
-    }
-    HIPCHK(launch_reset_work(c->stream, c->work, 1));
-    {
-        TimedScope ts(c, K_RENDER);
-        HIPCHK(launch_render(c->stream, c->fp64, a, dc, plan, (float*)c->rpart));
-    }
-    {
+    if (work) {
+        {
+            TimedScope ts(c, K_RENDER_PREFIX);
+            HIPCHK(launch_render_prefix(c->stream, c->fp64, a));
+        }
+        HIPCHK(launch_reset_work(c->stream, c->work, 1));
+        {
+            TimedScope ts(c, K_RENDER);
+            HIPCHK(launch_render(c->stream, c->fp64, a, dc, plan, (float*)c->rpart));
+        }
         TimedScope ts(c, K_RENDER_REDUCE);
         HIPCHK(launch_render_reduce(c->stream, dc, plan, (const float*)c->rpart, images));
     }
@@ -857,9 +869,14 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
     if ((rc = ensure_grids(c, nu))) return rc;
     const int64_t npx = (int64_t)dc.n * dc.W * dc.H;
     if ((rc = ensure_pix(c, npx))) return rc;
+    // batches with scattering paths (the kernels have nothing to do without them)
+    const bool work = p->n_slots > p->first_slot;
+    const GradPlan plan = plan_grad(s->nx, s->ny, s->nz, p->n_slots, p->first_slot, c->n_cu);
     {
         TimedScope ts(c, K_PREP);
-        HIPCHK(launch_fill(c->stream, grad, nu, 0.0));
+        // the slabs' reductions write every voxel; otherwise atomics add up on zeros
+        if (!work || !plan.lds) HIPCHK(launch_fill(c->stream, grad, nu, 0.0));
+        if (!work) return PRT_OK;
         HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
                                  c->grid_dlt));
         HIPCHK(launch_grad_prep(c->stream, residual, c->pix, dc, 1.0 / (double)p->n));
@@ -892,7 +909,6 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
         TimedScope ts(c, K_GRAD_WEIGHTS);
         HIPCHK(launch_grad_weights(c->stream, a, dc));
     }
-    const GradPlan plan = plan_grad(s->nx, s->ny, s->nz, p->n_slots, p->first_slot, c->n_cu);
     if ((rc = ensure_scratch(&c->gpart, &c->gpart_bytes, plan.partial_bytes))) return rc;
     for (int i = 0; i < plan.n_slabs; ++i) {
         HIPCHK(launch_reset_work(c->stream, c->work, 2));
