@@ -281,6 +281,24 @@ __device__ __forceinline__ void dda_walk_slab(int nx, int ny, int z0, int z1, Re
     dda_steps<Real>(nx, ny, z0, z1, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, t, tmax, pieces, f);
 }
 
+// Spatial sort key of a path (the store orders paths by size B, then by this
+// key): the Morton code of the coarse cell (8 cells per axis) holding the
+// path's first vertex after the source (its first scatter, or its entry
+// point when it has none).  Paths next to each other in the store then start
+// near each other, so their walks have similar lengths.
+constexpr int kCellBits = 3;
+constexpr int kCells = 1 << (3 * kCellBits);
+__host__ __device__ inline uint32_t cell_key(int v, int nx, int ny, int nz)
+{
+    const int ix = v % nx, iy = (v / nx) % ny, iz = v / (nx * ny);
+    const uint32_t cx = (uint32_t)(ix * (1 << kCellBits) / nx), cy = (uint32_t)(iy * (1 << kCellBits) / ny),
+                   cz = (uint32_t)(iz * (1 << kCellBits) / nz);
+    uint32_t m = 0;
+    for (int k = 0; k < kCellBits; ++k)
+        m |= ((cx >> k) & 1u) << (3 * k) | ((cy >> k) & 1u) << (3 * k + 1) | ((cz >> k) & 1u) << (3 * k + 2);
+    return m;
+}
+
 // Voxel index components of a linear voxel id.
 __device__ __forceinline__ void voxel_ijk(int v, int nx, int ny, int& ix, int& iy, int& iz)
 {

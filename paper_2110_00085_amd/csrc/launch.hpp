@@ -31,6 +31,7 @@ struct SampleArgs {
     float4* tmp;           // [n][max_order+2] records
     uint8_t* tB;
     uint8_t* tnv;
+    uint16_t* tC;          // spatial sort key per path (cell_key)
     unsigned int* next;    // path-id counter of the persistent sampler (zero at launch)
 };
 
@@ -73,8 +74,10 @@ struct TraceArgs {
 hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const float* bc_r, double beta_air,
                              int64_t nu, void* grid_tot, void* grid_dlt);
 hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu);
-hipError_t launch_sort_by_size(hipStream_t st, const uint8_t* key, int64_t n, int nbins, uint32_t* blockhist,
-                               int32_t* perm);
+// Stable sort of the paths by (size B, spatial key): perm[sorted position] =
+// path id.  hist: sort_scratch_words(n, nbins) words; tmp_perm: n entries.
+hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint16_t* cell, int64_t n, int nbins,
+                             uint32_t* hist, int32_t* tmp_perm, int32_t* perm);
 int64_t sort_scratch_words(int64_t n, int nbins);
 hipError_t launch_gather_sizes(hipStream_t st, const int32_t* perm, const uint8_t* tB, const uint8_t* tnv,
                                int64_t n, int64_t n_slots, uint8_t* B, uint8_t* nv);

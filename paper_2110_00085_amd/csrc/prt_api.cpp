@@ -71,6 +71,8 @@ struct prt_ctx_s {
     void* s_hist = nullptr;
     size_t s_hist_bytes = 0;
     void* s_off = nullptr;      // import offsets
+    void* s_perm = nullptr;     // permutation after the sort's first pass
+    size_t s_perm_bytes = 0;
     size_t s_off_bytes = 0;
     int64_t* meta = nullptr;    // 3 int64 read back after packing
     void* grid_tot = nullptr;
@@ -400,7 +402,7 @@ uint64_t store_bytes(const prt_paths_s* p)
 // addressed by tmp_off (CSR) or by id * tmp_stride.  Reads back the store
 // size once (one synchronisation).
 int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_off, int64_t tmp_stride,
-                const uint8_t* tB, const uint8_t* tnv)
+                const uint8_t* tB, const uint8_t* tnv, const uint16_t* tC)
 {
     const int64_t n = (int64_t)p->n;
     p->nb = (n + kWave - 1) / kWave;
@@ -409,9 +411,10 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
     int rc;
     if ((rc = reserve_paths(p, n))) return rc;
     if ((rc = ensure_scratch(&c->s_hist, &c->s_hist_bytes, sort_scratch_words(n, nbins) * sizeof(uint32_t)))) return rc;
+    if ((rc = ensure_scratch(&c->s_perm, &c->s_perm_bytes, (size_t)n * sizeof(int32_t)))) return rc;
     {
         TimedScope ts(c, K_SORT);
-        HIPCHK(launch_sort_by_size(c->stream, tB, n, nbins, (uint32_t*)c->s_hist, p->perm));
+        HIPCHK(launch_sort_paths(c->stream, tB, tC, n, nbins, (uint32_t*)c->s_hist, (int32_t*)c->s_perm, p->perm));
         HIPCHK(launch_gather_sizes(c->stream, p->perm, tB, tnv, n, p->n_slots, p->B, p->nv));
         HIPCHK(launch_batch_offsets(c->stream, p->nv, p->nb, p->batch_off, c->s_hist));
         HIPCHK(launch_store_meta(c->stream, p->B, n, p->batch_off, p->nb, c->meta));
@@ -441,7 +444,7 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     if ((rc = ensure_grids(c, nu))) return rc;
     if ((rc = grow(&p->beta_ref, &p->cap_nu, nu))) return rc;
     if ((rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes, (size_t)n * stride * sizeof(float4)))) return rc;
-    if ((rc = ensure_scratch(&c->s_keys, &c->s_keys_bytes, 2 * (size_t)n))) return rc;
+    if ((rc = ensure_scratch(&c->s_keys, &c->s_keys_bytes, 4 * (size_t)n))) return rc;
     p->n = (uint64_t)n;
     p->seed = seed;
     p->max_order = s->max_order;
@@ -451,6 +454,7 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     p->tape_valid = false;
     uint8_t* tB = (uint8_t*)c->s_keys;
     uint8_t* tnv = tB + n;
+    uint16_t* tC = (uint16_t*)(tB + 2 * n);
     HIPCHK(hipMemcpyAsync(p->beta_ref, s->beta_cloud, nu * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
     {
         TimedScope ts(c, K_PREP);
@@ -465,13 +469,14 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     a.tmp = (float4*)c->s_tmp;
     a.tB = tB;
     a.tnv = tnv;
+    a.tC = tC;
     a.next = c->work + 2;
     HIPCHK(launch_reset_work(c->stream, a.next, 1));
     {
         TimedScope ts(c, K_SAMPLE);
         HIPCHK(launch_sample(c->stream, c->fp64, a, c->n_cu));
     }
-    return build_store(c, p, (const float4*)c->s_tmp, nullptr, stride, tB, tnv);
+    return build_store(c, p, (const float4*)c->s_tmp, nullptr, stride, tB, tnv, tC);
 }
 
 // Tape capacity: one FP32 entry per (vertex record, camera) from the first
@@ -594,6 +599,7 @@ void prt_destroy(prt_ctx c)
     (void)hipFree(c->s_keys);
     (void)hipFree(c->s_hist);
     (void)hipFree(c->s_off);
+    (void)hipFree(c->s_perm);
     (void)hipFree(c->meta);
     (void)hipFree(c->part);
     (void)hipFree(c->out2);
@@ -686,9 +692,11 @@ int prt_paths_import(prt_ctx c, const prt_scene* s, uint64_t n_paths, const int6
         h[r] = q;
     }
     std::vector<uint8_t> hB(n), hnv(n);
+    std::vector<uint16_t> hC(n);
     for (int64_t i = 0; i < n; ++i) {
         hB[i] = (uint8_t)B[i];
         hnv[i] = (uint8_t)(off[i + 1] - off[i]);
+        hC[i] = (uint16_t)cell_key(vox[off[i] + (B[i] > 0 ? 1 : 0)], s->nx, s->ny, s->nz);
     }
     prt_paths p = new_store(c, s, n_paths, seed);
     auto bail = [&](int code) {
@@ -699,18 +707,20 @@ int prt_paths_import(prt_ctx c, const prt_scene* s, uint64_t n_paths, const int6
     if ((rc = grow(&p->beta_ref, &p->cap_nu, nu))) return bail(rc);
     if ((rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes, (size_t)nrec * sizeof(float4)))) return bail(rc);
     if ((rc = ensure_scratch(&c->s_off, &c->s_off_bytes, (size_t)(n + 1) * sizeof(int64_t)))) return bail(rc);
-    if ((rc = ensure_scratch(&c->s_keys, &c->s_keys_bytes, 2 * (size_t)n))) return bail(rc);
+    if ((rc = ensure_scratch(&c->s_keys, &c->s_keys_bytes, 4 * (size_t)n))) return bail(rc);
     float4* tmp = (float4*)c->s_tmp;
     int64_t* toff = (int64_t*)c->s_off;
     uint8_t* tB = (uint8_t*)c->s_keys;
     uint8_t* tnv = tB + n;
+    uint16_t* tC = (uint16_t*)(tB + 2 * n);
     hipError_t e = hipMemcpy(tmp, h.data(), nrec * sizeof(float4), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(toff, off, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tB, hB.data(), n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tnv, hnv.data(), n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(tC, hC.data(), n * sizeof(uint16_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->beta_ref, beta_ref, nu * sizeof(float), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(fail(PRT_E_HIP, "import upload: %s", hipGetErrorString(e)));
-    if ((rc = build_store(c, p, tmp, toff, 0, tB, tnv))) return bail(rc);
+    if ((rc = build_store(c, p, tmp, toff, 0, tB, tnv, tC))) return bail(rc);
     *out = p;
     return PRT_OK;
 }

@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
     double x = 0.0, y = 0.0, z = 0.0, tau = 0.0;
     double w[3] = {0.0, 0.0, 0.0};
     double u[4];
-    int ix = 0, iy = 0, iz = 0, b = 0, nv = 0;
+    int ix = 0, iy = 0, iz = 0, b = 0, nv = 0, v0 = 0;
     bool active = false, exhausted = false;
     for (;;) {
         if (!exhausted) {
@@ -96,7 +96,8 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
                     iy = min(max((int)floor(y), 0), s.ny - 1);
                     iz = min(max((int)floor(z), 0), s.nz - 1);
                     nv = 0;
-                    out[nv++] = vrec(x, y, z, ix + s.nx * (iy + s.ny * iz));
+                    v0 = ix + s.nx * (iy + s.ny * iz);
+                    out[nv++] = vrec(x, y, z, v0);
                     w[0] = s.sun[0]; w[1] = s.sun[1]; w[2] = s.sun[2];
                     // optical depth target in units of (1/km * grid length)
                     tau = -log(u[3]) / s.vk;
@@ -141,6 +142,7 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
             }
             ++b;
             out[nv++] = vrec(x, y, z, hit);
+            if (b == 1) v0 = hit;  // the sort key follows the first scatter
             done = b >= s.max_order;
             if (!done) {
                 voxel_ijk(hit, s.nx, s.ny, ix, iy, iz);
@@ -157,6 +159,7 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
         if (done) {
             a.tB[id] = (uint8_t)b;
             a.tnv[id] = (uint8_t)nv;
+            a.tC[id] = (uint16_t)cell_key(v0, s.nx, s.ny, s.nz);
             active = false;
         }
     }
@@ -175,14 +178,17 @@ hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu
 
 // ----------------------------------------------------- stable counting sort
 
-// Keys (path sizes) are processed in tiles of kSortTile; tile t's count of
+// Keys are processed in tiles of kSortTile positions; the key of position i
+// is key[in[i]] (or key[i] without an input permutation).  Tile t's count of
 // key k lives at hist[k * n_tiles + t], so an exclusive scan of hist in that
 // order gives every (key, tile) its first output position.
 constexpr int kSortTile = 1024;
-constexpr int kMaxBins = kMaxOrder + 1;
+constexpr int kMaxBins = kCells > kMaxOrder + 1 ? kCells : kMaxOrder + 1;
 
-__global__ void __launch_bounds__(256) sort_hist_kernel(const uint8_t* __restrict__ key, int64_t n, int nbins,
-                                                        int64_t n_tiles, uint32_t* __restrict__ hist)
+template <typename K>
+__global__ void __launch_bounds__(256) sort_hist_kernel(const K* __restrict__ key, const int32_t* __restrict__ in,
+                                                        int64_t n, int nbins, int64_t n_tiles,
+                                                        uint32_t* __restrict__ hist)
 {
     __shared__ uint32_t h[kMaxBins];
     for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
@@ -190,7 +196,7 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const uint8_t* __restric
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int j = threadIdx.x; j < kSortTile; j += blockDim.x) {
         const int64_t i = base + j;
-        if (i < n) atomicAdd(&h[min((int)key[i], nbins - 1)], 1u);
+        if (i < n) atomicAdd(&h[min((int)key[in ? in[i] : i], nbins - 1)], 1u);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nbins; k += blockDim.x) hist[(int64_t)k * n_tiles + blockIdx.x] = h[k];
@@ -264,30 +270,62 @@ static hipError_t scan_exclusive(hipStream_t st, T* a, int64_t n, T* scratch)
     return hipGetLastError();
 }
 
-// Thread k of a tile owns key k: it walks the tile in id order and assigns
-// consecutive output positions to the ids with that key (stable).
-__global__ void __launch_bounds__(128) sort_scatter_kernel(const uint8_t* __restrict__ key, int64_t n, int nbins,
-                                                           int64_t n_tiles, const uint32_t* __restrict__ off,
-                                                           int32_t* __restrict__ perm)
+// One wavefront per tile, which takes the tile 64 positions at a time in
+// position order: each lane finds the lanes holding its key (one ballot per
+// key bit), counts those below it, so equal keys keep their order, and the
+// last lane of each key advances that key's running output position in LDS.
+// Writes out[pos] = in[i] (or i).
+template <typename K>
+__global__ void __launch_bounds__(kWave) sort_scatter_kernel(const K* __restrict__ key,
+                                                             const int32_t* __restrict__ in, int64_t n, int nbins,
+                                                             int64_t n_tiles, const uint32_t* __restrict__ off,
+                                                             int32_t* __restrict__ out)
 {
-    __shared__ uint8_t kt[kSortTile];
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int j = threadIdx.x; j < kSortTile; j += blockDim.x) {
-        const int64_t i = base + j;
-        kt[j] = i < n ? (uint8_t)min((int)key[i], nbins - 1) : (uint8_t)0xFF;
-    }
+    __shared__ uint32_t base[kMaxBins];
+    for (int k = threadIdx.x; k < nbins; k += kWave) base[k] = off[(int64_t)k * n_tiles + blockIdx.x];
     __syncthreads();
-    const int k = threadIdx.x;
-    if (k >= nbins) return;
-    uint32_t pos = off[(int64_t)k * n_tiles + blockIdx.x];
-    const int cnt = (int)min((int64_t)kSortTile, n - base);
-    for (int j = 0; j < cnt; ++j)
-        if (kt[j] == k) perm[pos++] = (int32_t)(base + j);
+    const int lane = threadIdx.x;
+    const uint64_t below_mask = lane ? (~0ull >> (kWave - lane)) : 0ull;
+    int nbits = 1;
+    while ((1 << nbits) < nbins) ++nbits;
+    const int64_t t0 = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortTile / kWave; ++r) {
+        const int64_t i = t0 + r * kWave + lane;
+        const bool valid = i < n;
+        const int k = valid ? min((int)key[in ? in[i] : i], nbins - 1) : 0;
+        uint64_t same = __ballot(valid);
+        for (int bit = 0; bit < nbits; ++bit) {
+            const bool set = (k >> bit) & 1;
+            const uint64_t bb = __ballot(set);
+            same &= set ? bb : ~bb;
+        }
+        if (valid) {
+            const int below = __popcll(same & below_mask), total = __popcll(same);
+            out[base[k] + below] = in ? in[i] : (int32_t)i;
+            if (below == total - 1) base[k] += total;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename K>
+static hipError_t counting_sort(hipStream_t st, const K* key, const int32_t* in, int64_t n, int nbins,
+                                uint32_t* hist, int32_t* out)
+{
+    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    sort_hist_kernel<K><<<dim3((unsigned)n_tiles), dim3(256), 0, st>>>(key, in, n, nbins, n_tiles, hist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t m = n_tiles * nbins;
+    if ((e = scan_exclusive<uint32_t>(st, hist, m, hist + m)) != hipSuccess) return e;
+    sort_scatter_kernel<K><<<dim3((unsigned)n_tiles), dim3(kWave), 0, st>>>(key, in, n, nbins, n_tiles, hist, out);
+    return hipGetLastError();
 }
 
 int64_t sort_scratch_words(int64_t n, int nbins)
 {
-    const int64_t hist = ((n + kSortTile - 1) / kSortTile) * (int64_t)nbins;
+    const int64_t tiles = (n + kSortTile - 1) / kSortTile;
+    const int64_t hist = tiles * (int64_t)std::max(nbins, kCells);
     const int64_t sort_words = hist + scan_scratch_elems(hist);
     // launch_batch_offsets reuses the same scratch for its int64 scan
     const int64_t nb = (n + kWave - 1) / kWave;
@@ -295,17 +333,13 @@ int64_t sort_scratch_words(int64_t n, int nbins)
     return std::max<int64_t>(1, std::max(sort_words, boff_words));
 }
 
-hipError_t launch_sort_by_size(hipStream_t st, const uint8_t* key, int64_t n, int nbins, uint32_t* blockhist,
-                               int32_t* perm)
+hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint16_t* cell, int64_t n, int nbins,
+                             uint32_t* hist, int32_t* tmp_perm, int32_t* perm)
 {
-    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
-    sort_hist_kernel<<<dim3((unsigned)n_tiles), dim3(256), 0, st>>>(key, n, nbins, n_tiles, blockhist);
-    hipError_t e = hipGetLastError();
+    if (n <= 0) return hipSuccess;
+    hipError_t e = counting_sort<uint16_t>(st, cell, nullptr, n, kCells, hist, tmp_perm);
     if (e != hipSuccess) return e;
-    const int64_t m = n_tiles * nbins;
-    if ((e = scan_exclusive<uint32_t>(st, blockhist, m, blockhist + m)) != hipSuccess) return e;
-    sort_scatter_kernel<<<dim3((unsigned)n_tiles), dim3(128), 0, st>>>(key, n, nbins, n_tiles, blockhist, perm);
-    return hipGetLastError();
+    return counting_sort<uint8_t>(st, size_key, tmp_perm, n, nbins, hist, perm);
 }
 
 // --------------------------------------------------------------- packing

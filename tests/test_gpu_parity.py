@@ -87,7 +87,8 @@ def test_sample_fp64_matches_oracle(env):
         assert np.abs(a.astype(float) - b).max() <= 2e-6 * 8, i
         assert np.array_equal(vox[off[i]:off[i + 1]], ref.vox[ref.off[i]:ref.off[i + 1]])
     perm = P.prt_paths_permutation(ctx.handle, st.handle)
-    assert np.array_equal(perm, oracle.sort_permutation(B))
+    cells = oracle.path_cells((scene.nx, scene.ny, scene.nz), off, vox, B)
+    assert np.array_equal(perm, oracle.sort_permutation(B, cells))
 
 
 def test_resample_reuses_store(env):
@@ -127,7 +128,8 @@ def test_sample_fp32_close_to_oracle(env, name):
         dev.append(np.abs(a - b).max())
     assert np.median(dev) < 1e-4, np.median(dev)
     perm = P.prt_paths_permutation(ctx.handle, st.handle)
-    assert np.array_equal(perm, oracle.sort_permutation(B))
+    cells = oracle.path_cells((scene.nx, scene.ny, scene.nz), off, vox, B)
+    assert np.array_equal(perm, oracle.sort_permutation(B, cells))
 
 
 # ---------------------------------------------- render / grad / reweight
