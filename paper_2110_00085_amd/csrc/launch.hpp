@@ -47,10 +47,11 @@ struct TraceArgs {
     double* partial;          // reweight: per-block (sum r, sum r^2)
     int32_t brender;
     unsigned long long* counters;  // [0] voxel segs, [1] local estimates, [3] overhead segs
-    // Transmittance tape: render records every in-image contribution c_{b,d}
-    // (FP32) at tape[(batch_off[batch] - tape_base) * n_cams + (b*n_cams + d)*64 + lane];
+    // Transmittance tape: render records, for every (scatter b, camera d),
+    // (c_{b,d}, pixel index as int bits), or (0, -1) when x_b projects outside
+    // camera d, at tape[(batch_off[batch] - tape_base) * n_cams + (b*n_cams + d)*64 + lane];
     // grad reuses it when *tape_flag is 1 (same beta_t, cameras and scene).
-    float* tape;
+    float2* tape;
     int64_t tape_base;        // records of the leading batches without scatters
     // Render prefix: pbase[batch_off[batch] - tape_base + 64*b + lane] =
     // P_b / (beta_ref(x_b) + beta_air), the recycled weight of the sub-path

@@ -114,8 +114,8 @@ struct prt_paths_s {
     int64_t tape_base = 0;      // batch_off of the first batch with scattering paths
     // Transmittance tape written by prt_render (FP32 traversal mode), reused by
     // prt_grad when beta_t, the cameras and the scene constants are unchanged.
-    float* tape = nullptr;
-    size_t tape_cap = 0;        // entries
+    float2* tape = nullptr;
+    size_t tape_cap = 0;        // entries (c, pixel)
     float* tape_beta = nullptr; // beta_t of the render that wrote the tape
     bool tape_valid = false;
     DevCams tape_cams{};
@@ -393,7 +393,7 @@ int reserve_paths(prt_paths p, int64_t n)
 uint64_t store_bytes(const prt_paths_s* p)
 {
     return (uint64_t)p->cap_perm * 4 + (uint64_t)p->cap_slots + (uint64_t)p->cap_nv + (uint64_t)p->cap_boff * 8 +
-           (uint64_t)p->cap_records * 16 + (uint64_t)p->cap_nu * 4 + (uint64_t)p->tape_cap * 4 +
+           (uint64_t)p->cap_records * 16 + (uint64_t)p->cap_nu * 4 + (uint64_t)p->tape_cap * 8 +
            (p->tape_beta ? (uint64_t)p->cap_nu * 4 : 0);
 }
 
@@ -479,14 +479,14 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     return build_store(c, p, (const float4*)c->s_tmp, nullptr, stride, tB, tnv, tC);
 }
 
-// Tape capacity: one FP32 entry per (vertex record, camera) from the first
+// Tape capacity: one (FP32 c, pixel) entry per (vertex record, camera) from the first
 // scattering batch on; capped so that large workloads recompute instead.
 constexpr size_t kMaxTapeBytes = (size_t)16 << 30;
 
 int ensure_tape(prt_paths p, size_t n_cams, int64_t nu)
 {
     const size_t need = (size_t)(p->n_records - p->tape_base) * n_cams;
-    if (need * sizeof(float) > kMaxTapeBytes) return PRT_E_CAPACITY;
+    if (need * sizeof(float2) > kMaxTapeBytes) return PRT_E_CAPACITY;
     if (!p->tape_beta && hipMalloc((void**)&p->tape_beta, (size_t)nu * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         p->tape_beta = nullptr;
@@ -497,7 +497,7 @@ int ensure_tape(prt_paths p, size_t n_cams, int64_t nu)
     p->tape = nullptr;
     p->tape_cap = 0;
     const size_t want = std::max<size_t>((size_t)with_headroom((int64_t)need), 1);
-    if (hipMalloc((void**)&p->tape, want * sizeof(float)) != hipSuccess) {
+    if (hipMalloc((void**)&p->tape, want * sizeof(float2)) != hipSuccess) {
         (void)hipGetLastError();
         p->tape = nullptr;
         return PRT_E_NOMEM;

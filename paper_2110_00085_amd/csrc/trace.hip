@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
         if (Br <= 0) continue;
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
         const double* __restrict__ Pb = a.pbase + (a.st.batch_off[bt] - a.tape_base) + lane;
-        float* __restrict__ T = kTape ? a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane : nullptr;
+        float2* __restrict__ T = kTape ? a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane : nullptr;
         Vtx p0 = load_vtx(V, 0);
         for (int b = 1; b <= Br; ++b) {
             const Vtx p1 = load_vtx(V, b);
@@ -222,7 +222,10 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
             const double base = Pb[(int64_t)b * kWave];
             for (int d = d_lo; d < d_hi; ++d) {
                 const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
-                if (pix < 0) continue;
+                if (pix < 0) {
+                    if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = make_float2(0.f, __int_as_float(-1));
+                    continue;
+                }
                 const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
                 const double dist2 = ex * ex + ey * ey + ez * ez;
                 const double dist = sqrt(dist2);
@@ -232,7 +235,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                 const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
                 const Real tc = walk_sum<Real>(s, beta_tot, p1, u, dist, nseg);
                 const double c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
-                if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = (float)c;
+                if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = make_float2((float)c, __int_as_float(pix));
                 if (kImgLds) atomicAdd(&simg[d * npix + pix], (float)c);
                 else unsafeAtomicAdd(&a.img[(int64_t)d * npix + pix], c);
                 ++nle;
@@ -440,10 +443,20 @@ __device__ __forceinline__ void slab_tally_end(const SlabTally<kLds>& t, double*
 }
 
 // Weights from the transmittance tape, one lane per path: for every (b, d)
-// w_{b,d} = c_{b,d} rho_{d,p} (0 when x_b projects outside camera d), and per
-// vertex R_b, the connection vertex term sum_d w_{b,d} w_c f_HG / f_s,t at
-// x_b, and the coefficient w_c f_HG / f_s,t of the scatter at x_b between
-// segments b-1 and b.  Runs only when the tape matches beta_t.
+// w_{b,d} = c_{b,d} rho_{d,p} with c and the pixel p from the tape (0 when
+// x_b projects outside camera d), and per vertex R_b, the connection vertex
+// term sum_d w_{b,d} w_c f_HG / f_s,t at x_b, and the coefficient
+// w_c f_HG / f_s,t of the scatter at x_b between segments b-1 and b.  Runs
+// only when the tape matches beta_t (FP32 traversal mode): the per-camera
+// phase functions are evaluated in FP32, like the stored weights.
+__device__ __forceinline__ float phase_hg_f32(const DevScene& s, float mu)
+{
+    // 1 + g^2 - 2 g mu written as (1-g)^2 + 2 g (1-mu): no cancellation near mu = 1
+    const float g = (float)s.g;
+    const float d = (1.f - g) * (1.f - g) + 2.f * g * (1.f - mu);
+    return (float)s.hg_num / (d * sqrtf(d));
+}
+
 __global__ void __launch_bounds__(256) grad_weights_kernel(TraceArgs a, DevCams cams)
 {
     if (*a.tape_flag == 0) return;
@@ -457,9 +470,10 @@ __global__ void __launch_bounds__(256) grad_weights_kernel(TraceArgs a, DevCams 
     const int64_t bt = slot / kWave, lane = slot % kWave;
     const int64_t rec0 = a.st.batch_off[bt] - a.tape_base;
     const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
-    const float* __restrict__ Tp = a.tape + rec0 * cams.n + lane;
+    const float2* __restrict__ Tp = a.tape + rec0 * cams.n + lane;
     float* __restrict__ Wp = a.wtape + rec0 * cams.n + lane;
     float4* __restrict__ X = a.vaux + rec0 + lane;
+    const float wc = (float)s.w_c, wab = (float)(s.w_a * s.beta_air), ray_k = (float)(3.0 / (16.0 * kPi));
     uint64_t nle = 0;
     Vtx p0 = load_vtx(V, 0), p1 = load_vtx(V, 1);
     double w[3];
@@ -467,20 +481,22 @@ __global__ void __launch_bounds__(256) grad_weights_kernel(TraceArgs a, DevCams 
     for (int b = 1; b <= Bn; ++b) {
         const int v1 = clamp_vox(p1.v, nu);
         const double bct = (double)a.bc_t[v1];
-        double Rb = 0.0, vert = 0.0;
+        const float wcb = wc * (float)bct;
+        const float wf0 = (float)w[0], wf1 = (float)w[1], wf2 = (float)w[2];
+        float Rb = 0.f, vert = 0.f;
         for (int d = 0; d < cams.n; ++d) {
-            const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
+            const float2 t = Tp[(int64_t)(b * cams.n + d) * kWave];
+            const int pix = __float_as_int(t.y);
             float wf = 0.f;
             if (pix >= 0) {
-                const double wgt = (double)Tp[(int64_t)(b * cams.n + d) * kWave] * a.rho[(int64_t)d * npix + pix];
-                const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
-                const double id = 1.0 / sqrt(ex * ex + ey * ey + ez * ez);
-                const double mu = (w[0] * ex + w[1] * ey + w[2] * ez) * id;
-                const double hg = phase_hg(s, mu);
-                const double fst = fs_mix(s, bct, hg, phase_rayleigh(mu));
-                Rb += wgt;
-                if (fst > 0.0) vert += wgt * (s.w_c * hg / fst);
-                wf = (float)wgt;
+                wf = t.x * (float)a.rho[(int64_t)d * npix + pix];
+                const float ex = (float)(cams.pos[d][0] - p1.x), ey = (float)(cams.pos[d][1] - p1.y),
+                            ez = (float)(cams.pos[d][2] - p1.z);
+                const float mu = (wf0 * ex + wf1 * ey + wf2 * ez) * rsqrtf(ex * ex + ey * ey + ez * ez);
+                const float hg = phase_hg_f32(s, mu);
+                const float fst = wcb * hg + wab * ray_k * (1.f + mu * mu);
+                Rb += wf;
+                if (fst > 0.f) vert += wf * (wc * hg / fst);
                 ++nle;
             }
             Wp[(int64_t)(b * cams.n + d) * kWave] = wf;
@@ -496,7 +512,7 @@ __global__ void __launch_bounds__(256) grad_weights_kernel(TraceArgs a, DevCams 
             const double fst = fs_mix(s, bct, hg, phase_rayleigh(mu));
             if (fst > 0.0) coef = s.w_c * hg / fst;
         }
-        X[(int64_t)b * kWave] = make_float4((float)Rb, (float)vert, (float)coef, 0.f);
+        X[(int64_t)b * kWave] = make_float4(Rb, vert, (float)coef, 0.f);
         w[0] = wn[0]; w[1] = wn[1]; w[2] = wn[2];
         p1 = p2;
     }
