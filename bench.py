@@ -35,9 +35,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# HBM traffic per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counters scaled by a plain copy of known size; valid while the
+# kernel sources hash to the recorded value.
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+CSRC = os.path.join(ROOT, "paper_2110_00085_amd", "csrc")
+# device kernel measured for each timed hot-path scope
+DEVICE_KERNEL = {"grad": "grad_walk_kernel", "render": "render_kernel", "sample": "sample_kernel",
+                 "reweight": "reweight_kernel", "grad_weights": "grad_weights_kernel",
+                 "render_prefix": "render_prefix_kernel"}
+
 # VALU peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-operations/s
 # (one FP32 or FP64 FMA per lane per clock without packed math).
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+HBM_PEAK_GBS = 8000.0
 # algorithmic VALU lane-operations per unit of work: the arithmetic of one
 # voxel piece of a walk and of one local estimate (projection, phase
 # functions, weight), as the kernels perform it
@@ -59,6 +70,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (to scale FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="summarise rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv output of a bench run and of "
+                         "--copy-calibration into --traffic-json, then exit")
+    ap.add_argument("--traffic-json", default=TRAFFIC_JSON, help="where --pmc-summary writes its result")
     return ap.parse_args()
 
 
@@ -75,10 +90,78 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": 4 * n, "dispatches": 3}), flush=True)
 
 
+def source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def _pmc_rows(d, counter):
+    """(dispatch id, kernel name, value) of one counter from rocprofv3 csv output."""
+    import csv
+    import glob
+    out = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_json):
+    """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of every hot-path kernel
+    of a bench run, scaled by what the same counters read for the 1 GiB copy
+    of --copy-calibration; writes out_json and prints a markdown table."""
+    copy_kib = (1 << 30) / 1024.0
+    cf = [v for _, k, v in _pmc_rows(cfetch_dir, "FETCH_SIZE") if "copyBuffer" in k]
+    cw = [v for _, k, v in _pmc_rows(cwrite_dir, "WRITE_SIZE") if "copyBuffer" in k]
+    f_fac, w_fac = copy_kib / (sum(cf) / len(cf)), copy_kib / (sum(cw) / len(cw))
+    kernels = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        for _, k, v in _pmc_rows(d, counter):
+            for scope, sym in DEVICE_KERNEL.items():
+                if "prt::" + sym + "<" in k or "prt::" + sym + "(" in k:
+                    kernels.setdefault(scope, {}).setdefault(counter, []).append(v)
+    table = {}
+    print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per dispatch (scaled) |")
+    print("|---|---:|---:|---:|---:|")
+    for scope, c in sorted(kernels.items()):
+        fk = sum(c["FETCH_SIZE"]) / len(c["FETCH_SIZE"])
+        wk = sum(c["WRITE_SIZE"]) / len(c["WRITE_SIZE"])
+        b = 1024.0 * (fk * f_fac + wk * w_fac)
+        table[scope] = {"kernel": DEVICE_KERNEL[scope], "fetch_kib": fk, "write_kib": wk, "bytes_per_launch": b}
+        print(f"| {DEVICE_KERNEL[scope]} | {len(c['FETCH_SIZE'])} | {fk:.0f} | {wk:.0f} | {b:.4g} |")
+    print(f"\ncopy calibration (1 GiB): FETCH_SIZE reads {sum(cf) / len(cf):.0f} KiB (factor {f_fac:.3f}), "
+          f"WRITE_SIZE {sum(cw) / len(cw):.0f} KiB (factor {w_fac:.3f})")
+    with open(out_json, "w") as fh:
+        json.dump({"source_sha256": source_hash(), "fetch_factor": f_fac, "write_factor": w_fac,
+                   "kernels": table}, fh, indent=1)
+
+
+def traffic_for(scope):
+    """Scaled HBM bytes per launch of the kernel behind `scope`, or None when
+    no counters were taken for it or its sources changed since."""
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(scope)
+    return k["bytes_per_launch"] if k else None
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, args.traffic_json)
         return
     if args.gpus != 1:
         print("bench.py: the hot path runs on one GPU; --gpus must be 1 (sharding paths over GPUs is not "
@@ -183,8 +266,11 @@ def main():
     units = {"voxel_segment": c_r["voxel_segments"], "local_estimate": c_r["local_estimates"]}
     per = OPS.get(dom)
     roofline = {"bound": "alu", "kernel": dom, "achieved": None, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                "unit": "TOP/s", "frac": None, "traffic": None, "avg_launch_ms": dom_ms,
+                "unit": "TOP/s", "frac": None, "traffic": traffic_for(dom), "avg_launch_ms": dom_ms,
                 "launches_per_step": per_call}
+    if roofline["traffic"] is not None:
+        hbm = roofline["traffic"] / (dom_ms * 1e-3) / 1e9
+        roofline["hbm"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS}
     if per is not None:
         work = {k: units[k] / per_call for k in per}
         ops = sum(per[k] * work[k] for k in per)
