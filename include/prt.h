@@ -56,6 +56,7 @@ enum prt_precision {
 
 #define PRT_MAX_CAMERAS 24
 #define PRT_MAX_ORDER 64
+#define PRT_MAX_DIM 512   /* voxels per grid axis */
 
 /* Scene (Sec. 4.4 and Sec. 6.1): cloud extinction beta_c on the grid (the
    unknowns), constant air extinction, the two single-scattering albedos
@@ -63,7 +64,7 @@ enum prt_precision {
    function, Rayleigh air, and a sun of flux sun_flux with parallel rays from
    (zenith, azimuth) in degrees.  max_order caps the number of scattering
    events of a sampled path (1..PRT_MAX_ORDER).  Validated on every call:
-   finite values, beta_air >= 0, 0 < albedos <= 1, |g| < 1, 0 <= zenith < 90,
+   1 <= nx, ny, nz <= PRT_MAX_DIM (PRT_E_CAPACITY beyond), finite values, beta_air >= 0, 0 < albedos <= 1, |g| < 1, 0 <= zenith < 90,
    sun_flux > 0, voxel_km > 0. */
 typedef struct {
     int32_t nx, ny, nz, max_order;

@@ -163,26 +163,31 @@ __device__ __forceinline__ int project(const DevCams& c, int d, double x, double
 // The step is branchless: the axis of the nearest face is chosen with
 // selects, and each axis carries the number of faces left before the box
 // boundary, so leaving the box needs no index bound checks.  Every
-// iteration either leaves the loop or uses up one face of one axis, so the
-// walk ends after at most (faces left) + 1 pieces for any input, including
-// non-finite directions (whose components are treated as zero).  Face
-// parameters are always measured from p, so a walk that starts part way
-// (t > 0) produces the same pieces as one started at p.
+// iteration uses up one face of one axis and leaves the loop when an axis
+// has none left, so the walk ends after at most (faces left) + 1 pieces for
+// any input, including non-finite directions (whose components are treated
+// as zero).  Face parameters are always measured from p, so a walk that
+// starts part way (t > 0) produces the same pieces as one started at p.
 template <typename Real, typename F>
 __device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real px, Real py, Real pz, int ix, int iy,
                                           int iz, int sx, int sy, int sz, Real ivx, Real ivy, Real ivz, Real t,
                                           Real tmax, uint32_t& pieces, F&& f)
 {
     const Real inf = (Real)INFINITY;
-    Real tnx = sx > 0 ? ((Real)(ix + 1) - px) * ivx : (sx < 0 ? ((Real)ix - px) * ivx : inf);
-    Real tny = sy > 0 ? ((Real)(iy + 1) - py) * ivy : (sy < 0 ? ((Real)iy - py) * ivy : inf);
-    Real tnz = sz > 0 ? ((Real)(iz + 1) - pz) * ivz : (sz < 0 ? ((Real)iz - pz) * ivz : inf);
+    // face parameters, clamped to the start so that no piece is negative
+    Real tnx = fmax(sx > 0 ? ((Real)(ix + 1) - px) * ivx : (sx < 0 ? ((Real)ix - px) * ivx : inf), t);
+    Real tny = fmax(sy > 0 ? ((Real)(iy + 1) - py) * ivy : (sy < 0 ? ((Real)iy - py) * ivy : inf), t);
+    Real tnz = fmax(sz > 0 ? ((Real)(iz + 1) - pz) * ivz : (sz < 0 ? ((Real)iz - pz) * ivz : inf), t);
     const Real dtx = (Real)sx * ivx, dty = (Real)sy * ivy, dtz = (Real)sz * ivz;
-    // faces left before the boundary along each axis
-    int rx = sx > 0 ? nx - 1 - ix : ix;
-    int ry = sy > 0 ? ny - 1 - iy : iy;
-    int rz = sz > 0 ? z1 - 1 - iz : iz - z0;
-    const int faces = rx + ry + rz;
+    // Faces left before the boundary along each axis, packed in 10-bit fields
+    // that start at 512 + faces: a step past the last face of an axis clears
+    // that field's bit 9 (dimensions are at most 512 voxels).
+    const int rx = sx > 0 ? nx - 1 - ix : ix;
+    const int ry = sy > 0 ? ny - 1 - iy : iy;
+    const int rz = sz > 0 ? z1 - 1 - iz : iz - z0;
+    constexpr int kGuard = (1 << 9) | (1 << 19) | (1 << 29);
+    int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
+    const int R0 = R;
     const int dvx = sx, dvy = sy * nx, dvz = sz * nx * ny;
     int v = ix + nx * (iy + ny * (iz - z0));
     for (;;) {
@@ -190,22 +195,21 @@ __device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real p
         const bool go = tn < tmax;
         // the face parameters only grow, so te never decreases along the walk
         const Real te = go ? tn : tmax;
-        if (!f(v, t, fmax(te - t, (Real)0))) break;
+        if (!f(v, t, te - t)) break;
         t = te;
         const bool bx = tnx == tn;
         const bool by = !bx && tny == tn;
         const bool bz = !bx && !by;
-        const int r = bx ? rx : (by ? ry : rz);
-        if (!go || r <= 0) break;
-        rx -= bx ? 1 : 0;
-        ry -= by ? 1 : 0;
-        rz -= bz ? 1 : 0;
+        R -= bx ? 1 : (by ? 1 << 10 : 1 << 20);
         v += bx ? dvx : (by ? dvy : dvz);
         tnx += bx ? dtx : (Real)0;
         tny += by ? dty : (Real)0;
         tnz += bz ? dtz : (Real)0;
+        if (!go || (R & kGuard) != kGuard) break;
     }
-    pieces += (uint32_t)(faces - rx - ry - rz + 1);
+    // every piece (but one stopped by the functor) used up one face count
+    const int used = (R0 & 1023) + ((R0 >> 10) & 1023) + (R0 >> 20) - (R & 1023) - ((R >> 10) & 1023) - (R >> 20);
+    pieces += (uint32_t)used;
     return t;
 }
 

@@ -187,6 +187,8 @@ int check_scene(const prt_scene* s)
     if (s->nx < 1 || s->ny < 1 || s->nz < 1) return fail(PRT_E_INVALID, "grid dims must be >= 1");
     if ((int64_t)s->nx * s->ny * s->nz >= (int64_t)1 << 31)
         return fail(PRT_E_CAPACITY, "grid has more than 2^31 - 1 voxels");
+    if (s->nx > PRT_MAX_DIM || s->ny > PRT_MAX_DIM || s->nz > PRT_MAX_DIM)
+        return fail(PRT_E_CAPACITY, "grid dims must be <= %d", PRT_MAX_DIM);
     if (s->max_order < 1 || s->max_order > PRT_MAX_ORDER)
         return fail(PRT_E_CAPACITY, "max_order %d outside [1, %d]", s->max_order, PRT_MAX_ORDER);
     if (!finite_all({s->voxel_km, s->beta_air, s->albedo_cloud, s->albedo_air, s->g, s->sun_zenith_deg,
