@@ -65,6 +65,17 @@ def _workload(name):
         s = inputs.random_field((40, 40, 24), voxel_km=0.02, lo=0.0, hi=30.0, seed=40, albedo_cloud=0.99,
                                 g=0.85, max_order=12)
         return s, inputs.arc_cameras(s, [-50.0, -20.0, 0.0, 25.0, 55.0], 32, 32), 20_011, 1040
+    if name == "wide96":
+        # 96 x 96 x 12 grid: one 72 KB layer per slab would need 12 slabs, so the
+        # gradient falls back to FP64 atomics on the output
+        s = inputs.random_field((96, 96, 12), voxel_km=0.02, lo=0.0, hi=25.0, seed=96, albedo_cloud=0.99,
+                                g=0.85, max_order=10)
+        return s, inputs.arc_cameras(s, [-40.0, 0.0, 40.0], 24, 24), 6_007, 1096
+    if name == "manycams":
+        # 20 cameras of 48 x 48: the FP32 image partials (184 KB) exceed the LDS,
+        # so render falls back to FP64 atomics on the output images
+        s = inputs.cloud8()
+        return s, inputs.arc_cameras(s, np.linspace(-60.0, 60.0, 20), 48, 48), 10_000, 1001
     raise KeyError(name)
 
 
@@ -135,7 +146,7 @@ def test_sample_fp32_close_to_oracle(env, name):
 # ---------------------------------------------- render / grad / reweight
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "slabs40"])
+@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "slabs40", "wide96", "manycams"])
 def test_render_grad_reweight_match_oracle(env, prec, name):
     torch, P, api = env
     scene, cams, n, seed = _workload(name)
