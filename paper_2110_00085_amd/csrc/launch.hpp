@@ -95,21 +95,26 @@ hipError_t launch_store_meta(hipStream_t st, const uint8_t* B, int64_t n, const 
 // ---- hot path (trace.hip)
 // Where render tallies and reads: FP32 LDS image partials (reduced by a
 // second kernel) and/or the extinction grid cached in LDS, when they fit.
+// With img_tape (the render records the tape and one camera's FP64 image fits
+// the LDS) the render kernel tallies nothing and the images are formed from
+// the tape afterwards, which leaves the LDS to the extinction grid.
 struct RenderPlan {
-    bool img_lds = false, grid_lds = false;
+    bool img_lds = false, grid_lds = false, img_tape = false;
     int n_wg = 1;
     size_t partial_bytes = 0;
 };
-RenderPlan plan_render(int fp64, int64_t nu, int64_t nimg, int64_t n_slots, int64_t first_slot, int n_cu);
+RenderPlan plan_render(int fp64, int64_t nu, const DevCams& c, bool tape, int64_t n_slots, int64_t first_slot,
+                       int n_cu);
 // Per-vertex prefix weights of the render (one lane per path).
 hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a);
 // The persistent render kernel alone (its task counter a.work[0] must be zero,
 // a.pbase filled by launch_render_prefix);
 // with img_lds, launch_render_reduce then adds the partials into the images.
 hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
-                         float* partial);
-hipError_t launch_render_reduce(hipStream_t st, const DevCams& c, const RenderPlan& p, const float* partial,
-                                double* img);
+                         void* partial);
+// Images from the partials (img_lds) or from the tape (img_tape).
+hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
+                                const void* partial, double* img);
 // work[0..n) = 0 (n <= 64): task counters of the persistent kernels.
 hipError_t launch_reset_work(hipStream_t st, unsigned int* work, int n);
 hipError_t launch_render_finalize(hipStream_t st, double* img, const DevCams& c, double scale);

@@ -814,14 +814,6 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     const int64_t npx = (int64_t)dc.n * dc.W * dc.H;
     // batches with scattering paths (the kernels have nothing to do without them)
     const bool work = p->n_slots > p->first_slot;
-    const RenderPlan plan = plan_render(c->fp64, nu, npx, p->n_slots, p->first_slot, c->n_cu);
-    {
-        TimedScope ts(c, K_PREP);
-        // the LDS partials' reduction writes every pixel; otherwise tallies add up on zeros
-        if (!work || !plan.img_lds) HIPCHK(launch_fill(c->stream, images, npx, 0.0));
-        HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
-                                 c->grid_dlt));
-    }
     a.s = make_dev_scene(s);
     a.st = view_of(p);
     a.bc_t = s->beta_cloud;
@@ -845,6 +837,14 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
         p->tape_cams = dc;
         p->tape_scene = a.s;
     }
+    const RenderPlan plan = plan_render(c->fp64, nu, dc, a.tape != nullptr, p->n_slots, p->first_slot, c->n_cu);
+    {
+        TimedScope ts(c, K_PREP);
+        // the reductions write every pixel; otherwise tallies add up on zeros
+        if (!work || !(plan.img_lds || plan.img_tape)) HIPCHK(launch_fill(c->stream, images, npx, 0.0));
+        HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
+                                 c->grid_dlt));
+    }
     if ((rc = ensure_scratch(&c->rpart, &c->rpart_bytes, plan.partial_bytes))) return rc;
     if (work) {
         {
@@ -854,10 +854,10 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
         HIPCHK(launch_reset_work(c->stream, c->work, 1));
         {
             TimedScope ts(c, K_RENDER);
-            HIPCHK(launch_render(c->stream, c->fp64, a, dc, plan, (float*)c->rpart));
+            HIPCHK(launch_render(c->stream, c->fp64, a, dc, plan, c->rpart));
         }
         TimedScope ts(c, K_RENDER_REDUCE);
-        HIPCHK(launch_render_reduce(c->stream, dc, plan, (const float*)c->rpart, images));
+        HIPCHK(launch_render_reduce(c->stream, a, dc, plan, c->rpart, images));
     }
     {
         TimedScope ts(c, K_FINALIZE);

@@ -118,6 +118,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr size_t kLdsBudget = 128 * 1024;       // grids
 constexpr size_t kLdsImageBudget = 152 * 1024;  // image tallies (+ grid if both fit)
 constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs per launch sequence
+constexpr size_t kTapeImageLds = 64 * 1024;     // FP64 image of one camera, images formed from the tape
 
 // Prefix weights, one lane per path: walks the free-flight segments once and
 // stores, for every scatter b <= brender, base_b = P_b / (beta_ref(x_b) +
@@ -174,14 +175,19 @@ hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a)
 // heaviest batches first; per scatter b the task reads base_b and, for every
 // camera of its group, projects x_b, evaluates f_s,t and walks the
 // connection for its transmittance.
-// kGridLds: the total-extinction grid is cached in LDS.  kImgLds: the
-// workgroup tallies its contributions in an FP32 LDS image and writes it to
-// partial[blockIdx.x]; render_reduce_kernel adds the partials in FP64 in
-// workgroup order.  Otherwise every contribution is an FP64 atomic on the
-// output image.  kTape: every contribution is also recorded on the tape.
-template <typename Real, bool kGridLds, bool kImgLds, bool kTape>
+// kGridLds: the total-extinction grid is cached in LDS.  kImg: with
+// kImgLdsF32 the workgroup tallies its contributions in an FP32 LDS image and
+// writes it to partial[blockIdx.x], which render_reduce_kernel adds in FP64
+// in workgroup order; with kImgGlobal every contribution is an FP64 atomic on
+// the output image; with kImgFromTape there is no tally here (the images are
+// formed from the tape afterwards, which leaves the LDS to the grid).
+// kTape: every contribution is recorded on the tape.
+constexpr int kImgGlobal = 0, kImgLdsF32 = 1, kImgFromTape = 2;
+
+template <typename Real, bool kGridLds, int kImg, bool kTape>
 __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cams, float* __restrict__ partial)
 {
+    constexpr bool kImgLds = kImg == kImgLdsF32;
     extern __shared__ unsigned char smem[];
     const DevScene& s = a.s;
     const int nu = s.nx * s.ny * s.nz;
@@ -236,8 +242,8 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                 const Real tc = walk_sum<Real>(s, beta_tot, p1, u, dist, nseg);
                 const double c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
                 if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = make_float2((float)c, __int_as_float(pix));
-                if (kImgLds) atomicAdd(&simg[d * npix + pix], (float)c);
-                else unsafeAtomicAdd(&a.img[(int64_t)d * npix + pix], c);
+                if (kImg == kImgLdsF32) atomicAdd(&simg[d * npix + pix], (float)c);
+                else if (kImg == kImgGlobal) unsafeAtomicAdd(&a.img[(int64_t)d * npix + pix], c);
                 ++nle;
             }
             p0 = p1;
@@ -262,19 +268,61 @@ __global__ void __launch_bounds__(256) render_reduce_kernel(const float* __restr
     img[i] = acc;
 }
 
-template <typename Real, bool kGridLds, bool kImgLds, bool kTape>
+template <typename Real, bool kGridLds, int kImg, bool kTape>
 static hipError_t launch_render_t(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, float* partial)
 {
     const size_t nu = (size_t)a.s.nx * a.s.ny * a.s.nz;
     const size_t nimg = (size_t)c.W * c.H * c.n;
-    const size_t lds = (kGridLds ? nu * sizeof(Real) : 0) + (kImgLds ? nimg * sizeof(float) : 0);
+    const size_t lds = (kGridLds ? nu * sizeof(Real) : 0) + (kImg == kImgLdsF32 ? nimg * sizeof(float) : 0);
     if (lds) {
-        hipError_t e = hipFuncSetAttribute((const void*)render_kernel<Real, kGridLds, kImgLds, kTape>,
+        hipError_t e = hipFuncSetAttribute((const void*)render_kernel<Real, kGridLds, kImg, kTape>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    render_kernel<Real, kGridLds, kImgLds, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, partial);
+    render_kernel<Real, kGridLds, kImg, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, partial);
     return hipGetLastError();
+}
+
+// Images from the tape: workgroup (x, d) adds the contributions c_{b,d} of
+// every scatter of a strided share of the batches into an FP64 LDS image of
+// camera d and writes it to partial[d][x]; tape_image_reduce_kernel adds the
+// kTapeImageGroups partials of each pixel in a fixed order.
+constexpr int kTapeImageGroups = 64;
+
+__global__ void __launch_bounds__(256) tape_image_kernel(TraceArgs a, DevCams cams, double* __restrict__ partial)
+{
+    extern __shared__ unsigned char smem[];
+    double* __restrict__ simg = reinterpret_cast<double*>(smem);
+    const int npix = cams.W * cams.H;
+    const int d = blockIdx.y;
+    for (int i = threadIdx.x; i < npix; i += blockDim.x) simg[i] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, waves = blockDim.x / kWave;
+    const int64_t nb = a.st.n_slots / kWave;
+    for (int64_t bt = a.st.first_slot / kWave + (int64_t)blockIdx.x * waves + wave; bt < nb;
+         bt += (int64_t)gridDim.x * waves) {
+        const int Br = min((int)a.st.B[bt * kWave + lane], a.brender);
+        const float2* __restrict__ T = a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane;
+        for (int b = 1; b <= Br; ++b) {
+            const float2 t = T[(int64_t)(b * cams.n + d) * kWave];
+            const int pix = __float_as_int(t.y);
+            if (pix >= 0) atomicAdd(&simg[pix], (double)t.x);
+        }
+    }
+    __syncthreads();
+    double* __restrict__ out = partial + ((int64_t)d * gridDim.x + blockIdx.x) * npix;
+    for (int i = threadIdx.x; i < npix; i += blockDim.x) out[i] = simg[i];
+}
+
+__global__ void __launch_bounds__(256) tape_image_reduce_kernel(const double* __restrict__ partial, int groups,
+                                                                int npix, int64_t n, double* __restrict__ img)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t d = i / npix, p = i % npix;
+    double acc = 0.0;
+    for (int x = 0; x < groups; ++x) acc += partial[(d * groups + x) * npix + p];
+    img[i] = acc;
 }
 
 // Workgroups for a persistent launch over the batches that hold scattered paths.
@@ -285,10 +333,20 @@ static int persistent_groups(int64_t n_slots, int64_t first_slot, int n_cu, int 
     return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)n_cu * per_cu));
 }
 
-RenderPlan plan_render(int fp64, int64_t nu, int64_t nimg, int64_t n_slots, int64_t first_slot, int n_cu)
+RenderPlan plan_render(int fp64, int64_t nu, const DevCams& c, bool tape, int64_t n_slots, int64_t first_slot,
+                       int n_cu)
 {
     RenderPlan p;
+    const int64_t npix = (int64_t)c.W * c.H, nimg = npix * c.n;
     const int64_t img_bytes = nimg * 4, grid_bytes = nu * (fp64 ? 8 : 4);
+    if (tape && !fp64 && npix * 8 <= (int64_t)kTapeImageLds) {
+        // images from the tape: the LDS holds only the grid
+        p.img_tape = true;
+        p.grid_lds = grid_bytes <= (int64_t)kLdsBudget;
+        p.n_wg = persistent_groups(n_slots, first_slot, n_cu, p.grid_lds ? 1 : 2);
+        p.partial_bytes = (size_t)nimg * kTapeImageGroups * sizeof(double);
+        return p;
+    }
     // FP32 image partials only in FP32 traversal mode (the all-FP64 mode keeps FP64 tallies)
     p.img_lds = !fp64 && img_bytes <= (int64_t)kLdsImageBudget;
     p.grid_lds = grid_bytes + (p.img_lds ? img_bytes : 0) <= (int64_t)kLdsImageBudget &&
@@ -299,34 +357,54 @@ RenderPlan plan_render(int fp64, int64_t nu, int64_t nimg, int64_t n_slots, int6
 }
 
 hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
-                         float* partial)
+                         void* partial)
 {
     if (a.st.n_slots - a.st.first_slot <= 0) return hipSuccess;
     if (fp64) {  // the all-FP64 mode records no FP32 tape
-        if (p.grid_lds) return launch_render_t<double, true, false, false>(st, a, c, p.n_wg, nullptr);
-        return launch_render_t<double, false, false, false>(st, a, c, p.n_wg, nullptr);
+        if (p.grid_lds) return launch_render_t<double, true, kImgGlobal, false>(st, a, c, p.n_wg, nullptr);
+        return launch_render_t<double, false, kImgGlobal, false>(st, a, c, p.n_wg, nullptr);
     }
+    float* fpart = (float*)partial;
     const bool tape = a.tape != nullptr;
+    if (p.img_tape) {
+        if (p.grid_lds) return launch_render_t<float, true, kImgFromTape, true>(st, a, c, p.n_wg, nullptr);
+        return launch_render_t<float, false, kImgFromTape, true>(st, a, c, p.n_wg, nullptr);
+    }
     if (p.img_lds) {
         if (p.grid_lds)
-            return tape ? launch_render_t<float, true, true, true>(st, a, c, p.n_wg, partial)
-                        : launch_render_t<float, true, true, false>(st, a, c, p.n_wg, partial);
-        return tape ? launch_render_t<float, false, true, true>(st, a, c, p.n_wg, partial)
-                    : launch_render_t<float, false, true, false>(st, a, c, p.n_wg, partial);
+            return tape ? launch_render_t<float, true, kImgLdsF32, true>(st, a, c, p.n_wg, fpart)
+                        : launch_render_t<float, true, kImgLdsF32, false>(st, a, c, p.n_wg, fpart);
+        return tape ? launch_render_t<float, false, kImgLdsF32, true>(st, a, c, p.n_wg, fpart)
+                    : launch_render_t<float, false, kImgLdsF32, false>(st, a, c, p.n_wg, fpart);
     }
     if (p.grid_lds)
-        return tape ? launch_render_t<float, true, false, true>(st, a, c, p.n_wg, nullptr)
-                    : launch_render_t<float, true, false, false>(st, a, c, p.n_wg, nullptr);
-    return tape ? launch_render_t<float, false, false, true>(st, a, c, p.n_wg, nullptr)
-                : launch_render_t<float, false, false, false>(st, a, c, p.n_wg, nullptr);
+        return tape ? launch_render_t<float, true, kImgGlobal, true>(st, a, c, p.n_wg, nullptr)
+                    : launch_render_t<float, true, kImgGlobal, false>(st, a, c, p.n_wg, nullptr);
+    return tape ? launch_render_t<float, false, kImgGlobal, true>(st, a, c, p.n_wg, nullptr)
+                : launch_render_t<float, false, kImgGlobal, false>(st, a, c, p.n_wg, nullptr);
 }
 
-hipError_t launch_render_reduce(hipStream_t st, const DevCams& c, const RenderPlan& p, const float* partial,
-                                double* img)
+hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
+                                const void* partial, double* img)
 {
+    const int64_t npix = (int64_t)c.W * c.H, nimg = npix * c.n;
+    const unsigned blocks = (unsigned)((nimg + 255) / 256);
+    if (p.img_tape) {
+        const size_t lds = (size_t)npix * sizeof(double);
+        if (lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute((const void*)tape_image_kernel,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        tape_image_kernel<<<dim3(kTapeImageGroups, c.n), dim3(256), lds, st>>>(a, c, (double*)partial);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        tape_image_reduce_kernel<<<dim3(blocks), dim3(256), 0, st>>>((const double*)partial, kTapeImageGroups,
+                                                                      (int)npix, nimg, img);
+        return hipGetLastError();
+    }
     if (!p.img_lds) return hipSuccess;
-    const int64_t nimg = (int64_t)c.W * c.H * c.n;
-    render_reduce_kernel<<<dim3((unsigned)((nimg + 255) / 256)), dim3(256), 0, st>>>(partial, p.n_wg, nimg, img);
+    render_reduce_kernel<<<dim3(blocks), dim3(256), 0, st>>>((const float*)partial, p.n_wg, nimg, img);
     return hipGetLastError();
 }
 
