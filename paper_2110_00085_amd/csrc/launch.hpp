@@ -106,7 +106,7 @@ struct RenderPlan {
 RenderPlan plan_render(int fp64, int64_t nu, const DevCams& c, bool tape, int64_t n_slots, int64_t first_slot,
                        int n_cu);
 // Per-vertex prefix weights of the render (one lane per path).
-hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a);
+hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, int n_cu);
 // The persistent render kernel alone (its task counter a.work[0] must be zero,
 // a.pbase filled by launch_render_prefix);
 // with img_lds, launch_render_reduce then adds the partials into the images.
@@ -140,7 +140,8 @@ hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCa
                        void* partial);
 hipError_t launch_grad_reduce(hipStream_t st, const GradPlan& p, int nx, int ny, int nz, int slab,
                               const void* partial, double* grad);
-hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int64_t* n_blocks);
+// Per-workgroup sums of r and r^2 into a.partial[2*wg..]; *n_blocks workgroups.
+hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int n_cu, int64_t* n_blocks);
 // flag = 1 if a[i] == b[i] bitwise for all i < n, else 0.
 hipError_t launch_equal_flag(hipStream_t st, const float* a, const float* b, int64_t n, int* flag);
 

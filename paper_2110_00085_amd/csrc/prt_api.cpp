@@ -849,7 +849,7 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     if (work) {
         {
             TimedScope ts(c, K_RENDER_PREFIX);
-            HIPCHK(launch_render_prefix(c->stream, c->fp64, a));
+            HIPCHK(launch_render_prefix(c->stream, c->fp64, a, c->n_cu));
         }
         HIPCHK(launch_reset_work(c->stream, c->work, 1));
         {
@@ -962,7 +962,7 @@ int prt_reweight(prt_ctx c, const prt_scene* s, prt_paths p, double* mean_r, dou
     int64_t nb = 0;
     {
         TimedScope ts(c, K_REWEIGHT);
-        HIPCHK(launch_reweight(c->stream, c->fp64, a, &nb));
+        HIPCHK(launch_reweight(c->stream, c->fp64, a, c->n_cu, &nb));
         HIPCHK(launch_sum_pairs(c->stream, c->part, nb, c->out2));
     }
     double h[2];

@@ -120,55 +120,90 @@ constexpr size_t kLdsImageBudget = 152 * 1024;  // image tallies (+ grid if both
 constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs per launch sequence
 constexpr size_t kTapeImageLds = 64 * 1024;     // FP64 image of one camera, images formed from the tape
 
-// Prefix weights, one lane per path: walks the free-flight segments once and
-// stores, for every scatter b <= brender, base_b = P_b / (beta_ref(x_b) +
-// beta_air) with P_b = w0 prod_{k<b} exp(-(tau_t - tau_ref)(segment k))
-// prod_{1<=k<b} albedo_ref f_s,t / f_s,ref (x_k): every local estimate at
-// x_b is base_b f_s,t(x_b, mu_bd) exp(-tau_t(connection)) / r^2.
-template <typename Real>
-__global__ void __launch_bounds__(256) render_prefix_kernel(TraceArgs a)
+// Loads the field beta_t - beta_ref into LDS (kGridLds) for a persistent
+// workgroup and returns it (or the field in global memory).
+template <typename Real, bool kGridLds>
+__device__ __forceinline__ const Real* delta_grid(const TraceArgs& a, unsigned char* smem)
 {
-    const int64_t slot = a.st.first_slot / kWave * kWave + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= a.st.n_slots) return;
-    const int Br = min((int)a.st.B[slot], a.brender);
-    if (Br <= 0) return;
+    const Real* __restrict__ g = (const Real*)a.grid_dlt;
+    if (!kGridLds) return g;
+    Real* sg = reinterpret_cast<Real*>(smem);
+    const int nu = a.s.nx * a.s.ny * a.s.nz;
+    for (int i = threadIdx.x; i < nu; i += blockDim.x) sg[i] = g[i];
+    __syncthreads();
+    return sg;
+}
+
+// Prefix weights, one lane per path (persistent workgroups, the field
+// beta_t - beta_ref cached in LDS when it fits): walks the free-flight
+// segments once and stores, for every scatter b <= brender,
+// base_b = P_b / (beta_ref(x_b) + beta_air) with P_b = w0 prod_{k<b}
+// exp(-(tau_t - tau_ref)(segment k)) prod_{1<=k<b} albedo_ref f_s,t / f_s,ref (x_k):
+// every local estimate at x_b is base_b f_s,t(x_b, mu_bd) exp(-tau_t(connection)) / r^2.
+template <typename Real, bool kGridLds>
+__global__ void __launch_bounds__(kBlock) render_prefix_kernel(TraceArgs a)
+{
+    extern __shared__ unsigned char smem[];
+    const Real* gd = delta_grid<Real, kGridLds>(a, smem);
     const DevScene& s = a.s;
     const int nu = s.nx * s.ny * s.nz;
-    const Real* __restrict__ gd = (const Real*)a.grid_dlt;
-    const int64_t bt = slot / kWave, lane = slot % kWave;
-    const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
-    double* __restrict__ out = a.pbase + (a.st.batch_off[bt] - a.tape_base) + lane;
     uint64_t nseg = 0;
-    Vtx p0 = load_vtx(V, 0);
-    double P = s.w0;
-    double wprev[3] = {0.0, 0.0, 0.0};
-    for (int b = 1; b <= Br; ++b) {
-        const Vtx p1 = load_vtx(V, b);
-        double w[3];
-        const double L = seg_dir(p0, p1, w);
-        // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
-        const Real dt = walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, nseg);
-        P *= exp(-(double)dt * s.vk);
-        if (b >= 2) {
-            const int v = clamp_vox(p0.v, nu);
-            P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
-                              wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
+    for (int64_t slot = a.st.first_slot / kWave * kWave + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+         slot < a.st.n_slots; slot += (int64_t)gridDim.x * blockDim.x) {
+        const int Br = min((int)a.st.B[slot], a.brender);
+        if (Br <= 0) continue;
+        const int64_t bt = slot / kWave, lane = slot % kWave;
+        const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+        double* __restrict__ out = a.pbase + (a.st.batch_off[bt] - a.tape_base) + lane;
+        Vtx p0 = load_vtx(V, 0);
+        double P = s.w0;
+        double wprev[3] = {0.0, 0.0, 0.0};
+        for (int b = 1; b <= Br; ++b) {
+            const Vtx p1 = load_vtx(V, b);
+            double w[3];
+            const double L = seg_dir(p0, p1, w);
+            // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
+            const Real dt = walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, nseg);
+            P *= exp(-(double)dt * s.vk);
+            if (b >= 2) {
+                const int v = clamp_vox(p0.v, nu);
+                P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
+                                  wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
+            }
+            out[(int64_t)b * kWave] = P / ((double)a.st.beta_ref[clamp_vox(p1.v, nu)] + s.beta_air);
+            wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
+            p0 = p1;
         }
-        out[(int64_t)b * kWave] = P / ((double)a.st.beta_ref[clamp_vox(p1.v, nu)] + s.beta_air);
-        wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
-        p0 = p1;
     }
     flush_counts(a.counters, nseg, 0, 0);
 }
 
-hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a)
+// Persistent launch with the delta grid in LDS when it fits.
+template <typename K>
+static hipError_t launch_delta_kernel(hipStream_t st, K k, bool lds_grid, size_t grid_bytes, int n_wg,
+                                      const TraceArgs& a)
+{
+    const size_t lds = lds_grid ? grid_bytes : 0;
+    if (lds) {
+        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k<<<dim3(n_wg), dim3(kBlock), lds, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, int n_cu)
 {
     const int64_t slots = a.st.n_slots - a.st.first_slot / kWave * kWave;
     if (slots <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((slots + 255) / 256)), block(256);
-    if (fp64) render_prefix_kernel<double><<<grid, block, 0, st>>>(a);
-    else render_prefix_kernel<float><<<grid, block, 0, st>>>(a);
-    return hipGetLastError();
+    const size_t grid_bytes = (size_t)a.s.nx * a.s.ny * a.s.nz * (fp64 ? 8 : 4);
+    const bool lds = grid_bytes <= kLdsBudget;
+    const int n_wg = (int)std::max<int64_t>(1, std::min<int64_t>((slots + kBlock - 1) / kBlock, n_cu));
+    if (fp64)
+        return lds ? launch_delta_kernel(st, render_prefix_kernel<double, true>, true, grid_bytes, n_wg, a)
+                   : launch_delta_kernel(st, render_prefix_kernel<double, false>, false, grid_bytes, n_wg, a);
+    return lds ? launch_delta_kernel(st, render_prefix_kernel<float, true>, true, grid_bytes, n_wg, a)
+               : launch_delta_kernel(st, render_prefix_kernel<float, false>, false, grid_bytes, n_wg, a);
 }
 
 // Local estimates from the stored paths.  Tasks are (batch, camera group),
@@ -898,74 +933,85 @@ hipError_t launch_equal_flag(hipStream_t st, const float* x, const float* y, int
 // log r = log mu(x|beta_t) - log mu(x|beta_ref) over the whole stored path:
 // every segment's optical-depth difference (the exit segment included), the
 // extinction ratio at every scatter, and the direction-pdf ratio
-// f_p = f_s / beta_s at every scatter that has a successor vertex.  Per-block
-// sums of r and r^2 go to partial[2*block].
-template <typename Real>
-__global__ void __launch_bounds__(256) reweight_kernel(TraceArgs a)
+// f_p = f_s / beta_s at every scatter that has a successor vertex.  One lane
+// per path in persistent workgroups (the field beta_t - beta_ref cached in
+// LDS when it fits); per-workgroup sums of r and r^2 go to partial[2*wg].
+template <typename Real, bool kGridLds>
+__global__ void __launch_bounds__(kBlock) reweight_kernel(TraceArgs a)
 {
-    __shared__ double red[2][256];
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double r = 0.0;
-    if (slot < a.st.n_slots) {
+    extern __shared__ unsigned char smem[];
+    __shared__ double red[2][kWavesPerBlock];
+    const Real* gd = delta_grid<Real, kGridLds>(a, smem);
+    const DevScene& s = a.s;
+    const int nu = s.nx * s.ny * s.nz;
+    double rs = 0.0, r2s = 0.0;
+    uint64_t cnt = 0;
+    for (int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < a.st.n_slots;
+         slot += (int64_t)gridDim.x * blockDim.x) {
         const int nv = (int)a.st.nv[slot];
         const int Bn = (int)a.st.B[slot];
-        if (nv > 0) {
-            const DevScene& s = a.s;
-            const Real* __restrict__ gd = (const Real*)a.grid_dlt;
-            const float4* __restrict__ V = a.st.vtx + a.st.batch_off[slot / kWave] + (slot % kWave);
-            const int nu = s.nx * s.ny * s.nz;
-            uint64_t cnt = 0;
-            double lr = 0.0, ratio = 1.0;  // log r = lr + log(ratio)
-            Vtx p0 = load_vtx(V, 0);
-            double wprev[3] = {0.0, 0.0, 0.0};
-            for (int k = 0; k + 1 < nv; ++k) {
-                const Vtx p1 = load_vtx(V, k + 1);
-                double w[3];
-                const double L = seg_dir(p0, p1, w);
-                lr -= (double)walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, cnt) * s.vk;
-                if (k >= 1) {
-                    const int v = clamp_vox(p0.v, nu);
-                    const double bct = (double)a.bc_t[v], bcr = (double)a.st.beta_ref[v];
-                    const double mu = wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2];
-                    const double hg = phase_hg(s, mu), ra = phase_rayleigh(mu);
-                    const double bst = s.w_c * bct + s.w_a * s.beta_air, bsr = s.w_c * bcr + s.w_a * s.beta_air;
-                    ratio *= (fs_mix(s, bct, hg, ra) * bsr) / (fs_mix(s, bcr, hg, ra) * bst);
-                }
-                wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
-                p0 = p1;
+        if (nv <= 0) continue;
+        const float4* __restrict__ V = a.st.vtx + a.st.batch_off[slot / kWave] + (slot % kWave);
+        double lr = 0.0, ratio = 1.0;  // log r = lr + log(ratio)
+        Vtx p0 = load_vtx(V, 0);
+        double wprev[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k + 1 < nv; ++k) {
+            const Vtx p1 = load_vtx(V, k + 1);
+            double w[3];
+            const double L = seg_dir(p0, p1, w);
+            lr -= (double)walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, cnt) * s.vk;
+            if (k >= 1) {
+                const int v = clamp_vox(p0.v, nu);
+                const double bct = (double)a.bc_t[v], bcr = (double)a.st.beta_ref[v];
+                const double mu = wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2];
+                const double hg = phase_hg(s, mu), ra = phase_rayleigh(mu);
+                const double bst = s.w_c * bct + s.w_a * s.beta_air, bsr = s.w_c * bcr + s.w_a * s.beta_air;
+                ratio *= (fs_mix(s, bct, hg, ra) * bsr) / (fs_mix(s, bcr, hg, ra) * bst);
             }
-            for (int k = 1; k <= Bn; ++k) {
-                const int v = clamp_vox(vox_of(V[(int64_t)k * kWave]), nu);
-                ratio *= ((double)a.bc_t[v] + s.beta_air) / ((double)a.st.beta_ref[v] + s.beta_air);
-            }
-            r = exp(lr) * ratio;
+            wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
+            p0 = p1;
         }
+        for (int k = 1; k <= Bn; ++k) {
+            const int v = clamp_vox(vox_of(V[(int64_t)k * kWave]), nu);
+            ratio *= ((double)a.bc_t[v] + s.beta_air) / ((double)a.st.beta_ref[v] + s.beta_air);
+        }
+        const double r = exp(lr) * ratio;
+        rs += r;
+        r2s += r * r;
     }
-    red[0][threadIdx.x] = r;
-    red[1][threadIdx.x] = r * r;
+    // workgroup sums in a fixed order: within each wavefront, then over wavefronts
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        rs += __shfl_down(rs, o);
+        r2s += __shfl_down(r2s, o);
+    }
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    if (lane == 0) {
+        red[0][wave] = rs;
+        red[1][wave] = r2s;
+    }
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + o];
-            red[1][threadIdx.x] += red[1][threadIdx.x + o];
-        }
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        a.partial[2 * blockIdx.x] = red[0][0];
-        a.partial[2 * blockIdx.x + 1] = red[1][0];
+        double t0 = 0.0, t1 = 0.0;
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            t0 += red[0][w];
+            t1 += red[1][w];
+        }
+        a.partial[2 * blockIdx.x] = t0;
+        a.partial[2 * blockIdx.x + 1] = t1;
     }
 }
 
-hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int64_t* n_blocks)
+hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int n_cu, int64_t* n_blocks)
 {
-    const int64_t blocks = (a.st.n_slots + 255) / 256;
-    *n_blocks = blocks;
+    const size_t grid_bytes = (size_t)a.s.nx * a.s.ny * a.s.nz * (fp64 ? 8 : 4);
+    const bool lds = grid_bytes <= kLdsBudget;
+    const int n_wg = (int)std::max<int64_t>(1, std::min<int64_t>((a.st.n_slots + kBlock - 1) / kBlock, n_cu));
+    *n_blocks = n_wg;
     if (fp64)
-        reweight_kernel<double><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
-    else
-        reweight_kernel<float><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
-    return hipGetLastError();
+        return lds ? launch_delta_kernel(st, reweight_kernel<double, true>, true, grid_bytes, n_wg, a)
+                   : launch_delta_kernel(st, reweight_kernel<double, false>, false, grid_bytes, n_wg, a);
+    return lds ? launch_delta_kernel(st, reweight_kernel<float, true>, true, grid_bytes, n_wg, a)
+               : launch_delta_kernel(st, reweight_kernel<float, false>, false, grid_bytes, n_wg, a);
 }
 
 }  // namespace prt
