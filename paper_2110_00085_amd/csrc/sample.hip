@@ -115,16 +115,17 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
         const Real tend = dda_walk<Real>(
             s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy, iz, (Real)w[0], (Real)w[1], (Real)w[2],
             (Real)INFINITY, [&](int vv, Real t0, Real l) {
-                const Real bt = gt[vv];
-                const Real dt = bt * l;  // zero for an empty voxel or a zero-length piece
+                const Real dt = gt[vv] * l;  // zero for an empty voxel or a zero-length piece
                 if (taur < acc + dt) {
                     hit = vv;
-                    thit = t0 + (taur - acc) / bt;
+                    thit = t0;
                     return false;
                 }
                 acc += dt;
                 return true;
             });
+        // the division that places the scatter inside its voxel stays out of the loop
+        if (hit >= 0) thit += (taur - acc) / gt[hit];
         bool done;
         if (hit < 0) {
             const double te = (double)tend;

@@ -324,7 +324,7 @@ static hipError_t launch_render_t(hipStream_t st, const TraceArgs& a, const DevC
 // kTapeImageGroups partials of each pixel in a fixed order.
 constexpr int kTapeImageGroups = 64;
 
-__global__ void __launch_bounds__(256) tape_image_kernel(TraceArgs a, DevCams cams, double* __restrict__ partial)
+__global__ void __launch_bounds__(kBlock) tape_image_kernel(TraceArgs a, DevCams cams, double* __restrict__ partial)
 {
     extern __shared__ unsigned char smem[];
     double* __restrict__ simg = reinterpret_cast<double*>(smem);
@@ -431,7 +431,7 @@ hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCam
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
-        tape_image_kernel<<<dim3(kTapeImageGroups, c.n), dim3(256), lds, st>>>(a, c, (double*)partial);
+        tape_image_kernel<<<dim3(kTapeImageGroups, c.n), dim3(kBlock), lds, st>>>(a, c, (double*)partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         tape_image_reduce_kernel<<<dim3(blocks), dim3(256), 0, st>>>((const double*)partial, kTapeImageGroups,
