@@ -73,7 +73,8 @@ def _workload(name):
         return s, inputs.arc_cameras(s, [-40.0, 0.0, 40.0], 24, 24), 6_007, 1096
     if name == "manycams":
         # 20 cameras of 48 x 48: the FP32 image partials (184 KB) exceed the LDS,
-        # so render falls back to FP64 atomics on the output images
+        # so renders of fewer orders (no tape) fall back to FP64 atomics on the
+        # output images; the all-orders render forms them from the tape
         s = inputs.cloud8()
         return s, inputs.arc_cameras(s, np.linspace(-60.0, 60.0, 20), 48, 48), 10_000, 1001
     raise KeyError(name)
