@@ -35,6 +35,15 @@ struct SampleArgs {
     unsigned int* next;    // path-id counter of the persistent sampler (zero at launch)
 };
 
+// Task counters of the persistent kernels.  One atomic counter serialises
+// every wavefront's task requests on one address; a launch therefore spreads
+// its tasks over kTaskCounters counters on separate 128-byte lines, and a
+// context holds kWorkWords words of them (render/grad counters at word 0 and
+// 1 of each line, the sampler's id counter at word 2 of the first).
+constexpr int kTaskCounters = 8;
+constexpr int kTaskStride = 32;
+constexpr int kWorkWords = kTaskCounters * kTaskStride;
+
 struct TraceArgs {
     DevScene s;
     StoreView st;
@@ -64,9 +73,12 @@ struct TraceArgs {
     // w_c f_HG / f_s,t of the scatter at x_b, 0).
     float* wtape;
     float4* vaux;
-    // Dynamic schedule: wavefronts take tasks from *work (reset to 0 before the
-    // launch); task t covers batch n_batches-1-t/groups (heaviest first, the
-    // batches being sorted by size) and camera group t%groups.
+    // Dynamic schedule: wavefront w takes tasks from the counter
+    // work[(w % kTaskCounters) * kTaskStride] (reset to 0 before the launch),
+    // which hands out tasks c, c + kTaskCounters, c + 2 kTaskCounters, ... for
+    // c = w % kTaskCounters; task t covers batch n_batches-1-t/groups
+    // (heaviest first, the batches being sorted by size) and camera group
+    // t%groups.
     unsigned int* work;
     int groups;
 };
@@ -115,7 +127,8 @@ hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const Dev
 // Images from the partials (img_lds) or from the tape (img_tape).
 hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
                                 const void* partial, double* img);
-// work[0..n) = 0 (n <= 64): task counters of the persistent kernels.
+// work[c * kTaskStride + k] = 0 for c < kTaskCounters, k < n (n <= 8): the
+// first n counters of every line of a task-counter set.
 hipError_t launch_reset_work(hipStream_t st, unsigned int* work, int n);
 hipError_t launch_render_finalize(hipStream_t st, double* img, const DevCams& c, double scale);
 hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho, const DevCams& c, double scale);

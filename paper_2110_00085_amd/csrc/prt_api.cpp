@@ -85,7 +85,7 @@ struct prt_ctx_s {
     double* out2 = nullptr;     // two doubles of reduction output
     unsigned long long* counters = nullptr;  // 4
     int* flag = nullptr;        // device flag: the tape matches beta_t
-    unsigned int* work = nullptr;  // task counters of the persistent kernels [4]: render/grad 0-1, sampler 2
+    unsigned int* work = nullptr;  // task counters of the persistent kernels [kWorkWords]
     uint64_t paths_done = 0;
     bool timing = false;
     std::vector<Timed> pending;
@@ -560,7 +560,7 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
     if (hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&c->out2, 2 * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&c->flag, sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&c->work, 4 * sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void**)&c->work, kWorkWords * sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void**)&c->meta, 3 * sizeof(int64_t)) != hipSuccess) {
         (void)hipFree(c->work);
         (void)hipFree(c->flag);

@@ -45,8 +45,9 @@ __device__ __forceinline__ float4 vrec(double x, double y, double z, int v)
 }
 
 // Persistent sampler with path regeneration: a lane whose path has ended
-// takes the next path id from a device counter (one atomic per wavefront),
-// so wavefronts do not wait for their longest path.  Each path is sampled as
+// takes the next path id from its wavefront's pool of claimed ids, which is
+// refilled 64 ids at a time from a device counter, so wavefronts do not wait
+// for their longest path.  Each path is sampled as
 // follows.  Entry point uniform over the projected box area; free flights by
 // the DDA until the optical depth passes tau = -ln u; at a scatter the
 // particle type is drawn with probability beta_s^(j)/beta_s and a direction
@@ -69,42 +70,53 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
     double u[4];
     int ix = 0, iy = 0, iz = 0, b = 0, nv = 0, v0 = 0;
     bool active = false, exhausted = false;
+    // Ids claimed by this wavefront and not yet started: [pool, pool_end).
+    // Claiming 64 at a time keeps the shared counter's atomics rare.
+    int64_t pool = 0, pool_end = 0;
     for (;;) {
-        if (!exhausted) {
-            const uint64_t need = __ballot(!active);
-            if (need) {
-                const int leader = __ffsll((unsigned long long)need) - 1;
+        uint64_t need = __ballot(!active);
+        for (int round = 0; round < 2 && need && !exhausted; ++round) {
+            if (pool == pool_end) {
                 unsigned int base = 0;
-                if (lane == leader) base = atomicAdd(a.next, (unsigned int)__popcll(need));
-                base = __shfl(base, leader);
-                if ((int64_t)base + __popcll(need) >= a.n) exhausted = true;
-                const int64_t nid = (int64_t)base + __popcll(need & below);
-                if (!active && nid < a.n) {
-                    // start path nid at the source
-                    id = nid;
-                    out = a.tmp + id * stride;
-                    uniforms4(a.seed, (uint64_t)id, 0u, u);
-                    const double A = s.a_top + s.a_x + s.a_y;
-                    if (u[0] * A < s.a_top) {
-                        x = u[1] * s.nx; y = u[2] * s.ny; z = (double)s.nz;
-                    } else if (u[0] * A < s.a_top + s.a_x) {
-                        x = s.x_face; y = u[1] * s.ny; z = u[2] * s.nz;
-                    } else {
-                        x = u[1] * s.nx; y = s.y_face; z = u[2] * s.nz;
-                    }
-                    ix = min(max((int)floor(x), 0), s.nx - 1);
-                    iy = min(max((int)floor(y), 0), s.ny - 1);
-                    iz = min(max((int)floor(z), 0), s.nz - 1);
-                    nv = 0;
-                    v0 = ix + s.nx * (iy + s.ny * iz);
-                    out[nv++] = vrec(x, y, z, v0);
-                    w[0] = s.sun[0]; w[1] = s.sun[1]; w[2] = s.sun[2];
-                    // optical depth target in units of (1/km * grid length)
-                    tau = -log(u[3]) / s.vk;
-                    b = 0;
-                    active = true;
+                if (lane == 0) base = atomicAdd(a.next, (unsigned int)kWave);
+                base = __shfl(base, 0);
+                if ((int64_t)base >= a.n) {
+                    exhausted = true;
+                    break;
                 }
+                pool = base;
+                pool_end = min((int64_t)base + kWave, a.n);
             }
+            const int64_t take = min((int64_t)__popcll(need), pool_end - pool);
+            const int64_t rank = __popcll(need & below);
+            const int64_t nid = pool + rank;
+            pool += take;
+            if (!active && rank < take) {
+                // start path nid at the source
+                id = nid;
+                out = a.tmp + id * stride;
+                uniforms4(a.seed, (uint64_t)id, 0u, u);
+                const double A = s.a_top + s.a_x + s.a_y;
+                if (u[0] * A < s.a_top) {
+                    x = u[1] * s.nx; y = u[2] * s.ny; z = (double)s.nz;
+                } else if (u[0] * A < s.a_top + s.a_x) {
+                    x = s.x_face; y = u[1] * s.ny; z = u[2] * s.nz;
+                } else {
+                    x = u[1] * s.nx; y = s.y_face; z = u[2] * s.nz;
+                }
+                ix = min(max((int)floor(x), 0), s.nx - 1);
+                iy = min(max((int)floor(y), 0), s.ny - 1);
+                iz = min(max((int)floor(z), 0), s.nz - 1);
+                nv = 0;
+                v0 = ix + s.nx * (iy + s.ny * iz);
+                out[nv++] = vrec(x, y, z, v0);
+                w[0] = s.sun[0]; w[1] = s.sun[1]; w[2] = s.sun[2];
+                // optical depth target in units of (1/km * grid length)
+                tau = -log(u[3]) / s.vk;
+                b = 0;
+                active = true;
+            }
+            need = __ballot(!active);
         }
         if (!__any(active)) break;
         if (!active) continue;

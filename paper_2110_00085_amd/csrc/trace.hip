@@ -86,12 +86,18 @@ __device__ __forceinline__ double vertex_ratio(const DevScene& s, double bct, do
     return (bsr / btr) * (fst / fsr);
 }
 
-// Next task for this wavefront (lane 0 takes it from the counter).
-__device__ __forceinline__ unsigned int next_task(unsigned int* work)
+// Counter of this wavefront in a task-counter set.
+__device__ __forceinline__ unsigned int task_counter()
+{
+    return (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) % kTaskCounters;
+}
+
+// Next task for this wavefront from counter c (lane 0 takes it).
+__device__ __forceinline__ unsigned int next_task(unsigned int* work, unsigned int c)
 {
     unsigned int t = 0;
-    if (threadIdx.x % kWave == 0) t = atomicAdd(work, 1u);
-    return __shfl(t, 0);
+    if (threadIdx.x % kWave == 0) t = atomicAdd(work + c * kTaskStride, 1u);
+    return __shfl(t, 0) * kTaskCounters + c;
 }
 
 __device__ __forceinline__ void flush_counts(unsigned long long* c, uint64_t seg, uint64_t le, uint64_t ovh)
@@ -107,7 +113,7 @@ __device__ __forceinline__ void flush_counts(unsigned long long* c, uint64_t seg
 
 __global__ void reset_u32_kernel(unsigned int* p, int n)
 {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+    if ((int)threadIdx.x < kTaskCounters * n) p[(threadIdx.x / n) * kTaskStride + threadIdx.x % n] = 0u;
 }
 
 // Persistent launch: each workgroup of kBlock threads sets up its LDS (image
@@ -243,7 +249,8 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
     const int G = a.groups, cpg = (cams.n + G - 1) / G;
     const unsigned int n_tasks = (unsigned int)(nb - a.st.first_slot / kWave) * (unsigned int)G;
     uint64_t nseg = 0, nle = 0;
-    for (unsigned int task = next_task(a.work); task < n_tasks; task = next_task(a.work)) {
+    const unsigned int tc = task_counter();
+    for (unsigned int task = next_task(a.work, tc); task < n_tasks; task = next_task(a.work, tc)) {
         const int64_t bt = nb - 1 - (int64_t)(task / G);
         const int g = (int)(task % G);
         const int d_lo = g * cpg, d_hi = min(cams.n, d_lo + cpg);
@@ -659,7 +666,8 @@ __global__ void __launch_bounds__(kBlock) grad_walk_kernel(TraceArgs a, DevCams 
     const int G = a.groups, K = G + 1, cpg = (cams.n + G - 1) / G;
     const unsigned int n_tasks = (unsigned int)(nb - a.st.first_slot / kWave) * (unsigned int)K;
     uint64_t nseg = 0;
-    for (unsigned int task = next_task(a.work); task < n_tasks; task = next_task(a.work)) {
+    const unsigned int tc = task_counter();
+    for (unsigned int task = next_task(a.work, tc); task < n_tasks; task = next_task(a.work, tc)) {
         const int64_t bt = nb - 1 - (int64_t)(task / K);
         const int kind = (int)(task % K);
         const int64_t slot = bt * kWave + lane;
@@ -736,7 +744,8 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
     const bool count = z0 == 0;
     uint64_t nseg = 0, novh = 0;
     double R[kMaxOrder + 1];
-    for (unsigned int task = next_task(a.work); task < n_tasks; task = next_task(a.work)) {
+    const unsigned int tc = task_counter();
+    for (unsigned int task = next_task(a.work, tc); task < n_tasks; task = next_task(a.work, tc)) {
         const int64_t bt = nb - 1 - (int64_t)(task / G);
         const int g = (int)(task % G);
         const int d_lo = g * cpg, d_hi = min(cams.n, d_lo + cpg);
