@@ -225,6 +225,10 @@ int prt_counters(prt_ctx ctx, prt_counters_t* out, int reset);
    prt_kernel_name), total milliseconds and launch counts since the last
    reset.  Returns the number of kernel ids. */
 int prt_enable_timing(prt_ctx ctx, int enable);
+/* As prt_enable_timing, for the kernel ids whose bit is set in kernel_mask
+   only (0 stops recording): each event pair adds a little to the stream, so a
+   timed run can record just the kernel it reports. */
+int prt_enable_timing_mask(prt_ctx ctx, uint32_t kernel_mask);
 int prt_kernel_times(prt_ctx ctx, double* total_ms, int64_t* launches, int n, int reset);
 const char* prt_kernel_name(int id);
 

@@ -29,7 +29,8 @@ struct DevScene {
 
 // Cameras with positions converted to grid units.
 struct DevCams {
-    int n, W, H, pad;
+    int n, W, H;
+    int outside;  // every camera lies outside the grid box: connections end at the box boundary
     double pos[kMaxCams][3];
     double rot[kMaxCams][9];
     double f[kMaxCams];
@@ -168,7 +169,7 @@ __device__ __forceinline__ int project(const DevCams& c, int d, double x, double
 // any input, including non-finite directions (whose components are treated
 // as zero).  Face parameters are always measured from p, so a walk that
 // starts part way (t > 0) produces the same pieces as one started at p.
-template <typename Real, typename F>
+template <typename Real, bool kBounded = true, typename F>
 __device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real px, Real py, Real pz, int ix, int iy,
                                           int iz, int sx, int sy, int sz, Real ivx, Real ivy, Real ivz, Real t,
                                           Real tmax, uint32_t& pieces, F&& f)
@@ -192,9 +193,9 @@ __device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real p
     int v = ix + nx * (iy + ny * (iz - z0));
     for (;;) {
         const Real tn = fmin(tnx, fmin(tny, tnz));
-        const bool go = tn < tmax;
+        const bool go = !kBounded || tn < tmax;
         // the face parameters only grow, so te never decreases along the walk
-        const Real te = go ? tn : tmax;
+        const Real te = kBounded ? (go ? tn : tmax) : tn;
         if (!f(v, t, te - t)) break;
         t = te;
         const bool bx = tnx == tn;
@@ -205,7 +206,7 @@ __device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real p
         tnx += bx ? dtx : (Real)0;
         tny += by ? dty : (Real)0;
         tnz += bz ? dtz : (Real)0;
-        if (!go || (R & kGuard) != kGuard) break;
+        if ((kBounded && !go) || (R & kGuard) != kGuard) break;
     }
     // every piece (but one stopped by the functor) used up one face count
     const int used = (R0 & 1023) + ((R0 >> 10) & 1023) + (R0 >> 20) - (R & 1023) - ((R >> 10) & 1023) - (R >> 20);
@@ -242,7 +243,7 @@ __device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real p
 }
 
 // As dda_walk, adding the number of pieces visited to *pieces.
-template <typename Real, typename F>
+template <typename Real, bool kBounded = true, typename F>
 __device__ __forceinline__ Real dda_walk_counted(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy,
                                                  int iz, Real wx, Real wy, Real wz, Real tmax, uint32_t& pieces,
                                                  F&& f)
@@ -250,8 +251,8 @@ __device__ __forceinline__ Real dda_walk_counted(int nx, int ny, int nz, Real px
     int sx, sy, sz;
     Real ivx, ivy, ivz;
     if (!dda_dir(wx, wy, wz, sx, sy, sz, ivx, ivy, ivz)) return (Real)0;
-    return dda_steps<Real>(nx, ny, 0, nz, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, (Real)0, tmax, pieces,
-                           f);
+    return dda_steps<Real, kBounded>(nx, ny, 0, nz, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, (Real)0, tmax,
+                                     pieces, f);
 }
 
 // The part of that walk inside the slab of z layers [z0, z1) (pieces counted
@@ -261,7 +262,7 @@ __device__ __forceinline__ Real dda_walk_counted(int nx, int ny, int nz, Real px
 // it through the near z face (if the ray reaches that face inside the box
 // before tmax); the entry voxel is taken from the entry point, so a piece
 // next to the entry can differ from the whole-grid walk by rounding only.
-template <typename Real, typename F>
+template <typename Real, bool kBounded = true, typename F>
 __device__ __forceinline__ void dda_walk_slab(int nx, int ny, int z0, int z1, Real px, Real py, Real pz, int ix,
                                               int iy, int iz, Real wx, Real wy, Real wz, Real tmax,
                                               uint32_t& pieces, F&& f)
@@ -282,7 +283,7 @@ __device__ __forceinline__ void dda_walk_slab(int nx, int ny, int z0, int z1, Re
         iz = below ? z0 : z1 - 1;
         t = fmax(t, (Real)0);
     }
-    dda_steps<Real>(nx, ny, z0, z1, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, t, tmax, pieces, f);
+    dda_steps<Real, kBounded>(nx, ny, z0, z1, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, t, tmax, pieces, f);
 }
 
 // Spatial sort key of a path (the store orders paths by size B, then by this

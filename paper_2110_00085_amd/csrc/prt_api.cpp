@@ -87,7 +87,7 @@ struct prt_ctx_s {
     int* flag = nullptr;        // device flag: the tape matches beta_t
     unsigned int* work = nullptr;  // task counters of the persistent kernels [kWorkWords]
     uint64_t paths_done = 0;
-    bool timing = false;
+    uint32_t timing = 0;  // bit k set: kernel id k is timed
     std::vector<Timed> pending;
     std::vector<hipEvent_t> pool;
     double total_ms[K_COUNT] = {};
@@ -154,7 +154,7 @@ struct TimedScope {
     prt_ctx c;
     Timed t{};
     bool on;
-    TimedScope(prt_ctx ctx, int id) : c(ctx), on(ctx->timing)
+    TimedScope(prt_ctx ctx, int id) : c(ctx), on(((ctx->timing >> id) & 1u) != 0)
     {
         if (!on) return;
         t.id = id;
@@ -232,7 +232,7 @@ DevScene make_dev_scene(const prt_scene* s)
     return d;
 }
 
-int make_dev_cams(const prt_cameras* c, double vk, DevCams* out)
+int make_dev_cams(const prt_cameras* c, const prt_scene* s, DevCams* out)
 {
     if (!c) return fail(PRT_E_INVALID, "cameras is NULL");
     if (c->n < 1 || c->n > PRT_MAX_CAMERAS) return fail(PRT_E_CAPACITY, "camera count %d outside [1, %d]", c->n, PRT_MAX_CAMERAS);
@@ -243,6 +243,8 @@ int make_dev_cams(const prt_cameras* c, double vk, DevCams* out)
     out->n = c->n;
     out->W = c->width;
     out->H = c->height;
+    const double vk = s->voxel_km;
+    out->outside = 1;
     for (int d = 0; d < c->n; ++d) {
         for (int k = 0; k < 3; ++k) {
             if (!std::isfinite(c->pos[3 * d + k])) return fail(PRT_E_INVALID, "non-finite camera position");
@@ -254,6 +256,9 @@ int make_dev_cams(const prt_cameras* c, double vk, DevCams* out)
         }
         if (!(c->f_px[d] > 0) || !std::isfinite(c->f_px[d])) return fail(PRT_E_INVALID, "focal length must be > 0");
         out->f[d] = c->f_px[d];
+        const double* q = out->pos[d];
+        const bool out_d = q[0] < 0.0 || q[0] > s->nx || q[1] < 0.0 || q[1] > s->ny || q[2] < 0.0 || q[2] > s->nz;
+        if (!out_d) out->outside = 0;
     }
     return PRT_OK;
 }
@@ -807,7 +812,7 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     if (max_order_render < 0) return fail(PRT_E_INVALID, "max_order_render must be >= 0");
     TraceArgs a{};
     DevCams dc;
-    if ((rc = make_dev_cams(cams, s->voxel_km, &dc))) return rc;
+    if ((rc = make_dev_cams(cams, s, &dc))) return rc;
     DeviceGuard g(c->device);
     const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
     if ((rc = ensure_grids(c, nu))) return rc;
@@ -875,7 +880,7 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
     if ((rc = check_match(s, p))) return rc;
     if (!residual || !grad) return fail(PRT_E_INVALID, "residual/grad is NULL");
     DevCams dc;
-    if ((rc = make_dev_cams(cams, s->voxel_km, &dc))) return rc;
+    if ((rc = make_dev_cams(cams, s, &dc))) return rc;
     DeviceGuard g(c->device);
     const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
     if ((rc = ensure_grids(c, nu))) return rc;
@@ -1021,7 +1026,14 @@ int prt_counters(prt_ctx c, prt_counters_t* out, int reset)
 int prt_enable_timing(prt_ctx c, int enable)
 {
     if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
-    c->timing = enable != 0;
+    c->timing = enable != 0 ? ~0u : 0u;
+    return PRT_OK;
+}
+
+int prt_enable_timing_mask(prt_ctx c, uint32_t kernel_mask)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    c->timing = kernel_mask;
     return PRT_OK;
 }
 

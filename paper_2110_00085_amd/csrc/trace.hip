@@ -41,7 +41,7 @@ __device__ __forceinline__ int clamp_vox(int v, int nu) { return min(max(v, 0), 
 
 // Sum of beta(v) * length over the walk from vertex p (voxel p.v) along w
 // for length tmax (grid units); adds the number of pieces to count.
-template <typename Real, typename G>
+template <typename Real, bool kBounded = true, typename G>
 __device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx& p, const double w[3], double tmax,
                                          uint64_t& count)
 {
@@ -49,7 +49,7 @@ __device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx&
     voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
     Real acc = (Real)0;
     uint32_t n = 0;
-    dda_walk_counted<Real>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
+    dda_walk_counted<Real, kBounded>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
                            (Real)w[2], (Real)tmax, n, [&](int v, Real, Real l) {
                                acc += beta((uint32_t)v) * l;
                                return true;
@@ -61,14 +61,14 @@ __device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx&
 // Calls add(v, scale * length) for every piece of the walk that lies in the
 // slab of z layers [z0, z1), v numbered inside the slab (zero-length pieces
 // add zero).
-template <typename Real, typename A>
+template <typename Real, bool kBounded = true, typename A>
 __device__ __forceinline__ void walk_scatter(const DevScene& s, A&& add, const Vtx& p, const double w[3], double tmax,
                                              double scale, uint64_t& count, int z0, int z1)
 {
     int ix, iy, iz;
     voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
     uint32_t n = 0;
-    dda_walk_slab<Real>(s.nx, s.ny, z0, z1, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
+    dda_walk_slab<Real, kBounded>(s.nx, s.ny, z0, z1, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
                         (Real)w[2], (Real)tmax, n, [&](int v, Real, Real l) {
                             add((uint32_t)v, scale * (double)l);
                             return true;
@@ -281,7 +281,10 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                 const double u[3] = {ex * id, ey * id, ez * id};
                 const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
                 const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
-                const Real tc = walk_sum<Real>(s, beta_tot, p1, u, dist, nseg);
+                // with every camera outside the box the walk ends at the box boundary,
+                // before the camera, so it needs no length bound
+                const Real tc = cams.outside ? walk_sum<Real, false>(s, beta_tot, p1, u, dist, nseg)
+                                             : walk_sum<Real>(s, beta_tot, p1, u, dist, nseg);
                 const double c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
                 if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = make_float2((float)c, __int_as_float(pix));
                 if (kImg == kImgLdsF32) atomicAdd(&simg[d * npix + pix], (float)c);
@@ -577,6 +580,8 @@ __device__ __forceinline__ float phase_hg_f32(const DevScene& s, float mu)
     return (float)s.hg_num / (d * sqrtf(d));
 }
 
+constexpr int kGwCams = 8;
+
 __global__ void __launch_bounds__(256) grad_weights_kernel(TraceArgs a, DevCams cams)
 {
     if (*a.tape_flag == 0) return;
@@ -604,22 +609,39 @@ __global__ void __launch_bounds__(256) grad_weights_kernel(TraceArgs a, DevCams 
         const float wcb = wc * (float)bct;
         const float wf0 = (float)w[0], wf1 = (float)w[1], wf2 = (float)w[2];
         float Rb = 0.f, vert = 0.f;
-        for (int d = 0; d < cams.n; ++d) {
-            const float2 t = Tp[(int64_t)(b * cams.n + d) * kWave];
-            const int pix = __float_as_int(t.y);
-            float wf = 0.f;
-            if (pix >= 0) {
-                wf = t.x * (float)a.rho[(int64_t)d * npix + pix];
-                const float ex = (float)(cams.pos[d][0] - p1.x), ey = (float)(cams.pos[d][1] - p1.y),
-                            ez = (float)(cams.pos[d][2] - p1.z);
-                const float mu = (wf0 * ex + wf1 * ey + wf2 * ez) * rsqrtf(ex * ex + ey * ey + ez * ez);
-                const float hg = phase_hg_f32(s, mu);
-                const float fst = wcb * hg + wab * ray_k * (1.f + mu * mu);
-                Rb += wf;
-                if (fst > 0.f) vert += wf * (wc * hg / fst);
-                ++nle;
+        // cameras in groups of kGwCams: all tape loads of a group, then all
+        // residual gathers, then the arithmetic, so the loads overlap
+        for (int d0 = 0; d0 < cams.n; d0 += kGwCams) {
+            float2 tt[kGwCams];
+            double rr[kGwCams];
+#pragma unroll
+            for (int j = 0; j < kGwCams; ++j)
+                tt[j] = d0 + j < cams.n ? Tp[(int64_t)(b * cams.n + d0 + j) * kWave]
+                                        : make_float2(0.f, __int_as_float(-1));
+#pragma unroll
+            for (int j = 0; j < kGwCams; ++j) {
+                const int pix = __float_as_int(tt[j].y);
+                rr[j] = pix >= 0 ? a.rho[(int64_t)(d0 + j) * npix + pix] : 0.0;
             }
-            Wp[(int64_t)(b * cams.n + d) * kWave] = wf;
+#pragma unroll
+            for (int j = 0; j < kGwCams; ++j) {
+                const int d = d0 + j;
+                if (d >= cams.n) break;
+                const int pix = __float_as_int(tt[j].y);
+                float wf = 0.f;
+                if (pix >= 0) {
+                    wf = tt[j].x * (float)rr[j];
+                    const float ex = (float)(cams.pos[d][0] - p1.x), ey = (float)(cams.pos[d][1] - p1.y),
+                                ez = (float)(cams.pos[d][2] - p1.z);
+                    const float mu = (wf0 * ex + wf1 * ey + wf2 * ez) * rsqrtf(ex * ex + ey * ey + ez * ez);
+                    const float hg = phase_hg_f32(s, mu);
+                    const float fst = wcb * hg + wab * ray_k * (1.f + mu * mu);
+                    Rb += wf;
+                    if (fst > 0.f) vert += wf * (wc * hg / fst);
+                    ++nle;
+                }
+                Wp[(int64_t)(b * cams.n + d) * kWave] = wf;
+            }
         }
         // the scatter at x_b turns segment b-1 (direction w) into segment b
         double coef = 0.0, wn[3] = {0.0, 0.0, 0.0};
@@ -688,7 +710,10 @@ __global__ void __launch_bounds__(kBlock) grad_walk_kernel(TraceArgs a, DevCams 
                     const double dist = sqrt(ex * ex + ey * ey + ez * ez);
                     const double id = 1.0 / dist;
                     const double u[3] = {ex * id, ey * id, ez * id};
-                    walk_scatter<float>(s, add, p1, u, dist, -wgt * s.vk, nseg, z0, z1);
+                    if (cams.outside)
+                        walk_scatter<float, false>(s, add, p1, u, dist, -wgt * s.vk, nseg, z0, z1);
+                    else
+                        walk_scatter<float>(s, add, p1, u, dist, -wgt * s.vk, nseg, z0, z1);
                 }
                 if (kind == 0) {
                     const double vert = (double)X[(int64_t)b * kWave].y;

@@ -81,6 +81,7 @@ def lib():
             "prt_adam": ([_V, _I64, _V, _V, _V, _V, _V, _I32, _D, _D, _D, _D], C.c_int),
             "prt_counters": ([_V, C.POINTER(prt_counters_t), C.c_int], C.c_int),
             "prt_enable_timing": ([_V, C.c_int], C.c_int),
+            "prt_enable_timing_mask": ([_V, C.c_uint32], C.c_int),
             "prt_kernel_times": ([_V, _V, _V, C.c_int, C.c_int], C.c_int),
             "prt_kernel_name": ([C.c_int], C.c_char_p),
         }
@@ -247,6 +248,15 @@ def prt_counters(ctx, reset: bool = False) -> dict:
 
 def prt_enable_timing(ctx, enable: bool = True):
     _check(lib().prt_enable_timing(ctx, int(enable)))
+
+
+def prt_enable_timing_mask(ctx, kernel_ids):
+    """Time only the kernels named (or numbered) in kernel_ids."""
+    names = {prt_kernel_name(i): i for i in range(32)}
+    mask = 0
+    for k in kernel_ids:
+        mask |= 1 << (names[k] if isinstance(k, str) else int(k))
+    _check(lib().prt_enable_timing_mask(ctx, mask))
 
 
 def prt_kernel_times(ctx, reset: bool = False) -> dict:

@@ -77,6 +77,15 @@ def _workload(name):
         # output images; the all-orders render forms them from the tape
         s = inputs.cloud8()
         return s, inputs.arc_cameras(s, np.linspace(-60.0, 60.0, 20), 48, 48), 10_000, 1001
+    if name == "incam":
+        # one camera inside the grid box: its connections end at the camera,
+        # not at the box boundary
+        s = inputs.cloud8()
+        outside = inputs.arc_cameras(s, [-30.0, 30.0], 16, 16)
+        inside = inputs.cameras_at([[0.33, 0.07, 0.36]], [[0.2, 0.2, 0.2]], 16, 16, 6.0)
+        cams = inputs.Cameras(3, 16, 16, np.concatenate([outside.pos, inside.pos]),
+                              np.concatenate([outside.rot, inside.rot]), np.concatenate([outside.f_px, inside.f_px]))
+        return s, cams, 10_000, 1003
     raise KeyError(name)
 
 
@@ -147,7 +156,7 @@ def test_sample_fp32_close_to_oracle(env, name):
 # ---------------------------------------------- render / grad / reweight
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "slabs40", "wide96", "manycams"])
+@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "slabs40", "wide96", "manycams", "incam"])
 def test_render_grad_reweight_match_oracle(env, prec, name):
     torch, P, api = env
     scene, cams, n, seed = _workload(name)
