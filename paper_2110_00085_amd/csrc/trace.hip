@@ -76,6 +76,17 @@ __device__ __forceinline__ void walk_scatter(const DevScene& s, A&& add, const V
     count += n;
 }
 
+// Henyey-Greenstein phase function in FP32, 1 + g^2 - 2 g mu written as
+// (1-g)^2 + 2 g (1-mu) (no cancellation near mu = 1).
+__device__ __forceinline__ float phase_hg_f32_om(const DevScene& s, float one_minus_mu)
+{
+    const float g = (float)s.g;
+    const float d = (1.f - g) * (1.f - g) + 2.f * g * one_minus_mu;
+    return (float)s.hg_num / (d * sqrtf(d));
+}
+
+__device__ __forceinline__ float phase_hg_f32(const DevScene& s, float mu) { return phase_hg_f32_om(s, 1.f - mu); }
+
 // Factor of scatter vertex k (1 <= k < b) in the recycled contribution:
 // albedo_ref(x_k) * f_s,t(x_k, mu_k) / f_s,ref(x_k, mu_k).
 __device__ __forceinline__ double vertex_ratio(const DevScene& s, double bct, double bcr, double mu)
@@ -244,6 +255,8 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
     if (kGridLds || kImgLds) __syncthreads();
     auto beta_tot = [&](uint32_t v) -> Real { return kGridLds ? sgrid[v] : gtot[v]; };
     const double r2scale = 1.0 / (s.vk * s.vk);
+    const float vkf = (float)s.vk, wc_f = (float)s.w_c;
+    const float wab = (float)(s.w_a * s.beta_air), ray_k = (float)(3.0 / (16.0 * kPi));
     const int lane = threadIdx.x % kWave;
     const int64_t nb = a.st.n_slots / kWave;
     const int G = a.groups, cpg = (cams.n + G - 1) / G;
@@ -268,6 +281,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
             const int v1 = clamp_vox(p1.v, nu);
             const double bct = (double)a.bc_t[v1];
             const double base = Pb[(int64_t)b * kWave];
+            const float wcb = wc_f * (float)bct;
             for (int d = d_lo; d < d_hi; ++d) {
                 const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
                 if (pix < 0) {
@@ -275,17 +289,36 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                     continue;
                 }
                 const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
-                const double dist2 = ex * ex + ey * ey + ez * ez;
-                const double dist = sqrt(dist2);
-                const double id = 1.0 / dist;
-                const double u[3] = {ex * id, ey * id, ez * id};
-                const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
-                const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
-                // with every camera outside the box the walk ends at the box boundary,
-                // before the camera, so it needs no length bound
-                const Real tc = cams.outside ? walk_sum<Real, false>(s, beta_tot, p1, u, dist, nseg)
-                                             : walk_sum<Real>(s, beta_tot, p1, u, dist, nseg);
-                const double c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
+                double c;
+                if constexpr (sizeof(Real) == 4) {
+                    // FP32 traversal: the contribution is kept in FP32 (tape, image
+                    // partials), so the phase function, transmittance and 1/r^2 are
+                    // FP32; the direction and 1 - mu stay FP64 (a forward-peaked
+                    // phase function is sensitive to 1 - mu near mu = 1).
+                    const double d2 = ex * ex + ey * ey + ez * ez;
+                    double id = (double)rsqrtf((float)d2);
+                    id = id * (1.5 - 0.5 * d2 * id * id);  // one Newton step: ~1e-14 relative
+                    const double u[3] = {ex * id, ey * id, ez * id};
+                    const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
+                    const float muf = (float)mu;
+                    const float hg = phase_hg_f32_om(s, (float)(1.0 - mu));
+                    const float fst = wcb * hg + wab * ray_k * (1.f + muf * muf);
+                    // with every camera outside the box the walk ends at the box
+                    // boundary, before the camera, so it needs no length bound
+                    const Real tc = cams.outside ? walk_sum<Real, false>(s, beta_tot, p1, u, d2 * id, nseg)
+                                                 : walk_sum<Real>(s, beta_tot, p1, u, d2 * id, nseg);
+                    c = base * (double)(fst * expf(-(float)tc * vkf) * (float)(r2scale * id * id));
+                } else {
+                    const double dist2 = ex * ex + ey * ey + ez * ez;
+                    const double dist = sqrt(dist2);
+                    const double id = 1.0 / dist;
+                    const double u[3] = {ex * id, ey * id, ez * id};
+                    const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
+                    const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
+                    const Real tc = cams.outside ? walk_sum<Real, false>(s, beta_tot, p1, u, dist, nseg)
+                                                 : walk_sum<Real>(s, beta_tot, p1, u, dist, nseg);
+                    c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
+                }
                 if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = make_float2((float)c, __int_as_float(pix));
                 if (kImg == kImgLdsF32) atomicAdd(&simg[d * npix + pix], (float)c);
                 else if (kImg == kImgGlobal) unsafeAtomicAdd(&a.img[(int64_t)d * npix + pix], c);
@@ -572,13 +605,6 @@ __device__ __forceinline__ void slab_tally_end(const SlabTally<kLds>& t, double*
 // w_c f_HG / f_s,t of the scatter at x_b between segments b-1 and b.  Runs
 // only when the tape matches beta_t (FP32 traversal mode): the per-camera
 // phase functions are evaluated in FP32, like the stored weights.
-__device__ __forceinline__ float phase_hg_f32(const DevScene& s, float mu)
-{
-    // 1 + g^2 - 2 g mu written as (1-g)^2 + 2 g (1-mu): no cancellation near mu = 1
-    const float g = (float)s.g;
-    const float d = (1.f - g) * (1.f - g) + 2.f * g * (1.f - mu);
-    return (float)s.hg_num / (d * sqrtf(d));
-}
 
 constexpr int kGwCams = 8;
 
