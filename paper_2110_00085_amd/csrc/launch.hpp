@@ -88,12 +88,13 @@ hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const 
                              int64_t nu, void* grid_tot, void* grid_dlt);
 hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu);
 // Stable sort of the paths by (size B, spatial key): perm[sorted position] =
-// path id.  hist: sort_scratch_words(n, nbins) words; tmp_perm: n entries.
-hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint16_t* cell, int64_t n, int nbins,
-                             uint32_t* hist, int32_t* tmp_perm, int32_t* perm);
+// path id, B[position] = size, nv[position] = tnv[path id] for positions < n
+// and 0 up to n_slots.  hist: sort_scratch_words(n, nbins) words; tmp_perm: n
+// entries.
+hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint8_t* tnv, const uint16_t* cell,
+                             int64_t n, int64_t n_slots, int nbins, uint32_t* hist, int32_t* tmp_perm, int32_t* perm,
+                             uint8_t* B, uint8_t* nv);
 int64_t sort_scratch_words(int64_t n, int nbins);
-hipError_t launch_gather_sizes(hipStream_t st, const int32_t* perm, const uint8_t* tB, const uint8_t* tnv,
-                               int64_t n, int64_t n_slots, uint8_t* B, uint8_t* nv);
 // scratch: the sort's scratch (sort_scratch_words(64 * nb, ...) words) may be reused.
 hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, int64_t* batch_off, void* scratch);
 hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, const int64_t* tmp_off,
@@ -117,6 +118,9 @@ struct RenderPlan {
 };
 RenderPlan plan_render(int fp64, int64_t nu, const DevCams& c, bool tape, int64_t n_slots, int64_t first_slot,
                        int n_cu);
+// Whether the render prefix and the reweight form beta_t - beta_ref in LDS
+// (then they need no prepared delta grid).
+bool delta_grid_lds(int fp64, int64_t nu);
 // Per-vertex prefix weights of the render (one lane per path).
 hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, int n_cu);
 // The persistent render kernel alone (its task counter a.work[0] must be zero,
@@ -124,9 +128,10 @@ hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, in
 // with img_lds, launch_render_reduce then adds the partials into the images.
 hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
                          void* partial);
-// Images from the partials (img_lds) or from the tape (img_tape).
+// Images from the partials (img_lds) or from the tape (img_tape), divided by
+// N Omega_p (scale = 1/N) like launch_render_finalize.
 hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
-                                const void* partial, double* img);
+                                const void* partial, double scale, double* img);
 // work[c * kTaskStride + k] = 0 for c < kTaskCounters, k < n (n <= 8): the
 // first n counters of every line of a task-counter set.
 hipError_t launch_reset_work(hipStream_t st, unsigned int* work, int n);

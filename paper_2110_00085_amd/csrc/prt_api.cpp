@@ -421,8 +421,8 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
     if ((rc = ensure_scratch(&c->s_perm, &c->s_perm_bytes, (size_t)n * sizeof(int32_t)))) return rc;
     {
         TimedScope ts(c, K_SORT);
-        HIPCHK(launch_sort_paths(c->stream, tB, tC, n, nbins, (uint32_t*)c->s_hist, (int32_t*)c->s_perm, p->perm));
-        HIPCHK(launch_gather_sizes(c->stream, p->perm, tB, tnv, n, p->n_slots, p->B, p->nv));
+        HIPCHK(launch_sort_paths(c->stream, tB, tnv, tC, n, p->n_slots, nbins, (uint32_t*)c->s_hist,
+                                 (int32_t*)c->s_perm, p->perm, p->B, p->nv));
         HIPCHK(launch_batch_offsets(c->stream, p->nv, p->nb, p->batch_off, c->s_hist));
         HIPCHK(launch_store_meta(c->stream, p->B, n, p->batch_off, p->nb, c->meta));
     }
@@ -847,8 +847,10 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
         TimedScope ts(c, K_PREP);
         // the reductions write every pixel; otherwise tallies add up on zeros
         if (!work || !(plan.img_lds || plan.img_tape)) HIPCHK(launch_fill(c->stream, images, npx, 0.0));
-        HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
-                                 c->grid_dlt));
+        // kernels that hold a grid in LDS form it there from the fields
+        if (work && (!plan.grid_lds || !delta_grid_lds(c->fp64, nu)))
+            HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
+                                     c->grid_dlt));
     }
     if ((rc = ensure_scratch(&c->rpart, &c->rpart_bytes, plan.partial_bytes))) return rc;
     if (work) {
@@ -862,9 +864,10 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
             HIPCHK(launch_render(c->stream, c->fp64, a, dc, plan, c->rpart));
         }
         TimedScope ts(c, K_RENDER_REDUCE);
-        HIPCHK(launch_render_reduce(c->stream, a, dc, plan, c->rpart, images));
+        HIPCHK(launch_render_reduce(c->stream, a, dc, plan, c->rpart, 1.0 / (double)p->n, images));
     }
-    {
+    // the reductions above also divide by N Omega_p; atomic tallies get it here
+    if (work && !(plan.img_lds || plan.img_tape)) {
         TimedScope ts(c, K_FINALIZE);
         HIPCHK(launch_render_finalize(c->stream, images, dc, 1.0 / (double)p->n));
     }
@@ -951,7 +954,7 @@ int prt_reweight(prt_ctx c, const prt_scene* s, prt_paths p, double* mean_r, dou
     if ((rc = ensure_grids(c, nu))) return rc;
     const int64_t nblk = (p->n_slots + 255) / 256;
     if ((rc = ensure_part(c, 2 * nblk))) return rc;
-    {
+    if (!delta_grid_lds(c->fp64, nu)) {
         TimedScope ts(c, K_PREP);
         HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
                                  c->grid_dlt));

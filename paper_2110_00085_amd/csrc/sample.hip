@@ -196,6 +196,16 @@ hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu
 // key k lives at hist[k * n_tiles + t], so an exclusive scan of hist in that
 // order gives every (key, tile) its first output position.
 constexpr int kSortTile = 1024;
+
+// Optional outputs of a scatter pass: key_out[dst] = key of the element,
+// aux_out[dst] = aux_in[element] for every sorted position dst, and zeros in
+// [n, n_pad).
+struct SortExtra {
+    const uint8_t* aux_in = nullptr;
+    uint8_t* key_out = nullptr;
+    uint8_t* aux_out = nullptr;
+    int64_t n_pad = 0;
+};
 constexpr int kMaxBins = kCells > kMaxOrder + 1 ? kCells : kMaxOrder + 1;
 
 template <typename K>
@@ -292,8 +302,13 @@ template <typename K>
 __global__ void __launch_bounds__(kWave) sort_scatter_kernel(const K* __restrict__ key,
                                                              const int32_t* __restrict__ in, int64_t n, int nbins,
                                                              int64_t n_tiles, const uint32_t* __restrict__ off,
-                                                             int32_t* __restrict__ out)
+                                                             int32_t* __restrict__ out, SortExtra x)
 {
+    if (x.key_out && blockIdx.x == 0)
+        for (int64_t i = n + threadIdx.x; i < x.n_pad; i += kWave) {
+            x.key_out[i] = 0;
+            x.aux_out[i] = 0;
+        }
     __shared__ uint32_t base[kMaxBins];
     for (int k = threadIdx.x; k < nbins; k += kWave) base[k] = off[(int64_t)k * n_tiles + blockIdx.x];
     __syncthreads();
@@ -314,7 +329,13 @@ __global__ void __launch_bounds__(kWave) sort_scatter_kernel(const K* __restrict
         }
         if (valid) {
             const int below = __popcll(same & below_mask), total = __popcll(same);
-            out[base[k] + below] = in ? in[i] : (int32_t)i;
+            const int32_t id = in ? in[i] : (int32_t)i;
+            const uint32_t dst = base[k] + below;
+            out[dst] = id;
+            if (x.key_out) {
+                x.key_out[dst] = (uint8_t)key[id];
+                x.aux_out[dst] = x.aux_in[id];
+            }
             if (below == total - 1) base[k] += total;
         }
         __syncthreads();
@@ -323,7 +344,7 @@ __global__ void __launch_bounds__(kWave) sort_scatter_kernel(const K* __restrict
 
 template <typename K>
 static hipError_t counting_sort(hipStream_t st, const K* key, const int32_t* in, int64_t n, int nbins,
-                                uint32_t* hist, int32_t* out)
+                                uint32_t* hist, int32_t* out, SortExtra x = SortExtra{})
 {
     const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
     sort_hist_kernel<K><<<dim3((unsigned)n_tiles), dim3(256), 0, st>>>(key, in, n, nbins, n_tiles, hist);
@@ -331,7 +352,8 @@ static hipError_t counting_sort(hipStream_t st, const K* key, const int32_t* in,
     if (e != hipSuccess) return e;
     const int64_t m = n_tiles * nbins;
     if ((e = scan_exclusive<uint32_t>(st, hist, m, hist + m)) != hipSuccess) return e;
-    sort_scatter_kernel<K><<<dim3((unsigned)n_tiles), dim3(kWave), 0, st>>>(key, in, n, nbins, n_tiles, hist, out);
+    sort_scatter_kernel<K><<<dim3((unsigned)n_tiles), dim3(kWave), 0, st>>>(key, in, n, nbins, n_tiles, hist, out,
+                                                                            x);
     return hipGetLastError();
 }
 
@@ -346,42 +368,23 @@ int64_t sort_scratch_words(int64_t n, int nbins)
     return std::max<int64_t>(1, std::max(sort_words, boff_words));
 }
 
-hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint16_t* cell, int64_t n, int nbins,
-                             uint32_t* hist, int32_t* tmp_perm, int32_t* perm)
+hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint8_t* tnv, const uint16_t* cell,
+                             int64_t n, int64_t n_slots, int nbins, uint32_t* hist, int32_t* tmp_perm, int32_t* perm,
+                             uint8_t* B, uint8_t* nv)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e = counting_sort<uint16_t>(st, cell, nullptr, n, kCells, hist, tmp_perm);
     if (e != hipSuccess) return e;
-    return counting_sort<uint8_t>(st, size_key, tmp_perm, n, nbins, hist, perm);
+    // the size pass also writes every slot's B and vertex count (zero past n)
+    SortExtra x;
+    x.aux_in = tnv;
+    x.key_out = B;
+    x.aux_out = nv;
+    x.n_pad = n_slots;
+    return counting_sort<uint8_t>(st, size_key, tmp_perm, n, nbins, hist, perm, x);
 }
 
 // --------------------------------------------------------------- packing
-
-__global__ void __launch_bounds__(256) gather_sizes_kernel(const int32_t* __restrict__ perm,
-                                                           const uint8_t* __restrict__ tB,
-                                                           const uint8_t* __restrict__ tnv, int64_t n,
-                                                           int64_t n_slots, uint8_t* __restrict__ B,
-                                                           uint8_t* __restrict__ nv)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_slots) return;
-    if (i < n) {
-        const int32_t id = perm[i];
-        B[i] = tB[id];
-        nv[i] = tnv[id];
-    } else {
-        B[i] = 0;
-        nv[i] = 0;
-    }
-}
-
-hipError_t launch_gather_sizes(hipStream_t st, const int32_t* perm, const uint8_t* tB, const uint8_t* tnv,
-                               int64_t n, int64_t n_slots, uint8_t* B, uint8_t* nv)
-{
-    gather_sizes_kernel<<<dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, st>>>(perm, tB, tnv, n, n_slots,
-                                                                                      B, nv);
-    return hipGetLastError();
-}
 
 // batch_off[b] = 64 * sum_{b' < b} rows(b'), rows(b) = max stored vertices
 // over the batch; batch_off[nb] is the total record count.  One wavefront

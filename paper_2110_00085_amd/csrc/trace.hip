@@ -137,19 +137,20 @@ constexpr size_t kLdsImageBudget = 152 * 1024;  // image tallies (+ grid if both
 constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs per launch sequence
 constexpr size_t kTapeImageLds = 64 * 1024;     // FP64 image of one camera, images formed from the tape
 
-// Loads the field beta_t - beta_ref into LDS (kGridLds) for a persistent
-// workgroup and returns it (or the field in global memory).
+// The field beta_t - beta_ref for a persistent workgroup: formed in LDS from
+// beta_t and beta_ref (kGridLds), else the one prepared in global memory.
 template <typename Real, bool kGridLds>
 __device__ __forceinline__ const Real* delta_grid(const TraceArgs& a, unsigned char* smem)
 {
-    const Real* __restrict__ g = (const Real*)a.grid_dlt;
-    if (!kGridLds) return g;
+    if (!kGridLds) return (const Real*)a.grid_dlt;
     Real* sg = reinterpret_cast<Real*>(smem);
     const int nu = a.s.nx * a.s.ny * a.s.nz;
-    for (int i = threadIdx.x; i < nu; i += blockDim.x) sg[i] = g[i];
+    for (int i = threadIdx.x; i < nu; i += blockDim.x) sg[i] = (Real)((double)a.bc_t[i] - (double)a.st.beta_ref[i]);
     __syncthreads();
     return sg;
 }
+
+bool delta_grid_lds(int fp64, int64_t nu) { return (size_t)nu * (fp64 ? 8 : 4) <= kLdsBudget; }
 
 // Prefix weights, one lane per path (persistent workgroups, the field
 // beta_t - beta_ref cached in LDS when it fits): walks the free-flight
@@ -249,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
     Real* __restrict__ sgrid = reinterpret_cast<Real*>(smem + (kImgLds ? (size_t)nimg * sizeof(float) : 0));
     const Real* __restrict__ gtot = (const Real*)a.grid_tot;
     if (kGridLds)
-        for (int i = threadIdx.x; i < nu; i += kBlock) sgrid[i] = gtot[i];
+        for (int i = threadIdx.x; i < nu; i += kBlock) sgrid[i] = (Real)((double)a.bc_t[i] + s.beta_air);
     if (kImgLds)
         for (int i = threadIdx.x; i < nimg; i += kBlock) simg[i] = 0.f;
     if (kGridLds || kImgLds) __syncthreads();
@@ -335,15 +336,33 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
     }
 }
 
-// img[i] = sum over workgroups of partial[w][i] (FP64, workgroup order).
+// Exact pixel solid angle: F(x,y) = atan(xy / (f sqrt(x^2+y^2+f^2))) is the
+// solid angle of [0,x]x[0,y] on the image plane at distance f.
+__device__ __forceinline__ double pixel_solid_angle(double f, int W, int H, int row, int col)
+{
+    auto F = [f](double x, double y) { return atan(x * y / (f * sqrt(x * x + y * y + f * f))); };
+    const double x1 = col - 0.5 * W, x2 = x1 + 1.0, y1 = row - 0.5 * H, y2 = y1 + 1.0;
+    return F(x2, y2) - F(x1, y2) - F(x2, y1) + F(x1, y1);
+}
+
+// Factor turning pixel i's tally into radiance: scale / Omega_p.
+__device__ __forceinline__ double pixel_scale(const DevCams& c, int64_t i, double scale)
+{
+    const int64_t npix = (int64_t)c.W * c.H;
+    const int d = (int)(i / npix), p = (int)(i % npix);
+    return scale / pixel_solid_angle(c.f[d], c.W, c.H, p / c.W, p % c.W);
+}
+
+// img[i] = sum over workgroups of partial[w][i] (FP64, workgroup order),
+// times scale / Omega_p.
 __global__ void __launch_bounds__(256) render_reduce_kernel(const float* __restrict__ partial, int n_wg, int64_t n,
-                                                            double* __restrict__ img)
+                                                            DevCams c, double scale, double* __restrict__ img)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double acc = 0.0;
     for (int w = 0; w < n_wg; ++w) acc += (double)partial[(int64_t)w * n + i];
-    img[i] = acc;
+    img[i] = acc * pixel_scale(c, i, scale);
 }
 
 template <typename Real, bool kGridLds, int kImg, bool kTape>
@@ -393,14 +412,15 @@ __global__ void __launch_bounds__(kBlock) tape_image_kernel(TraceArgs a, DevCams
 }
 
 __global__ void __launch_bounds__(256) tape_image_reduce_kernel(const double* __restrict__ partial, int groups,
-                                                                int npix, int64_t n, double* __restrict__ img)
+                                                                int npix, int64_t n, DevCams c, double scale,
+                                                                double* __restrict__ img)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t d = i / npix, p = i % npix;
     double acc = 0.0;
     for (int x = 0; x < groups; ++x) acc += partial[(d * groups + x) * npix + p];
-    img[i] = acc;
+    img[i] = acc * pixel_scale(c, i, scale);
 }
 
 // Workgroups for a persistent launch over the batches that hold scattered paths.
@@ -463,7 +483,7 @@ hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const Dev
 }
 
 hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
-                                const void* partial, double* img)
+                                const void* partial, double scale, double* img)
 {
     const int64_t npix = (int64_t)c.W * c.H, nimg = npix * c.n;
     const unsigned blocks = (unsigned)((nimg + 255) / 256);
@@ -478,11 +498,11 @@ hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCam
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         tape_image_reduce_kernel<<<dim3(blocks), dim3(256), 0, st>>>((const double*)partial, kTapeImageGroups,
-                                                                      (int)npix, nimg, img);
+                                                                      (int)npix, nimg, c, scale, img);
         return hipGetLastError();
     }
     if (!p.img_lds) return hipSuccess;
-    render_reduce_kernel<<<dim3(blocks), dim3(256), 0, st>>>((const float*)partial, p.n_wg, nimg, img);
+    render_reduce_kernel<<<dim3(blocks), dim3(256), 0, st>>>((const float*)partial, p.n_wg, nimg, c, scale, img);
     return hipGetLastError();
 }
 
@@ -492,14 +512,6 @@ hipError_t launch_reset_work(hipStream_t st, unsigned int* work, int n)
     return hipGetLastError();
 }
 
-// Exact pixel solid angle: F(x,y) = atan(xy / (f sqrt(x^2+y^2+f^2))) is the
-// solid angle of [0,x]x[0,y] on the image plane at distance f.
-__device__ __forceinline__ double pixel_solid_angle(double f, int W, int H, int row, int col)
-{
-    auto F = [f](double x, double y) { return atan(x * y / (f * sqrt(x * x + y * y + f * f))); };
-    const double x1 = col - 0.5 * W, x2 = x1 + 1.0, y1 = row - 0.5 * H, y2 = y1 + 1.0;
-    return F(x2, y2) - F(x1, y2) - F(x2, y1) + F(x1, y1);
-}
 
 // images = tallies / (N Omega_p)
 __global__ void __launch_bounds__(256) render_finalize_kernel(double* __restrict__ img, DevCams c, double scale)
@@ -507,8 +519,7 @@ __global__ void __launch_bounds__(256) render_finalize_kernel(double* __restrict
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t npix = (int64_t)c.W * c.H;
     if (i >= npix * c.n) return;
-    const int d = (int)(i / npix), p = (int)(i % npix);
-    img[i] *= scale / pixel_solid_angle(c.f[d], c.W, c.H, p / c.W, p % c.W);
+    img[i] *= pixel_scale(c, i, scale);
 }
 
 hipError_t launch_render_finalize(hipStream_t st, double* img, const DevCams& c, double scale)
@@ -525,8 +536,7 @@ __global__ void __launch_bounds__(256) grad_prep_kernel(const double* __restrict
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t npix = (int64_t)c.W * c.H;
     if (i >= npix * c.n) return;
-    const int d = (int)(i / npix), p = (int)(i % npix);
-    rho[i] = res[i] * scale / pixel_solid_angle(c.f[d], c.W, c.H, p / c.W, p % c.W);
+    rho[i] = res[i] * pixel_scale(c, i, scale);
 }
 
 hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho, const DevCams& c, double scale)
