@@ -146,7 +146,7 @@ struct GradPlan {
     int n_wg = 1;
     size_t partial_bytes = 0;
 };
-GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu);
+GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu, bool tape);
 // Gradient weights from the tape (runs only when *a.tape_flag is 1).
 hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c);
 // Gradient terms of slab i (z layers [i*slab_layers, min(nz, (i+1)*slab_layers))):

@@ -488,7 +488,7 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
 
 // Tape capacity: one (FP32 c, pixel) entry per (vertex record, camera) from the first
 // scattering batch on; capped so that large workloads recompute instead.
-constexpr size_t kMaxTapeBytes = (size_t)16 << 30;
+constexpr size_t kMaxTapeBytes = (size_t)64 << 30;
 
 int ensure_tape(prt_paths p, size_t n_cams, int64_t nu)
 {
@@ -891,7 +891,20 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
     if ((rc = ensure_pix(c, npx))) return rc;
     // batches with scattering paths (the kernels have nothing to do without them)
     const bool work = p->n_slots > p->first_slot;
-    const GradPlan plan = plan_grad(s->nx, s->ny, s->nz, p->n_slots, p->first_slot, c->n_cu);
+    const DevScene ds = make_dev_scene(s);
+    const size_t recs = (size_t)(p->n_records - p->tape_base);  // records from the first scattering batch on
+    // the tape of the last render serves when it was recorded for these
+    // cameras and this scene (and, checked on the device, this beta_t)
+    bool tape = work && recs > 0 && p->tape_valid && !c->fp64 && std::memcmp(&p->tape_cams, &dc, sizeof dc) == 0 &&
+                std::memcmp(&p->tape_scene, &ds, sizeof ds) == 0;
+    if (tape) {
+        // weights and per-vertex sums for the walks on the tape; without room
+        // for them the gradient recomputes
+        if (ensure_scratch(&c->gw, &c->gw_bytes, recs * dc.n * sizeof(float)) != PRT_OK ||
+            ensure_scratch(&c->gaux, &c->gaux_bytes, recs * sizeof(float4)) != PRT_OK)
+            tape = false;
+    }
+    const GradPlan plan = plan_grad(s->nx, s->ny, s->nz, p->n_slots, p->first_slot, c->n_cu, tape);
     {
         TimedScope ts(c, K_PREP);
         // the slabs' reductions write every voxel; otherwise atomics add up on zeros
@@ -902,7 +915,7 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
         HIPCHK(launch_grad_prep(c->stream, residual, c->pix, dc, 1.0 / (double)p->n));
     }
     TraceArgs a{};
-    a.s = make_dev_scene(s);
+    a.s = ds;
     a.st = view_of(p);
     a.bc_t = s->beta_cloud;
     a.grid_tot = c->grid_tot;
@@ -913,17 +926,12 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
     a.counters = c->counters;
     a.work = c->work;
     a.groups = camera_groups(dc.n);
-    const size_t recs = (size_t)(p->n_records - p->tape_base);  // records from the first scattering batch on
-    if (recs > 0 && p->tape_valid && !c->fp64 && std::memcmp(&p->tape_cams, &dc, sizeof dc) == 0 &&
-        std::memcmp(&p->tape_scene, &a.s, sizeof a.s) == 0) {
+    if (tape) {
         // the tape is used only if beta_t equals the field it was recorded with
         HIPCHK(launch_equal_flag(c->stream, s->beta_cloud, p->tape_beta, nu, c->flag));
         a.tape = p->tape;
         a.tape_base = p->tape_base;
         a.tape_flag = c->flag;
-        // weights and per-vertex sums for the walks on the tape
-        if ((rc = ensure_scratch(&c->gw, &c->gw_bytes, recs * dc.n * sizeof(float)))) return rc;
-        if ((rc = ensure_scratch(&c->gaux, &c->gaux_bytes, recs * sizeof(float4)))) return rc;
         a.wtape = (float*)c->gw;
         a.vaux = (float4*)c->gaux;
         TimedScope ts(c, K_GRAD_WEIGHTS);

@@ -134,7 +134,8 @@ constexpr int kBlock = 1024;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr size_t kLdsBudget = 128 * 1024;       // grids
 constexpr size_t kLdsImageBudget = 152 * 1024;  // image tallies (+ grid if both fit)
-constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs per launch sequence
+constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs when each slab recomputes the weights
+constexpr int64_t kMaxTapeGradSlabs = 64;       // LDS gradient slabs when the weights come from the tape
 constexpr size_t kTapeImageLds = 64 * 1024;     // FP64 image of one camera, images formed from the tape
 
 // The field beta_t - beta_ref for a persistent workgroup: formed in LDS from
@@ -929,15 +930,17 @@ static hipError_t launch_grad_t(hipStream_t st, const TraceArgs& a, const DevCam
     return launch_persistent(st, grad_kernel<Real, kLds>, p.n_wg, lds, b, c, z0, z1, partial);
 }
 
-GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu)
+GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu, bool tape)
 {
     GradPlan p;
     const int64_t layer_bytes = (int64_t)nx * ny * (int64_t)sizeof(double);
     const int64_t layers = std::min<int64_t>(nz, (int64_t)kLdsBudget / layer_bytes);
     const int64_t slabs = layers > 0 ? (nz + layers - 1) / layers : 0;
-    // Every slab repeats the per-contribution set-up of pass 1, so past a few
-    // slabs FP64 atomics on the output are cheaper.
-    p.lds = layers > 0 && slabs <= kMaxGradSlabs;
+    // Without the tape every slab recomputes the contributions, so past a few
+    // slabs FP64 atomics on the output are cheaper; with it a slab only walks,
+    // and LDS tallies stay cheaper than global FP64 atomics (~1600 clocks per
+    // wavefront instruction) up to many slabs.
+    p.lds = layers > 0 && slabs <= (tape ? kMaxTapeGradSlabs : kMaxGradSlabs);
     p.slab_layers = p.lds ? (int)layers : nz;
     p.n_slabs = p.lds ? (int)slabs : 1;
     const int64_t batches = (n_slots - first_slot + kWave - 1) / kWave;
