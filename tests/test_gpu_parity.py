@@ -248,6 +248,126 @@ def test_full_size_cloud32(env):
     assert abs(mr - mr_ref) <= 1e-5 * mr_ref and abs(ess - ess_ref) <= 1e-5 * ess_ref
 
 
+@pytest.mark.parametrize("name", ["plume64", "field128"])
+def test_full_size_large_workloads(env, name):
+    """The 64^3 plume (9 x 128^2 cameras, 2^26 paths, 20 orders) and the
+    128x128x64 cloud field (20 x 256^2 cameras, 2^28 paths, 30 orders) at
+    full size in FP32 traversal (the oracle cannot render them whole):
+    sampled paths of 2000 random ids against the oracle's; render, gradient
+    and r sums of the full store against a split of the same paths into a
+    store A (the first 50 000 ids) and a store B (the rest), each rendered on
+    its own; and store A against the oracle."""
+    torch, P, api = env
+    if name == "plume64":
+        scene = inputs.plume64()
+        cams, n = inputs.plume64_cameras(scene), 1 << 26
+    else:
+        scene = inputs.field128()
+        cams, n = inputs.field128_cameras(scene), 1 << 28
+    seed, n_a = 1004, 50_000
+    ch = P.CamerasHost(cams)
+    ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
+    say(f"full size {name} n={n}: sample")
+    st = api.PathStore.sample(ctx, scene, _dev(torch, scene.beta_cloud), seed, n)
+    beta_t = _perturbed(scene, seed=9, amp=0.1)
+    bt = _dev(torch, beta_t)
+    say(f"full size {name}: render, grad, reweight")
+    img = api.render(ctx, scene, bt, ch, st).cpu().numpy()
+    res = np.random.default_rng(5).standard_normal(img.shape) * np.abs(img).mean()
+    res_d = torch.as_tensor(res).cuda()
+    g = api.grad(ctx, scene, bt, ch, st, res_d).cpu().numpy()
+    mr, ess = P.prt_reweight(ctx.handle, P.make_scene(scene, bt), st.handle)
+    assert np.isfinite(img).all() and img.min() >= 0.0 and np.abs(img).max() > 0
+    assert np.isfinite(g).all() and np.abs(g).max() > 0
+    say(f"full size {name}: export")
+    off, xyz, vox, B, br = st.export()
+    st.close()
+    ctx.close()
+    # sampled paths, one by one
+    ids = np.sort(np.random.default_rng(6).choice(n, 2000, replace=False))
+    say(f"full size {name}: oracle sampling of {len(ids)} ids")
+    ref = oracle.sample(scene, seed, ids=ids, n_total=n)
+    same = B[ids] == ref.B
+    assert same.mean() >= 0.995, same.mean()
+    dev = [np.abs(xyz[off[i]:off[i + 1]].astype(float) - ref.xyz[ref.off[k]:ref.off[k + 1]]).max()
+           for k, i in enumerate(ids) if same[k] and B[i] > 0]
+    assert np.median(dev) < 1e-4, np.median(dev)
+    # the same paths split into two stores
+    ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
+    e = int(off[n_a])
+    parts = {"A": (off[:n_a + 1], xyz[:e], vox[:e], B[:n_a]),
+             "B": (off[n_a:] - off[n_a], xyz[e:], vox[e:], B[n_a:])}
+    out = {}
+    for k, (o, x, v, b) in parts.items():
+        say(f"full size {name}: store {k} ({len(b)} paths)")
+        sk = api.PathStore.from_host(ctx, scene, _dev(torch, scene.beta_cloud), o, x, v, b, br, seed)
+        out[k] = (api.render(ctx, scene, bt, ch, sk).cpu().numpy(), api.grad(ctx, scene, bt, ch, sk, res_d).cpu().numpy(),
+                  P.prt_reweight(ctx.handle, P.make_scene(scene, bt), sk.handle), len(b))
+        if k == "A":
+            paths_a = oracle.Paths(o.copy(), x.astype(np.float32), v.copy(), b.astype(B.dtype), n_a, seed, br)
+        sk.close()
+    ctx.close()
+    (img_a, g_a, (mr_a, ess_a), na), (img_b, g_b, (mr_b, ess_b), nb) = out["A"], out["B"]
+    # images and r sums are FP64 sums of identical terms; the gradient weights
+    # are stored in FP32 after the 1/N scaling, so they round differently
+    assert _rel(na * img_a + nb * img_b, n * img) <= 1e-10
+    assert _rel(na * g_a + nb * g_b, n * g) <= 1e-6
+    assert abs(na * mr_a + nb * mr_b - n * mr) <= 1e-10 * n * mr
+    r2 = lambda m, s_, k: (m * k) ** 2 / s_
+    assert abs(r2(mr_a, ess_a, na) + r2(mr_b, ess_b, nb) - r2(mr, ess, n)) <= 1e-9 * r2(mr, ess, n)
+    say(f"full size {name}: oracle on store A")
+    ref_img = oracle.render(scene, cams, paths_a, beta_t=beta_t)
+    assert _rel(img_a, ref_img) <= TOL["fp32"]["img"], _rel(img_a, ref_img)
+    ref_g = oracle.grad(scene, cams, paths_a, res, beta_t=beta_t)
+    assert _rel(g_a, ref_g) <= TOL["fp32"]["grad"], _rel(g_a, ref_g)
+    mr_ref, ess_ref = oracle.reweight(scene, paths_a, beta_t=beta_t)
+    assert abs(mr_a - mr_ref) <= 1e-5 * mr_ref and abs(ess_a - ess_ref) <= 1e-5 * ess_ref
+
+
+def test_finite_differences_full_size_cloud32(env):
+    """The differentiable step's check at its full size: the 32^3 field with
+    2^22 stored paths in all-FP64 mode, L2 loss against images of a second
+    seeded field rendered from fresh paths; prt_grad against differences of
+    the loss at fixed paths on 64 random voxels (seed 33): central
+    differences, or a one-sided three-point difference where beta < 2h."""
+    torch, P, api = env
+    scene = inputs.cloud32()
+    cams = inputs.cloud32_cameras(scene)
+    n = 1 << 22
+    ch = P.CamerasHost(cams)
+    ctx = api.Context(0, P.PRT_ALL_FP64)
+    say("finite differences cloud32 n=2^22 fp64: target images")
+    tgt_scene = scene.with_beta(inputs.gaussian_field_cloud(32, 3))
+    st_t = api.PathStore.sample(ctx, tgt_scene, _dev(torch, tgt_scene.beta_cloud), 2003, n)
+    tgt = api.render(ctx, tgt_scene, _dev(torch, tgt_scene.beta_cloud), ch, st_t)
+    st_t.close()
+    say("finite differences: sample, render, grad")
+    b0 = _dev(torch, scene.beta_cloud)
+    st = api.PathStore.sample(ctx, scene, b0, 1003, n)
+    img = api.render(ctx, scene, b0, ch, st)
+    g = api.grad(ctx, scene, b0, ch, st, (img - tgt).contiguous()).cpu().numpy().ravel()
+
+    def L(b):
+        im = api.render(ctx, scene, b, ch, st)
+        return float(0.5 * ((im - tgt) ** 2).sum())
+
+    h = 2.0 ** -6  # beta +- h is exact in FP32 for beta < 2^17
+    flat = b0.view(-1)
+    voxels = np.random.default_rng(33).choice(flat.numel(), 64, replace=False)
+    say("finite differences: 64 voxels")
+    for v in voxels:
+        def at(k):
+            b = flat.clone()
+            b[v] += k * h
+            return L(b.view_as(b0))
+        if float(flat[v]) >= 2 * h:
+            fd = (at(1) - at(-1)) / (2 * h)
+        else:
+            fd = (-3.0 * at(0) + 4.0 * at(1) - at(2)) / (2 * h)
+        assert abs(fd - g[v]) <= 1e-5 * np.abs(g).max() + 1e-4 * abs(fd), (int(v), fd, g[v])
+    st.close()
+
+
 # ------------------------------------------------------------- loop glue
 
 def test_loss_and_adam_match_oracle(env):
