@@ -39,6 +39,7 @@ if ROOT not in sys.path:
 # WRITE_SIZE counters scaled by a plain copy of known size; valid while the
 # kernel sources hash to the recorded value.
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+VALU_JSON = os.path.join(ROOT, "profiles", "pmc_valu.json")
 CSRC = os.path.join(ROOT, "paper_2110_00085_amd", "csrc")
 # device kernel measured for each timed hot-path scope
 DEVICE_KERNEL = {"grad": "grad_walk_kernel", "render": "render_kernel", "sample": "sample_kernel",
@@ -74,6 +75,11 @@ def parse():
                     help="summarise rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv output of a bench run and of "
                          "--copy-calibration into --traffic-json, then exit")
     ap.add_argument("--traffic-json", default=TRAFFIC_JSON, help="where --pmc-summary writes its result")
+    ap.add_argument("--valu-summary", nargs=2, metavar=("VALU_DIR", "OCC_DIR"),
+                    help="summarise rocprofv3 --pmc VALUBusy VALUUtilization and --pmc MeanOccupancyPerCU "
+                         "LDSBankConflict SQ_INSTS_VALU csv output of a bench run into --valu-json, "
+                         "then exit")
+    ap.add_argument("--valu-json", default=VALU_JSON, help="where --valu-summary writes its result")
     return ap.parse_args()
 
 
@@ -141,6 +147,50 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_json):
                    "kernels": table}, fh, indent=1)
 
 
+def valu_summary(valu_dir, occ_dir, out_json):
+    """Means over the dispatches of every hot-path kernel of VALU busy (% of
+    VALU issue cycles), VALU lane utilisation (% of lanes active per VALU
+    instruction), mean wavefronts per CU, LDS bank-conflict cycles (%) and
+    VALU instructions per dispatch; writes out_json, prints a markdown table."""
+    cols = (("VALUBusy", valu_dir), ("VALUUtilization", valu_dir), ("MeanOccupancyPerCU", occ_dir),
+            ("LDSBankConflict", occ_dir), ("SQ_INSTS_VALU", occ_dir))
+    kernels = {}
+    for counter, d in cols:
+        for _, k, v in _pmc_rows(d, counter):
+            for scope, sym in DEVICE_KERNEL.items():
+                if "prt::" + sym + "<" in k or "prt::" + sym + "(" in k:
+                    kernels.setdefault(scope, {}).setdefault(counter, []).append(v)
+    mean = lambda c, n: sum(c.get(n, [0.0])) / max(len(c.get(n, [])), 1)
+    table = {}
+    print("| kernel | dispatches | VALU busy % | VALU lane use % | waves per CU | LDS bank conflict % | "
+          "VALU instr per dispatch |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for scope, c in sorted(kernels.items()):
+        row = {"kernel": DEVICE_KERNEL[scope], "valu_busy_pct": mean(c, "VALUBusy"),
+               "valu_lane_util_pct": mean(c, "VALUUtilization"), "waves_per_cu": mean(c, "MeanOccupancyPerCU"),
+               "lds_bank_conflict_pct": mean(c, "LDSBankConflict"), "valu_instr": mean(c, "SQ_INSTS_VALU")}
+        table[scope] = row
+        print(f"| {row['kernel']} | {len(c.get('VALUBusy', []))} | {row['valu_busy_pct']:.1f} | "
+              f"{row['valu_lane_util_pct']:.1f} | {row['waves_per_cu']:.1f} | {row['lds_bank_conflict_pct']:.2f} | "
+              f"{row['valu_instr']:.3g} |")
+    with open(out_json, "w") as fh:
+        json.dump({"source_sha256": source_hash(), "kernels": table}, fh, indent=1)
+
+
+def valu_for(scope):
+    """VALU counters of the kernel behind `scope` from --valu-json, or None
+    when none were taken for it or its sources changed since."""
+    try:
+        with open(VALU_JSON) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(scope)
+    return {"busy_pct": k["valu_busy_pct"], "lane_util_pct": k["valu_lane_util_pct"]} if k else None
+
+
 def traffic_for(scope):
     """Scaled HBM bytes per launch of the kernel behind `scope`, or None when
     no counters were taken for it or its sources changed since."""
@@ -162,6 +212,9 @@ def main():
         return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, args.traffic_json)
+        return
+    if args.valu_summary:
+        valu_summary(*args.valu_summary, args.valu_json)
         return
     if args.gpus != 1:
         print("bench.py: the hot path runs on one GPU; --gpus must be 1 (sharding paths over GPUs is not "
@@ -277,6 +330,7 @@ def main():
     roofline = {"bound": "alu", "kernel": dom, "achieved": None, "peak": VALU_LANE_OPS_PEAK / 1e12,
                 "unit": "TOP/s", "frac": None, "traffic": traffic_for(dom), "avg_launch_ms": dom_ms,
                 "launches_per_step": per_call}
+    roofline["valu"] = valu_for(dom)
     if roofline["traffic"] is not None:
         hbm = roofline["traffic"] / (dom_ms * 1e-3) / 1e9
         roofline["hbm"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS}
