@@ -80,6 +80,12 @@ def parse():
                          "LDSBankConflict SQ_INSTS_VALU csv output of a bench run into --valu-json, "
                          "then exit")
     ap.add_argument("--valu-json", default=VALU_JSON, help="where --valu-summary writes its result")
+    ap.add_argument("--reuse-study", action="store_true",
+                    help="reuse against fresh resampling at equal gradient error on --workload (default plume64 "
+                         "for the study): Adam iterations on recycled paths, and at checkpoints the recycled "
+                         "gradient's error and one fresh gradient's error against the mean of 8 fresh gradients")
+    ap.add_argument("--study-iters", type=int, default=30)
+    ap.add_argument("--study-paths", type=int, default=0, help="paths per store (default: the workload's)")
     return ap.parse_args()
 
 
@@ -205,6 +211,103 @@ def traffic_for(scope):
     return k["bytes_per_launch"] if k else None
 
 
+def reuse_study(args):
+    """Path reuse against fresh resampling at equal gradient error.
+
+    Adam (lr 0.1 km^-1, beta >= 0) runs on recycled paths from beta^0 (the
+    workload's field) towards images of a second seeded field, resampling
+    only when |mean r - 1| > 0.2.  At checkpoints k the recycled gradient g_k
+    and one gradient g_f from freshly sampled paths at beta_k are compared
+    with g_ref, the mean of 8 further fresh gradients at beta_k:
+    e = ||g - g_ref|| / ||g_ref||.  Iteration times: recycled (render, loss,
+    grad, Adam, reweight) and fresh (the same plus resampling).  A fresh
+    gradient of the recycled one's error needs (e_f / e_k)^2 as many paths,
+    so reuse is faster at equal error by that factor times the fresh
+    iteration time over the recycled one."""
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_2110_00085_amd import api, prt as P
+    name = args.workload if args.workload != "cloud32" else "plume64"
+    make_scene, make_cams, n_paths, seed = inputs.WORKLOADS[name]
+    n = args.study_paths or n_paths
+    scene = make_scene()
+    cams = make_cams(scene)
+    ch = P.CamerasHost(cams)
+    ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
+    h = ctx.handle
+    dev = torch.device("cuda:0")
+    tgt_scene = make_scene(seed=7) if name != "cloud8" else scene.with_beta(scene.beta_cloud * 1.2)
+    st = api.PathStore.sample(ctx, tgt_scene, torch.as_tensor(tgt_scene.beta_cloud).to(dev), seed + 2000, n)
+    target = api.render(ctx, tgt_scene, torch.as_tensor(tgt_scene.beta_cloud).to(dev), ch, st)
+    st.close()
+    beta32 = torch.as_tensor(scene.beta_cloud).to(dev).contiguous()
+    beta64 = beta32.double()
+    m = torch.zeros_like(beta64)
+    v = torch.zeros_like(beta64)
+    img = torch.empty(ch.image_shape, dtype=torch.float64, device=dev)
+    res = torch.empty_like(img)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty((scene.nz, scene.ny, scene.nx), dtype=torch.float64, device=dev)
+    sc = P.make_scene(scene, beta32)
+    print(f"[study] {name}: {scene.nx}x{scene.ny}x{scene.nz}, {cams.n} cams {cams.width}^2, {n} paths, "
+          f"{args.study_iters} iterations", flush=True)
+
+    def grad_on(store):
+        P.prt_render(h, sc, ch, store.handle, scene.max_order, img)
+        P.prt_loss(h, img, target, res, loss)
+        P.prt_grad(h, sc, ch, store.handle, res, grad)
+        return grad.clone()
+
+    def fresh_grad(s_):
+        fs = api.PathStore.sample(ctx, scene, beta32, s_, n)
+        g = grad_on(fs)
+        fs.close()
+        return g
+
+    store = api.PathStore.sample(ctx, scene, beta32, seed, n)
+    resamples, t_rec, checkpoints, rows = 0, [], {5, 10, 20, args.study_iters}, []
+    for it in range(1, args.study_iters + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = grad_on(store)
+        P.prt_adam(h, beta64, beta32, grad, m, v, it, 0.1)
+        mr, ess = P.prt_reweight(h, sc, store.handle)
+        t_rec.append(time.perf_counter() - t0)
+        if it in checkpoints:
+            # beta has moved on; the recycled gradient at the new beta_k
+            g_k = grad_on(store).double()
+            g_f = fresh_grad(10_000 + it).double()
+            g_ref = sum(fresh_grad(20_000 + 100 * it + j).double() for j in range(8)) / 8
+            nr = float(torch.linalg.vector_norm(g_ref))
+            e_k = float(torch.linalg.vector_norm(g_k - g_ref)) / nr
+            e_f = float(torch.linalg.vector_norm(g_f - g_ref)) / nr
+            rows.append({"iteration": it, "mean_r": mr, "ess": ess, "e_recycled": e_k, "e_fresh": e_f,
+                         "loss": float(loss.item()), "resamples": resamples})
+            print(f"[study] it {it}: loss {loss.item():.4e} mean r {mr:.4f} ess/N {ess / n:.3f} "
+                  f"e_recycled {e_k:.4f} e_fresh {e_f:.4f} resamples {resamples}", flush=True)
+        if abs(mr - 1.0) > 0.2:
+            store.resample(scene, beta32, seed + it, n)
+            resamples += 1
+    # iteration times: recycled (median of the loop) and fresh (with resampling)
+    t_fresh = []
+    for k in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        store.resample(scene, beta32, 30_000 + k, n)
+        grad_on(store)
+        P.prt_adam(h, beta64.clone(), beta32.clone(), grad, m.clone(), v.clone(), 1, 0.0)
+        P.prt_reweight(h, sc, store.handle)
+        t_fresh.append(time.perf_counter() - t0)
+    tr, tf = float(np.median(t_rec)), float(np.median(t_fresh))
+    ratio = float(np.mean([(r["e_fresh"] / r["e_recycled"]) ** 2 for r in rows]))
+    print(json.dumps({"study": "reuse vs fresh resampling", "workload": name, "paths": n,
+                      "ms_recycled_iteration": 1e3 * tr, "ms_fresh_iteration": 1e3 * tf,
+                      "paths_factor_equal_error": ratio, "equal_error_speedup_of_reuse": tf * ratio / tr,
+                      "checkpoints": rows}), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -215,6 +318,9 @@ def main():
         return
     if args.valu_summary:
         valu_summary(*args.valu_summary, args.valu_json)
+        return
+    if args.reuse_study:
+        reuse_study(args)
         return
     if args.gpus != 1:
         print("bench.py: the hot path runs on one GPU; --gpus must be 1 (sharding paths over GPUs is not "
