@@ -475,18 +475,16 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cams, target.cpu().numpy(), seed, min(args.cpu_paths, n_paths),
-                                           n_paths)
+                                           n_paths, args.workload)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(scene, cams, target, seed, n_cpu, n_total):
-    """The FP64 oracle doing one full step (sample, render, loss, grad, Adam,
-    reweight) on the first n_cpu paths of the same stream."""
+def oracle_step_seconds(scene, cams, target, seed, n_cpu):
+    """Seconds of the FP64 oracle doing one full step (sample, render, loss,
+    grad, Adam, reweight) on the first n_cpu paths of the stream."""
     import numpy as np
 
     import oracle
-    if not os.path.exists(os.path.join(ROOT, "oracle", "libprt_oracle.so")):
-        oracle.build()
     t0 = time.perf_counter()
     paths = oracle.sample(scene, seed, n_cpu)
     img = oracle.render(scene, cams, paths)
@@ -495,10 +493,37 @@ def cpu_baseline(scene, cams, target, seed, n_cpu, n_total):
     beta = scene.beta_cloud.astype(np.float64)
     beta, _, _ = oracle.adam_step(beta, g, np.zeros_like(beta), np.zeros_like(beta), 1, 0.1)
     oracle.reweight(scene, paths, beta_t=beta.astype(np.float32))
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(scene, cams, target, seed, n_cpu, n_total, workload):
+    """The oracle's full-step rate on the host's cores, and on one core (a
+    child process with OMP_NUM_THREADS=1 on 1/16 of the sample)."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+
+    import oracle
+    if not os.path.exists(os.path.join(ROOT, "oracle", "libprt_oracle.so")):
+        oracle.build()
+    dt = oracle_step_seconds(scene, cams, target, seed, n_cpu)
+    n1 = max(1, n_cpu // 16)
+    one = None
+    with tempfile.TemporaryDirectory() as d:
+        f = os.path.join(d, "target.npy")
+        np.save(f, target)
+        code = ("import sys, json, numpy as np; sys.path.insert(0, sys.argv[1]); import bench, inputs; "
+                "mk, mc, _, _ = inputs.WORKLOADS[sys.argv[2]]; s = mk(); "
+                "print(bench.oracle_step_seconds(s, mc(s), np.load(sys.argv[3]), int(sys.argv[4]), int(sys.argv[5])))")
+        r = subprocess.run([sys.executable, "-c", code, ROOT, workload, f, str(seed), str(n1)], capture_output=True,
+                           text=True, env=dict(os.environ, OMP_NUM_THREADS="1"))
+        if r.returncode == 0:
+            one = n1 / float(r.stdout.strip().splitlines()[-1])
     return {"value": n_cpu / dt, "unit": "paths/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"one full step on the first {n_cpu} of the {n_total} paths (same seeds), FP64, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s; the 1-core rate on the first {n1}",
+            "value_1core": one}
 
 
 if __name__ == "__main__":
