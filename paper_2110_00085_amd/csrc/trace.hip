@@ -167,8 +167,10 @@ __global__ void __launch_bounds__(kBlock) render_prefix_kernel(TraceArgs a)
     const DevScene& s = a.s;
     const int nu = s.nx * s.ny * s.nz;
     uint64_t nseg = 0;
-    for (int64_t slot = a.st.first_slot / kWave * kWave + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-         slot < a.st.n_slots; slot += (int64_t)gridDim.x * blockDim.x) {
+    // slots in batch order from the heaviest batch (the end of the store) down
+    const int64_t n_work = a.st.n_slots - a.st.first_slot / kWave * kWave;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_work; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t slot = (a.st.n_slots / kWave - 1 - r / kWave) * kWave + r % kWave;
         const int Br = min((int)a.st.B[slot], a.brender);
         if (Br <= 0) continue;
         const int64_t bt = slot / kWave, lane = slot % kWave;
@@ -622,8 +624,11 @@ constexpr int kGwCams = 8;
 __global__ void __launch_bounds__(256) grad_weights_kernel(TraceArgs a, DevCams cams)
 {
     if (*a.tape_flag == 0) return;
-    const int64_t slot = a.st.first_slot / kWave * kWave + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= a.st.n_slots) return;
+    // heaviest batches (largest B, at the end of the store) first
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t bt_first = a.st.n_slots / kWave - 1 - t / kWave;
+    if (bt_first < a.st.first_slot / kWave) return;
+    const int64_t slot = bt_first * kWave + t % kWave;
     const int Bn = (int)a.st.B[slot];
     if (Bn <= 0) return;
     const DevScene& s = a.s;
@@ -1019,8 +1024,10 @@ __global__ void __launch_bounds__(kBlock) reweight_kernel(TraceArgs a)
     const int nu = s.nx * s.ny * s.nz;
     double rs = 0.0, r2s = 0.0;
     uint64_t cnt = 0;
-    for (int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; slot < a.st.n_slots;
-         slot += (int64_t)gridDim.x * blockDim.x) {
+    // slots in batch order from the heaviest batch (the end of the store) down
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.st.n_slots;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t slot = (a.st.n_slots / kWave - 1 - q / kWave) * kWave + q % kWave;
         const int nv = (int)a.st.nv[slot];
         const int Bn = (int)a.st.B[slot];
         if (nv <= 0) continue;
