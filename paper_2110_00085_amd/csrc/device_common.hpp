@@ -81,43 +81,50 @@ __device__ __forceinline__ double phase_rayleigh(double mu)
     return (3.0 / (16.0 * kPi)) * (1.0 + mu * mu);
 }
 
-__device__ __forceinline__ double sample_hg(double u, double g)
+// (the sampling helpers below run in the event precision E of the sampler:
+// double in the all-FP64 mode, float with FP32 traversal)
+__device__ __forceinline__ void sincos_e(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ void sincos_e(float x, float* s, float* c) { sincosf(x, s, c); }
+template <typename E>
+__device__ __forceinline__ E sample_hg(E u, E g)
 {
-    double mu;
-    if (fabs(g) < 1e-6) {
-        mu = 2.0 * u - 1.0;
+    E mu;
+    if (fabs(g) < (E)1e-6) {
+        mu = (E)2 * u - (E)1;
     } else {
-        const double s = (1.0 - g * g) / (1.0 - g + 2.0 * g * u);
-        mu = (1.0 + g * g - s * s) / (2.0 * g);
+        const E s = ((E)1 - g * g) / ((E)1 - g + (E)2 * g * u);
+        mu = ((E)1 + g * g - s * s) / ((E)2 * g);
     }
-    return fmin(1.0, fmax(-1.0, mu));
+    return fmin((E)1, fmax((E)-1, mu));
 }
 
 // Rayleigh: the cubic mu^3 + 3 mu + 4 - 8u = 0 has the single real root s - 1/s,
 // s = cbrt(q + sqrt(q^2 + 1)), q = 4u - 2.
-__device__ __forceinline__ double sample_rayleigh(double u)
+template <typename E>
+__device__ __forceinline__ E sample_rayleigh(E u)
 {
-    const double q = 4.0 * u - 2.0;
-    const double s = cbrt(q + sqrt(q * q + 1.0));
-    return fmin(1.0, fmax(-1.0, s - 1.0 / s));
+    const E q = (E)4 * u - (E)2;
+    const E s = cbrt(q + sqrt(q * q + (E)1));
+    return fmin((E)1, fmax((E)-1, s - (E)1 / s));
 }
 
 // New direction at cosine mu, azimuth phi about n, in the branchless
 // orthonormal basis of Duff et al. (JCGT 2017); renormalised.
-__device__ __forceinline__ void scatter_direction(const double n[3], double mu, double phi, double out[3])
+template <typename E>
+__device__ __forceinline__ void scatter_direction(const E n[3], E mu, E phi, E out[3])
 {
-    const double sgn = n[2] >= 0.0 ? 1.0 : -1.0;
-    const double a = -1.0 / (sgn + n[2]);
-    const double b = n[0] * n[1] * a;
-    const double e1x = 1.0 + sgn * n[0] * n[0] * a, e1y = sgn * b, e1z = -sgn * n[0];
-    const double e2x = b, e2y = sgn + n[1] * n[1] * a, e2z = -n[1];
-    const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
-    double sp, cp;
-    sincos(phi, &sp, &cp);
-    const double wx = mu * n[0] + st * (cp * e1x + sp * e2x);
-    const double wy = mu * n[1] + st * (cp * e1y + sp * e2y);
-    const double wz = mu * n[2] + st * (cp * e1z + sp * e2z);
-    const double inv = 1.0 / sqrt(wx * wx + wy * wy + wz * wz);
+    const E sgn = n[2] >= (E)0 ? (E)1 : (E)-1;
+    const E a = (E)-1 / (sgn + n[2]);
+    const E b = n[0] * n[1] * a;
+    const E e1x = (E)1 + sgn * n[0] * n[0] * a, e1y = sgn * b, e1z = -sgn * n[0];
+    const E e2x = b, e2y = sgn + n[1] * n[1] * a, e2z = -n[1];
+    const E st = sqrt(fmax((E)0, (E)1 - mu * mu));
+    E sp, cp;
+    sincos_e(phi, &sp, &cp);
+    const E wx = mu * n[0] + st * (cp * e1x + sp * e2x);
+    const E wy = mu * n[1] + st * (cp * e1y + sp * e2y);
+    const E wz = mu * n[2] + st * (cp * e1z + sp * e2z);
+    const E inv = (E)1 / sqrt(wx * wx + wy * wy + wz * wz);
     out[0] = wx * inv;
     out[1] = wy * inv;
     out[2] = wz * inv;

@@ -63,10 +63,12 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
     const int stride = s.max_order + 2;
     const int lane = threadIdx.x % kWave;
     const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;  // lanes under this one
+    // path state and event arithmetic in the traversal precision
+    using E = Real;
     int64_t id = 0;
     float4* __restrict__ out = nullptr;
-    double x = 0.0, y = 0.0, z = 0.0, tau = 0.0;
-    double w[3] = {0.0, 0.0, 0.0};
+    E x = 0, y = 0, z = 0, tau = 0;
+    E w[3] = {0, 0, 0};
     double u[4];
     int ix = 0, iy = 0, iz = 0, b = 0, nv = 0, v0 = 0;
     bool active = false, exhausted = false;
@@ -98,11 +100,11 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
                 uniforms4(a.seed, (uint64_t)id, 0u, u);
                 const double A = s.a_top + s.a_x + s.a_y;
                 if (u[0] * A < s.a_top) {
-                    x = u[1] * s.nx; y = u[2] * s.ny; z = (double)s.nz;
+                    x = (E)(u[1] * s.nx); y = (E)(u[2] * s.ny); z = (E)s.nz;
                 } else if (u[0] * A < s.a_top + s.a_x) {
-                    x = s.x_face; y = u[1] * s.ny; z = u[2] * s.nz;
+                    x = (E)s.x_face; y = (E)(u[1] * s.ny); z = (E)(u[2] * s.nz);
                 } else {
-                    x = u[1] * s.nx; y = s.y_face; z = u[2] * s.nz;
+                    x = (E)(u[1] * s.nx); y = (E)s.y_face; z = (E)(u[2] * s.nz);
                 }
                 ix = min(max((int)floor(x), 0), s.nx - 1);
                 iy = min(max((int)floor(y), 0), s.ny - 1);
@@ -110,9 +112,9 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
                 nv = 0;
                 v0 = ix + s.nx * (iy + s.ny * iz);
                 out[nv++] = vrec(x, y, z, v0);
-                w[0] = s.sun[0]; w[1] = s.sun[1]; w[2] = s.sun[2];
+                w[0] = (E)s.sun[0]; w[1] = (E)s.sun[1]; w[2] = (E)s.sun[2];
                 // optical depth target in units of (1/km * grid length)
-                tau = -log(u[3]) / s.vk;
+                tau = -log((E)u[3]) / (E)s.vk;
                 b = 0;
                 active = true;
             }
@@ -140,19 +142,12 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
         if (hit >= 0) thit += (taur - acc) / gt[hit];
         bool done;
         if (hit < 0) {
-            const double te = (double)tend;
-            out[nv++] = vrec(x + te * w[0], y + te * w[1], z + te * w[2], -1);
+            out[nv++] = vrec(x + tend * w[0], y + tend * w[1], z + tend * w[2], -1);
             done = true;
         } else {
-            if (sizeof(Real) == 8) {
-                const double th = (double)thit;
-                x = x + th * w[0]; y = y + th * w[1]; z = z + th * w[2];
-            } else {
-                const float th = (float)thit;
-                x = (double)((float)x + th * (float)w[0]);
-                y = (double)((float)y + th * (float)w[1]);
-                z = (double)((float)z + th * (float)w[2]);
-            }
+            x = x + thit * w[0];
+            y = y + thit * w[1];
+            z = z + thit * w[2];
             ++b;
             out[nv++] = vrec(x, y, z, hit);
             if (b == 1) v0 = hit;  // the sort key follows the first scatter
@@ -160,13 +155,14 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
             if (!done) {
                 voxel_ijk(hit, s.nx, s.ny, ix, iy, iz);
                 uniforms4(a.seed, (uint64_t)id, (uint32_t)b, u);
+                // the particle choice is taken in FP64 in both precisions
                 const double bsc = s.w_c * (double)a.beta_c[hit];
                 const double bs = bsc + s.w_a * s.beta_air;
-                const double mu = (u[0] * bs < bsc) ? sample_hg(u[1], s.g) : sample_rayleigh(u[1]);
-                double wn[3];
-                scatter_direction(w, mu, 2.0 * kPi * u[2], wn);
+                const E mu = (u[0] * bs < bsc) ? sample_hg<E>((E)u[1], (E)s.g) : sample_rayleigh<E>((E)u[1]);
+                E wn[3];
+                scatter_direction<E>(w, mu, (E)(2.0 * kPi) * (E)u[2], wn);
                 w[0] = wn[0]; w[1] = wn[1]; w[2] = wn[2];
-                tau = -log(u[3]) / s.vk;
+                tau = -log((E)u[3]) / (E)s.vk;
             }
         }
         if (done) {
