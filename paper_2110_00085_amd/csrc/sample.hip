@@ -36,8 +36,12 @@ hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const 
 
 // ---------------------------------------------------------------- sampler
 
-// Resident 256-thread workgroups per CU for the persistent sampler.
-constexpr int kSampleBlocksPerCU = 8;
+// Persistent sampler: one workgroup of kSampleBlock threads per CU holding the
+// extinction grid in LDS when it fits kSampleLds, else kSampleBlocksPerCU
+// workgroups per CU reading it from L2.
+constexpr int kSampleBlock = 1024;
+constexpr size_t kSampleLds = 128 * 1024;
+constexpr int kSampleBlocksPerCU = 2;
 
 __device__ __forceinline__ float4 vrec(double x, double y, double z, int v)
 {
@@ -55,11 +59,20 @@ __device__ __forceinline__ float4 vrec(double x, double y, double z, int v)
 // max_order scatters.  Vertices go to row id of tmp (stride max_order+2).
 // The uniforms of path id come from its own Philox counters, so the result
 // does not depend on which lane samples it.
-template <typename Real>
-__global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
+template <typename Real, bool kGridLds>
+__global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
 {
     const DevScene& s = a.s;
+    extern __shared__ unsigned char smem[];
     const Real* __restrict__ gt = (const Real*)a.grid_tot;
+    if (kGridLds) {
+        // the extinction grid in LDS: a piece's lookup waits ~100 clocks, not an L2 round trip
+        Real* sg = reinterpret_cast<Real*>(smem);
+        const int nu = s.nx * s.ny * s.nz;
+        for (int i = threadIdx.x; i < nu; i += blockDim.x) sg[i] = gt[i];
+        __syncthreads();
+        gt = sg;
+    }
     const int stride = s.max_order + 2;
     const int lane = threadIdx.x % kWave;
     const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;  // lanes under this one
@@ -174,15 +187,29 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
     }
 }
 
+template <typename Real, bool kGridLds>
+static hipError_t launch_sample_t(hipStream_t st, const SampleArgs& a, int64_t blocks, size_t lds)
+{
+    if (lds) {
+        hipError_t e = hipFuncSetAttribute((const void*)sample_kernel<Real, kGridLds>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    sample_kernel<Real, kGridLds><<<dim3((unsigned)blocks), dim3(kSampleBlock), lds, st>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu)
 {
     if (a.n <= 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>((a.n + 255) / 256, (int64_t)n_cu * kSampleBlocksPerCU);
+    const size_t lds = (size_t)a.s.nx * a.s.ny * a.s.nz * (fp64 ? 8 : 4);
+    const bool grid_lds = lds <= kSampleLds;
+    const int64_t blocks = std::min<int64_t>((a.n + kSampleBlock - 1) / kSampleBlock,
+                                             (int64_t)n_cu * (grid_lds ? 1 : kSampleBlocksPerCU));
     if (fp64)
-        sample_kernel<double><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
-    else
-        sample_kernel<float><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a);
-    return hipGetLastError();
+        return grid_lds ? launch_sample_t<double, true>(st, a, blocks, lds)
+                        : launch_sample_t<double, false>(st, a, blocks, 0);
+    return grid_lds ? launch_sample_t<float, true>(st, a, blocks, lds) : launch_sample_t<float, false>(st, a, blocks, 0);
 }
 
 // ----------------------------------------------------- stable counting sort
