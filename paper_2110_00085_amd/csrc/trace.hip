@@ -5,7 +5,9 @@
 // One lane per stored path; a wavefront holds a batch of 64 paths of
 // (nearly) equal size B thanks to the sort, so lanes leave the scatter loop
 // together.  The voxel walk runs in Real (float or double); projection,
-// phase functions, path weights and all tallies are FP64.
+// path weights and all tallies are FP64.  With FP32 traversal the factors of
+// a stored contribution after the projection (phase function, transmittance,
+// 1/r^2) and the gradient weights are FP32, as they are stored in FP32.
 #include <algorithm>
 
 #include "launch.hpp"
