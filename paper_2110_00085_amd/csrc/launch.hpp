@@ -39,7 +39,9 @@ struct SampleArgs {
 // every wavefront's task requests on one address; a launch therefore spreads
 // its tasks over kTaskCounters counters on separate 128-byte lines, and a
 // context holds kWorkWords words of them (render/grad counters at word 0 and
-// 1 of each line, the sampler's id counter at word 2 of the first).
+// 1 of each line, the sampler's id counter at word 2 of the first, and at
+// words 3 and 4 of the first the finished-workgroup counts of the loss and
+// the reweight).
 constexpr int kTaskCounters = 8;
 constexpr int kTaskStride = 32;
 constexpr int kWorkWords = kTaskCounters * kTaskStride;
@@ -81,11 +83,21 @@ struct TraceArgs {
     // t%groups.
     unsigned int* work;
     int groups;
+    // render prefix: also copies beta_t here (the tape's field) when set, and
+    // zeroes the render's task counters
+    float* copy_beta;
+    // reweight: (sum r, sum r^2) of all paths go to rw_out[0..1] (pinned host
+    // memory), *rw_done counts finished workgroups (zero at launch, rearmed)
+    double* rw_out;
+    unsigned int* rw_done;
 };
 
 // ---- sampling, sorting, packing (sample.hip)
+// grid_tot = beta_t + beta_air and (if given) grid_dlt = beta_t - beta_ref in
+// the traversal precision; also copy = beta_t and *zero = 0 when given.
 hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const float* bc_r, double beta_air,
-                             int64_t nu, void* grid_tot, void* grid_dlt);
+                             int64_t nu, void* grid_tot, void* grid_dlt, float* copy = nullptr,
+                             unsigned int* zero = nullptr);
 hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu);
 // Stable sort of the paths by (size B, spatial key): perm[sorted position] =
 // path id, B[position] = size, nv[position] = tnv[path id] for positions < n
@@ -132,11 +144,12 @@ hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const Dev
 // N Omega_p (scale = 1/N) like launch_render_finalize.
 hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
                                 const void* partial, double scale, double* img);
-// work[c * kTaskStride + k] = 0 for c < kTaskCounters, k < n (n <= 8): the
-// first n counters of every line of a task-counter set.
-hipError_t launch_reset_work(hipStream_t st, unsigned int* work, int n);
 hipError_t launch_render_finalize(hipStream_t st, double* img, const DevCams& c, double scale);
-hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho, const DevCams& c, double scale);
+// rho = residual / (N Omega_p) (scale = 1/N); also sets *flag = 1 when flag is
+// given and zeroes the first two counters of every line of the task-counter
+// set work (the first gradient slab's).
+hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho, const DevCams& c, double scale,
+                            int* flag, unsigned int* work);
 // How the gradient is tallied: per-workgroup FP64 LDS partials of one slab of
 // z layers at a time (reduced by a second kernel), when a layer fits the LDS
 // budget and the grid needs few slabs, else FP64 atomics on the output.
@@ -156,19 +169,22 @@ hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams
 // launch_grad_reduce then writes the slab's gradient.
 hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p, int slab,
                        void* partial);
+// (also zeroes the task counters in work for the next slab's launch)
 hipError_t launch_grad_reduce(hipStream_t st, const GradPlan& p, int nx, int ny, int nz, int slab,
-                              const void* partial, double* grad);
+                              const void* partial, double* grad, unsigned int* work);
 // Per-workgroup sums of r and r^2 into a.partial[2*wg..]; *n_blocks workgroups.
 hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int n_cu, int64_t* n_blocks);
-// flag = 1 if a[i] == b[i] bitwise for all i < n, else 0.
+// flag = 0 if a[i] != b[i] bitwise for some i < n (flag set to 1 beforehand,
+// by launch_grad_prep).
 hipError_t launch_equal_flag(hipStream_t st, const float* a, const float* b, int64_t n, int* flag);
 
 // ---- loop glue (loop.hip)
 hipError_t launch_fill(hipStream_t st, double* p, int64_t n, double v);
+// loss = 0.5 sum (img - tgt)^2 and res = img - tgt; *done counts finished
+// workgroups (zero at launch, rearmed by the kernel).
 hipError_t launch_loss(hipStream_t st, int64_t n, const double* img, const double* tgt, double* res,
-                       double* partial, double* loss);
+                       double* partial, double* loss, unsigned int* done);
 int64_t loss_blocks(int64_t n);
-hipError_t launch_sum_pairs(hipStream_t st, const double* partial, int64_t n_blocks, double* out2);
 hipError_t launch_adam(hipStream_t st, int64_t n, double* beta, float* beta_f32, const double* grad, double* m,
                        double* v, double lr, double b1, double b2, double eps, double bc1, double bc2);
 

@@ -74,7 +74,13 @@ struct prt_ctx_s {
     void* s_perm = nullptr;     // permutation after the sort's first pass
     size_t s_perm_bytes = 0;
     size_t s_off_bytes = 0;
-    int64_t* meta = nullptr;    // 3 int64 read back after packing
+    // pinned host words the kernels write directly (read after a stream sync):
+    // the store's 3 int64 sizes after packing, and the reweight's 2 sums
+    void* hpin = nullptr;
+    int64_t* hmeta = nullptr;
+    double* hsum = nullptr;
+    int64_t* dmeta = nullptr;   // the same words as device pointers
+    double* dsum = nullptr;
     void* grid_tot = nullptr;
     void* grid_dlt = nullptr;
     size_t grid_bytes = 0;
@@ -82,7 +88,6 @@ struct prt_ctx_s {
     size_t pix_n = 0;
     double* part = nullptr;     // reduction partials
     size_t part_n = 0;
-    double* out2 = nullptr;     // two doubles of reduction output
     unsigned long long* counters = nullptr;  // 4
     int* flag = nullptr;        // device flag: the tape matches beta_t
     unsigned int* work = nullptr;  // task counters of the persistent kernels [kWorkWords]
@@ -424,14 +429,13 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
         HIPCHK(launch_sort_paths(c->stream, tB, tnv, tC, n, p->n_slots, nbins, (uint32_t*)c->s_hist,
                                  (int32_t*)c->s_perm, p->perm, p->B, p->nv));
         HIPCHK(launch_batch_offsets(c->stream, p->nv, p->nb, p->batch_off, c->s_hist));
-        HIPCHK(launch_store_meta(c->stream, p->B, n, p->batch_off, p->nb, c->meta));
+        HIPCHK(launch_store_meta(c->stream, p->B, n, p->batch_off, p->nb, c->dmeta));
     }
-    int64_t meta[3] = {0, 0, 0};
-    HIPCHK(hipMemcpyAsync(meta, c->meta, sizeof meta, hipMemcpyDeviceToHost, c->stream));
+    // store_meta_kernel wrote the sizes into pinned host memory
     HIPCHK(hipStreamSynchronize(c->stream));
-    p->n_records = meta[0];
-    p->first_slot = meta[1];
-    p->tape_base = meta[2];
+    p->n_records = c->hmeta[0];
+    p->first_slot = c->hmeta[1];
+    p->tape_base = c->hmeta[2];
     if ((rc = grow(&p->vtx, &p->cap_records, p->n_records))) return rc;
     {
         TimedScope ts(c, K_PACK);
@@ -462,10 +466,11 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     uint8_t* tB = (uint8_t*)c->s_keys;
     uint8_t* tnv = tB + n;
     uint16_t* tC = (uint16_t*)(tB + 2 * n);
-    HIPCHK(hipMemcpyAsync(p->beta_ref, s->beta_cloud, nu * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
     {
+        // the reference snapshot beta_ref = beta_t, the sampler's grid and its id counter
         TimedScope ts(c, K_PREP);
-        HIPCHK(launch_prep_grids(c->stream, c->fp64, p->beta_ref, nullptr, s->beta_air, nu, c->grid_tot, nullptr));
+        HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, nullptr, s->beta_air, nu, c->grid_tot, nullptr,
+                                 p->beta_ref, c->work + 2));
     }
     SampleArgs a;
     a.s = make_dev_scene(s);
@@ -478,7 +483,6 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     a.tnv = tnv;
     a.tC = tC;
     a.next = c->work + 2;
-    HIPCHK(launch_reset_work(c->stream, a.next, 1));
     {
         TimedScope ts(c, K_SAMPLE);
         HIPCHK(launch_sample(c->stream, c->fp64, a, c->n_cu));
@@ -562,21 +566,31 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
     c->fp64 = precision == PRT_ALL_FP64;
     if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
         c->n_cu = 1;
+    void* dpin = nullptr;
     if (hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc((void**)&c->out2, 2 * sizeof(double)) != hipSuccess ||
         hipMalloc((void**)&c->flag, sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&c->work, kWorkWords * sizeof(unsigned int)) != hipSuccess ||
-        hipMalloc((void**)&c->meta, 3 * sizeof(int64_t)) != hipSuccess) {
+        hipHostMalloc(&c->hpin, 64, hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer(&dpin, c->hpin, 0) != hipSuccess) {
+        (void)hipGetLastError();
         (void)hipFree(c->work);
         (void)hipFree(c->flag);
         (void)hipFree(c->counters);
-        (void)hipFree(c->out2);
+        if (c->hpin) (void)hipHostFree(c->hpin);
         delete c;
         return fail(PRT_E_NOMEM, "context allocation failed");
     }
-    if (hipMemset(c->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
+    c->hmeta = (int64_t*)c->hpin;
+    c->hsum = (double*)((char*)c->hpin + 32);
+    c->dmeta = (int64_t*)dpin;
+    c->dsum = (double*)((char*)dpin + 32);
+    // task counters start at zero; kernels that count finished workgroups rearm theirs
+    if (hipMemset(c->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->work, 0, kWorkWords * sizeof(unsigned int)) != hipSuccess) {
+        (void)hipFree(c->work);
+        (void)hipFree(c->flag);
         (void)hipFree(c->counters);
-        (void)hipFree(c->out2);
+        (void)hipHostFree(c->hpin);
         delete c;
         return fail(PRT_E_HIP, "context init failed");
     }
@@ -607,9 +621,8 @@ void prt_destroy(prt_ctx c)
     (void)hipFree(c->s_hist);
     (void)hipFree(c->s_off);
     (void)hipFree(c->s_perm);
-    (void)hipFree(c->meta);
+    (void)hipHostFree(c->hpin);
     (void)hipFree(c->part);
-    (void)hipFree(c->out2);
     (void)hipFree(c->flag);
     (void)hipFree(c->work);
     (void)hipFree(c->counters);
@@ -837,7 +850,7 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     p->tape_valid = false;
     if (!c->fp64 && a.brender >= s->max_order && (rc = ensure_tape(p, (size_t)dc.n, nu)) == PRT_OK) {
         a.tape = p->tape;
-        HIPCHK(hipMemcpyAsync(p->tape_beta, s->beta_cloud, nu * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        a.copy_beta = p->tape_beta;  // by the render prefix kernel
         p->tape_valid = true;
         p->tape_cams = dc;
         p->tape_scene = a.s;
@@ -856,9 +869,9 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     if (work) {
         {
             TimedScope ts(c, K_RENDER_PREFIX);
+            // also zeroes the render's task counters and copies the tape's beta_t
             HIPCHK(launch_render_prefix(c->stream, c->fp64, a, c->n_cu));
         }
-        HIPCHK(launch_reset_work(c->stream, c->work, 1));
         {
             TimedScope ts(c, K_RENDER);
             HIPCHK(launch_render(c->stream, c->fp64, a, dc, plan, c->rpart));
@@ -912,7 +925,10 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
         if (!work) return PRT_OK;
         HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
                                  c->grid_dlt));
-        HIPCHK(launch_grad_prep(c->stream, residual, c->pix, dc, 1.0 / (double)p->n));
+        // also sets the tape flag (cleared by launch_equal_flag on a mismatch) and
+        // zeroes the first slab's task counters
+        HIPCHK(launch_grad_prep(c->stream, residual, c->pix, dc, 1.0 / (double)p->n, tape ? c->flag : nullptr,
+                                c->work));
     }
     TraceArgs a{};
     a.s = ds;
@@ -938,14 +954,15 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
         HIPCHK(launch_grad_weights(c->stream, a, dc));
     }
     if ((rc = ensure_scratch(&c->gpart, &c->gpart_bytes, plan.partial_bytes))) return rc;
+    // task counters: zeroed by launch_grad_prep for the first slab, by each
+    // slab's reduction for the next (one slab only when there is no reduction)
     for (int i = 0; i < plan.n_slabs; ++i) {
-        HIPCHK(launch_reset_work(c->stream, c->work, 2));
         {
             TimedScope ts(c, K_GRAD);
             HIPCHK(launch_grad(c->stream, c->fp64, a, dc, plan, i, c->gpart));
         }
         TimedScope ts(c, K_GRAD_REDUCE);
-        HIPCHK(launch_grad_reduce(c->stream, plan, s->nx, s->ny, s->nz, i, c->gpart, grad));
+        HIPCHK(launch_grad_reduce(c->stream, plan, s->nx, s->ny, s->nz, i, c->gpart, grad, c->work));
     }
     return PRT_OK;
 }
@@ -975,15 +992,16 @@ int prt_reweight(prt_ctx c, const prt_scene* s, prt_paths p, double* mean_r, dou
     a.grid_dlt = c->grid_dlt;
     a.partial = c->part;
     a.counters = c->counters;
+    a.rw_out = c->dsum;
+    a.rw_done = c->work + 4;
     int64_t nb = 0;
     {
         TimedScope ts(c, K_REWEIGHT);
         HIPCHK(launch_reweight(c->stream, c->fp64, a, c->n_cu, &nb));
-        HIPCHK(launch_sum_pairs(c->stream, c->part, nb, c->out2));
     }
-    double h[2];
-    HIPCHK(hipMemcpyAsync(h, c->out2, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    // the reweight kernel's last workgroup wrote the sums into pinned host memory
     HIPCHK(hipStreamSynchronize(c->stream));
+    const double h[2] = {c->hsum[0], c->hsum[1]};
     *mean_r = h[0] / (double)p->n;
     *ess = h[1] > 0 ? h[0] * h[0] / h[1] : 0.0;
     return PRT_OK;
@@ -997,7 +1015,7 @@ int prt_loss(prt_ctx c, int64_t n, const double* images, const double* target, d
     int rc = ensure_part(c, 2 * loss_blocks(n));
     if (rc) return rc;
     TimedScope ts(c, K_LOSS);
-    HIPCHK(launch_loss(c->stream, n, images, target, residual, c->part, loss));
+    HIPCHK(launch_loss(c->stream, n, images, target, residual, c->part, loss, c->work + 3));
     return PRT_OK;
 }
 

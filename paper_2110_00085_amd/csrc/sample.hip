@@ -12,25 +12,28 @@ template <typename Real>
 __global__ void __launch_bounds__(256) prep_grids_kernel(const float* __restrict__ bc_t,
                                                          const float* __restrict__ bc_r, double beta_air,
                                                          int64_t nu, Real* __restrict__ tot,
-                                                         Real* __restrict__ dlt)
+                                                         Real* __restrict__ dlt, float* __restrict__ copy,
+                                                         unsigned int* __restrict__ zero)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (zero && i == 0) *zero = 0u;
     if (i >= nu) return;
     const double t = (double)bc_t[i];
     tot[i] = (Real)(t + beta_air);
     if (dlt) dlt[i] = (Real)(t - (double)bc_r[i]);
+    if (copy) copy[i] = bc_t[i];
 }
 
 hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const float* bc_r, double beta_air,
-                             int64_t nu, void* grid_tot, void* grid_dlt)
+                             int64_t nu, void* grid_tot, void* grid_dlt, float* copy, unsigned int* zero)
 {
     const int64_t blocks = (nu + 255) / 256;
     if (fp64)
         prep_grids_kernel<double><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(
-            bc_t, bc_r, beta_air, nu, (double*)grid_tot, (double*)grid_dlt);
+            bc_t, bc_r, beta_air, nu, (double*)grid_tot, (double*)grid_dlt, copy, zero);
     else
         prep_grids_kernel<float><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(
-            bc_t, bc_r, beta_air, nu, (float*)grid_tot, (float*)grid_dlt);
+            bc_t, bc_r, beta_air, nu, (float*)grid_tot, (float*)grid_dlt, copy, zero);
     return hipGetLastError();
 }
 

@@ -124,10 +124,6 @@ __device__ __forceinline__ void flush_counts(unsigned long long* c, uint64_t seg
 
 // ------------------------------------------------------------------ render
 
-__global__ void reset_u32_kernel(unsigned int* p, int n)
-{
-    if ((int)threadIdx.x < kTaskCounters * n) p[(threadIdx.x / n) * kTaskStride + threadIdx.x % n] = 0u;
-}
 
 // Persistent launch: each workgroup of kBlock threads sets up its LDS (image
 // tallies, extinction grid), then its wavefronts take (batch, camera group)
@@ -165,6 +161,13 @@ template <typename Real, bool kGridLds>
 __global__ void __launch_bounds__(kBlock) render_prefix_kernel(TraceArgs a)
 {
     extern __shared__ unsigned char smem[];
+    // the render kernel that follows takes its tasks from zeroed counters
+    if (blockIdx.x == 0 && threadIdx.x < kTaskCounters) a.work[threadIdx.x * kTaskStride] = 0u;
+    if (a.copy_beta) {
+        const int nu_ = a.s.nx * a.s.ny * a.s.nz;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nu_; i += gridDim.x * blockDim.x)
+            a.copy_beta[i] = a.bc_t[i];
+    }
     const Real* gd = delta_grid<Real, kGridLds>(a, smem);
     const DevScene& s = a.s;
     const int nu = s.nx * s.ny * s.nz;
@@ -511,11 +514,6 @@ hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCam
     return hipGetLastError();
 }
 
-hipError_t launch_reset_work(hipStream_t st, unsigned int* work, int n)
-{
-    reset_u32_kernel<<<dim3(1), dim3(64), 0, st>>>(work, n);
-    return hipGetLastError();
-}
 
 
 // images = tallies / (N Omega_p)
@@ -536,18 +534,22 @@ hipError_t launch_render_finalize(hipStream_t st, double* img, const DevCams& c,
 
 // rho = residual / (N Omega_p)
 __global__ void __launch_bounds__(256) grad_prep_kernel(const double* __restrict__ res, double* __restrict__ rho,
-                                                        DevCams c, double scale)
+                                                        DevCams c, double scale, int* __restrict__ flag,
+                                                        unsigned int* __restrict__ work)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && flag) *flag = 1;
+    if (i < 2 * kTaskCounters) work[(i / 2) * kTaskStride + i % 2] = 0u;
     const int64_t npix = (int64_t)c.W * c.H;
     if (i >= npix * c.n) return;
     rho[i] = res[i] * pixel_scale(c, i, scale);
 }
 
-hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho, const DevCams& c, double scale)
+hipError_t launch_grad_prep(hipStream_t st, const double* residual, double* rho, const DevCams& c, double scale,
+                            int* flag, unsigned int* work)
 {
-    const int64_t n = (int64_t)c.W * c.H * c.n;
-    grad_prep_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(residual, rho, c, scale);
+    const int64_t n = std::max<int64_t>((int64_t)c.W * c.H * c.n, 2 * kTaskCounters);
+    grad_prep_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(residual, rho, c, scale, flag, work);
     return hipGetLastError();
 }
 
@@ -898,9 +900,11 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
 
 // grad[v] = sum over workgroups of partial[w][v], in workgroup order.
 __global__ void __launch_bounds__(256) grad_reduce_kernel(const double* __restrict__ partial, int n_wg, int64_t nv,
-                                                          double* __restrict__ grad)
+                                                          double* __restrict__ grad, unsigned int* __restrict__ work)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // zeroes the task counters of the next slab's launch
+    if (v < 2 * kTaskCounters) work[(v / 2) * kTaskStride + v % 2] = 0u;
     if (v >= nv) return;
     double acc = 0.0;
     for (int w = 0; w < n_wg; ++w) acc += partial[(int64_t)w * nv + v];
@@ -978,14 +982,15 @@ hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCa
 }
 
 hipError_t launch_grad_reduce(hipStream_t st, const GradPlan& p, int nx, int ny, int nz, int slab,
-                              const void* partial, double* grad)
+                              const void* partial, double* grad, unsigned int* work)
 {
     if (!p.lds) return hipSuccess;
     int z0, z1;
     grad_slab(p, nz, slab, &z0, &z1);
     const int64_t layer = (int64_t)nx * ny, nv = (int64_t)(z1 - z0) * layer;
-    grad_reduce_kernel<<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st>>>((const double*)partial, p.n_wg,
-                                                                                nv, grad + z0 * layer);
+    const int64_t threads = std::max<int64_t>(nv, 2 * kTaskCounters);
+    grad_reduce_kernel<<<dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st>>>(
+        (const double*)partial, p.n_wg, nv, grad + z0 * layer, work);
     return hipGetLastError();
 }
 
@@ -997,13 +1002,9 @@ __global__ void __launch_bounds__(256) equal_flag_kernel(const float* __restrict
     if (i < n && __float_as_int(x[i]) != __float_as_int(y[i])) *flag = 0;
 }
 
-__global__ void set_flag_kernel(int* flag, int v) { *flag = v; }
 
 hipError_t launch_equal_flag(hipStream_t st, const float* x, const float* y, int64_t n, int* flag)
 {
-    set_flag_kernel<<<dim3(1), dim3(1), 0, st>>>(flag, 1);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     equal_flag_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(x, y, n, flag);
     return hipGetLastError();
 }
@@ -1081,6 +1082,8 @@ __global__ void __launch_bounds__(kBlock) reweight_kernel(TraceArgs a)
         a.partial[2 * blockIdx.x] = t0;
         a.partial[2 * blockIdx.x + 1] = t1;
     }
+    // the last workgroup writes (sum r, sum r^2)
+    finish_pairs(a.partial, a.rw_out, 1.0, true, a.rw_done);
 }
 
 hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int n_cu, int64_t* n_blocks)
