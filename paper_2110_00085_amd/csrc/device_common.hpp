@@ -156,52 +156,6 @@ __device__ __forceinline__ int project(const DevCams& c, int d, double x, double
     return row * c.W + col;
 }
 
-// ------------------------------------------------------- last-group sums
-
-// Every workgroup of the launch has written the pair (partial[2 g],
-// partial[2 g + 1]); the workgroup that arrives last at *done adds the pairs
-// in workgroup order (fixed per launch size: the result is reproducible),
-// writes out[0] = scale0 * sum0 and, with two_outputs, out[1] = sum1 (out may
-// be pinned host memory), and rearms *done for the next launch.  Called by
-// every thread of every workgroup after thread 0 has written its pair.
-__device__ inline void finish_pairs(const double* partial, double* out, double scale0, bool two_outputs,
-                                    unsigned int* done)
-{
-    __shared__ bool last;
-    __shared__ double red[2][1024 / kWave];
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double a = 0.0, b = 0.0;
-    for (unsigned int g = threadIdx.x; g < gridDim.x; g += blockDim.x) {
-        a += __hip_atomic_load(partial + 2 * g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        b += __hip_atomic_load(partial + 2 * g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        a += __shfl_down(a, o);
-        b += __shfl_down(b, o);
-    }
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    if (lane == 0) {
-        red[0][wave] = a;
-        red[1][wave] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t0 = 0.0, t1 = 0.0;
-        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
-            t0 += red[0][w];
-            t1 += red[1][w];
-        }
-        out[0] = t0 * scale0;
-        if (two_outputs) out[1] = t1;
-        *done = 0u;
-    }
-}
-
 // ------------------------------------------------------------- DDA walker
 
 // Steps of the incremental voxel walk along p + t w, from voxel (ix,iy,iz)

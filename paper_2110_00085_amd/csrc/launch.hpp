@@ -39,9 +39,7 @@ struct SampleArgs {
 // every wavefront's task requests on one address; a launch therefore spreads
 // its tasks over kTaskCounters counters on separate 128-byte lines, and a
 // context holds kWorkWords words of them (render/grad counters at word 0 and
-// 1 of each line, the sampler's id counter at word 2 of the first, and at
-// words 3 and 4 of the first the finished-workgroup counts of the loss and
-// the reweight).
+// 1 of each line, the sampler's id counter at word 2 of the first).
 constexpr int kTaskCounters = 8;
 constexpr int kTaskStride = 32;
 constexpr int kWorkWords = kTaskCounters * kTaskStride;
@@ -86,10 +84,6 @@ struct TraceArgs {
     // render prefix: also copies beta_t here (the tape's field) when set, and
     // zeroes the render's task counters
     float* copy_beta;
-    // reweight: (sum r, sum r^2) of all paths go to rw_out[0..1] (pinned host
-    // memory), *rw_done counts finished workgroups (zero at launch, rearmed)
-    double* rw_out;
-    unsigned int* rw_done;
 };
 
 // ---- sampling, sorting, packing (sample.hip)
@@ -180,11 +174,13 @@ hipError_t launch_equal_flag(hipStream_t st, const float* a, const float* b, int
 
 // ---- loop glue (loop.hip)
 hipError_t launch_fill(hipStream_t st, double* p, int64_t n, double v);
-// loss = 0.5 sum (img - tgt)^2 and res = img - tgt; *done counts finished
-// workgroups (zero at launch, rearmed by the kernel).
+// loss = 0.5 sum (img - tgt)^2 and res = img - tgt.
 hipError_t launch_loss(hipStream_t st, int64_t n, const double* img, const double* tgt, double* res,
-                       double* partial, double* loss, unsigned int* done);
+                       double* partial, double* loss);
 int64_t loss_blocks(int64_t n);
+// out2[0] = sum of partial[2 i], out2[1] = sum of partial[2 i + 1] over
+// i < n_blocks, in a fixed order (out2 may be pinned host memory).
+hipError_t launch_sum_pairs(hipStream_t st, const double* partial, int64_t n_blocks, double* out2);
 hipError_t launch_adam(hipStream_t st, int64_t n, double* beta, float* beta_f32, const double* grad, double* m,
                        double* v, double lr, double b1, double b2, double eps, double bc1, double bc2);
 

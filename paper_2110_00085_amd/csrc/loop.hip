@@ -25,8 +25,7 @@ int64_t loss_blocks(int64_t n) { return (n + kLossItems - 1) / kLossItems; }
 // residual = images - target; per-block sums of residual^2 into partial[2*b]
 __global__ void __launch_bounds__(256) loss_kernel(int64_t n, const double* __restrict__ img,
                                                    const double* __restrict__ tgt, double* __restrict__ res,
-                                                   double* __restrict__ partial, double* __restrict__ loss,
-                                                   unsigned int* __restrict__ done)
+                                                   double* __restrict__ partial)
 {
     __shared__ double red[256];
     const int64_t base = (int64_t)blockIdx.x * kLossItems;
@@ -49,15 +48,52 @@ __global__ void __launch_bounds__(256) loss_kernel(int64_t n, const double* __re
         partial[2 * blockIdx.x] = red[0];
         partial[2 * blockIdx.x + 1] = 0.0;
     }
-    // the last workgroup writes 0.5 * sum of squares
-    finish_pairs(partial, loss, 0.5, false, done);
+}
+
+// out2[0] = scale0 * sum of partial[2i]; out2[1] = sum of partial[2i+1]
+// (only when scale0 == 1); one block, fixed order.  A separate launch rather
+// than a last-workgroup sum: the device-scope fence that the latter needs
+// writes back the XCD's L2 in every workgroup, which cost ~60 us in the
+// reweight.
+__global__ void __launch_bounds__(256) sum_pairs_kernel(const double* __restrict__ partial, int64_t nb,
+                                                        double* __restrict__ out2, double scale0)
+{
+    __shared__ double red[2][256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) {
+        a += partial[2 * i];
+        b += partial[2 * i + 1];
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + o];
+            red[1][threadIdx.x] += red[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out2[0] = red[0][0] * scale0;
+        if (scale0 == 1.0) out2[1] = red[1][0];
+    }
 }
 
 hipError_t launch_loss(hipStream_t st, int64_t n, const double* img, const double* tgt, double* res,
-                       double* partial, double* loss, unsigned int* done)
+                       double* partial, double* loss)
 {
     const int64_t nb = loss_blocks(n);
-    loss_kernel<<<dim3((unsigned)nb), dim3(256), 0, st>>>(n, img, tgt, res, partial, loss, done);
+    loss_kernel<<<dim3((unsigned)nb), dim3(256), 0, st>>>(n, img, tgt, res, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sum_pairs_kernel<<<dim3(1), dim3(256), 0, st>>>(partial, nb, loss, 0.5);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_pairs(hipStream_t st, const double* partial, int64_t n_blocks, double* out2)
+{
+    sum_pairs_kernel<<<dim3(1), dim3(256), 0, st>>>(partial, n_blocks, out2, 1.0);
     return hipGetLastError();
 }
 

@@ -584,7 +584,7 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
     c->hsum = (double*)((char*)c->hpin + 32);
     c->dmeta = (int64_t*)dpin;
     c->dsum = (double*)((char*)dpin + 32);
-    // task counters start at zero; kernels that count finished workgroups rearm theirs
+    // task counters start at zero
     if (hipMemset(c->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(c->work, 0, kWorkWords * sizeof(unsigned int)) != hipSuccess) {
         (void)hipFree(c->work);
@@ -992,14 +992,13 @@ int prt_reweight(prt_ctx c, const prt_scene* s, prt_paths p, double* mean_r, dou
     a.grid_dlt = c->grid_dlt;
     a.partial = c->part;
     a.counters = c->counters;
-    a.rw_out = c->dsum;
-    a.rw_done = c->work + 4;
     int64_t nb = 0;
     {
         TimedScope ts(c, K_REWEIGHT);
         HIPCHK(launch_reweight(c->stream, c->fp64, a, c->n_cu, &nb));
+        HIPCHK(launch_sum_pairs(c->stream, c->part, nb, c->dsum));
     }
-    // the reweight kernel's last workgroup wrote the sums into pinned host memory
+    // the sums went to pinned host memory
     HIPCHK(hipStreamSynchronize(c->stream));
     const double h[2] = {c->hsum[0], c->hsum[1]};
     *mean_r = h[0] / (double)p->n;
@@ -1015,7 +1014,7 @@ int prt_loss(prt_ctx c, int64_t n, const double* images, const double* target, d
     int rc = ensure_part(c, 2 * loss_blocks(n));
     if (rc) return rc;
     TimedScope ts(c, K_LOSS);
-    HIPCHK(launch_loss(c->stream, n, images, target, residual, c->part, loss, c->work + 3));
+    HIPCHK(launch_loss(c->stream, n, images, target, residual, c->part, loss));
     return PRT_OK;
 }
 

@@ -1082,8 +1082,6 @@ __global__ void __launch_bounds__(kBlock) reweight_kernel(TraceArgs a)
         a.partial[2 * blockIdx.x] = t0;
         a.partial[2 * blockIdx.x + 1] = t1;
     }
-    // the last workgroup writes (sum r, sum r^2)
-    finish_pairs(a.partial, a.rw_out, 1.0, true, a.rw_done);
 }
 
 hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int n_cu, int64_t* n_blocks)
