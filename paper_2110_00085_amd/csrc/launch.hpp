@@ -63,8 +63,9 @@ struct TraceArgs {
     float2* tape;
     int64_t tape_base;        // records of the leading batches without scatters
     // Render prefix: pbase[batch_off[batch] - tape_base + 64*b + lane] =
-    // P_b / (beta_ref(x_b) + beta_air), the recycled weight of the sub-path
-    // x_0..x_b without its last direction factor and connection.
+    // base_b / base_{b-1} (base_0 = 1), base_b = P_b / (beta_ref(x_b) +
+    // beta_air) being the recycled weight of the sub-path x_0..x_b without its
+    // last direction factor and connection.
     double* pbase;
     const int* tape_flag;
     // Gradient weights (tape case): wtape has the tape's layout and holds
@@ -84,6 +85,18 @@ struct TraceArgs {
     // render prefix: also copies beta_t here (the tape's field) when set, and
     // zeroes the render's task counters
     float* copy_beta;
+};
+
+// Per-vertex task levels of the render prefix and the gradient weights: one
+// task per (batch, scatter index b) with a path of at least b scatters.  The
+// store is sorted by B, so the batches of level b are [first_batch[b],
+// n_batches); levels run from b = bmax down to 1, level b's tasks start at
+// start[b], and total counts them all.
+struct GwLevels {
+    int bmax;
+    uint32_t total;
+    int32_t first_batch[kMaxOrder + 1];
+    uint32_t start[kMaxOrder + 1];
 };
 
 // ---- sampling, sorting, packing (sample.hip)
@@ -107,7 +120,10 @@ hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, c
                        int64_t tmp_stride, const uint8_t* nv, const int64_t* batch_off, int64_t n,
                        int64_t n_slots, float4* vtx);
 // meta[0] = batch_off[nb] (records), meta[1] = first slot with B > 0 (n if
-// none), meta[2] = batch_off of that slot's batch (records of B = 0 batches).
+// none), meta[2] = batch_off of that slot's batch (records of B = 0 batches),
+// meta[kMetaFirstGe + k] = first slot with B >= k (n if none), k = 1..kMaxOrder.
+constexpr int kMetaFirstGe = 8;
+constexpr int kMetaWords = kMetaFirstGe + kMaxOrder + 1;
 hipError_t launch_store_meta(hipStream_t st, const uint8_t* B, int64_t n, const int64_t* batch_off, int64_t nb,
                              int64_t* meta);
 
@@ -127,8 +143,8 @@ RenderPlan plan_render(int fp64, int64_t nu, const DevCams& c, bool tape, int64_
 // Whether the render prefix and the reweight form beta_t - beta_ref in LDS
 // (then they need no prepared delta grid).
 bool delta_grid_lds(int fp64, int64_t nu);
-// Per-vertex prefix weights of the render (one lane per path).
-hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, int n_cu);
+// Per-vertex prefix factors of the render, one task per (batch, b <= brender).
+hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, const GwLevels& lv, int n_cu);
 // The persistent render kernel alone (its task counter a.work[0] must be zero,
 // a.pbase filled by launch_render_prefix);
 // with img_lds, launch_render_reduce then adds the partials into the images.
@@ -155,7 +171,7 @@ struct GradPlan {
 };
 GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu, bool tape);
 // Gradient weights from the tape (runs only when *a.tape_flag is 1).
-hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c);
+hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c, const GwLevels& lv, int n_cu);
 // Gradient terms of slab i (z layers [i*slab_layers, min(nz, (i+1)*slab_layers))):
 // the persistent grad kernels (task counters a.work[0] and a.work[1] must be
 // zero): with a tape flag, the walk kernel on the stored weights and the

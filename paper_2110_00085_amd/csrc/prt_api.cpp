@@ -75,7 +75,8 @@ struct prt_ctx_s {
     size_t s_perm_bytes = 0;
     size_t s_off_bytes = 0;
     // pinned host words the kernels write directly (read after a stream sync):
-    // the store's 3 int64 sizes after packing, and the reweight's 2 sums
+    // the store's meta words after packing (words 0-2 and kMetaFirstGe on),
+    // and the reweight's 2 sums (bytes 32-47, words 4-5 of the meta layout)
     void* hpin = nullptr;
     int64_t* hmeta = nullptr;
     double* hsum = nullptr;
@@ -106,6 +107,9 @@ struct prt_paths_s {
     int64_t cap_perm = 0, cap_slots = 0, cap_nv = 0, cap_boff = 0, cap_records = 0, cap_nu = 0;
     uint64_t n = 0;
     int64_t nb = 0, n_slots = 0, first_slot = 0;
+    // largest B, and for b = 1..bmax the batch of the first sorted slot with B >= b
+    int bmax = 0;
+    int32_t first_batch_ge[kMaxOrder + 1] = {};
     int32_t max_order = 0, nx = 0, ny = 0, nz = 0;
     uint64_t seed = 0;
     float4* vtx = nullptr;
@@ -436,6 +440,13 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
     p->n_records = c->hmeta[0];
     p->first_slot = c->hmeta[1];
     p->tape_base = c->hmeta[2];
+    p->bmax = 0;
+    for (int k = 1; k <= p->max_order && k <= kMaxOrder; ++k) {
+        const int64_t f = c->hmeta[kMetaFirstGe + k];
+        if (f >= n) break;
+        p->bmax = k;
+        p->first_batch_ge[k] = (int32_t)(f / kWave);
+    }
     if ((rc = grow(&p->vtx, &p->cap_records, p->n_records))) return rc;
     {
         TimedScope ts(c, K_PACK);
@@ -530,6 +541,19 @@ prt_paths new_store(prt_ctx c, const prt_scene* s, uint64_t n, uint64_t seed)
     return p;
 }
 
+// Per-vertex task levels of the store up to scatter index bmax.
+GwLevels task_levels(const prt_paths_s* p, int bmax)
+{
+    GwLevels lv{};
+    lv.bmax = std::min(bmax, p->bmax);
+    for (int b = lv.bmax; b >= 1; --b) {
+        lv.first_batch[b] = p->first_batch_ge[b];
+        lv.start[b] = lv.total;
+        lv.total += (uint32_t)(p->nb - p->first_batch_ge[b]);
+    }
+    return lv;
+}
+
 StoreView view_of(prt_paths p)
 {
     StoreView v;
@@ -570,7 +594,7 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
     if (hipMalloc((void**)&c->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&c->flag, sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&c->work, kWorkWords * sizeof(unsigned int)) != hipSuccess ||
-        hipHostMalloc(&c->hpin, 64, hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(&c->hpin, kMetaWords * sizeof(int64_t), hipHostMallocCoherent) != hipSuccess ||
         hipHostGetDevicePointer(&dpin, c->hpin, 0) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(c->work);
@@ -666,6 +690,7 @@ int prt_resample(prt_ctx c, const prt_scene* s, uint64_t seed, uint64_t n_paths,
         // the store is left empty but valid
         p->n = 0;
         p->nb = p->n_slots = p->first_slot = p->n_records = 0;
+        p->bmax = 0;
         p->tape_valid = false;
         return rc;
     }
@@ -870,7 +895,7 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
         {
             TimedScope ts(c, K_RENDER_PREFIX);
             // also zeroes the render's task counters and copies the tape's beta_t
-            HIPCHK(launch_render_prefix(c->stream, c->fp64, a, c->n_cu));
+            HIPCHK(launch_render_prefix(c->stream, c->fp64, a, task_levels(p, a.brender), c->n_cu));
         }
         {
             TimedScope ts(c, K_RENDER);
@@ -951,7 +976,7 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
         a.wtape = (float*)c->gw;
         a.vaux = (float4*)c->gaux;
         TimedScope ts(c, K_GRAD_WEIGHTS);
-        HIPCHK(launch_grad_weights(c->stream, a, dc));
+        HIPCHK(launch_grad_weights(c->stream, a, dc, task_levels(p, p->bmax), c->n_cu));
     }
     if ((rc = ensure_scratch(&c->gpart, &c->gpart_bytes, plan.partial_bytes))) return rc;
     // task counters: zeroed by launch_grad_prep for the first slab, by each

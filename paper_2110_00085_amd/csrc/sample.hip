@@ -472,21 +472,26 @@ hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, c
 __global__ void store_meta_kernel(const uint8_t* __restrict__ B, int64_t n, const int64_t* __restrict__ batch_off,
                                   int64_t nb, int64_t* __restrict__ meta)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int64_t lo = 0, hi = n;  // slots are sorted by B: binary search for the first B > 0
+    // slots are sorted by B: thread k-1 binary-searches the first slot with B >= k
+    const int k = (int)threadIdx.x + 1;
+    if (blockIdx.x != 0 || k > kMaxOrder) return;
+    int64_t lo = 0, hi = n;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo) / 2;
-        if (B[mid] > 0) hi = mid; else lo = mid + 1;
+        if ((int)B[mid] >= k) hi = mid; else lo = mid + 1;
     }
-    meta[0] = batch_off[nb];
-    meta[1] = lo;
-    meta[2] = lo < n ? batch_off[lo / kWave] : batch_off[nb];
+    meta[kMetaFirstGe + k] = lo;
+    if (k == 1) {
+        meta[0] = batch_off[nb];
+        meta[1] = lo;
+        meta[2] = lo < n ? batch_off[lo / kWave] : batch_off[nb];
+    }
 }
 
 hipError_t launch_store_meta(hipStream_t st, const uint8_t* B, int64_t n, const int64_t* batch_off, int64_t nb,
                              int64_t* meta)
 {
-    store_meta_kernel<<<dim3(1), dim3(64), 0, st>>>(B, n, batch_off, nb, meta);
+    store_meta_kernel<<<dim3(1), dim3(kMaxOrder), 0, st>>>(B, n, batch_off, nb, meta);
     return hipGetLastError();
 }
 

@@ -151,14 +151,18 @@ __device__ __forceinline__ const Real* delta_grid(const TraceArgs& a, unsigned c
 
 bool delta_grid_lds(int fp64, int64_t nu) { return (size_t)nu * (fp64 ? 8 : 4) <= kLdsBudget; }
 
-// Prefix weights, one lane per path (persistent workgroups, the field
-// beta_t - beta_ref cached in LDS when it fits): walks the free-flight
-// segments once and stores, for every scatter b <= brender,
+// Prefix weights, one wavefront per task (batch, b) with the field
+// beta_t - beta_ref cached in LDS when it fits (persistent workgroups): a lane
+// holds one path of the batch at its scatter b <= brender and stores
+// q_b = base_b / base_{b-1} (base_0 = 1), where
 // base_b = P_b / (beta_ref(x_b) + beta_air) with P_b = w0 prod_{k<b}
 // exp(-(tau_t - tau_ref)(segment k)) prod_{1<=k<b} albedo_ref f_s,t / f_s,ref (x_k):
-// every local estimate at x_b is base_b f_s,t(x_b, mu_bd) exp(-tau_t(connection)) / r^2.
+// every local estimate at x_b is base_b f_s,t(x_b, mu_bd) exp(-tau_t(connection)) / r^2,
+// and the render forms base_b as the running product of q_1..q_b.  The
+// factor of scatter b needs only the segment x_{b-1} -> x_b and the vertex
+// x_{b-1}, so the segments of a path are walked by different wavefronts.
 template <typename Real, bool kGridLds>
-__global__ void __launch_bounds__(kBlock) render_prefix_kernel(TraceArgs a)
+__global__ void __launch_bounds__(kBlock) render_prefix_kernel(TraceArgs a, GwLevels lv)
 {
     extern __shared__ unsigned char smem[];
     // the render kernel that follows takes its tasks from zeroed counters
@@ -171,65 +175,69 @@ __global__ void __launch_bounds__(kBlock) render_prefix_kernel(TraceArgs a)
     const Real* gd = delta_grid<Real, kGridLds>(a, smem);
     const DevScene& s = a.s;
     const int nu = s.nx * s.ny * s.nz;
+    const int64_t nb = a.st.n_slots / kWave;
+    const int lane = threadIdx.x % kWave;
+    const uint32_t waves = gridDim.x * kWavesPerBlock;
     uint64_t nseg = 0;
-    // slots in batch order from the heaviest batch (the end of the store) down
-    const int64_t n_work = a.st.n_slots - a.st.first_slot / kWave * kWave;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_work; r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t slot = (a.st.n_slots / kWave - 1 - r / kWave) * kWave + r % kWave;
-        const int Br = min((int)a.st.B[slot], a.brender);
-        if (Br <= 0) continue;
-        const int64_t bt = slot / kWave, lane = slot % kWave;
+    int b = lv.bmax;
+    for (uint32_t task = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; task < lv.total; task += waves) {
+        // levels are contiguous task ranges in falling b (wavefront-uniform)
+        while (task >= lv.start[b] + (uint32_t)(nb - lv.first_batch[b])) --b;
+        const int64_t bt = lv.first_batch[b] + (int64_t)(task - lv.start[b]);
+        const int64_t slot = bt * kWave + lane;
+        if (b > min((int)a.st.B[slot], a.brender)) continue;
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
-        double* __restrict__ out = a.pbase + (a.st.batch_off[bt] - a.tape_base) + lane;
-        Vtx p0 = load_vtx(V, 0);
-        double P = s.w0;
-        double wprev[3] = {0.0, 0.0, 0.0};
-        for (int b = 1; b <= Br; ++b) {
-            const Vtx p1 = load_vtx(V, b);
-            double w[3];
-            const double L = seg_dir(p0, p1, w);
-            // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
-            const Real dt = walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, nseg);
-            P *= exp(-(double)dt * s.vk);
-            if (b >= 2) {
-                const int v = clamp_vox(p0.v, nu);
-                P *= vertex_ratio(s, (double)a.bc_t[v], (double)a.st.beta_ref[v],
-                                  wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2]);
-            }
-            out[(int64_t)b * kWave] = P / ((double)a.st.beta_ref[clamp_vox(p1.v, nu)] + s.beta_air);
-            wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
-            p0 = p1;
+        const Vtx p0 = load_vtx(V, b - 1), p1 = load_vtx(V, b);
+        double w[3];
+        const double L = seg_dir(p0, p1, w);
+        // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
+        const Real dt = walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, nseg);
+        double q = exp(-(double)dt * s.vk);
+        if (b == 1) {
+            q *= s.w0;
+        } else {
+            // albedo_ref f_s,t / f_s,ref at x_{b-1} times base_{b-1}'s denominator
+            const Vtx pm = load_vtx(V, b - 2);
+            double wp[3];
+            seg_dir(pm, p0, wp);
+            const int v = clamp_vox(p0.v, nu);
+            const double bct = (double)a.bc_t[v], bcr = (double)a.st.beta_ref[v];
+            const double mu = wp[0] * w[0] + wp[1] * w[1] + wp[2] * w[2];
+            const double hg = phase_hg(s, mu), ra = phase_rayleigh(mu);
+            q *= (s.w_c * bcr + s.w_a * s.beta_air) * (fs_mix(s, bct, hg, ra) / fs_mix(s, bcr, hg, ra));
         }
+        a.pbase[(a.st.batch_off[bt] - a.tape_base) + lane + (int64_t)b * kWave] =
+            q / ((double)a.st.beta_ref[clamp_vox(p1.v, nu)] + s.beta_air);
     }
     flush_counts(a.counters, nseg, 0, 0);
 }
 
 // Persistent launch with the delta grid in LDS when it fits.
-template <typename K>
+template <typename K, typename... Args>
 static hipError_t launch_delta_kernel(hipStream_t st, K k, bool lds_grid, size_t grid_bytes, int n_wg,
-                                      const TraceArgs& a)
+                                      const Args&... args)
 {
     const size_t lds = lds_grid ? grid_bytes : 0;
     if (lds) {
         hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k<<<dim3(n_wg), dim3(kBlock), lds, st>>>(a);
+    k<<<dim3(n_wg), dim3(kBlock), lds, st>>>(args...);
     return hipGetLastError();
 }
 
-hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, int n_cu)
+hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, const GwLevels& lv, int n_cu)
 {
-    const int64_t slots = a.st.n_slots - a.st.first_slot / kWave * kWave;
-    if (slots <= 0) return hipSuccess;
+    if (lv.total == 0) return hipSuccess;
     const size_t grid_bytes = (size_t)a.s.nx * a.s.ny * a.s.nz * (fp64 ? 8 : 4);
     const bool lds = grid_bytes <= kLdsBudget;
-    const int n_wg = (int)std::max<int64_t>(1, std::min<int64_t>((slots + kBlock - 1) / kBlock, n_cu));
+    const int n_wg = (int)std::max<int64_t>(
+        1, std::min<int64_t>(((int64_t)lv.total + kWavesPerBlock - 1) / kWavesPerBlock, n_cu));
     if (fp64)
-        return lds ? launch_delta_kernel(st, render_prefix_kernel<double, true>, true, grid_bytes, n_wg, a)
-                   : launch_delta_kernel(st, render_prefix_kernel<double, false>, false, grid_bytes, n_wg, a);
-    return lds ? launch_delta_kernel(st, render_prefix_kernel<float, true>, true, grid_bytes, n_wg, a)
-               : launch_delta_kernel(st, render_prefix_kernel<float, false>, false, grid_bytes, n_wg, a);
+        return lds ? launch_delta_kernel(st, render_prefix_kernel<double, true>, true, grid_bytes, n_wg, a, lv)
+                   : launch_delta_kernel(st, render_prefix_kernel<double, false>, false, grid_bytes, n_wg, a, lv);
+    return lds ? launch_delta_kernel(st, render_prefix_kernel<float, true>, true, grid_bytes, n_wg, a, lv)
+               : launch_delta_kernel(st, render_prefix_kernel<float, false>, false, grid_bytes, n_wg, a, lv);
 }
 
 // Local estimates from the stored paths.  Tasks are (batch, camera group),
@@ -283,13 +291,14 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
         const double* __restrict__ Pb = a.pbase + (a.st.batch_off[bt] - a.tape_base) + lane;
         float2* __restrict__ T = kTape ? a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane : nullptr;
         Vtx p0 = load_vtx(V, 0);
+        double base = 1.0;
         for (int b = 1; b <= Br; ++b) {
             const Vtx p1 = load_vtx(V, b);
             double w[3];
             seg_dir(p0, p1, w);
             const int v1 = clamp_vox(p1.v, nu);
             const double bct = (double)a.bc_t[v1];
-            const double base = Pb[(int64_t)b * kWave];
+            base *= Pb[(int64_t)b * kWave];
             const float wcb = wc_f * (float)bct;
             for (int d = d_lo; d < d_hi; ++d) {
                 const int pix = project(cams, d, p1.x, p1.y, p1.z, s.vk);
@@ -615,41 +624,50 @@ __device__ __forceinline__ void slab_tally_end(const SlabTally<kLds>& t, double*
     for (int i = threadIdx.x; i < t.nsv; i += kBlock) out[i] = t.out[i];
 }
 
-// Weights from the transmittance tape, one lane per path: for every (b, d)
-// w_{b,d} = c_{b,d} rho_{d,p} with c and the pixel p from the tape (0 when
-// x_b projects outside camera d), and per vertex R_b, the connection vertex
-// term sum_d w_{b,d} w_c f_HG / f_s,t at x_b, and the coefficient
-// w_c f_HG / f_s,t of the scatter at x_b between segments b-1 and b.  Runs
-// only when the tape matches beta_t (FP32 traversal mode): the per-camera
-// phase functions are evaluated in FP32, like the stored weights.
+// Weights from the transmittance tape, one wavefront per task (batch, b): a
+// lane holds one path of the batch at its scatter b and writes, for every
+// camera d, w_{b,d} = c_{b,d} rho_{d,p} with c and the pixel p from the tape
+// (0 when x_b projects outside camera d), and for the vertex R_b, the
+// connection vertex term sum_d w_{b,d} w_c f_HG / f_s,t at x_b, and the
+// coefficient w_c f_HG / f_s,t of the scatter at x_b between segments b-1 and
+// b.  The vertices of a path are independent here, so a path's vertices go to
+// different wavefronts and their loads overlap.  Runs only when the tape
+// matches beta_t (FP32 traversal mode): the per-camera phase functions are
+// evaluated in FP32, like the stored weights.
 
 constexpr int kGwCams = 8;
+constexpr int kGwBlock = 256;
+constexpr int kGwBlocksPerCU = 8;
 
-__global__ void __launch_bounds__(256) grad_weights_kernel(TraceArgs a, DevCams cams)
+__global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, DevCams cams, GwLevels lv)
 {
     if (*a.tape_flag == 0) return;
-    // heaviest batches (largest B, at the end of the store) first
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t bt_first = a.st.n_slots / kWave - 1 - t / kWave;
-    if (bt_first < a.st.first_slot / kWave) return;
-    const int64_t slot = bt_first * kWave + t % kWave;
-    const int Bn = (int)a.st.B[slot];
-    if (Bn <= 0) return;
+    __shared__ unsigned long long wg_le;
+    if (threadIdx.x == 0) wg_le = 0;
+    __syncthreads();
     const DevScene& s = a.s;
     const int nu = s.nx * s.ny * s.nz;
     const int npix = cams.W * cams.H;
-    const int64_t bt = slot / kWave, lane = slot % kWave;
-    const int64_t rec0 = a.st.batch_off[bt] - a.tape_base;
-    const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
-    const float2* __restrict__ Tp = a.tape + rec0 * cams.n + lane;
-    float* __restrict__ Wp = a.wtape + rec0 * cams.n + lane;
-    float4* __restrict__ X = a.vaux + rec0 + lane;
+    const int64_t nb = a.st.n_slots / kWave;
+    const int lane = threadIdx.x % kWave;
+    const uint32_t waves = gridDim.x * (kGwBlock / kWave);
     const float wc = (float)s.w_c, wab = (float)(s.w_a * s.beta_air), ray_k = (float)(3.0 / (16.0 * kPi));
     uint64_t nle = 0;
-    Vtx p0 = load_vtx(V, 0), p1 = load_vtx(V, 1);
-    double w[3];
-    seg_dir(p0, p1, w);
-    for (int b = 1; b <= Bn; ++b) {
+    int b = lv.bmax;
+    for (uint32_t task = blockIdx.x * (kGwBlock / kWave) + threadIdx.x / kWave; task < lv.total; task += waves) {
+        // levels are contiguous task ranges in falling b (wavefront-uniform)
+        while (task >= lv.start[b] + (uint32_t)(nb - lv.first_batch[b])) --b;
+        const int64_t bt = lv.first_batch[b] + (int64_t)(task - lv.start[b]);
+        const int64_t slot = bt * kWave + lane;
+        const int Bn = (int)a.st.B[slot];
+        if (b > Bn) continue;
+        const int64_t rec0 = a.st.batch_off[bt] - a.tape_base;
+        const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+        const float2* __restrict__ Tp = a.tape + rec0 * cams.n + lane;
+        float* __restrict__ Wp = a.wtape + rec0 * cams.n + lane;
+        const Vtx p0 = load_vtx(V, b - 1), p1 = load_vtx(V, b);
+        double w[3];
+        seg_dir(p0, p1, w);
         const int v1 = clamp_vox(p1.v, nu);
         const double bct = (double)a.bc_t[v1];
         const float wcb = wc * (float)bct;
@@ -690,28 +708,30 @@ __global__ void __launch_bounds__(256) grad_weights_kernel(TraceArgs a, DevCams 
             }
         }
         // the scatter at x_b turns segment b-1 (direction w) into segment b
-        double coef = 0.0, wn[3] = {0.0, 0.0, 0.0};
-        Vtx p2 = p1;
+        double coef = 0.0;
         if (b < Bn) {
-            p2 = load_vtx(V, b + 1);
+            const Vtx p2 = load_vtx(V, b + 1);
+            double wn[3];
             seg_dir(p1, p2, wn);
             const double mu = w[0] * wn[0] + w[1] * wn[1] + w[2] * wn[2];
             const double hg = phase_hg(s, mu);
             const double fst = fs_mix(s, bct, hg, phase_rayleigh(mu));
             if (fst > 0.0) coef = s.w_c * hg / fst;
         }
-        X[(int64_t)b * kWave] = make_float4(Rb, vert, (float)coef, 0.f);
-        w[0] = wn[0]; w[1] = wn[1]; w[2] = wn[2];
-        p1 = p2;
+        a.vaux[rec0 + lane + (int64_t)b * kWave] = make_float4(Rb, vert, (float)coef, 0.f);
     }
-    flush_counts(a.counters, 0, nle, 0);
+    // one counter update per workgroup
+    if (nle) atomicAdd(&wg_le, (unsigned long long)nle);
+    __syncthreads();
+    if (threadIdx.x == 0 && wg_le) atomicAdd(&a.counters[1], wg_le);
 }
 
-hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c)
+hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c, const GwLevels& lv, int n_cu)
 {
-    const int64_t slots = a.st.n_slots - a.st.first_slot / kWave * kWave;
-    if (slots <= 0) return hipSuccess;
-    grad_weights_kernel<<<dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st>>>(a, c);
+    if (lv.total == 0) return hipSuccess;
+    const uint32_t per_wg = kGwBlock / kWave;
+    const int64_t blocks = std::min<int64_t>(((int64_t)lv.total + per_wg - 1) / per_wg, (int64_t)n_cu * kGwBlocksPerCU);
+    grad_weights_kernel<<<dim3((unsigned)blocks), dim3(kGwBlock), 0, st>>>(a, c, lv);
     return hipGetLastError();
 }
 
