@@ -136,6 +136,7 @@ hipError_t launch_store_meta(hipStream_t st, const uint8_t* B, int64_t n, const 
 struct RenderPlan {
     bool img_lds = false, grid_lds = false, img_tape = false;
     int n_wg = 1;
+    int img_groups = 0;  // img_tape: image partials per camera
     size_t partial_bytes = 0;
 };
 RenderPlan plan_render(int fp64, int64_t nu, const DevCams& c, bool tape, int64_t n_slots, int64_t first_slot,

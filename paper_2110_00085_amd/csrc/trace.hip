@@ -400,8 +400,17 @@ static hipError_t launch_render_t(hipStream_t st, const TraceArgs& a, const DevC
 // Images from the tape: workgroup (x, d) adds the contributions c_{b,d} of
 // every scatter of a strided share of the batches into an FP64 LDS image of
 // camera d and writes it to partial[d][x]; tape_image_reduce_kernel adds the
-// kTapeImageGroups partials of each pixel in a fixed order.
-constexpr int kTapeImageGroups = 64;
+// partials of each pixel in a fixed order.  The groups x are as many as fit
+// the chip at once (kTapeImageBlocksPerCU workgroups per CU over all cameras),
+// and a wavefront issues the tape loads of up to kTapeImageLoads scatters of
+// its batch before it adds them, with the next batch's sizes already loading.
+constexpr int kTapeImageBlocksPerCU = 2;
+constexpr int kTapeImageLoads = 8;
+
+int tape_image_groups(int n_cu, int n_cams)
+{
+    return std::max(1, kTapeImageBlocksPerCU * n_cu / std::max(1, n_cams));
+}
 
 __global__ void __launch_bounds__(kBlock) tape_image_kernel(TraceArgs a, DevCams cams, double* __restrict__ partial)
 {
@@ -411,17 +420,28 @@ __global__ void __launch_bounds__(kBlock) tape_image_kernel(TraceArgs a, DevCams
     const int d = blockIdx.y;
     for (int i = threadIdx.x; i < npix; i += blockDim.x) simg[i] = 0.0;
     __syncthreads();
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, waves = blockDim.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t nb = a.st.n_slots / kWave;
-    for (int64_t bt = a.st.first_slot / kWave + (int64_t)blockIdx.x * waves + wave; bt < nb;
-         bt += (int64_t)gridDim.x * waves) {
-        const int Br = min((int)a.st.B[bt * kWave + lane], a.brender);
-        const float2* __restrict__ T = a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + lane;
-        for (int b = 1; b <= Br; ++b) {
-            const float2 t = T[(int64_t)(b * cams.n + d) * kWave];
-            const int pix = __float_as_int(t.y);
-            if (pix >= 0) atomicAdd(&simg[pix], (double)t.x);
+    const int64_t stride = (int64_t)cams.n * kWave;
+    int64_t bt = a.st.first_slot / kWave + (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    int Br = bt < nb ? min((int)a.st.B[bt * kWave + lane], a.brender) : 0;
+    for (; bt < nb; bt += waves) {
+        const int64_t btn = bt + waves;
+        const int Bnext = btn < nb ? min((int)a.st.B[btn * kWave + lane], a.brender) : 0;
+        const float2* __restrict__ T = a.tape + (a.st.batch_off[bt] - a.tape_base) * cams.n + d * kWave + lane;
+        for (int b0 = 1; b0 <= Br; b0 += kTapeImageLoads) {
+            float2 t[kTapeImageLoads];
+#pragma unroll
+            for (int j = 0; j < kTapeImageLoads; ++j)
+                t[j] = b0 + j <= Br ? T[(int64_t)(b0 + j) * stride] : make_float2(0.f, __int_as_float(-1));
+#pragma unroll
+            for (int j = 0; j < kTapeImageLoads; ++j) {
+                const int pix = __float_as_int(t[j].y);
+                if (pix >= 0) atomicAdd(&simg[pix], (double)t[j].x);
+            }
         }
+        Br = Bnext;
     }
     __syncthreads();
     double* __restrict__ out = partial + ((int64_t)d * gridDim.x + blockIdx.x) * npix;
@@ -459,7 +479,8 @@ RenderPlan plan_render(int fp64, int64_t nu, const DevCams& c, bool tape, int64_
         p.img_tape = true;
         p.grid_lds = grid_bytes <= (int64_t)kLdsBudget;
         p.n_wg = persistent_groups(n_slots, first_slot, n_cu, p.grid_lds ? 1 : 2);
-        p.partial_bytes = (size_t)nimg * kTapeImageGroups * sizeof(double);
+        p.img_groups = tape_image_groups(n_cu, c.n);
+        p.partial_bytes = (size_t)nimg * p.img_groups * sizeof(double);
         return p;
     }
     // FP32 image partials only in FP32 traversal mode (the all-FP64 mode keeps FP64 tallies)
@@ -511,10 +532,10 @@ hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCam
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
-        tape_image_kernel<<<dim3(kTapeImageGroups, c.n), dim3(kBlock), lds, st>>>(a, c, (double*)partial);
+        tape_image_kernel<<<dim3(p.img_groups, c.n), dim3(kBlock), lds, st>>>(a, c, (double*)partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        tape_image_reduce_kernel<<<dim3(blocks), dim3(256), 0, st>>>((const double*)partial, kTapeImageGroups,
+        tape_image_reduce_kernel<<<dim3(blocks), dim3(256), 0, st>>>((const double*)partial, p.img_groups,
                                                                       (int)npix, nimg, c, scale, img);
         return hipGetLastError();
     }
