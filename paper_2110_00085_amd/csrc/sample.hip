@@ -439,6 +439,8 @@ hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, i
 
 // One thread per sorted slot: copy the path's records into its lane of the
 // batch (rows beyond its own vertex count are zero-filled).
+constexpr int kPackLoads = 4;
+
 __global__ void __launch_bounds__(256) pack_kernel(const int32_t* __restrict__ perm, const float4* __restrict__ tmp,
                                                    const int64_t* __restrict__ tmp_off, int64_t tmp_stride,
                                                    const uint8_t* __restrict__ nv,
@@ -456,7 +458,15 @@ __global__ void __launch_bounds__(256) pack_kernel(const int32_t* __restrict__ p
         const int64_t id = perm[i];
         src = tmp + (tmp_off ? tmp_off[id] : id * tmp_stride);
     }
-    for (int64_t k = 0; k < rows; ++k) dst[k * kWave] = k < cnt ? src[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // kPackLoads records of the path in flight at a time
+    for (int64_t k0 = 0; k0 < rows; k0 += kPackLoads) {
+        float4 r[kPackLoads];
+#pragma unroll
+        for (int j = 0; j < kPackLoads; ++j) r[j] = k0 + j < cnt ? src[k0 + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < kPackLoads; ++j)
+            if (k0 + j < rows) dst[(k0 + j) * kWave] = r[j];
+    }
 }
 
 hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, const int64_t* tmp_off,

@@ -939,17 +939,43 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
     slab_tally_end<kLds>(tally, partial);
 }
 
-// grad[v] = sum over workgroups of partial[w][v], in workgroup order.
-__global__ void __launch_bounds__(256) grad_reduce_kernel(const double* __restrict__ partial, int n_wg, int64_t nv,
-                                                          double* __restrict__ grad, unsigned int* __restrict__ work)
+// grad[v] = sum over workgroups of partial[w][v] in a fixed order: a
+// workgroup covers 64 voxels, its wavefront c sums the partials of the c-th
+// contiguous share of the workgroups (kReduceChunks shares, kReduceLoads loads
+// in flight per lane), and the shares are added in order.
+constexpr int kReduceChunks = 8;
+constexpr int kReduceLoads = 8;
+
+__global__ void __launch_bounds__(kReduceChunks * kWave) grad_reduce_kernel(const double* __restrict__ partial,
+                                                                           int n_wg, int64_t nv,
+                                                                           double* __restrict__ grad,
+                                                                           unsigned int* __restrict__ work)
 {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double red[kReduceChunks][kWave];
     // zeroes the task counters of the next slab's launch
-    if (v < 2 * kTaskCounters) work[(v / 2) * kTaskStride + v % 2] = 0u;
-    if (v >= nv) return;
+    if (blockIdx.x == 0 && threadIdx.x < 2 * kTaskCounters)
+        work[(threadIdx.x / 2) * kTaskStride + threadIdx.x % 2] = 0u;
+    const int lane = threadIdx.x % kWave, c = threadIdx.x / kWave;
+    const int64_t v = (int64_t)blockIdx.x * kWave + lane;
+    const int cs = (n_wg + kReduceChunks - 1) / kReduceChunks;
+    const int w0 = c * cs, w1 = min(n_wg, w0 + cs);
     double acc = 0.0;
-    for (int w = 0; w < n_wg; ++w) acc += partial[(int64_t)w * nv + v];
-    grad[v] = acc;
+    if (v < nv) {
+        for (int w = w0; w < w1; w += kReduceLoads) {
+            double x[kReduceLoads];
+#pragma unroll
+            for (int j = 0; j < kReduceLoads; ++j) x[j] = w + j < w1 ? partial[(int64_t)(w + j) * nv + v] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kReduceLoads; ++j) acc += x[j];
+        }
+    }
+    red[c][lane] = acc;
+    __syncthreads();
+    if (c == 0 && v < nv) {
+        double t = 0.0;
+        for (int k = 0; k < kReduceChunks; ++k) t += red[k][lane];
+        grad[v] = t;
+    }
 }
 
 template <typename Kern>
@@ -1029,9 +1055,8 @@ hipError_t launch_grad_reduce(hipStream_t st, const GradPlan& p, int nx, int ny,
     int z0, z1;
     grad_slab(p, nz, slab, &z0, &z1);
     const int64_t layer = (int64_t)nx * ny, nv = (int64_t)(z1 - z0) * layer;
-    const int64_t threads = std::max<int64_t>(nv, 2 * kTaskCounters);
-    grad_reduce_kernel<<<dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st>>>(
-        (const double*)partial, p.n_wg, nv, grad + z0 * layer, work);
+    grad_reduce_kernel<<<dim3((unsigned)std::max<int64_t>(1, (nv + kWave - 1) / kWave)), dim3(kReduceChunks * kWave),
+                         0, st>>>((const double*)partial, p.n_wg, nv, grad + z0 * layer, work);
     return hipGetLastError();
 }
 
