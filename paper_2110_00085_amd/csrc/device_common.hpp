@@ -236,20 +236,23 @@ __device__ __forceinline__ bool dda_dir(Real wx, Real wy, Real wz, int& sx, int&
     return sx != 0 || sy != 0 || sz != 0;
 }
 
-// Walk over the whole grid from p (in voxel (ix,iy,iz)) for t in [0, tmax].
+// Walk over the whole grid from p (in voxel (ix,iy,iz)) until the ray leaves
+// the grid (or the functor stops it); no length bound, so the loop tests only
+// the face counts.
 template <typename Real, typename F>
 __device__ __forceinline__ Real dda_walk(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy,
-                                         int iz, Real wx, Real wy, Real wz, Real tmax, F&& f)
+                                         int iz, Real wx, Real wy, Real wz, F&& f)
 {
     int sx, sy, sz;
     Real ivx, ivy, ivz;
     if (!dda_dir(wx, wy, wz, sx, sy, sz, ivx, ivy, ivz)) return (Real)0;
     uint32_t pieces = 0;
-    return dda_steps<Real>(nx, ny, 0, nz, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, (Real)0, tmax, pieces,
-                           f);
+    return dda_steps<Real, false>(nx, ny, 0, nz, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, (Real)0,
+                                  (Real)INFINITY, pieces, f);
 }
 
-// As dda_walk, adding the number of pieces visited to *pieces.
+// As dda_walk for t in [0, tmax] (unbounded without kBounded), adding the
+// number of pieces visited to *pieces.
 template <typename Real, bool kBounded = true, typename F>
 __device__ __forceinline__ Real dda_walk_counted(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy,
                                                  int iz, Real wx, Real wy, Real wz, Real tmax, uint32_t& pieces,

@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
         int hit = -1;
         const Real tend = dda_walk<Real>(
             s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy, iz, (Real)w[0], (Real)w[1], (Real)w[2],
-            (Real)INFINITY, [&](int vv, Real t0, Real l) {
+            [&](int vv, Real t0, Real l) {
                 const Real dt = gt[vv] * l;  // zero for an empty voxel or a zero-length piece
                 if (taur < acc + dt) {
                     hit = vv;

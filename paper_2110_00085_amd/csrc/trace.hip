@@ -456,7 +456,15 @@ __global__ void __launch_bounds__(256) tape_image_reduce_kernel(const double* __
     if (i >= n) return;
     const int64_t d = i / npix, p = i % npix;
     double acc = 0.0;
-    for (int x = 0; x < groups; ++x) acc += partial[(d * groups + x) * npix + p];
+    // the groups in order, kTapeImageLoads loads in flight
+    for (int x0 = 0; x0 < groups; x0 += kTapeImageLoads) {
+        double t[kTapeImageLoads];
+#pragma unroll
+        for (int j = 0; j < kTapeImageLoads; ++j)
+            t[j] = x0 + j < groups ? partial[(d * groups + x0 + j) * npix + p] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kTapeImageLoads; ++j) acc += t[j];
+    }
     img[i] = acc * pixel_scale(c, i, scale);
 }
 
