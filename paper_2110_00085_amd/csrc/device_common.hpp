@@ -221,6 +221,12 @@ __device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real p
     return t;
 }
 
+// Inverse of a direction component: FP32 walks take the hardware reciprocal
+// (within 1 ulp; the walk's pieces need no correctly rounded inverse, and its
+// face counts, not the face parameters, bound it), FP64 walks the division.
+__device__ __forceinline__ float dda_inv(float w) { return __builtin_amdgcn_rcpf(w); }
+__device__ __forceinline__ double dda_inv(double w) { return 1.0 / w; }
+
 // Direction signs and inverse components; false when w has no nonzero
 // component.
 template <typename Real>
@@ -230,9 +236,9 @@ __device__ __forceinline__ bool dda_dir(Real wx, Real wy, Real wz, int& sx, int&
     sx = wx > (Real)0 ? 1 : (wx < (Real)0 ? -1 : 0);
     sy = wy > (Real)0 ? 1 : (wy < (Real)0 ? -1 : 0);
     sz = wz > (Real)0 ? 1 : (wz < (Real)0 ? -1 : 0);
-    ivx = sx ? (Real)1 / wx : (Real)0;
-    ivy = sy ? (Real)1 / wy : (Real)0;
-    ivz = sz ? (Real)1 / wz : (Real)0;
+    ivx = sx ? dda_inv(wx) : (Real)0;
+    ivy = sy ? dda_inv(wy) : (Real)0;
+    ivz = sz ? dda_inv(wz) : (Real)0;
     return sx != 0 || sy != 0 || sz != 0;
 }
 

@@ -79,12 +79,14 @@ __device__ __forceinline__ void walk_scatter(const DevScene& s, A&& add, const V
 }
 
 // Henyey-Greenstein phase function in FP32, 1 + g^2 - 2 g mu written as
-// (1-g)^2 + 2 g (1-mu) (no cancellation near mu = 1).
+// (1-g)^2 + 2 g (1-mu) (no cancellation near mu = 1); the hardware square
+// root and reciprocal (each within 1 ulp) stand in for the correctly rounded
+// ones, since the FP32 contribution carries ~1e-7 relative error anyway.
 __device__ __forceinline__ float phase_hg_f32_om(const DevScene& s, float one_minus_mu)
 {
     const float g = (float)s.g;
     const float d = (1.f - g) * (1.f - g) + 2.f * g * one_minus_mu;
-    return (float)s.hg_num / (d * sqrtf(d));
+    return (float)s.hg_num * __builtin_amdgcn_rcpf(d * __builtin_amdgcn_sqrtf(d));
 }
 
 __device__ __forceinline__ float phase_hg_f32(const DevScene& s, float mu) { return phase_hg_f32_om(s, 1.f - mu); }
