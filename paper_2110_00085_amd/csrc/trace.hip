@@ -803,10 +803,14 @@ __global__ void __launch_bounds__(kBlock) grad_walk_kernel(TraceArgs a, DevCams 
                 for (int d = d_lo; d < d_hi; ++d) {
                     const double wgt = (double)Wp[(int64_t)(b * cams.n + d) * kWave];
                     if (wgt == 0.0) continue;
-                    const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
-                    const double dist = sqrt(ex * ex + ey * ey + ez * ez);
-                    const double id = 1.0 / dist;
-                    const double u[3] = {ex * id, ey * id, ez * id};
+                    // the walk runs in FP32: its direction and length are formed in
+                    // FP32 from the FP64 offset (hardware reciprocal square root)
+                    const float ex = (float)(cams.pos[d][0] - p1.x), ey = (float)(cams.pos[d][1] - p1.y),
+                                ez = (float)(cams.pos[d][2] - p1.z);
+                    const float d2 = ex * ex + ey * ey + ez * ez;
+                    const float id = __builtin_amdgcn_rsqf(d2);
+                    const double u[3] = {(double)(ex * id), (double)(ey * id), (double)(ez * id)};
+                    const double dist = (double)(d2 * id);
                     if (cams.outside)
                         walk_scatter<float, false>(s, add, p1, u, dist, -wgt * s.vk, nseg, z0, z1);
                     else
