@@ -156,6 +156,28 @@ __device__ __forceinline__ int project(const DevCams& c, int d, double x, double
     return row * c.W + col;
 }
 
+// ------------------------------------------------------------ LDS fills
+
+// dst[i] = value(i) for i < n by the workgroup's threads, kFillLoads values
+// per thread loaded before any is stored (the loads of a plain loop wait one
+// at a time); value is called with an index clamped to n - 1, so every load
+// stays in bounds.
+constexpr int kFillLoads = 8;
+
+template <typename T, typename F>
+__device__ __forceinline__ void lds_fill(T* dst, int n, F&& value)
+{
+    const int step = (int)blockDim.x;
+    for (int i0 = (int)threadIdx.x; i0 < n; i0 += kFillLoads * step) {
+        T v[kFillLoads];
+#pragma unroll
+        for (int j = 0; j < kFillLoads; ++j) v[j] = value(min(i0 + j * step, n - 1));
+#pragma unroll
+        for (int j = 0; j < kFillLoads; ++j)
+            if (i0 + j * step < n) dst[i0 + j * step] = v[j];
+    }
+}
+
 // ------------------------------------------------------------- DDA walker
 
 // Steps of the incremental voxel walk along p + t w, from voxel (ix,iy,iz)

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
         // the extinction grid in LDS: a piece's lookup waits ~100 clocks, not an L2 round trip
         Real* sg = reinterpret_cast<Real*>(smem);
         const int nu = s.nx * s.ny * s.nz;
-        for (int i = threadIdx.x; i < nu; i += blockDim.x) sg[i] = gt[i];
+        lds_fill(sg, nu, [&](int i) { return gt[i]; });
         __syncthreads();
         gt = sg;
     }

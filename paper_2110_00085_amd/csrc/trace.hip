@@ -146,7 +146,7 @@ __device__ __forceinline__ const Real* delta_grid(const TraceArgs& a, unsigned c
     if (!kGridLds) return (const Real*)a.grid_dlt;
     Real* sg = reinterpret_cast<Real*>(smem);
     const int nu = a.s.nx * a.s.ny * a.s.nz;
-    for (int i = threadIdx.x; i < nu; i += blockDim.x) sg[i] = (Real)((double)a.bc_t[i] - (double)a.st.beta_ref[i]);
+    lds_fill(sg, nu, [&](int i) { return (Real)((double)a.bc_t[i] - (double)a.st.beta_ref[i]); });
     __syncthreads();
     return sg;
 }
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
     Real* __restrict__ sgrid = reinterpret_cast<Real*>(smem + (kImgLds ? (size_t)nimg * sizeof(float) : 0));
     const Real* __restrict__ gtot = (const Real*)a.grid_tot;
     if (kGridLds)
-        for (int i = threadIdx.x; i < nu; i += kBlock) sgrid[i] = (Real)((double)a.bc_t[i] + s.beta_air);
+        lds_fill(sgrid, nu, [&](int i) { return (Real)((double)a.bc_t[i] + s.beta_air); });
     if (kImgLds)
         for (int i = threadIdx.x; i < nimg; i += kBlock) simg[i] = 0.f;
     if (kGridLds || kImgLds) __syncthreads();
