@@ -667,6 +667,8 @@ __device__ __forceinline__ void slab_tally_end(const SlabTally<kLds>& t, double*
 // evaluated in FP32, like the stored weights.
 
 constexpr int kGwCams = 8;
+// cameras per camera group: at most 3 groups of the kMaxCams cameras
+constexpr int kGroupCams = (kMaxCams + 2) / 3;
 constexpr int kGwBlock = 256;
 constexpr int kGwBlocksPerCU = 8;
 
@@ -796,12 +798,28 @@ __global__ void __launch_bounds__(kBlock) grad_walk_kernel(TraceArgs a, DevCams 
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
         const float4* __restrict__ X = a.vaux + rec0 + lane;
         if (kind < G) {
-            const int d_lo = kind * cpg, d_hi = min(cams.n, d_lo + cpg);
-            const float* __restrict__ Wp = a.wtape + rec0 * cams.n + lane;
+            const int d_lo = kind * cpg, nd = min(cams.n, d_lo + cpg) - d_lo;
+            const float* __restrict__ Wp = a.wtape + rec0 * cams.n + d_lo * kWave + lane;
+            // the vertex and the group's weights of scatter b+1 load while
+            // scatter b walks
+            Vtx pn = load_vtx(V, 1);
+            float wn[kGroupCams];
+#pragma unroll
+            for (int j = 0; j < kGroupCams; ++j) wn[j] = j < nd ? Wp[(int64_t)(cams.n + j) * kWave] : 0.f;
             for (int b = 1; b <= Bn; ++b) {
-                const Vtx p1 = load_vtx(V, b);
-                for (int d = d_lo; d < d_hi; ++d) {
-                    const double wgt = (double)Wp[(int64_t)(b * cams.n + d) * kWave];
+                const Vtx p1 = pn;
+                float wc[kGroupCams];
+#pragma unroll
+                for (int j = 0; j < kGroupCams; ++j) wc[j] = wn[j];
+                if (b < Bn) {
+                    pn = load_vtx(V, b + 1);
+#pragma unroll
+                    for (int j = 0; j < kGroupCams; ++j)
+                        wn[j] = j < nd ? Wp[(int64_t)((b + 1) * cams.n + j) * kWave] : 0.f;
+                }
+                for (int j = 0; j < nd; ++j) {
+                    const int d = d_lo + j;
+                    const double wgt = (double)wc[j];
                     if (wgt == 0.0) continue;
                     // the walk runs in FP32: its direction and length are formed in
                     // FP32 from the FP64 offset (hardware reciprocal square root)
