@@ -690,15 +690,29 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
     for (uint32_t task = blockIdx.x * (kGwBlock / kWave) + threadIdx.x / kWave; task < lv.total; task += waves) {
         // levels are contiguous task ranges in falling b (wavefront-uniform)
         while (task >= lv.start[b] + (uint32_t)(nb - lv.first_batch[b])) --b;
-        const int64_t bt = lv.first_batch[b] + (int64_t)(task - lv.start[b]);
+        // the batch index is wavefront-uniform: its offsets come from scalar loads
+        const int64_t bt = __builtin_amdgcn_readfirstlane((int)(lv.first_batch[b] + (int64_t)(task - lv.start[b])));
         const int64_t slot = bt * kWave + lane;
-        const int Bn = (int)a.st.B[slot];
-        if (b > Bn) continue;
         const int64_t rec0 = a.st.batch_off[bt] - a.tape_base;
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
         const float2* __restrict__ Tp = a.tape + rec0 * cams.n + lane;
         float* __restrict__ Wp = a.wtape + rec0 * cams.n + lane;
+        // Rows b-1 and b of the vertices and row b of the tape exist for every
+        // lane of a batch on level b (some lane has B >= b), so they load
+        // together with the lane's B; a lane with B < b computes on its padding
+        // or stale rows and neither gathers nor stores.
         const Vtx p0 = load_vtx(V, b - 1), p1 = load_vtx(V, b);
+        const int Bn = (int)a.st.B[slot];
+        const bool act = b <= Bn;
+        // tape records of kGwCams cameras from d0 on, one group ahead of its
+        // arithmetic (a camera index past the last loads the last camera's
+        // record, in bounds and without a branch, and is masked below)
+        float2 tn[kGwCams];
+        auto load_group = [&](int d0) {
+#pragma unroll
+            for (int j = 0; j < kGwCams; ++j) tn[j] = Tp[(int64_t)(b * cams.n + min(d0 + j, cams.n - 1)) * kWave];
+        };
+        load_group(0);
         double w[3];
         seg_dir(p0, p1, w);
         const int v1 = clamp_vox(p1.v, nu);
@@ -712,11 +726,11 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
             float2 tt[kGwCams];
             double rr[kGwCams];
 #pragma unroll
-            for (int j = 0; j < kGwCams; ++j)
-                tt[j] = d0 + j < cams.n ? Tp[(int64_t)(b * cams.n + d0 + j) * kWave]
-                                        : make_float2(0.f, __int_as_float(-1));
+            for (int j = 0; j < kGwCams; ++j) tt[j] = tn[j];
+            if (d0 + kGwCams < cams.n) load_group(d0 + kGwCams);
 #pragma unroll
             for (int j = 0; j < kGwCams; ++j) {
+                if (!act || d0 + j >= cams.n) tt[j].y = __int_as_float(-1);
                 const int pix = __float_as_int(tt[j].y);
                 rr[j] = pix >= 0 ? a.rho[(int64_t)(d0 + j) * npix + pix] : 0.0;
             }
@@ -737,9 +751,10 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
                     if (fst > 0.f) vert += wf * (wc * hg / fst);
                     ++nle;
                 }
-                Wp[(int64_t)(b * cams.n + d) * kWave] = wf;
+                if (act) Wp[(int64_t)(b * cams.n + d) * kWave] = wf;
             }
         }
+        if (!act) continue;
         // the scatter at x_b turns segment b-1 (direction w) into segment b
         double coef = 0.0;
         if (b < Bn) {
