@@ -434,6 +434,29 @@ def test_edge_cases(env):
     st1 = _store(api, ctx, torch, s1, p1)
     img1 = api.render(ctx, s1, _dev(torch, s1.beta_cloud), ch, st1).cpu().numpy()
     assert _rel(img1, oracle.render(s1, cams, p1)) <= 1e-5
+    # paths capped at 1 and 2 orders in a field 3x as thick (most scattering
+    # paths end at the cap, without an exit vertex): render, gradient on the
+    # tape and reweight at a perturbed field against the oracle
+    for cap in (1, 2):
+        sc = inputs.cloud8()
+        sc.max_order = cap
+        sc = sc.with_beta(3.0 * sc.beta_cloud)
+        pc = oracle.sample(sc, 19, 4000)
+        assert (pc.B == cap).mean() > 0.1, (pc.B == cap).mean()
+        stc = _store(api, ctx, torch, sc, pc)
+        beta_c = _perturbed(sc, seed=23, amp=0.1)
+        btc = _dev(torch, beta_c)
+        imgc = api.render(ctx, sc, btc, ch, stc).cpu().numpy()
+        refc = oracle.render(sc, cams, pc, beta_t=beta_c)
+        assert _rel(imgc, refc) <= TOL["fp32"]["img"], (cap, _rel(imgc, refc))
+        resc = np.random.default_rng(29).standard_normal(refc.shape) * np.abs(refc).mean()
+        gc = api.grad(ctx, sc, btc, ch, stc, torch.as_tensor(resc).cuda()).cpu().numpy()
+        grefc = oracle.grad(sc, cams, pc, resc, beta_t=beta_c)
+        assert _rel(gc, grefc) <= TOL["fp32"]["grad"], (cap, _rel(gc, grefc))
+        mr, ess = P.prt_reweight(ctx.handle, P.make_scene(sc, btc), stc.handle)
+        mr_ref, ess_ref = oracle.reweight(sc, pc, beta_t=beta_c)
+        assert abs(mr - mr_ref) <= TOL["fp32"]["rw"] * abs(mr_ref), (cap, mr, mr_ref)
+        assert abs(ess - ess_ref) <= TOL["fp32"]["rw"] * abs(ess_ref), (cap, ess, ess_ref)
     # cameras that see nothing
     far = inputs.cameras_at([[100.0, 100.0, 100.0]], [[200.0, 200.0, 200.0]], 8, 8, 10.0)
     assert np.abs(api.render(ctx, s1, _dev(torch, s1.beta_cloud), P.CamerasHost(far), st1).cpu().numpy()).max() == 0.0
