@@ -92,7 +92,7 @@ struct TraceArgs {
 // store is sorted by B, so the batches of level b are [first_batch[b],
 // n_batches); levels run from b = bmax down to 1, level b's tasks start at
 // start[b], and total counts them all.
-struct GwLevels {
+struct VertexLevels {
     int bmax;
     uint32_t total;
     int32_t first_batch[kMaxOrder + 1];
@@ -145,7 +145,7 @@ RenderPlan plan_render(int fp64, int64_t nu, const DevCams& c, bool tape, int64_
 // (then they need no prepared delta grid).
 bool delta_grid_lds(int fp64, int64_t nu);
 // Per-vertex prefix factors of the render, one task per (batch, b <= brender).
-hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, const GwLevels& lv, int n_cu);
+hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, const VertexLevels& lv, int n_cu);
 // The persistent render kernel alone (its task counter a.work[0] must be zero,
 // a.pbase filled by launch_render_prefix);
 // with img_lds, launch_render_reduce then adds the partials into the images.
@@ -172,7 +172,7 @@ struct GradPlan {
 };
 GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu, bool tape);
 // Gradient weights from the tape (runs only when *a.tape_flag is 1).
-hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c, const GwLevels& lv, int n_cu);
+hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c, const VertexLevels& lv, int n_cu);
 // Gradient terms of slab i (z layers [i*slab_layers, min(nz, (i+1)*slab_layers))):
 // the persistent grad kernels (task counters a.work[0] and a.work[1] must be
 // zero): with a tape flag, the walk kernel on the stored weights and the

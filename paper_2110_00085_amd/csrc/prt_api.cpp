@@ -542,9 +542,9 @@ prt_paths new_store(prt_ctx c, const prt_scene* s, uint64_t n, uint64_t seed)
 }
 
 // Per-vertex task levels of the store up to scatter index bmax.
-GwLevels task_levels(const prt_paths_s* p, int bmax)
+VertexLevels task_levels(const prt_paths_s* p, int bmax)
 {
-    GwLevels lv{};
+    VertexLevels lv{};
     lv.bmax = std::min(bmax, p->bmax);
     for (int b = lv.bmax; b >= 1; --b) {
         lv.first_batch[b] = p->first_batch_ge[b];

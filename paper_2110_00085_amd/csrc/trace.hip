@@ -164,7 +164,7 @@ bool delta_grid_lds(int fp64, int64_t nu) { return (size_t)nu * (fp64 ? 8 : 4) <
 // factor of scatter b needs only the segment x_{b-1} -> x_b and the vertex
 // x_{b-1}, so the segments of a path are walked by different wavefronts.
 template <typename Real, bool kGridLds>
-__global__ void __launch_bounds__(kBlock) render_prefix_kernel(TraceArgs a, GwLevels lv)
+__global__ void __launch_bounds__(kBlock) render_prefix_kernel(TraceArgs a, VertexLevels lv)
 {
     extern __shared__ unsigned char smem[];
     // the render kernel that follows takes its tasks from zeroed counters
@@ -228,7 +228,7 @@ static hipError_t launch_delta_kernel(hipStream_t st, K k, bool lds_grid, size_t
     return hipGetLastError();
 }
 
-hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, const GwLevels& lv, int n_cu)
+hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, const VertexLevels& lv, int n_cu)
 {
     if (lv.total == 0) return hipSuccess;
     const size_t grid_bytes = (size_t)a.s.nx * a.s.ny * a.s.nz * (fp64 ? 8 : 4);
@@ -672,7 +672,7 @@ constexpr int kGroupCams = (kMaxCams + 2) / 3;
 constexpr int kGwBlock = 256;
 constexpr int kGwBlocksPerCU = 8;
 
-__global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, DevCams cams, GwLevels lv)
+__global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, DevCams cams, VertexLevels lv)
 {
     if (*a.tape_flag == 0) return;
     __shared__ unsigned long long wg_le;
@@ -774,7 +774,7 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
     if (threadIdx.x == 0 && wg_le) atomicAdd(&a.counters[1], wg_le);
 }
 
-hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c, const GwLevels& lv, int n_cu)
+hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c, const VertexLevels& lv, int n_cu)
 {
     if (lv.total == 0) return hipSuccess;
     const uint32_t per_wg = kGwBlock / kWave;
