@@ -433,10 +433,12 @@ def main():
     per_call = launches / args.steps
     units = {"voxel_segment": c_r["voxel_segments"], "local_estimate": c_r["local_estimates"]}
     per = OPS.get(dom)
+    # the counter summaries were taken on the default command's workload
+    profiled = args.workload == "cloud32" and args.paths == 0 and args.precision == "fp32"
     roofline = {"bound": "alu", "kernel": dom, "achieved": None, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                "unit": "TOP/s", "frac": None, "traffic": traffic_for(dom), "avg_launch_ms": dom_ms,
-                "launches_per_step": per_call}
-    roofline["valu"] = valu_for(dom)
+                "unit": "TOP/s", "frac": None, "traffic": traffic_for(dom) if profiled else None,
+                "avg_launch_ms": dom_ms, "launches_per_step": per_call}
+    roofline["valu"] = valu_for(dom) if profiled else None
     if roofline["traffic"] is not None:
         hbm = roofline["traffic"] / (dom_ms * 1e-3) / 1e9
         roofline["hbm"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS}
