@@ -87,6 +87,7 @@ def lib():
         L.prto_reweight.argtypes = [C.POINTER(_Scene), _P, _P, C.c_int64, _P, _P, _P, _P, _P]
         L.prto_reweight.restype = C.c_int
         L.prto_num_threads.restype = C.c_int
+        L.prto_space_carve.argtypes = [C.POINTER(_Scene), C.POINTER(_Cams), _P, _P, _P]
         _lib = L
     return _lib
 
@@ -304,35 +305,24 @@ def reweight(scene, paths: Paths, beta_t=None):
     return float(r.sum() / paths.n_total), float(r.sum() ** 2 / (r * r).sum())
 
 
-def cell_keys(vox, dims) -> np.ndarray:
-    """Spatial secondary sort key of voxels: the Morton code (x bit 3k, y bit
-    3k+1, z bit 3k+2) of the coarse cell (c_a = i_a * 8 // n_a, 8 cells per
-    axis).  A layout convention of the path store, not part of the method."""
-    nx, ny, nz = dims
-    v = np.asarray(vox, np.int64)
-    c = [(v % nx) * 8 // nx, (v // nx) % ny * 8 // ny, v // (nx * ny) * 8 // nz]
-    m = np.zeros_like(v)
-    for k in range(3):
-        for a in range(3):
-            m |= ((c[a] >> k) & 1) << (3 * k + a)
-    return m
+def sort_permutation(B) -> np.ndarray:
+    """Stable order of paths by size B (Alg. 2, 'Sort'; Sec. 5.3): sorted
+    position -> path id, equal sizes keeping their id order."""
+    return np.argsort(np.asarray(B), kind="stable")
 
 
-def path_cells(dims, off, vox, B) -> np.ndarray:
-    """Cell key of every path's first vertex after the source: its first
-    scatter, or its entry point when it has none."""
-    off, B = np.asarray(off), np.asarray(B)
-    first = np.asarray(vox)[off[:-1] + (B > 0)]
-    return cell_keys(first, dims)
-
-
-def sort_permutation(B, cells=None) -> np.ndarray:
-    """Stable order of paths by size B (Alg. 2, 'Sort'; Sec. 5.3), ties broken
-    by the spatial key `cells` when given, then by path id."""
-    B = np.asarray(B)
-    if cells is None:
-        return np.argsort(B, kind="stable")
-    return np.lexsort((np.asarray(cells), B))
+def space_carve(scene, cams, images, threshold) -> np.ndarray:
+    """Photo-hull mask [nz][ny][nx] (uint8, 1 = kept): a voxel is removed when
+    a camera sees its centre on a pixel at or below that camera's threshold
+    (Sec. 6.1, initialisation by space carving)."""
+    sc = _scene_struct(scene)
+    h = _CamsHolder(cams)
+    img = np.ascontiguousarray(images, dtype=np.float64)
+    assert img.shape == (cams.n, cams.height, cams.width)
+    thr = np.ascontiguousarray(np.broadcast_to(np.asarray(threshold, np.float64), (cams.n,)))
+    mask = np.zeros(scene.nz * scene.ny * scene.nx, np.uint8)
+    lib().prto_space_carve(C.byref(sc), C.byref(h.s), _ptr(img), _ptr(thr), _ptr(mask))
+    return mask.reshape(scene.nz, scene.ny, scene.nx)
 
 
 # ------------------------------------------------------------ loop glue

@@ -734,16 +734,22 @@ int prto_grad(const po_scene* s, const po_cams* cm, const double* beta_t, const 
 /* log of the full sampled-path pdf (Eq. final_mu, with the escape probability
    of the last segment when the path left the box and the direction pdf at
    every scatter that has a successor vertex), up to the source factor 1/A
-   which cancels in the ratio. */
+   which cancels in the ratio.  The pdf carries the extinction beta(x_k) of
+   every scatter vertex, so it is zero (log = -inf) when one of them is zero,
+   whatever the phase function there. */
 static double po_log_full_pdf(const po_scene* s, const double* bc, const po_path* P, po_work* W)
 {
     double lp = 0.0;
+    for (int k = 1; k <= P->B; ++k) {
+        double b = po_beta(s, bc, P->v[k]);
+        if (!(b > 0.0)) return -INFINITY;
+        lp += log(b);
+    }
     for (int k = 0; k + 1 < P->nv; ++k) {
         double t_end;
         int np = po_ray_pieces(s, P->x[k], P->w[k], P->len[k], W->pc, W->tb, &t_end);
         lp -= po_tau(s, bc, W->pc, np);
     }
-    for (int k = 1; k <= P->B; ++k) lp += log(po_beta(s, bc, P->v[k]));
     for (int k = 1; k + 1 < P->nv; ++k) {
         double mu = po_dot(P->w[k - 1], P->w[k]);
         lp += log(po_fs(s, bc, P->v[k], mu)) - log(po_beta_s(s, bc, P->v[k]));
@@ -771,6 +777,30 @@ int prto_reweight(const po_scene* s, const double* beta_t, const double* beta_re
         po_work_free(&W);
     }
     return err ? -1 : 0;
+}
+
+/* ----------------------------------------------------- space carving */
+
+/* Photo-hull initialisation (Sec. 6.1, space carving after Kutulakos &
+   Seitz): a voxel is removed when some camera sees its centre on a pixel
+   whose value is at most that camera's threshold; a camera that does not see
+   the centre (behind it or outside its image) removes nothing.  mask[v] = 1
+   for the voxels kept. */
+void prto_space_carve(const po_scene* s, const po_cams* cm, const double* images, const double* threshold,
+                      uint8_t* mask)
+{
+    const size_t npx = (size_t)cm->width * cm->height;
+    for (int iz = 0; iz < s->nz; ++iz)
+        for (int iy = 0; iy < s->ny; ++iy)
+            for (int ix = 0; ix < s->nx; ++ix) {
+                double xkm[3] = {(ix + 0.5) * s->voxel_km, (iy + 0.5) * s->voxel_km, (iz + 0.5) * s->voxel_km};
+                int keep = 1;
+                for (int d = 0; d < cm->n; ++d) {
+                    int pix = po_project(cm, d, xkm);
+                    if (pix >= 0 && images[npx * (size_t)d + (size_t)pix] <= threshold[d]) keep = 0;
+                }
+                mask[ix + (size_t)s->nx * (iy + (size_t)s->ny * iz)] = (uint8_t)keep;
+            }
 }
 
 int prto_num_threads(void)

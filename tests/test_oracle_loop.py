@@ -13,33 +13,6 @@ def test_sort_is_stable_by_path_size(oracle_lib):
         assert (np.diff(ids) > 0).all()
 
 
-def test_sort_by_size_then_cell(oracle_lib):
-    rng = np.random.default_rng(4)
-    B = rng.integers(0, 6, 4000)
-    cells = rng.integers(0, 512, 4000)
-    perm = oracle_lib.sort_permutation(B, cells)
-    key = B[perm] * 512 + cells[perm]
-    assert (np.diff(key) >= 0).all()
-    for k in np.unique(key):
-        assert (np.diff(perm[key == k]) > 0).all()  # stable
-
-
-def test_cell_keys_by_hand(oracle_lib):
-    dims = (16, 8, 24)
-
-    def vox(ix, iy, iz):
-        return ix + dims[0] * (iy + dims[1] * iz)
-
-    cases = {vox(0, 0, 0): 0, vox(2, 0, 0): 1, vox(0, 1, 0): 2, vox(0, 0, 3): 4, vox(4, 0, 0): 8,
-             vox(1, 0, 2): 0, vox(15, 7, 23): 511, vox(8, 0, 0): 64, vox(0, 4, 12): 128 + 256}
-    got = oracle_lib.cell_keys(list(cases), dims)
-    assert got.tolist() == list(cases.values())
-    # the first vertex after the source: the first scatter, else the entry point
-    off = np.array([0, 2, 5])
-    v = np.array([vox(15, 7, 23), -1, vox(0, 0, 0), vox(2, 0, 0), -1])
-    assert oracle_lib.path_cells(dims, off, v, np.array([0, 1])).tolist() == [511, 1]
-
-
 def test_loss_and_residual():
     import oracle
     img = np.arange(12.0).reshape(3, 2, 2)

@@ -295,6 +295,25 @@ def test_recycled_render_is_unbiased_and_mean_r_is_one(oracle_lib):
     assert np.abs(oracle_lib.log_r(base, P_ref)).max() == 0.0
 
 
+def test_correction_factor_is_zero_exactly_for_impossible_paths(oracle_lib):
+    """The path pdf (Eq. final_mu) carries the extinction of every scatter
+    vertex: with no air and beta_t = 0 in one voxel, exactly the paths that
+    scatter in that voxel have r = 0 (log r = -inf), every other r is finite
+    and positive, and no NaN appears."""
+    sc = inputs.cloud8()
+    sc.beta_air = 0.0
+    P = oracle_lib.sample(sc, 77, 4000)
+    scat = [set(P.vox[P.off[i] + 1:P.off[i] + 1 + P.B[i]].tolist()) for i in range(P.n)]
+    v0 = int(np.bincount(np.concatenate([list(x) for x in scat if x])).argmax())
+    beta_t = sc.beta_cloud.ravel().copy()
+    beta_t[v0] = 0.0
+    lr = oracle_lib.log_r(sc, P, beta_t=beta_t.reshape(sc.beta_cloud.shape))
+    hits = np.array([v0 in x for x in scat])
+    assert hits.sum() > 20
+    assert np.array_equal(np.isneginf(lr), hits)
+    assert np.isfinite(lr[~hits]).all()
+
+
 # --------------------------------------------------------------- gradient
 
 def test_gradient_matches_central_differences(oracle_lib):
