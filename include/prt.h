@@ -125,6 +125,15 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out);
    with it stay valid. */
 void prt_destroy(prt_ctx ctx);
 int prt_set_stream(prt_ctx ctx, void* hip_stream);
+/* Largest temporary, in bytes, that prt_sample / prt_resample may allocate to
+   draw the paths in one pass (n_paths * (max_order + 2) vertex records of
+   16 bytes, held until the paths are sorted).  A resample that would need
+   more draws every path twice from its Philox stream: first only its size
+   and sort key, then, once the sort (Sec. 5.3) has fixed its place, its
+   vertices straight into the store.  Both give the same store; the second
+   pass checks every path's size against the first and fails with PRT_E_HIP
+   otherwise.  Default 8 GiB; 0 always takes two passes. */
+int prt_set_sample_scratch_limit(prt_ctx ctx, uint64_t bytes);
 /* Thread-local text of the last error (never NULL). */
 const char* prt_last_error(void);
 
@@ -213,6 +222,19 @@ int prt_loss(prt_ctx ctx, int64_t n, const double* images, const double* target,
    projection beta >= 0 and an FP32 copy into beta_f32[n] (device). */
 int prt_adam(prt_ctx ctx, int64_t n, double* beta, float* beta_f32, const double* grad, double* m,
              double* v, int32_t t, double lr, double b1, double b2, double eps);
+
+/* Space carving (Sec. 6.1: the reconstruction starts from the photo hull of
+   the images, after Kutulakos & Seitz, filled with the mean extinction of the
+   cloud).  Voxel v is removed (mask[v] = 0) when some camera d sees the
+   centre of v (the projection of prt_cameras) on a pixel p with
+   images[d][p] <= threshold[d]; a camera that does not see the centre
+   (behind it, or outside its image) removes nothing; otherwise mask[v] = 1.
+   images: device FP64 [n][H][W]; threshold: HOST double [n] (NaN rejected);
+   mask: device uint8 [nz][ny][nx], overwritten; beta_out: optional device
+   float32 [nz][ny][nx], set to fill_value (finite, >= 0) where kept and 0
+   elsewhere.  scene gives the grid geometry (its beta_cloud is not read). */
+int prt_space_carve(prt_ctx ctx, const prt_scene* scene, const prt_cameras* cams, const double* images,
+                    const double* threshold, double fill_value, uint8_t* mask, float* beta_out);
 
 /* ----------------------------------------------------------- telemetry */
 

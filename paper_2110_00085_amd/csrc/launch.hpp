@@ -22,13 +22,25 @@ struct StoreView {
     const float* beta_ref;  // reference cloud field
 };
 
+// Where the sampler puts a path's vertex records: row id of tmp (one-pass
+// resample; tmp has max_order+2 records per path), straight into the packed
+// store (vtx non-null: the second pass of a two-pass resample, slot = inv[id],
+// vertex k at vtx[batch_off[slot/64] + 64 k + slot%64]), or nowhere (both
+// null: the first pass of a two-pass resample, which only records sizes and
+// sort keys).  The second pass draws the same paths again from the same
+// Philox streams with the same code; it checks each path's size against the
+// first pass's and sets *mismatch otherwise.
 struct SampleArgs {
     DevScene s;
     const float* beta_c;   // cloud field the paths are drawn from
     const void* grid_tot;  // Real[N_u]: beta_c + beta_air
     uint64_t seed;
     int64_t n;
-    float4* tmp;           // [n][max_order+2] records
+    float4* tmp;           // [n][max_order+2] records, or null
+    float4* vtx;           // packed store records, or null
+    const int64_t* batch_off;
+    const int32_t* inv;    // path id -> sorted slot
+    int* mismatch;
     uint8_t* tB;
     uint8_t* tnv;
     uint16_t* tC;          // spatial sort key per path (cell_key)
@@ -108,11 +120,11 @@ hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const 
 hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu);
 // Stable sort of the paths by (size B, spatial key): perm[sorted position] =
 // path id, B[position] = size, nv[position] = tnv[path id] for positions < n
-// and 0 up to n_slots.  hist: sort_scratch_words(n, nbins) words; tmp_perm: n
-// entries.
+// and 0 up to n_slots, and (when inv is given) inv[path id] = sorted position.
+// hist: sort_scratch_words(n, nbins) words; tmp_perm: n entries.
 hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint8_t* tnv, const uint16_t* cell,
                              int64_t n, int64_t n_slots, int nbins, uint32_t* hist, int32_t* tmp_perm, int32_t* perm,
-                             uint8_t* B, uint8_t* nv);
+                             uint8_t* B, uint8_t* nv, int32_t* inv);
 int64_t sort_scratch_words(int64_t n, int nbins);
 // scratch: the sort's scratch (sort_scratch_words(64 * nb, ...) words) may be reused.
 hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, int64_t* batch_off, void* scratch);
@@ -128,13 +140,13 @@ hipError_t launch_store_meta(hipStream_t st, const uint8_t* B, int64_t n, const 
                              int64_t* meta);
 
 // ---- hot path (trace.hip)
-// Where render tallies and reads: FP32 LDS image partials (reduced by a
-// second kernel) and/or the extinction grid cached in LDS, when they fit.
-// With img_tape (the render records the tape and one camera's FP64 image fits
-// the LDS) the render kernel tallies nothing and the images are formed from
-// the tape afterwards, which leaves the LDS to the extinction grid.
+// Where render tallies and reads: with img_tape (the render records the
+// tape and one camera's FP64 image fits the LDS) the render kernel tallies
+// nothing and the images are formed from the tape afterwards in FP64 LDS
+// images; otherwise every contribution is an FP64 atomic on the output.
+// grid_lds: the extinction grid is cached in LDS.
 struct RenderPlan {
-    bool img_lds = false, grid_lds = false, img_tape = false;
+    bool grid_lds = false, img_tape = false;
     int n_wg = 1;
     int img_groups = 0;  // img_tape: image partials per camera
     size_t partial_bytes = 0;
@@ -147,12 +159,10 @@ bool delta_grid_lds(int fp64, int64_t nu);
 // Per-vertex prefix factors of the render, one task per (batch, b <= brender).
 hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, const VertexLevels& lv, int n_cu);
 // The persistent render kernel alone (its task counter a.work[0] must be zero,
-// a.pbase filled by launch_render_prefix);
-// with img_lds, launch_render_reduce then adds the partials into the images.
-hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
-                         void* partial);
-// Images from the partials (img_lds) or from the tape (img_tape), divided by
-// N Omega_p (scale = 1/N) like launch_render_finalize.
+// a.pbase filled by launch_render_prefix).
+hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p);
+// Images from the tape (img_tape; nothing otherwise), divided by N Omega_p
+// (scale = 1/N) like launch_render_finalize; partial holds p.partial_bytes.
 hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
                                 const void* partial, double scale, double* img);
 hipError_t launch_render_finalize(hipStream_t st, double* img, const DevCams& c, double scale);
@@ -198,6 +208,13 @@ int64_t loss_blocks(int64_t n);
 // out2[0] = sum of partial[2 i], out2[1] = sum of partial[2 i + 1] over
 // i < n_blocks, in a fixed order (out2 may be pinned host memory).
 hipError_t launch_sum_pairs(hipStream_t st, const double* partial, int64_t n_blocks, double* out2);
+struct CarveThresholds {
+    double t[kMaxCams];
+};
+// mask[v] = 1 unless some camera sees the centre of voxel v on a pixel at or
+// below its threshold; beta[v] (when given) = fill where kept, else 0.
+hipError_t launch_space_carve(hipStream_t st, int nx, int ny, int nz, double vk, const DevCams& c,
+                              const CarveThresholds& t, const double* img, float fill, uint8_t* mask, float* beta);
 hipError_t launch_adam(hipStream_t st, int64_t n, double* beta, float* beta_f32, const double* grad, double* m,
                        double* v, double lr, double b1, double b2, double eps, double bc1, double bc2);
 

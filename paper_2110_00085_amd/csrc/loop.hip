@@ -1,6 +1,7 @@
 // Loop glue of the optimisation (Alg. 2): appearance loss and residual
-// (Eq. appearance_loss), the Adam step with projection onto beta >= 0, and
-// fixed-order FP64 reductions.
+// (Eq. appearance_loss), the Adam step with projection onto beta >= 0,
+// fixed-order FP64 reductions, and the space-carving initialisation of the
+// reconstruction (Sec. 6.1).
 #include "launch.hpp"
 
 namespace prt {
@@ -122,6 +123,37 @@ hipError_t launch_adam(hipStream_t st, int64_t n, double* beta, float* beta_f32,
 {
     adam_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, beta, beta_f32, grad, m, v, lr, b1, b2,
                                                                         eps, bc1, bc2);
+    return hipGetLastError();
+}
+
+// Space carving (photo hull): one thread per voxel projects the voxel centre
+// into every camera (FP64 pinhole projection) and removes the voxel when a
+// camera sees it on a pixel at or below that camera's threshold.
+__global__ void __launch_bounds__(256) space_carve_kernel(int nx, int ny, int nz, double vk, DevCams c,
+                                                          CarveThresholds t, const double* __restrict__ img,
+                                                          float fill, uint8_t* __restrict__ mask,
+                                                          float* __restrict__ beta)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (int64_t)nx * ny * nz) return;
+    int ix, iy, iz;
+    voxel_ijk((int)v, nx, ny, ix, iy, iz);
+    const int64_t npix = (int64_t)c.W * c.H;
+    bool keep = true;
+    for (int d = 0; d < c.n; ++d) {
+        const int pix = project(c, d, ix + 0.5, iy + 0.5, iz + 0.5, vk);
+        if (pix >= 0 && img[d * npix + pix] <= t.t[d]) keep = false;
+    }
+    mask[v] = keep ? 1 : 0;
+    if (beta) beta[v] = keep ? fill : 0.f;
+}
+
+hipError_t launch_space_carve(hipStream_t st, int nx, int ny, int nz, double vk, const DevCams& c,
+                              const CarveThresholds& t, const double* img, float fill, uint8_t* mask, float* beta)
+{
+    const int64_t nu = (int64_t)nx * ny * nz;
+    space_carve_kernel<<<dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, st>>>(nx, ny, nz, vk, c, t, img, fill,
+                                                                               mask, beta);
     return hipGetLastError();
 }
 

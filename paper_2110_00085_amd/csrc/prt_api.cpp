@@ -48,6 +48,8 @@ struct Timed {
     hipEvent_t a, b;
 };
 
+constexpr int kMismatchWord = 6;
+
 }  // namespace
 
 struct prt_ctx_s {
@@ -71,12 +73,15 @@ struct prt_ctx_s {
     void* s_hist = nullptr;
     size_t s_hist_bytes = 0;
     void* s_off = nullptr;      // import offsets
-    void* s_perm = nullptr;     // permutation after the sort's first pass
+    void* s_perm = nullptr;     // permutation after the sort's first pass, then id -> slot
     size_t s_perm_bytes = 0;
+    // largest one-pass sampling temporary; larger resamples take two passes
+    uint64_t sample_tmp_limit = (uint64_t)8 << 30;
     size_t s_off_bytes = 0;
     // pinned host words the kernels write directly (read after a stream sync):
     // the store's meta words after packing (words 0-2 and kMetaFirstGe on),
-    // and the reweight's 2 sums (bytes 32-47, words 4-5 of the meta layout)
+    // the reweight's 2 sums (bytes 32-47, words 4-5 of the meta layout) and
+    // the two-pass sampler's mismatch flag (word kMismatchWord)
     void* hpin = nullptr;
     int64_t* hmeta = nullptr;
     double* hsum = nullptr;
@@ -413,12 +418,11 @@ uint64_t store_bytes(const prt_paths_s* p)
            (p->tape_beta ? (uint64_t)p->cap_nu * 4 : 0);
 }
 
-// Shared tail of sample, resample and import: sort the temporary paths by
-// size, lay them out in wavefront batches and fill the store.  tmp rows are
-// addressed by tmp_off (CSR) or by id * tmp_stride.  Reads back the store
-// size once (one synchronisation).
-int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_off, int64_t tmp_stride,
-                const uint8_t* tB, const uint8_t* tnv, const uint16_t* tC)
+// Shared part of sample, resample and import: sort the paths by size (and
+// spatial key), lay out the wavefront batches and read back the store size
+// (one synchronisation), then grow the store's record buffer.  With inv,
+// also writes inv[path id] = sorted slot.
+int layout_store(prt_ctx c, prt_paths p, const uint8_t* tB, const uint8_t* tnv, const uint16_t* tC, int32_t** inv)
 {
     const int64_t n = (int64_t)p->n;
     p->nb = (n + kWave - 1) / kWave;
@@ -427,11 +431,12 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
     int rc;
     if ((rc = reserve_paths(p, n))) return rc;
     if ((rc = ensure_scratch(&c->s_hist, &c->s_hist_bytes, sort_scratch_words(n, nbins) * sizeof(uint32_t)))) return rc;
-    if ((rc = ensure_scratch(&c->s_perm, &c->s_perm_bytes, (size_t)n * sizeof(int32_t)))) return rc;
+    if ((rc = ensure_scratch(&c->s_perm, &c->s_perm_bytes, (size_t)n * (inv ? 2 : 1) * sizeof(int32_t)))) return rc;
+    if (inv) *inv = (int32_t*)c->s_perm + n;
     {
         TimedScope ts(c, K_SORT);
         HIPCHK(launch_sort_paths(c->stream, tB, tnv, tC, n, p->n_slots, nbins, (uint32_t*)c->s_hist,
-                                 (int32_t*)c->s_perm, p->perm, p->B, p->nv));
+                                 (int32_t*)c->s_perm, p->perm, p->B, p->nv, inv ? *inv : nullptr));
         HIPCHK(launch_batch_offsets(c->stream, p->nv, p->nb, p->batch_off, c->s_hist));
         HIPCHK(launch_store_meta(c->stream, p->B, n, p->batch_off, p->nb, c->dmeta));
     }
@@ -447,7 +452,17 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
         p->bmax = k;
         p->first_batch_ge[k] = (int32_t)(f / kWave);
     }
-    if ((rc = grow(&p->vtx, &p->cap_records, p->n_records))) return rc;
+    return grow(&p->vtx, &p->cap_records, p->n_records);
+}
+
+// Sort temporary paths (rows of tmp addressed by tmp_off, CSR, or by
+// id * tmp_stride) into the store.
+int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_off, int64_t tmp_stride,
+                const uint8_t* tB, const uint8_t* tnv, const uint16_t* tC)
+{
+    int rc;
+    if ((rc = layout_store(c, p, tB, tnv, tC, nullptr))) return rc;
+    const int64_t n = (int64_t)p->n;
     {
         TimedScope ts(c, K_PACK);
         HIPCHK(launch_pack(c->stream, p->perm, tmp, tmp_off, tmp_stride, p->nv, p->batch_off, n, p->n_slots, p->vtx));
@@ -455,17 +470,22 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
     return PRT_OK;
 }
 
-// Samples n paths into p (allocated or reused) under scene->beta_cloud.
+// Samples n paths into p (allocated or reused) under scene->beta_cloud.  When
+// the one-pass temporary (max_order+2 records per path) would exceed the
+// context's limit, every path is drawn twice: first only its size and sort
+// key, then, once the sort has fixed its slot, its vertices straight into the
+// store.
 int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_paths p)
 {
     const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
     const int64_t stride = s->max_order + 2;
+    const bool one_pass = (uint64_t)n * (uint64_t)stride * sizeof(float4) <= c->sample_tmp_limit;
     int rc;
     // earlier work may still read the store's or the context's buffers
     HIPCHK(hipDeviceSynchronize());
     if ((rc = ensure_grids(c, nu))) return rc;
     if ((rc = grow(&p->beta_ref, &p->cap_nu, nu))) return rc;
-    if ((rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes, (size_t)n * stride * sizeof(float4)))) return rc;
+    if (one_pass && (rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes, (size_t)n * stride * sizeof(float4)))) return rc;
     if ((rc = ensure_scratch(&c->s_keys, &c->s_keys_bytes, 4 * (size_t)n))) return rc;
     p->n = (uint64_t)n;
     p->seed = seed;
@@ -489,7 +509,11 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     a.grid_tot = c->grid_tot;
     a.seed = seed;
     a.n = n;
-    a.tmp = (float4*)c->s_tmp;
+    a.tmp = one_pass ? (float4*)c->s_tmp : nullptr;
+    a.vtx = nullptr;
+    a.batch_off = nullptr;
+    a.inv = nullptr;
+    a.mismatch = nullptr;
     a.tB = tB;
     a.tnv = tnv;
     a.tC = tC;
@@ -498,7 +522,26 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
         TimedScope ts(c, K_SAMPLE);
         HIPCHK(launch_sample(c->stream, c->fp64, a, c->n_cu));
     }
-    return build_store(c, p, (const float4*)c->s_tmp, nullptr, stride, tB, tnv, tC);
+    if (one_pass) return build_store(c, p, (const float4*)c->s_tmp, nullptr, stride, tB, tnv, tC);
+    int32_t* inv = nullptr;
+    if ((rc = layout_store(c, p, tB, tnv, tC, &inv))) return rc;
+    // second pass: padding rows are zero, the sampler writes every path's records
+    volatile int* mismatch = (volatile int*)(c->hmeta + kMismatchWord);
+    *mismatch = 0;
+    HIPCHK(hipMemsetAsync(p->vtx, 0, (size_t)p->n_records * sizeof(float4), c->stream));
+    HIPCHK(hipMemsetAsync(c->work + 2, 0, sizeof(unsigned int), c->stream));
+    a.vtx = p->vtx;
+    a.batch_off = p->batch_off;
+    a.inv = inv;
+    a.mismatch = (int*)(c->dmeta + kMismatchWord);
+    {
+        TimedScope ts(c, K_SAMPLE);
+        HIPCHK(launch_sample(c->stream, c->fp64, a, c->n_cu));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (*mismatch != 0)
+        return fail(PRT_E_HIP, "two-pass resample: a path redrawn in the second pass differs from the first");
+    return PRT_OK;
 }
 
 // Tape capacity: one (FP32 c, pixel) entry per (vertex record, camera) from the first
@@ -651,6 +694,13 @@ void prt_destroy(prt_ctx c)
     (void)hipFree(c->work);
     (void)hipFree(c->counters);
     delete c;
+}
+
+int prt_set_sample_scratch_limit(prt_ctx c, uint64_t bytes)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    c->sample_tmp_limit = bytes;
+    return PRT_OK;
 }
 
 int prt_set_stream(prt_ctx c, void* hip_stream)
@@ -884,7 +934,7 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
     {
         TimedScope ts(c, K_PREP);
         // the reductions write every pixel; otherwise tallies add up on zeros
-        if (!work || !(plan.img_lds || plan.img_tape)) HIPCHK(launch_fill(c->stream, images, npx, 0.0));
+        if (!work || !plan.img_tape) HIPCHK(launch_fill(c->stream, images, npx, 0.0));
         // kernels that hold a grid in LDS form it there from the fields
         if (work && (!plan.grid_lds || !delta_grid_lds(c->fp64, nu)))
             HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
@@ -899,13 +949,13 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
         }
         {
             TimedScope ts(c, K_RENDER);
-            HIPCHK(launch_render(c->stream, c->fp64, a, dc, plan, c->rpart));
+            HIPCHK(launch_render(c->stream, c->fp64, a, dc, plan));
         }
         TimedScope ts(c, K_RENDER_REDUCE);
         HIPCHK(launch_render_reduce(c->stream, a, dc, plan, c->rpart, 1.0 / (double)p->n, images));
     }
     // the reductions above also divide by N Omega_p; atomic tallies get it here
-    if (work && !(plan.img_lds || plan.img_tape)) {
+    if (work && !plan.img_tape) {
         TimedScope ts(c, K_FINALIZE);
         HIPCHK(launch_render_finalize(c->stream, images, dc, 1.0 / (double)p->n));
     }
@@ -1054,6 +1104,27 @@ int prt_adam(prt_ctx c, int64_t n, double* beta, float* beta_f32, const double* 
     TimedScope ts(c, K_ADAM);
     HIPCHK(launch_adam(c->stream, n, beta, beta_f32, grad, m, v, lr, b1, b2, eps, 1.0 - std::pow(b1, t),
                        1.0 - std::pow(b2, t)));
+    return PRT_OK;
+}
+
+int prt_space_carve(prt_ctx c, const prt_scene* s, const prt_cameras* cams, const double* images,
+                    const double* threshold, double fill_value, uint8_t* mask, float* beta_out)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    int rc = check_scene(s);
+    if (rc) return rc;
+    if (!images || !threshold || !mask) return fail(PRT_E_INVALID, "images/threshold/mask is NULL");
+    if (!std::isfinite(fill_value) || fill_value < 0) return fail(PRT_E_INVALID, "fill_value must be finite and >= 0");
+    DevCams dc;
+    if ((rc = make_dev_cams(cams, s, &dc))) return rc;
+    CarveThresholds t{};
+    for (int d = 0; d < dc.n; ++d) {
+        if (std::isnan(threshold[d])) return fail(PRT_E_INVALID, "threshold %d is NaN", d);
+        t.t[d] = threshold[d];
+    }
+    DeviceGuard g(c->device);
+    HIPCHK(launch_space_carve(c->stream, s->nx, s->ny, s->nz, s->voxel_km, dc, t, images, (float)fill_value, mask,
+                              beta_out));
     return PRT_OK;
 }
 

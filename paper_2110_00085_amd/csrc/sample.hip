@@ -46,6 +46,16 @@ constexpr int kSampleBlock = 1024;
 constexpr size_t kSampleLds = 128 * 1024;
 constexpr int kSampleBlocksPerCU = 2;
 
+// A uniform of (0,1) in the event precision, still below 1: in FP32 the
+// largest uniforms round to 1.0f, which would give a free flight of zero
+// optical depth (a scatter on top of the previous vertex).
+template <typename E>
+__device__ __forceinline__ E open_unit(double u);
+template <>
+__device__ __forceinline__ double open_unit<double>(double u) { return u; }
+template <>
+__device__ __forceinline__ float open_unit<float>(double u) { return fminf((float)u, 0x1.fffffep-1f); }
+
 __device__ __forceinline__ float4 vrec(double x, double y, double z, int v)
 {
     return make_float4((float)x, (float)y, (float)z, __int_as_float(v));
@@ -59,9 +69,9 @@ __device__ __forceinline__ float4 vrec(double x, double y, double z, int v)
 // the DDA until the optical depth passes tau = -ln u; at a scatter the
 // particle type is drawn with probability beta_s^(j)/beta_s and a direction
 // from its phase function; the path ends when it leaves the box or after
-// max_order scatters.  Vertices go to row id of tmp (stride max_order+2).
-// The uniforms of path id come from its own Philox counters, so the result
-// does not depend on which lane samples it.
+// max_order scatters.  Vertices go where SampleArgs says (a row of tmp, the
+// packed store, or nowhere).  The uniforms of path id come from its own
+// Philox counters, so the result does not depend on which lane samples it.
 template <typename Real, bool kGridLds>
 __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
 {
@@ -82,7 +92,8 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
     // path state and event arithmetic in the traversal precision
     using E = Real;
     int64_t id = 0;
-    float4* __restrict__ out = nullptr;
+    float4* __restrict__ out = nullptr;  // record k of the path at out[k * ostr]
+    int64_t ostr = 1;
     E x = 0, y = 0, z = 0, tau = 0;
     E w[3] = {0, 0, 0};
     double u[4];
@@ -112,7 +123,16 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
             if (!active && rank < take) {
                 // start path nid at the source
                 id = nid;
-                out = a.tmp + id * stride;
+                if (a.tmp) {
+                    out = a.tmp + id * stride;
+                    ostr = 1;
+                } else if (a.vtx) {
+                    const int64_t sl = a.inv[id];
+                    out = a.vtx + a.batch_off[sl / kWave] + sl % kWave;
+                    ostr = kWave;
+                } else {
+                    out = nullptr;
+                }
                 uniforms4(a.seed, (uint64_t)id, 0u, u);
                 const double A = s.a_top + s.a_x + s.a_y;
                 if (u[0] * A < s.a_top) {
@@ -127,10 +147,11 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
                 iz = min(max((int)floor(z), 0), s.nz - 1);
                 nv = 0;
                 v0 = ix + s.nx * (iy + s.ny * iz);
-                out[nv++] = vrec(x, y, z, v0);
+                if (out) out[nv * ostr] = vrec(x, y, z, v0);
+                ++nv;
                 w[0] = (E)s.sun[0]; w[1] = (E)s.sun[1]; w[2] = (E)s.sun[2];
                 // optical depth target in units of (1/km * grid length)
-                tau = -log((E)u[3]) / (E)s.vk;
+                tau = -log(open_unit<E>(u[3])) / (E)s.vk;
                 b = 0;
                 active = true;
             }
@@ -158,14 +179,16 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
         if (hit >= 0) thit += (taur - acc) / gt[hit];
         bool done;
         if (hit < 0) {
-            out[nv++] = vrec(x + tend * w[0], y + tend * w[1], z + tend * w[2], -1);
+            if (out) out[nv * ostr] = vrec(x + tend * w[0], y + tend * w[1], z + tend * w[2], -1);
+            ++nv;
             done = true;
         } else {
             x = x + thit * w[0];
             y = y + thit * w[1];
             z = z + thit * w[2];
             ++b;
-            out[nv++] = vrec(x, y, z, hit);
+            if (out) out[nv * ostr] = vrec(x, y, z, hit);
+            ++nv;
             if (b == 1) v0 = hit;  // the sort key follows the first scatter
             done = b >= s.max_order;
             if (!done) {
@@ -178,13 +201,18 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
                 E wn[3];
                 scatter_direction<E>(w, mu, (E)(2.0 * kPi) * (E)u[2], wn);
                 w[0] = wn[0]; w[1] = wn[1]; w[2] = wn[2];
-                tau = -log((E)u[3]) / (E)s.vk;
+                tau = -log(open_unit<E>(u[3])) / (E)s.vk;
             }
         }
         if (done) {
-            a.tB[id] = (uint8_t)b;
-            a.tnv[id] = (uint8_t)nv;
-            a.tC[id] = (uint16_t)cell_key(v0, s.nx, s.ny, s.nz);
+            if (a.vtx) {
+                // second pass: the path must have the size the first pass found
+                if (a.tB[id] != (uint8_t)b || a.tnv[id] != (uint8_t)nv) *a.mismatch = 1;
+            } else {
+                a.tB[id] = (uint8_t)b;
+                a.tnv[id] = (uint8_t)nv;
+                a.tC[id] = (uint16_t)cell_key(v0, s.nx, s.ny, s.nz);
+            }
             active = false;
         }
     }
@@ -230,6 +258,7 @@ struct SortExtra {
     const uint8_t* aux_in = nullptr;
     uint8_t* key_out = nullptr;
     uint8_t* aux_out = nullptr;
+    int32_t* inv_out = nullptr;  // inv_out[element] = dst
     int64_t n_pad = 0;
 };
 constexpr int kMaxBins = kCells > kMaxOrder + 1 ? kCells : kMaxOrder + 1;
@@ -362,6 +391,7 @@ __global__ void __launch_bounds__(kWave) sort_scatter_kernel(const K* __restrict
                 x.key_out[dst] = (uint8_t)key[id];
                 x.aux_out[dst] = x.aux_in[id];
             }
+            if (x.inv_out) x.inv_out[id] = (int32_t)dst;
             if (below == total - 1) base[k] += total;
         }
         __syncthreads();
@@ -396,7 +426,7 @@ int64_t sort_scratch_words(int64_t n, int nbins)
 
 hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint8_t* tnv, const uint16_t* cell,
                              int64_t n, int64_t n_slots, int nbins, uint32_t* hist, int32_t* tmp_perm, int32_t* perm,
-                             uint8_t* B, uint8_t* nv)
+                             uint8_t* B, uint8_t* nv, int32_t* inv)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e = counting_sort<uint16_t>(st, cell, nullptr, n, kCells, hist, tmp_perm);
@@ -406,6 +436,7 @@ hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint
     x.aux_in = tnv;
     x.key_out = B;
     x.aux_out = nv;
+    x.inv_out = inv;
     x.n_pad = n_slots;
     return counting_sort<uint8_t>(st, size_key, tmp_perm, n, nbins, hist, perm, x);
 }

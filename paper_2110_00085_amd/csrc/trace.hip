@@ -133,7 +133,6 @@ __device__ __forceinline__ void flush_counts(unsigned long long* c, uint64_t seg
 constexpr int kBlock = 1024;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr size_t kLdsBudget = 128 * 1024;       // grids
-constexpr size_t kLdsImageBudget = 152 * 1024;  // image tallies (+ grid if both fit)
 constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs when each slab recomputes the weights
 constexpr int64_t kMaxTapeGradSlabs = 64;       // LDS gradient slabs when the weights come from the tape
 constexpr size_t kTapeImageLds = 64 * 1024;     // FP64 image of one camera, images formed from the tape
@@ -247,31 +246,25 @@ hipError_t launch_render_prefix(hipStream_t st, int fp64, const TraceArgs& a, co
 // camera of its group, projects x_b, evaluates f_s,t and walks the
 // connection for its transmittance.
 // kGridLds: the total-extinction grid is cached in LDS.  kImg: with
-// kImgLdsF32 the workgroup tallies its contributions in an FP32 LDS image and
-// writes it to partial[blockIdx.x], which render_reduce_kernel adds in FP64
-// in workgroup order; with kImgGlobal every contribution is an FP64 atomic on
-// the output image; with kImgFromTape there is no tally here (the images are
-// formed from the tape afterwards, which leaves the LDS to the grid).
+// kImgGlobal every contribution is an FP64 atomic on the output image; with
+// kImgFromTape there is no tally here (the images are formed from the tape
+// afterwards, in FP64, which leaves the LDS to the grid).
 // kTape: every contribution is recorded on the tape.
-constexpr int kImgGlobal = 0, kImgLdsF32 = 1, kImgFromTape = 2;
+constexpr int kImgGlobal = 0, kImgFromTape = 2;
 
 template <typename Real, bool kGridLds, int kImg, bool kTape>
-__global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cams, float* __restrict__ partial)
+__global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cams)
 {
-    constexpr bool kImgLds = kImg == kImgLdsF32;
     extern __shared__ unsigned char smem[];
     const DevScene& s = a.s;
     const int nu = s.nx * s.ny * s.nz;
     const int npix = cams.W * cams.H;
-    const int nimg = npix * cams.n;
-    float* __restrict__ simg = reinterpret_cast<float*>(smem);
-    Real* __restrict__ sgrid = reinterpret_cast<Real*>(smem + (kImgLds ? (size_t)nimg * sizeof(float) : 0));
+    Real* __restrict__ sgrid = reinterpret_cast<Real*>(smem);
     const Real* __restrict__ gtot = (const Real*)a.grid_tot;
-    if (kGridLds)
+    if (kGridLds) {
         lds_fill(sgrid, nu, [&](int i) { return (Real)((double)a.bc_t[i] + s.beta_air); });
-    if (kImgLds)
-        for (int i = threadIdx.x; i < nimg; i += kBlock) simg[i] = 0.f;
-    if (kGridLds || kImgLds) __syncthreads();
+        __syncthreads();
+    }
     auto beta_tot = [&](uint32_t v) -> Real { return kGridLds ? sgrid[v] : gtot[v]; };
     const double r2scale = 1.0 / (s.vk * s.vk);
     const float vkf = (float)s.vk, wc_f = (float)s.w_c;
@@ -311,8 +304,8 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                 const double ex = cams.pos[d][0] - p1.x, ey = cams.pos[d][1] - p1.y, ez = cams.pos[d][2] - p1.z;
                 double c;
                 if constexpr (sizeof(Real) == 4) {
-                    // FP32 traversal: the contribution is kept in FP32 (tape, image
-                    // partials), so the phase function, transmittance and 1/r^2 are
+                    // FP32 traversal: the contribution is kept in FP32 (tape), so
+                    // the phase function, transmittance and 1/r^2 are
                     // FP32; the direction and 1 - mu stay FP64 (a forward-peaked
                     // phase function is sensitive to 1 - mu near mu = 1).
                     const double d2 = ex * ex + ey * ey + ez * ez;
@@ -340,19 +333,13 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                     c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
                 }
                 if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = make_float2((float)c, __int_as_float(pix));
-                if (kImg == kImgLdsF32) atomicAdd(&simg[d * npix + pix], (float)c);
-                else if (kImg == kImgGlobal) unsafeAtomicAdd(&a.img[(int64_t)d * npix + pix], c);
+                if (kImg == kImgGlobal) unsafeAtomicAdd(&a.img[(int64_t)d * npix + pix], c);
                 ++nle;
             }
             p0 = p1;
         }
     }
     flush_counts(a.counters, nseg, nle, 0);
-    if (kImgLds) {
-        __syncthreads();
-        float* __restrict__ out = partial + (int64_t)blockIdx.x * nimg;
-        for (int i = threadIdx.x; i < nimg; i += kBlock) out[i] = simg[i];
-    }
 }
 
 // Exact pixel solid angle: F(x,y) = atan(xy / (f sqrt(x^2+y^2+f^2))) is the
@@ -372,30 +359,17 @@ __device__ __forceinline__ double pixel_scale(const DevCams& c, int64_t i, doubl
     return scale / pixel_solid_angle(c.f[d], c.W, c.H, p / c.W, p % c.W);
 }
 
-// img[i] = sum over workgroups of partial[w][i] (FP64, workgroup order),
-// times scale / Omega_p.
-__global__ void __launch_bounds__(256) render_reduce_kernel(const float* __restrict__ partial, int n_wg, int64_t n,
-                                                            DevCams c, double scale, double* __restrict__ img)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double acc = 0.0;
-    for (int w = 0; w < n_wg; ++w) acc += (double)partial[(int64_t)w * n + i];
-    img[i] = acc * pixel_scale(c, i, scale);
-}
-
 template <typename Real, bool kGridLds, int kImg, bool kTape>
-static hipError_t launch_render_t(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg, float* partial)
+static hipError_t launch_render_t(hipStream_t st, const TraceArgs& a, const DevCams& c, int n_wg)
 {
     const size_t nu = (size_t)a.s.nx * a.s.ny * a.s.nz;
-    const size_t nimg = (size_t)c.W * c.H * c.n;
-    const size_t lds = (kGridLds ? nu * sizeof(Real) : 0) + (kImg == kImgLdsF32 ? nimg * sizeof(float) : 0);
+    const size_t lds = kGridLds ? nu * sizeof(Real) : 0;
     if (lds) {
         hipError_t e = hipFuncSetAttribute((const void*)render_kernel<Real, kGridLds, kImg, kTape>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    render_kernel<Real, kGridLds, kImg, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c, partial);
+    render_kernel<Real, kGridLds, kImg, kTape><<<dim3(n_wg), dim3(kBlock), lds, st>>>(a, c);
     return hipGetLastError();
 }
 
@@ -483,7 +457,7 @@ RenderPlan plan_render(int fp64, int64_t nu, const DevCams& c, bool tape, int64_
 {
     RenderPlan p;
     const int64_t npix = (int64_t)c.W * c.H, nimg = npix * c.n;
-    const int64_t img_bytes = nimg * 4, grid_bytes = nu * (fp64 ? 8 : 4);
+    const int64_t grid_bytes = nu * (fp64 ? 8 : 4);
     if (tape && !fp64 && npix * 8 <= (int64_t)kTapeImageLds) {
         // images from the tape: the LDS holds only the grid
         p.img_tape = true;
@@ -493,41 +467,29 @@ RenderPlan plan_render(int fp64, int64_t nu, const DevCams& c, bool tape, int64_
         p.partial_bytes = (size_t)nimg * p.img_groups * sizeof(double);
         return p;
     }
-    // FP32 image partials only in FP32 traversal mode (the all-FP64 mode keeps FP64 tallies)
-    p.img_lds = !fp64 && img_bytes <= (int64_t)kLdsImageBudget;
-    p.grid_lds = grid_bytes + (p.img_lds ? img_bytes : 0) <= (int64_t)kLdsImageBudget &&
-                 grid_bytes <= (int64_t)kLdsBudget;
-    p.n_wg = persistent_groups(n_slots, first_slot, n_cu, (p.img_lds || p.grid_lds) ? 1 : 2);
-    p.partial_bytes = p.img_lds ? (size_t)p.n_wg * nimg * sizeof(float) : 0;
+    // otherwise every contribution is an FP64 atomic on the output images
+    p.grid_lds = grid_bytes <= (int64_t)kLdsBudget;
+    p.n_wg = persistent_groups(n_slots, first_slot, n_cu, p.grid_lds ? 1 : 2);
     return p;
 }
 
-hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
-                         void* partial)
+hipError_t launch_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const RenderPlan& p)
 {
     if (a.st.n_slots - a.st.first_slot <= 0) return hipSuccess;
     if (fp64) {  // the all-FP64 mode records no FP32 tape
-        if (p.grid_lds) return launch_render_t<double, true, kImgGlobal, false>(st, a, c, p.n_wg, nullptr);
-        return launch_render_t<double, false, kImgGlobal, false>(st, a, c, p.n_wg, nullptr);
+        if (p.grid_lds) return launch_render_t<double, true, kImgGlobal, false>(st, a, c, p.n_wg);
+        return launch_render_t<double, false, kImgGlobal, false>(st, a, c, p.n_wg);
     }
-    float* fpart = (float*)partial;
     const bool tape = a.tape != nullptr;
     if (p.img_tape) {
-        if (p.grid_lds) return launch_render_t<float, true, kImgFromTape, true>(st, a, c, p.n_wg, nullptr);
-        return launch_render_t<float, false, kImgFromTape, true>(st, a, c, p.n_wg, nullptr);
-    }
-    if (p.img_lds) {
-        if (p.grid_lds)
-            return tape ? launch_render_t<float, true, kImgLdsF32, true>(st, a, c, p.n_wg, fpart)
-                        : launch_render_t<float, true, kImgLdsF32, false>(st, a, c, p.n_wg, fpart);
-        return tape ? launch_render_t<float, false, kImgLdsF32, true>(st, a, c, p.n_wg, fpart)
-                    : launch_render_t<float, false, kImgLdsF32, false>(st, a, c, p.n_wg, fpart);
+        if (p.grid_lds) return launch_render_t<float, true, kImgFromTape, true>(st, a, c, p.n_wg);
+        return launch_render_t<float, false, kImgFromTape, true>(st, a, c, p.n_wg);
     }
     if (p.grid_lds)
-        return tape ? launch_render_t<float, true, kImgGlobal, true>(st, a, c, p.n_wg, nullptr)
-                    : launch_render_t<float, true, kImgGlobal, false>(st, a, c, p.n_wg, nullptr);
-    return tape ? launch_render_t<float, false, kImgGlobal, true>(st, a, c, p.n_wg, nullptr)
-                : launch_render_t<float, false, kImgGlobal, false>(st, a, c, p.n_wg, nullptr);
+        return tape ? launch_render_t<float, true, kImgGlobal, true>(st, a, c, p.n_wg)
+                    : launch_render_t<float, true, kImgGlobal, false>(st, a, c, p.n_wg);
+    return tape ? launch_render_t<float, false, kImgGlobal, true>(st, a, c, p.n_wg)
+                : launch_render_t<float, false, kImgGlobal, false>(st, a, c, p.n_wg);
 }
 
 hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCams& c, const RenderPlan& p,
@@ -535,7 +497,8 @@ hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCam
 {
     const int64_t npix = (int64_t)c.W * c.H, nimg = npix * c.n;
     const unsigned blocks = (unsigned)((nimg + 255) / 256);
-    if (p.img_tape) {
+    if (!p.img_tape) return hipSuccess;
+    {
         const size_t lds = (size_t)npix * sizeof(double);
         if (lds > 64 * 1024) {
             hipError_t e = hipFuncSetAttribute((const void*)tape_image_kernel,
@@ -549,9 +512,6 @@ hipError_t launch_render_reduce(hipStream_t st, const TraceArgs& a, const DevCam
                                                                       (int)npix, nimg, c, scale, img);
         return hipGetLastError();
     }
-    if (!p.img_lds) return hipSuccess;
-    render_reduce_kernel<<<dim3(blocks), dim3(256), 0, st>>>((const float*)partial, p.n_wg, nimg, c, scale, img);
-    return hipGetLastError();
 }
 
 
@@ -1127,9 +1087,14 @@ hipError_t launch_equal_flag(hipStream_t st, const float* x, const float* y, int
 // log r = log mu(x|beta_t) - log mu(x|beta_ref) over the whole stored path:
 // every segment's optical-depth difference (the exit segment included), the
 // extinction ratio at every scatter, and the direction-pdf ratio
-// f_p = f_s / beta_s at every scatter that has a successor vertex.  One lane
-// per path in persistent workgroups (the field beta_t - beta_ref cached in
-// LDS when it fits); per-workgroup sums of r and r^2 go to partial[2*wg].
+// f_p = f_s / beta_s at every scatter that has a successor vertex.  The sum is
+// taken in log space in FP64: each scatter adds the log of its own factor
+// (extinction ratio times direction-pdf ratio), so no running product can
+// overflow or underflow.  A path that beta_t cannot produce (zero extinction,
+// or zero directional function, at one of its scatters) has r = 0: the
+// sampling pdf of Eq. final_mu carries beta(x_k) at every scatter vertex.  One
+// lane per path in persistent workgroups (the field beta_t - beta_ref cached
+// in LDS when it fits); per-workgroup sums of r and r^2 go to partial[2*wg].
 template <typename Real, bool kGridLds>
 __global__ void __launch_bounds__(kBlock) reweight_kernel(TraceArgs a)
 {
@@ -1148,7 +1113,8 @@ __global__ void __launch_bounds__(kBlock) reweight_kernel(TraceArgs a)
         const int Bn = (int)a.st.B[slot];
         if (nv <= 0) continue;
         const float4* __restrict__ V = a.st.vtx + a.st.batch_off[slot / kWave] + (slot % kWave);
-        double lr = 0.0, ratio = 1.0;  // log r = lr + log(ratio)
+        double lr = 0.0;     // log r
+        bool possible = true;  // false once some factor of mu(x|beta_t) is zero
         Vtx p0 = load_vtx(V, 0);
         double wprev[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k + 1 < nv; ++k) {
@@ -1157,21 +1123,33 @@ __global__ void __launch_bounds__(kBlock) reweight_kernel(TraceArgs a)
             const double L = seg_dir(p0, p1, w);
             lr -= (double)walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, cnt) * s.vk;
             if (k >= 1) {
+                // scatter k (it has the successor k+1): extinction ratio and
+                // direction-pdf ratio f_s,t bs_ref / (f_s,ref bs_t)
                 const int v = clamp_vox(p0.v, nu);
                 const double bct = (double)a.bc_t[v], bcr = (double)a.st.beta_ref[v];
                 const double mu = wprev[0] * w[0] + wprev[1] * w[1] + wprev[2] * w[2];
                 const double hg = phase_hg(s, mu), ra = phase_rayleigh(mu);
                 const double bst = s.w_c * bct + s.w_a * s.beta_air, bsr = s.w_c * bcr + s.w_a * s.beta_air;
-                ratio *= (fs_mix(s, bct, hg, ra) * bsr) / (fs_mix(s, bcr, hg, ra) * bst);
+                const double fst = fs_mix(s, bct, hg, ra), fsr = fs_mix(s, bcr, hg, ra);
+                if (fst > 0.0 && bst > 0.0)
+                    lr += log(((bct + s.beta_air) * fst * bsr) / ((bcr + s.beta_air) * fsr * bst));
+                else
+                    possible = false;
             }
             wprev[0] = w[0]; wprev[1] = w[1]; wprev[2] = w[2];
             p0 = p1;
         }
-        for (int k = 1; k <= Bn; ++k) {
-            const int v = clamp_vox(vox_of(V[(int64_t)k * kWave]), nu);
-            ratio *= ((double)a.bc_t[v] + s.beta_air) / ((double)a.st.beta_ref[v] + s.beta_air);
+        // the last scatter of a path capped at max_order has no successor: its
+        // extinction ratio alone
+        if (Bn > 0 && Bn + 1 == nv) {
+            const int v = clamp_vox(vox_of(V[(int64_t)Bn * kWave]), nu);
+            const double bt = (double)a.bc_t[v] + s.beta_air;
+            if (bt > 0.0)
+                lr += log(bt / ((double)a.st.beta_ref[v] + s.beta_air));
+            else
+                possible = false;
         }
-        const double r = exp(lr) * ratio;
+        const double r = possible ? exp(lr) : 0.0;
         rs += r;
         r2s += r * r;
     }

@@ -66,6 +66,7 @@ def lib():
             "prt_create": ([C.c_int, _V, C.c_int, C.POINTER(_V)], C.c_int),
             "prt_destroy": ([_V], None),
             "prt_set_stream": ([_V, _V], C.c_int),
+            "prt_set_sample_scratch_limit": ([_V, _U64], C.c_int),
             "prt_last_error": ([], C.c_char_p),
             "prt_sample": ([_V, C.POINTER(prt_scene), _U64, _U64, C.POINTER(_V)], C.c_int),
             "prt_resample": ([_V, C.POINTER(prt_scene), _U64, _U64, _V], C.c_int),
@@ -79,6 +80,7 @@ def lib():
             "prt_reweight": ([_V, C.POINTER(prt_scene), _V, C.POINTER(_D), C.POINTER(_D)], C.c_int),
             "prt_loss": ([_V, _I64, _V, _V, _V, _V], C.c_int),
             "prt_adam": ([_V, _I64, _V, _V, _V, _V, _V, _I32, _D, _D, _D, _D], C.c_int),
+            "prt_space_carve": ([_V, C.POINTER(prt_scene), C.POINTER(prt_cameras), _V, _V, _D, _V, _V], C.c_int),
             "prt_counters": ([_V, C.POINTER(prt_counters_t), C.c_int], C.c_int),
             "prt_enable_timing": ([_V, C.c_int], C.c_int),
             "prt_enable_timing_mask": ([_V, C.c_uint32], C.c_int),
@@ -159,6 +161,10 @@ def prt_set_stream(ctx, stream: int):
     _check(lib().prt_set_stream(ctx, stream))
 
 
+def prt_set_sample_scratch_limit(ctx, n_bytes: int):
+    _check(lib().prt_set_sample_scratch_limit(ctx, int(n_bytes)))
+
+
 def prt_sample(ctx, scene: prt_scene, seed: int, n_paths: int):
     h = _V()
     _check(lib().prt_sample(ctx, C.byref(scene), seed, n_paths, C.byref(h)))
@@ -237,6 +243,15 @@ def prt_adam(ctx, beta, beta_f32, grad, m, v, t: int, lr: float, b1: float = 0.9
              eps: float = 1e-8):
     _check(lib().prt_adam(ctx, beta.numel(), _dptr(beta), _dptr(beta_f32), _dptr(grad), _dptr(m), _dptr(v),
                           int(t), lr, b1, b2, eps))
+
+
+def prt_space_carve(ctx, scene: prt_scene, cams: CamerasHost, images, threshold, fill_value: float, mask,
+                    beta_out=None):
+    """images: device float64 [n][H][W]; threshold: per-camera sequence or a
+    scalar; mask: device uint8 [nz][ny][nx]; beta_out: optional device float32."""
+    thr = np.ascontiguousarray(np.broadcast_to(np.asarray(threshold, np.float64), (cams.n,)))
+    _check(lib().prt_space_carve(ctx, C.byref(scene), C.byref(cams.s), _dptr(images), _hptr(thr),
+                                 float(fill_value), _dptr(mask), None if beta_out is None else _dptr(beta_out)))
 
 
 def prt_counters(ctx, reset: bool = False) -> dict:
