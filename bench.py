@@ -10,18 +10,22 @@ backward), N / (step time).  The recycled step (the same without the
 resample, which path recycling skips on most iterations) is reported
 alongside.
 
-Workload (default): 32^3 smoothed random cloud, 20 m voxels, 0-60 1/km,
-w_c 0.99, g 0.85, air 0.01 1/km Rayleigh, sun at 30 deg; 9 cameras of
-64x64 px from -60 to +60 deg; 2^22 paths, at most 20 scatters; FP32
-traversal with FP64 weights and tallies.  Target images come from a second
-seeded field rendered with fresh paths.
+Workload (default): 128x128x64 broken-cumulus field, 20 m voxels, ten
+seeded ellipsoid blobs of log-normal(3, 0.7) 1/km extinction, w_c 0.999,
+g 0.85, air 0.01 1/km Rayleigh, sun at 30 deg; 20 cameras of 256x256 px
+from -60 to +60 deg; 2^28 paths, at most 30 scatters; FP32 traversal with
+FP64 path weights and tallies.  Target images come from the same field
+scaled by 1.1, rendered with fresh paths.  The 32^3 cloud (9 cameras of
+64x64 px, 2^22 paths, 20 orders) is measured first and reported under
+"secondary".
 
 Roofline: the dominant kernel's launches are timed with HIP events on the
 library's stream; its algorithmic work (voxel-segments and local estimates
 counted by the kernels) is converted to VALU lane-operations with fixed
 per-unit costs and compared with the chip's VALU lane-op peak.
-The CPU baseline is the FP64 oracle doing one full step on a bounded sample
-of the same workload on this host's cores.
+The CPU baseline is the FP64 oracle doing one full step on a prefix of the
+same path stream (2^22 paths by default) on this host's cores; paths are
+independent, so its paths/s rate stands for the whole workload.
 """
 from __future__ import annotations
 
@@ -42,7 +46,7 @@ TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 VALU_JSON = os.path.join(ROOT, "profiles", "pmc_valu.json")
 CSRC = os.path.join(ROOT, "paper_2110_00085_amd", "csrc")
 # device kernel measured for each timed hot-path scope
-DEVICE_KERNEL = {"grad": "grad_walk_kernel", "render": "render_kernel", "sample": "sample_kernel",
+DEVICE_KERNEL = {"grad": "grad_bin_walk_kernel", "render": "render_kernel", "sample": "sample_kernel",
                  "reweight": "reweight_kernel", "grad_weights": "grad_weights_kernel",
                  "render_prefix": "render_prefix_kernel"}
 
@@ -64,11 +68,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cloud32")
+    ap.add_argument("--workload", default="field128",
+                    help="measured workload (default: the largest, 128x128x64 with 2^28 paths)")
     ap.add_argument("--paths", type=int, default=0, help="override the number of paths")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--cpu-paths", type=int, default=1 << 22, help="paths in the CPU-baseline sample")
+    ap.add_argument("--cpu-paths", type=int, default=1 << 22,
+                    help="paths in the CPU-baseline sample (a prefix of the workload's path stream)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary cloud32 measurement reported next to a larger workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (to scale FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -80,10 +88,18 @@ def parse():
                          "LDSBankConflict SQ_INSTS_VALU csv output of a bench run into --valu-json, "
                          "then exit")
     ap.add_argument("--valu-json", default=VALU_JSON, help="where --valu-summary writes its result")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="print a markdown table of the kernel_stats.csv that rocprofv3 --kernel-trace --stats "
+                         "--output-format csv wrote under TRACE_DIR, then exit")
     ap.add_argument("--reuse-study", action="store_true",
                     help="reuse against fresh resampling at equal gradient error on --workload (default plume64 "
                          "for the study): Adam iterations on recycled paths, and at checkpoints the recycled "
                          "gradient's error and one fresh gradient's error against the mean of 8 fresh gradients")
+    ap.add_argument("--sort-ablation", action="store_true",
+                    help="path sorting (Sec. 5.3) on --workload: the production kernels against the thread-per-path "
+                         "kernels on the same store, with the paths sorted by size and in the order they were drawn")
+    ap.add_argument("--ablation-parts", default="render,grad", help="which passes the ablation times")
+    ap.add_argument("--ablation-reps", type=int, default=5)
     ap.add_argument("--study-iters", type=int, default=30)
     ap.add_argument("--study-paths", type=int, default=0, help="paths per store (default: the workload's)")
     return ap.parse_args()
@@ -123,10 +139,37 @@ def _pmc_rows(d, counter):
     return out
 
 
-def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_json):
+def _update_json(path, workload, entry):
+    """Store entry under workloads[workload] of the JSON file at path."""
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        t = {}
+    t.setdefault("workloads", {})[workload] = entry
+    with open(path, "w") as fh:
+        json.dump(t, fh, indent=1)
+
+
+def _summary_for(path, workload):
+    """The entry of workload in a counter summary JSON, or None when absent or
+    taken on other kernel sources."""
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get("workloads", {}).get(workload)
+    if not e or e.get("source_sha256") != source_hash():
+        return None
+    return e
+
+
+def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_json, workload):
     """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of every hot-path kernel
     of a bench run, scaled by what the same counters read for the 1 GiB copy
-    of --copy-calibration; writes out_json and prints a markdown table."""
+    of --copy-calibration; stores them for the workload in out_json and
+    prints a markdown table."""
     copy_kib = (1 << 30) / 1024.0
     cf = [v for _, k, v in _pmc_rows(cfetch_dir, "FETCH_SIZE") if "copyBuffer" in k]
     cw = [v for _, k, v in _pmc_rows(cwrite_dir, "WRITE_SIZE") if "copyBuffer" in k]
@@ -148,12 +191,11 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_json):
         print(f"| {DEVICE_KERNEL[scope]} | {len(c['FETCH_SIZE'])} | {fk:.0f} | {wk:.0f} | {b:.4g} |")
     print(f"\ncopy calibration (1 GiB): FETCH_SIZE reads {sum(cf) / len(cf):.0f} KiB (factor {f_fac:.3f}), "
           f"WRITE_SIZE {sum(cw) / len(cw):.0f} KiB (factor {w_fac:.3f})")
-    with open(out_json, "w") as fh:
-        json.dump({"source_sha256": source_hash(), "fetch_factor": f_fac, "write_factor": w_fac,
-                   "kernels": table}, fh, indent=1)
+    _update_json(out_json, workload, {"source_sha256": source_hash(), "fetch_factor": f_fac,
+                                      "write_factor": w_fac, "kernels": table})
 
 
-def valu_summary(valu_dir, occ_dir, out_json):
+def valu_summary(valu_dir, occ_dir, out_json, workload):
     """Means over the dispatches of every hot-path kernel of VALU busy (% of
     VALU issue cycles), VALU lane utilisation (% of lanes active per VALU
     instruction), mean wavefronts per CU, LDS bank-conflict cycles (%) and
@@ -179,35 +221,40 @@ def valu_summary(valu_dir, occ_dir, out_json):
         print(f"| {row['kernel']} | {len(c.get('VALUBusy', []))} | {row['valu_busy_pct']:.1f} | "
               f"{row['valu_lane_util_pct']:.1f} | {row['waves_per_cu']:.1f} | {row['lds_bank_conflict_pct']:.2f} | "
               f"{row['valu_instr']:.3g} |")
-    with open(out_json, "w") as fh:
-        json.dump({"source_sha256": source_hash(), "kernels": table}, fh, indent=1)
+    _update_json(out_json, workload, {"source_sha256": source_hash(), "kernels": table})
 
 
-def valu_for(scope):
-    """VALU counters of the kernel behind `scope` from --valu-json, or None
-    when none were taken for it or its sources changed since."""
-    try:
-        with open(VALU_JSON) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if t.get("source_sha256") != source_hash():
-        return None
-    k = t.get("kernels", {}).get(scope)
+def trace_summary(trace_dir):
+    """Markdown table (kernel, calls, total / average / min / max ms, share)
+    of rocprofv3's kernel_stats.csv, kernels by total time."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        sys.exit(f"no kernel_stats.csv under {trace_dir}")
+    rows = list(csv.DictReader(open(files[0])))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    print("| kernel | calls | total ms | avg ms | % | min ms | max ms |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for r in rows:
+        print(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+              f"{float(r['AverageNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} | {float(r['MinNs']) / 1e6:.4f} | "
+              f"{float(r['MaxNs']) / 1e6:.4f} |")
+
+
+def valu_for(scope, workload):
+    """VALU counters of the kernel behind `scope` on `workload` from
+    --valu-json, or None when none were taken or its sources changed since."""
+    e = _summary_for(VALU_JSON, workload)
+    k = e.get("kernels", {}).get(scope) if e else None
     return {"busy_pct": k["valu_busy_pct"], "lane_util_pct": k["valu_lane_util_pct"]} if k else None
 
 
-def traffic_for(scope):
-    """Scaled HBM bytes per launch of the kernel behind `scope`, or None when
-    no counters were taken for it or its sources changed since."""
-    try:
-        with open(TRAFFIC_JSON) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if t.get("source_sha256") != source_hash():
-        return None
-    k = t.get("kernels", {}).get(scope)
+def traffic_for(scope, workload):
+    """Scaled HBM bytes per launch of the kernel behind `scope` on
+    `workload`, or None when no counters were taken or its sources changed."""
+    e = _summary_for(TRAFFIC_JSON, workload)
+    k = e.get("kernels", {}).get(scope) if e else None
     return k["bytes_per_launch"] if k else None
 
 
@@ -308,32 +355,18 @@ def reuse_study(args):
                       "checkpoints": rows}), flush=True)
 
 
-def main():
-    args = parse()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.pmc_summary:
-        pmc_summary(*args.pmc_summary, args.traffic_json)
-        return
-    if args.valu_summary:
-        valu_summary(*args.valu_summary, args.valu_json)
-        return
-    if args.reuse_study:
-        reuse_study(args)
-        return
-    if args.gpus != 1:
-        print("bench.py: the hot path runs on one GPU; --gpus must be 1 (sharding paths over GPUs is not "
-              "implemented)", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
+def run_workload(args, name, steps, warmup, breakdown_steps, recycled_steps, cpu_paths):
+    """One workload: warmup full steps, an untimed per-kernel breakdown, the
+    timed full steps (events around the dominant kernel only), recycled
+    steps; returns the result dict (metric line fields, roofline and, when
+    cpu_paths > 0, the oracle's rate on the first cpu_paths paths)."""
     import torch
 
     import inputs
     from paper_2110_00085_amd import api, prt as P
 
-    make_scene, make_cams, n_paths, seed = inputs.WORKLOADS[args.workload]
-    if args.paths:
+    make_scene, make_cams, n_paths, seed = inputs.WORKLOADS[name]
+    if args.paths and name == args.workload:
         n_paths = args.paths
     scene = make_scene()
     cams = make_cams(scene)
@@ -341,18 +374,21 @@ def main():
     prec = P.PRT_ALL_FP64 if args.precision == "fp64" else P.PRT_TRAVERSAL_FP32
     dev = torch.device("cuda:0")
     torch.cuda.set_device(0)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info(0)[0]
     ctx = api.Context(0, prec)
     h = ctx.handle
-    print(f"[bench] workload {args.workload}: grid {scene.nx}x{scene.ny}x{scene.nz}, {cams.n} cams "
+    print(f"[bench] workload {name}: grid {scene.nx}x{scene.ny}x{scene.nz}, {cams.n} cams "
           f"{cams.width}x{cams.height}, {n_paths} paths, {scene.max_order} orders, {args.precision}", flush=True)
 
     # target images from a second seeded field with fresh paths (untimed)
-    tgt_scene = scene.with_beta(inputs.gaussian_field_cloud(scene.nx, 3)) if args.workload == "cloud32" else \
+    tgt_scene = scene.with_beta(inputs.gaussian_field_cloud(scene.nx, 3)) if name == "cloud32" else \
         scene.with_beta(scene.beta_cloud * 1.1)
     tb = torch.as_tensor(tgt_scene.beta_cloud).to(dev)
     st_t = api.PathStore.sample(ctx, tgt_scene, tb, seed + 1000, n_paths)
     target = api.render(ctx, tgt_scene, tb, ch, st_t)
     st_t.close()
+    del tb
 
     beta32 = torch.as_tensor(scene.beta_cloud).to(dev).contiguous()
     beta64 = beta32.double()
@@ -384,23 +420,25 @@ def main():
         resample()
         return iterate()
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         full_step()
     torch.cuda.synchronize()
+    hbm_used = (free0 - torch.cuda.mem_get_info(0)[0]) / 2 ** 30
 
-    # algorithmic work of one render and one grad on the current store
+    # algorithmic work of one render on the current store
     P.prt_counters(h, reset=True)
     P.prt_render(h, sc, ch, state["store"].handle, scene.max_order, img)
     c_r = P.prt_counters(h, reset=True)
 
-    # per-kernel breakdown: K full steps with an event pair around every
+    # per-kernel breakdown: full steps with an event pair around every
     # kernel (untimed; the events add a little to each step)
     P.prt_enable_timing(h, True)
     P.prt_kernel_times(h, reset=True)
-    for _ in range(args.steps):
+    for _ in range(breakdown_steps):
         full_step()
     kbreak = P.prt_kernel_times(h, reset=True)
     dom = max(kbreak, key=lambda k: kbreak[k][0])
+    print(f"[bench] {name}: breakdown over {breakdown_steps} steps done, dominant kernel {dom}", flush=True)
 
     # timed region: K full steps, events around the dominant kernel only
     P.prt_enable_timing_mask(h, [dom])
@@ -408,39 +446,41 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rw = None
-    for _ in range(args.steps):
+    for _ in range(steps):
         rw = full_step()
     torch.cuda.synchronize()
     t_full = time.perf_counter() - t0
     ktimes = P.prt_kernel_times(h, reset=True)
     P.prt_enable_timing(h, False)
+    print(f"[bench] {name}: {steps} timed steps in {t_full:.2f} s", flush=True)
 
     # recycled steps (no resample) for reference
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(recycled_steps):
         iterate()
     torch.cuda.synchronize()
     t_rec = time.perf_counter() - t0
 
-    ms_step = 1e3 * t_full / args.steps
-    value = n_paths / (t_full / args.steps)
+    ms_step = 1e3 * t_full / steps
+    value = n_paths / (t_full / steps)
     # roofline of the dominant kernel (most time per step), timed in the timed
-    # region; a grad call may launch its kernel once per z slab, so work is
-    # spread over its launches
+    # region; a grad call may launch its kernel more than once, so its work
+    # is spread over its launches
     launches = max(ktimes[dom][1], 1)
     dom_ms = ktimes[dom][0] / launches
-    per_call = launches / args.steps
+    per_call = launches / steps
     units = {"voxel_segment": c_r["voxel_segments"], "local_estimate": c_r["local_estimates"]}
     per = OPS.get(dom)
-    # the counter summaries were taken on the default command's workload
-    profiled = args.workload == "cloud32" and args.paths == 0 and args.precision == "fp32"
+    # counter summaries apply only to the workload and sources they were taken on
+    traffic, valu = traffic_for(dom, name), valu_for(dom, name)
+    if args.paths or args.precision != "fp32":
+        traffic = valu = None
     roofline = {"bound": "alu", "kernel": dom, "achieved": None, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                "unit": "TOP/s", "frac": None, "traffic": traffic_for(dom) if profiled else None,
-                "avg_launch_ms": dom_ms, "launches_per_step": per_call}
-    roofline["valu"] = valu_for(dom) if profiled else None
-    if roofline["traffic"] is not None:
-        hbm = roofline["traffic"] / (dom_ms * 1e-3) / 1e9
+                "unit": "TOP/s", "frac": None, "traffic": traffic, "avg_launch_ms": dom_ms,
+                "launches_per_step": per_call, "valu": valu}
+    if traffic is not None:
+        hbm = traffic / (dom_ms * 1e-3) / 1e9
         roofline["hbm"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS}
     if per is not None:
         work = {k: units[k] / per_call for k in per}
@@ -454,30 +494,142 @@ def main():
         "value": value,
         "unit": "paths/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 traversal, f64 weights/tallies" if args.precision == "fp32" else "f64",
+        "dtype": ("f32 traversal; f32 stored contributions c and gradient weights w; "
+                  "f64 path weights, log r, image and gradient tallies") if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {scene.nx}x{scene.ny}x{scene.nz} grid "
+        "config": {"workload": f"{name}: {scene.nx}x{scene.ny}x{scene.nz} grid "
                                f"{scene.voxel_km * 1000:g} m voxels, {cams.n} cameras {cams.width}x{cams.height}, "
                                f"{n_paths} paths, {scene.max_order} orders, step = resample+render+loss+grad"
                                f"+adam+reweight",
                    "paths": n_paths, "precision": args.precision},
-        "recycled_ms_per_step": 1e3 * t_rec / args.steps,
-        "recycled_paths_per_s": n_paths / (t_rec / args.steps),
+        "recycled_ms_per_step": 1e3 * t_rec / max(recycled_steps, 1),
+        "recycled_paths_per_s": n_paths / (t_rec / max(recycled_steps, 1)) if recycled_steps else None,
+        "voxel_segments_per_render": units["voxel_segment"],
+        "local_estimates_per_render": units["local_estimate"],
         "voxel_segments_per_s_render": units["voxel_segment"] / (kbreak["render"][0] / max(kbreak["render"][1], 1) * 1e-3),
-        "kernel_ms_per_step": {k: kbreak[k][0] / args.steps for k in kbreak if kbreak[k][1]},
+        "kernel_ms_per_step": {k: kbreak[k][0] / breakdown_steps for k in kbreak if kbreak[k][1]},
+        "hbm_in_use_gib": hbm_used,
         "mean_r_last": rw[0] if rw else None,
         "roofline": roofline,
     }
+    if cpu_paths > 0:
+        out["cpu_baseline"] = cpu_baseline(scene, cams, target.cpu().numpy(), seed, min(cpu_paths, n_paths),
+                                           n_paths, name)
+    state["store"].close()
+    ctx.close()
+    del target, img, res, grad, beta32, beta64, m, v
+    torch.cuda.empty_cache()
+    return out
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(scene, cams, target.cpu().numpy(), seed, min(args.cpu_paths, n_paths),
-                                           n_paths, args.workload)
+
+def sort_ablation(args):
+    """Path sorting (Sec. 5.3, "up to 3x" with 32-thread groups) at wave64.
+
+    On one store of the workload: the production kernels (persistent
+    wavefront tasks over the size-sorted, batch-major store), and the
+    thread-per-path kernels on per-path copies of the same paths in size
+    order and in drawing order.  Each pass is timed over --ablation-reps
+    calls after one untimed call (which also builds the per-path copies)."""
+    import torch
+
+    import inputs
+    from paper_2110_00085_amd import api, prt as P
+    name = args.workload
+    make_scene, make_cams, n_paths, seed = inputs.WORKLOADS[name]
+    if args.paths:
+        n_paths = args.paths
+    scene = make_scene()
+    cams = make_cams(scene)
+    ch = P.CamerasHost(cams)
+    ctx = api.Context(0, P.PRT_ALL_FP64 if args.precision == "fp64" else P.PRT_TRAVERSAL_FP32)
+    h = ctx.handle
+    dev = torch.device("cuda:0")
+    beta = torch.as_tensor(scene.beta_cloud).to(dev).contiguous()
+    st = api.PathStore.sample(ctx, scene, beta, seed, n_paths)
+    sc = P.make_scene(scene, beta)
+    img = api.render(ctx, scene, beta, ch, st)
+    res = (img * 0.05).contiguous()
+    g = torch.empty((scene.nz, scene.ny, scene.nx), dtype=torch.float64, device=dev)
+    parts = args.ablation_parts.split(",")
+    print(f"[ablation] {name}: {n_paths} paths, parts {parts}, {args.ablation_reps} reps", flush=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.ablation_reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / args.ablation_reps
+
+    out = {"study": "path sorting", "workload": name, "paths": n_paths, "precision": args.precision, "ms": {}}
+    for part in parts:
+        if part == "render":
+            runs = {"production": lambda: P.prt_render(h, sc, ch, st.handle, scene.max_order, img),
+                    "thread_per_path_sorted": lambda: P.prt_tpp_render(h, sc, ch, st.handle, P.PRT_ORDER_BY_SIZE, img),
+                    "thread_per_path_unsorted": lambda: P.prt_tpp_render(h, sc, ch, st.handle, P.PRT_ORDER_BY_ID, img)}
+        else:
+            # the production gradient walks on the transmittance tape of the last render
+            P.prt_render(h, sc, ch, st.handle, scene.max_order, img)
+            runs = {"production": lambda: P.prt_grad(h, sc, ch, st.handle, res, g),
+                    "thread_per_path_sorted": lambda: P.prt_tpp_grad(h, sc, ch, st.handle, P.PRT_ORDER_BY_SIZE, res, g),
+                    "thread_per_path_unsorted": lambda: P.prt_tpp_grad(h, sc, ch, st.handle, P.PRT_ORDER_BY_ID, res, g)}
+        for k, fn in runs.items():
+            out["ms"][f"{part}_{k}"] = timed(fn)
+            print(f"[ablation] {part} {k}: {out['ms'][f'{part}_{k}']:.3f} ms", flush=True)
+        m = out["ms"]
+        out[f"{part}_sorting_speedup"] = m[f"{part}_thread_per_path_unsorted"] / m[f"{part}_thread_per_path_sorted"]
+        out[f"{part}_production_vs_unsorted"] = m[f"{part}_thread_per_path_unsorted"] / m[f"{part}_production"]
+    print(json.dumps(out), flush=True)
+    st.close()
+    ctx.close()
+
+
+def main():
+    args = parse()
+    if args.sort_ablation:
+        sort_ablation(args)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, args.traffic_json, args.workload)
+        return
+    if args.valu_summary:
+        valu_summary(*args.valu_summary, args.valu_json, args.workload)
+        return
+    if args.reuse_study:
+        reuse_study(args)
+        return
+    if args.gpus != 1:
+        print("bench.py: the hot path runs on one GPU; --gpus must be 1 (sharding paths over GPUs is not "
+              "implemented)", file=sys.stderr)
+        sys.exit(2)
+    import inputs
+    large = inputs.WORKLOADS[args.workload][2] >= (1 << 24) and not args.paths
+    # the untimed breakdown and recycled passes are shortened on the large
+    # workloads so that the default run stays within a few minutes
+    bsteps = min(args.steps, 2) if large else args.steps
+    rsteps = min(args.steps, 3) if large else args.steps
+    secondary = {}
+    if args.workload != "cloud32" and not args.no_secondary:
+        s = run_workload(args, "cloud32", 20, 5, 20, 20, 0)
+        secondary["cloud32"] = {k: s[k] for k in ("value", "ms_per_step", "recycled_ms_per_step",
+                                                  "kernel_ms_per_step", "roofline", "config")}
+    out = run_workload(args, args.workload, args.steps, args.warmup, bsteps, rsteps,
+                       0 if args.no_cpu_baseline else args.cpu_paths)
+    if secondary:
+        out["secondary"] = secondary
     print(json.dumps(out), flush=True)
 
 
@@ -524,7 +676,9 @@ def cpu_baseline(scene, cams, target, seed, n_cpu, n_total, workload):
             one = n1 / float(r.stdout.strip().splitlines()[-1])
     return {"value": n_cpu / dt, "unit": "paths/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"one full step on the first {n_cpu} of the {n_total} paths (same seeds), FP64, "
-                      f"{dt:.1f} s; the 1-core rate on the first {n1}",
+                      f"{dt:.1f} s; the 1-core rate on the first {n1}"
+                      + ("; rate extrapolated to the whole workload (paths are independent)"
+                         if n_cpu < n_total else ""),
             "value_1core": one}
 
 

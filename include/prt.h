@@ -236,6 +236,27 @@ int prt_adam(prt_ctx ctx, int64_t n, double* beta, float* beta_f32, const double
 int prt_space_carve(prt_ctx ctx, const prt_scene* scene, const prt_cameras* cams, const double* images,
                     const double* threshold, double fill_value, uint8_t* mask, float* beta_out);
 
+/* -------------------------------------------- path-sorting ablation */
+
+/* The paper's GPU design for comparison (Sec. 5.3, path sorting): one thread
+   per stored path walks all of its scatters and cameras, as the paper's
+   kernels do, on a per-path copy of the store taken in `order`:
+   PRT_ORDER_BY_SIZE (the store's order, sorted by path size as Alg. 2's
+   "Sort" step) or PRT_ORDER_BY_ID (the order the paths were drawn in, i.e.
+   no sorting).  The copy is built on first use after each (re)fill of the
+   store and kept with it.  prt_tpp_render computes the images of
+   prt_render (all orders; FP64 atomics on the images); prt_tpp_grad the
+   gradient of prt_grad, recomputing every contribution (LDS slab tallies or
+   FP64 atomics, as prt_grad without a tape).  Same arguments, layouts,
+   ownership and errors as prt_render / prt_grad; PRT_E_INVALID for another
+   order.  Async. */
+#define PRT_ORDER_BY_SIZE 0
+#define PRT_ORDER_BY_ID 1
+int prt_tpp_render(prt_ctx ctx, const prt_scene* scene, const prt_cameras* cams, prt_paths paths, int32_t order,
+                   double* images);
+int prt_tpp_grad(prt_ctx ctx, const prt_scene* scene, const prt_cameras* cams, prt_paths paths, int32_t order,
+                 const double* residual, double* grad);
+
 /* ----------------------------------------------------------- telemetry */
 
 /* Read (and optionally reset) the work counters.  Synchronises. */

@@ -198,28 +198,16 @@ __device__ __forceinline__ void lds_fill(T* dst, int n, F&& value)
 // any input, including non-finite directions (whose components are treated
 // as zero).  Face parameters are always measured from p, so a walk that
 // starts part way (t > 0) produces the same pieces as one started at p.
-template <typename Real, bool kBounded = true, typename F>
-__device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real px, Real py, Real pz, int ix, int iy,
-                                          int iz, int sx, int sy, int sz, Real ivx, Real ivy, Real ivz, Real t,
-                                          Real tmax, uint32_t& pieces, F&& f)
+// The step loop shared by every walk: R packs the faces left before the
+// boundary along x, y and z in 10-bit fields that start at 512 + faces (a
+// step past the last face of an axis clears that field's bit 9; dimensions
+// are at most 512 voxels), v is the voxel index, dvx/dvy/dvz the index steps.
+template <typename Real, bool kBounded, typename F>
+__device__ __forceinline__ Real dda_loop(int R, int v, int dvx, int dvy, int dvz, Real tnx, Real tny, Real tnz,
+                                         Real dtx, Real dty, Real dtz, Real t, Real tmax, uint32_t& pieces, F&& f)
 {
-    const Real inf = (Real)INFINITY;
-    // face parameters, clamped to the start so that no piece is negative
-    Real tnx = fmax(sx > 0 ? ((Real)(ix + 1) - px) * ivx : (sx < 0 ? ((Real)ix - px) * ivx : inf), t);
-    Real tny = fmax(sy > 0 ? ((Real)(iy + 1) - py) * ivy : (sy < 0 ? ((Real)iy - py) * ivy : inf), t);
-    Real tnz = fmax(sz > 0 ? ((Real)(iz + 1) - pz) * ivz : (sz < 0 ? ((Real)iz - pz) * ivz : inf), t);
-    const Real dtx = (Real)sx * ivx, dty = (Real)sy * ivy, dtz = (Real)sz * ivz;
-    // Faces left before the boundary along each axis, packed in 10-bit fields
-    // that start at 512 + faces: a step past the last face of an axis clears
-    // that field's bit 9 (dimensions are at most 512 voxels).
-    const int rx = sx > 0 ? nx - 1 - ix : ix;
-    const int ry = sy > 0 ? ny - 1 - iy : iy;
-    const int rz = sz > 0 ? z1 - 1 - iz : iz - z0;
     constexpr int kGuard = (1 << 9) | (1 << 19) | (1 << 29);
-    int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
     const int R0 = R;
-    const int dvx = sx, dvy = sy * nx, dvz = sz * nx * ny;
-    int v = ix + nx * (iy + ny * (iz - z0));
     for (;;) {
         const Real tn = fmin(tnx, fmin(tny, tnz));
         const bool go = !kBounded || tn < tmax;
@@ -241,6 +229,30 @@ __device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real p
     const int used = (R0 & 1023) + ((R0 >> 10) & 1023) + (R0 >> 20) - (R & 1023) - ((R >> 10) & 1023) - (R >> 20);
     pieces += (uint32_t)used;
     return t;
+}
+
+// Face parameter of the next face along one axis (direction sign s, inverse
+// component iv) from voxel i, clamped to the start t so that no piece is
+// negative.
+template <typename Real>
+__device__ __forceinline__ Real dda_first_face(int s, int i, Real p, Real iv, Real t)
+{
+    return fmax(s > 0 ? ((Real)(i + 1) - p) * iv : (s < 0 ? ((Real)i - p) * iv : (Real)INFINITY), t);
+}
+
+template <typename Real, bool kBounded = true, typename F>
+__device__ __forceinline__ Real dda_steps(int nx, int ny, int z0, int z1, Real px, Real py, Real pz, int ix, int iy,
+                                          int iz, int sx, int sy, int sz, Real ivx, Real ivy, Real ivz, Real t,
+                                          Real tmax, uint32_t& pieces, F&& f)
+{
+    const int rx = sx > 0 ? nx - 1 - ix : ix;
+    const int ry = sy > 0 ? ny - 1 - iy : iy;
+    const int rz = sz > 0 ? z1 - 1 - iz : iz - z0;
+    const int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
+    return dda_loop<Real, kBounded>(R, ix + nx * (iy + ny * (iz - z0)), sx, sy * nx, sz * nx * ny,
+                                    dda_first_face(sx, ix, px, ivx, t), dda_first_face(sy, iy, py, ivy, t),
+                                    dda_first_face(sz, iz, pz, ivz, t), (Real)sx * ivx, (Real)sy * ivy,
+                                    (Real)sz * ivz, t, tmax, pieces, f);
 }
 
 // Inverse of a direction component: FP32 walks take the hardware reciprocal
@@ -322,6 +334,61 @@ __device__ __forceinline__ void dda_walk_slab(int nx, int ny, int z0, int z1, Re
         t = fmax(t, (Real)0);
     }
     dda_steps<Real, kBounded>(nx, ny, z0, z1, px, py, pz, ix, iy, iz, sx, sy, sz, ivx, ivy, ivz, t, tmax, pieces, f);
+}
+
+// An axis-aligned block of the grid, voxels [lo[a], hi[a]) along axis a,
+// numbered inside the block as sum over a of (i_a - lo[a]) * st[a].
+struct SubBox {
+    int lo[3], hi[3];
+    int st[3];
+};
+
+// The part of the walk from p (in voxel (ix,iy,iz)) along w, t in [0, tmax]
+// (unbounded without kBounded), that lies in the block b: the pieces of the
+// whole-grid walk that fall in it, voxels numbered inside the block, pieces
+// counted as in dda_walk_counted.  When p lies outside the block the walk
+// enters it where the ray meets the block (if it does before tmax); the
+// entry voxel is taken from the entry point, so a piece next to the entry can
+// differ from the whole-grid walk by rounding only.
+template <typename Real, bool kBounded = true, typename F>
+__device__ __forceinline__ void dda_walk_box(const SubBox& b, Real px, Real py, Real pz, int ix, int iy, int iz,
+                                             Real wx, Real wy, Real wz, Real tmax, uint32_t& pieces, F&& f)
+{
+    int sx, sy, sz;
+    Real ivx, ivy, ivz;
+    if (!dda_dir(wx, wy, wz, sx, sy, sz, ivx, ivy, ivz)) return;
+    Real t = (Real)0;
+    const bool inside = ix >= b.lo[0] && ix < b.hi[0] && iy >= b.lo[1] && iy < b.hi[1] && iz >= b.lo[2] &&
+                        iz < b.hi[2];
+    if (!inside) {
+        // slab clipping of the ray against the block
+        Real tn = (Real)0, tf = kBounded ? tmax : (Real)INFINITY;
+        const int s[3] = {sx, sy, sz}, i[3] = {ix, iy, iz};
+        const Real p[3] = {px, py, pz}, iv[3] = {ivx, ivy, ivz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (s[a] == 0) {
+                if (i[a] < b.lo[a] || i[a] >= b.hi[a]) return;
+            } else {
+                const Real t1 = ((Real)b.lo[a] - p[a]) * iv[a], t2 = ((Real)b.hi[a] - p[a]) * iv[a];
+                tn = fmax(tn, fmin(t1, t2));
+                tf = fmin(tf, fmax(t1, t2));
+            }
+        }
+        if (!(tn < tf)) return;
+        t = tn;
+        ix = min(max((int)floor(px + t * wx), b.lo[0]), b.hi[0] - 1);
+        iy = min(max((int)floor(py + t * wy), b.lo[1]), b.hi[1] - 1);
+        iz = min(max((int)floor(pz + t * wz), b.lo[2]), b.hi[2] - 1);
+    }
+    const int rx = sx > 0 ? b.hi[0] - 1 - ix : ix - b.lo[0];
+    const int ry = sy > 0 ? b.hi[1] - 1 - iy : iy - b.lo[1];
+    const int rz = sz > 0 ? b.hi[2] - 1 - iz : iz - b.lo[2];
+    const int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
+    const int v = (ix - b.lo[0]) * b.st[0] + (iy - b.lo[1]) * b.st[1] + (iz - b.lo[2]) * b.st[2];
+    dda_loop<Real, kBounded>(R, v, sx * b.st[0], sy * b.st[1], sz * b.st[2], dda_first_face(sx, ix, px, ivx, t),
+                             dda_first_face(sy, iy, py, ivy, t), dda_first_face(sz, iz, pz, ivz, t),
+                             (Real)sx * ivx, (Real)sy * ivy, (Real)sz * ivz, t, tmax, pieces, f);
 }
 
 // Spatial sort key of a path (the store orders paths by size B, then by this

@@ -97,7 +97,36 @@ struct TraceArgs {
     // render prefix: also copies beta_t here (the tape's field) when set, and
     // zeroes the render's task counters
     float* copy_beta;
+    // Binned gradient (tape case): trange[2*t], trange[2*t+1] = first and last
+    // slab that a walk of gradient task t reaches (t numbered as in the walk
+    // kernels: batch n_batches-1-t/(groups+1), kind t%(groups+1)); set by the
+    // weights kernel when non-null.
+    int* trange;
+    int bin_axis, bin_layers;  // slab axis and layers per slab of those ranges
+    // and, per connection, its own slab range lo | hi << 16 in the tape's
+    // layout (0xffff when the connection has no weight)
+    uint32_t* rtape;
 };
+
+// Slabs of the binned gradient: layers of the grid along `axis`, `layers`
+// per slab (the last one may be thinner), each slab tallied in LDS with its
+// voxels numbered (i_b + n_b (i_c + n_c (i_axis - first layer))), b < c the
+// other two axes.
+struct GradBins {
+    int axis;
+    int layers;
+    int n_slabs;
+    int64_t n_tasks;     // (batches from the first scattering one) * (groups + 1)
+    int64_t n_blocks;    // blocks of kBinTasks tasks
+    uint32_t* cnt;       // [n_slabs * n_blocks + 1], scanned in place
+    uint32_t* list;      // task ids, slab after slab
+    int64_t list_cap;
+    uint32_t* chunks;    // [n_slabs + 2]: first chunk of each slab, chunk count, chunk size
+    double* partial;     // per chunk: the slab's sums
+};
+constexpr int kBinTasks = 1024;
+constexpr int kMaxBinSlabs = 512;  // slabs the binning kernels count per block
+constexpr int kBinChunkWord = 3;  // chunk counter of the binned walk: word 3 of the task-counter set
 
 // Per-vertex task levels of the render prefix and the gradient weights: one
 // task per (batch, scatter index b) with a path of at least b scatters.  The
@@ -138,6 +167,12 @@ constexpr int kMetaFirstGe = 8;
 constexpr int kMetaWords = kMetaFirstGe + kMaxOrder + 1;
 hipError_t launch_store_meta(hipStream_t st, const uint8_t* B, int64_t n, const int64_t* batch_off, int64_t nb,
                              int64_t* meta);
+// Exclusive prefix sum of n uint32 values in place; scratch holds
+// scan_u32_scratch_words(n) words.
+int64_t scan_u32_scratch_words(int64_t n);
+hipError_t launch_scan_u32(hipStream_t st, uint32_t* a, int64_t n, uint32_t* scratch);
+// The same for int64 values (scratch: scan_u32_scratch_words(n) int64 words).
+hipError_t launch_scan_i64(hipStream_t st, int64_t* a, int64_t n, int64_t* scratch);
 
 // ---- hot path (trace.hip)
 // Where render tallies and reads: with img_tape (the render records the
@@ -181,6 +216,8 @@ struct GradPlan {
     size_t partial_bytes = 0;
 };
 GradPlan plan_grad(int nx, int ny, int nz, int64_t n_slots, int64_t first_slot, int n_cu, bool tape);
+// z layers [*z0, *z1) of slab i of a plan.
+void grad_slab(const GradPlan& p, int nz, int i, int* z0, int* z1);
 // Gradient weights from the tape (runs only when *a.tape_flag is 1).
 hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams& c, const VertexLevels& lv, int n_cu);
 // Gradient terms of slab i (z layers [i*slab_layers, min(nz, (i+1)*slab_layers))):
@@ -188,16 +225,63 @@ hipError_t launch_grad_weights(hipStream_t st, const TraceArgs& a, const DevCams
 // zero): with a tape flag, the walk kernel on the stored weights and the
 // recomputing kernel, exactly one of which does work; with lds,
 // launch_grad_reduce then writes the slab's gradient.
+// With walk_on_tape false and a tape flag given, only the recomputing kernel
+// is launched (it works when the tape does not match).
 hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p, int slab,
-                       void* partial);
+                       void* partial, bool walk_on_tape = true);
 // (also zeroes the task counters in work for the next slab's launch)
+// (skipped, but for the counters, when skip is non-null and *skip is 1)
 hipError_t launch_grad_reduce(hipStream_t st, const GradPlan& p, int nx, int ny, int nz, int slab,
-                              const void* partial, double* grad, unsigned int* work);
+                              const void* partial, double* grad, unsigned int* work, const int* skip = nullptr);
+// Binned gradient on the tape (every kernel returns at once unless
+// *a.tape_flag is 1): choose_grad_bins picks the slab axis (the one along
+// which the connections to the cameras and the sun's rays move least) and the
+// slab thickness; launch_grad_bin_init clears the task ranges and zeroes grad;
+// after launch_grad_weights has set the ranges, launch_grad_bin_lists counts
+// the tasks per slab, scans and lists them slab after slab;
+// launch_grad_bin_walk cuts the lists into chunks and runs the persistent walk
+// kernel (chunk counter at work[kBinChunkWord] zero at launch), which tallies
+// a chunk's slab in LDS and writes it out as the chunk's partial; and
+// launch_grad_bin_reduce adds each voxel's partials into grad.
+GradBins choose_grad_bins(const DevScene& s, const DevCams& c, int64_t n_tasks);
+// Whether one layer of the chosen axis fits the LDS and the slabs are few
+// enough for the binning kernels' per-slab counters.
+bool grad_bins_fit(const DevScene& s, const GradBins& g);
+hipError_t launch_grad_bin_init(hipStream_t st, const TraceArgs& a, const GradBins& g);
+hipError_t launch_grad_bin_lists(hipStream_t st, const TraceArgs& a, const GradBins& g, uint32_t* scan_scratch);
+hipError_t launch_grad_bin_walk(hipStream_t st, const TraceArgs& a, const DevCams& c, const GradBins& g, int n_cu);
+hipError_t launch_grad_bin_reduce(hipStream_t st, const TraceArgs& a, const GradBins& g);
+// Bytes of g.partial for a walk launch on n_cu workgroups.
+size_t grad_bin_partial_bytes(const DevScene& s, const GradBins& g, int n_cu);
 // Per-workgroup sums of r and r^2 into a.partial[2*wg..]; *n_blocks workgroups.
 hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int n_cu, int64_t* n_blocks);
 // flag = 0 if a[i] != b[i] bitwise for some i < n (flag set to 1 beforehand,
 // by launch_grad_prep).
 hipError_t launch_equal_flag(hipStream_t st, const float* a, const float* b, int64_t n, int* flag);
+
+// ---- path-sorting ablation (ablation.hip)
+// A per-path (CSR) copy of a store in one order: path q's records are
+// rec[off[q] .. off[q+1]), its size B[q]; n paths.
+struct TppView {
+    const float4* rec;
+    const int64_t* off;
+    const uint8_t* B;
+    int64_t n;
+};
+// Layout of the copy in `order` (0: the store's order, sorted by size; 1:
+// path-id order, inv[id] = slot written from perm): off[0..n] = exclusive
+// scan of the record counts (off[n] = total), qB = sizes; then the copy.
+hipError_t launch_tpp_layout(hipStream_t st, const StoreView& sv, int64_t n, const int32_t* perm, int order,
+                             int32_t* inv, int64_t* off, uint8_t* qB, void* scan_scratch);
+hipError_t launch_tpp_copy(hipStream_t st, const StoreView& sv, int64_t n, const int32_t* inv, int order,
+                           const int64_t* off, float4* rec);
+// One thread per path: images (raw tallies, FP64 atomics on a.img) and the
+// gradient terms of slab `slab` of plan p (LDS partials or FP64 atomics on
+// a.grad, as the recomputing gradient kernel).
+hipError_t launch_tpp_render(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const TppView& v,
+                             int n_cu);
+hipError_t launch_tpp_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const TppView& v,
+                           const GradPlan& p, int slab, double* partial);
 
 // ---- loop glue (loop.hip)
 hipError_t launch_fill(hipStream_t st, double* p, int64_t n, double v);

@@ -37,11 +37,14 @@ int fail(int code, const char* fmt, ...)
 
 enum KernelId {
     K_SAMPLE = 0, K_SORT, K_PACK, K_PREP, K_RENDER, K_FINALIZE, K_GRAD, K_REWEIGHT, K_LOSS, K_ADAM,
-    K_RENDER_REDUCE, K_GRAD_REDUCE, K_GRAD_WEIGHTS, K_RENDER_PREFIX, K_COUNT
+    K_RENDER_REDUCE, K_GRAD_REDUCE, K_GRAD_WEIGHTS, K_RENDER_PREFIX, K_GRAD_BIN, K_GRAD_RECOMPUTE, K_TPP_LAYOUT,
+    K_TPP_RENDER, K_TPP_GRAD, K_COUNT
 };
 const char* kKernelNames[K_COUNT] = {"sample", "sort",          "pack",        "prep",         "render",
                                      "render_finalize", "grad",  "reweight",    "loss",         "adam",
-                                     "render_reduce",   "grad_reduce", "grad_weights", "render_prefix"};
+                                     "render_reduce",   "grad_reduce", "grad_weights", "render_prefix",
+                                     "grad_bin",        "grad_recompute", "tpp_layout",   "tpp_render",
+                                     "tpp_grad"};
 
 struct Timed {
     int id;
@@ -64,6 +67,17 @@ struct prt_ctx_s {
     void* pb = nullptr;         // render prefix weights per vertex record (double)
     void* gw = nullptr;         // gradient weights per (vertex, camera), tape layout
     void* gaux = nullptr;       // per-vertex gradient sums (float4)
+    // binned gradient: task slab ranges, per-slab counts (+ scan scratch), task lists
+    void* bin_trange = nullptr;
+    size_t bin_trange_bytes = 0;
+    void* bin_cnt = nullptr;
+    size_t bin_cnt_bytes = 0;
+    void* bin_list = nullptr;
+    size_t bin_list_bytes = 0;
+    void* bin_part = nullptr;   // per-chunk slab partials
+    size_t bin_part_bytes = 0;
+    void* bin_rtape = nullptr;  // per-connection slab ranges (tape layout)
+    size_t bin_rtape_bytes = 0;
     size_t rpart_bytes = 0;
     // sampling / sorting temporaries (grow-only)
     void* s_tmp = nullptr;
@@ -134,6 +148,16 @@ struct prt_paths_s {
     bool tape_valid = false;
     DevCams tape_cams{};
     DevScene tape_scene{};
+    // per-path copies for the path-sorting ablation, one per order (built on
+    // first use after each (re)fill)
+    struct TppCopy {
+        float4* rec = nullptr;
+        int64_t* off = nullptr;
+        uint8_t* B = nullptr;
+        int32_t* inv = nullptr;
+        int64_t cap_rec = 0, cap_n = 0;
+        bool valid = false;
+    } tpp[2];
 };
 
 namespace {
@@ -381,6 +405,12 @@ void free_store(prt_paths p)
     (void)hipFree(p->beta_ref);
     (void)hipFree(p->tape);
     (void)hipFree(p->tape_beta);
+    for (auto& t : p->tpp) {
+        (void)hipFree(t.rec);
+        (void)hipFree(t.off);
+        (void)hipFree(t.B);
+        (void)hipFree(t.inv);
+    }
     delete p;
 }
 
@@ -494,6 +524,7 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     p->ny = s->ny;
     p->nz = s->nz;
     p->tape_valid = false;
+    p->tpp[0].valid = p->tpp[1].valid = false;
     uint8_t* tB = (uint8_t*)c->s_keys;
     uint8_t* tnv = tB + n;
     uint16_t* tC = (uint16_t*)(tB + 2 * n);
@@ -547,6 +578,11 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
 // Tape capacity: one (FP32 c, pixel) entry per (vertex record, camera) from the first
 // scattering batch on; capped so that large workloads recompute instead.
 constexpr size_t kMaxTapeBytes = (size_t)64 << 30;
+// Tape-driven gradients whose grid needs at most this many LDS slabs walk
+// every task once per slab; larger grids bin the walks by slab.
+constexpr int kSlabWalkMax = 4;
+// Largest task-list allocation of the binned gradient (every task in every slab).
+constexpr size_t kMaxBinListBytes = (size_t)8 << 30;
 
 int ensure_tape(prt_paths p, size_t n_cams, int64_t nu)
 {
@@ -682,6 +718,11 @@ void prt_destroy(prt_ctx c)
     (void)hipFree(c->rpart);
     (void)hipFree(c->gw);
     (void)hipFree(c->gaux);
+    (void)hipFree(c->bin_trange);
+    (void)hipFree(c->bin_cnt);
+    (void)hipFree(c->bin_list);
+    (void)hipFree(c->bin_part);
+    (void)hipFree(c->bin_rtape);
     (void)hipFree(c->pb);
     (void)hipFree(c->s_tmp);
     (void)hipFree(c->s_keys);
@@ -742,6 +783,7 @@ int prt_resample(prt_ctx c, const prt_scene* s, uint64_t seed, uint64_t n_paths,
         p->nb = p->n_slots = p->first_slot = p->n_records = 0;
         p->bmax = 0;
         p->tape_valid = false;
+        p->tpp[0].valid = p->tpp[1].valid = false;
         return rc;
     }
     return PRT_OK;
@@ -992,12 +1034,56 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
             ensure_scratch(&c->gaux, &c->gaux_bytes, recs * sizeof(float4)) != PRT_OK)
             tape = false;
     }
-    const GradPlan plan = plan_grad(s->nx, s->ny, s->nz, p->n_slots, p->first_slot, c->n_cu, tape);
+    // with the tape, a grid needing more than a few LDS slabs has its walks
+    // binned by slab (one persistent launch) when the lists fit; the slab
+    // loop below then only holds the recomputing kernel, which works when the
+    // tape turns out not to match beta_t.  Up to kSlabWalkMax slabs, one walk
+    // launch per slab costs less than the binning.
+    GradBins bins{};
+    bool binned = false;
+    const GradPlan per_slab = plan_grad(s->nx, s->ny, s->nz, p->n_slots, p->first_slot, c->n_cu, true);
+    if (tape && !(per_slab.lds && per_slab.n_slabs <= kSlabWalkMax)) {
+        const int64_t kinds = camera_groups(dc.n) + 1;
+        // tasks as the walk kernels number them: every batch from the one
+        // holding the first scattering path, times the walk kinds
+        bins = choose_grad_bins(ds, dc, (p->nb - p->first_slot / kWave) * kinds);
+        const size_t list_words = (size_t)bins.n_tasks * (size_t)bins.n_slabs;
+        const int64_t cnt_words = (int64_t)bins.n_slabs * bins.n_blocks + 1;
+        binned = grad_bins_fit(ds, bins) && list_words * sizeof(uint32_t) <= kMaxBinListBytes &&
+                 ensure_scratch(&c->bin_trange, &c->bin_trange_bytes, (size_t)bins.n_tasks * 2 * sizeof(int)) ==
+                     PRT_OK &&
+                 ensure_scratch(&c->bin_cnt, &c->bin_cnt_bytes,
+                                (size_t)(cnt_words + scan_u32_scratch_words(cnt_words)) * sizeof(uint32_t)) == PRT_OK &&
+                 ensure_scratch(&c->bin_list, &c->bin_list_bytes,
+                                (std::max<size_t>(list_words, 1) + bins.n_slabs + 2) * sizeof(uint32_t)) == PRT_OK &&
+                 ensure_scratch(&c->bin_part, &c->bin_part_bytes, grad_bin_partial_bytes(ds, bins, c->n_cu)) == PRT_OK &&
+                 ensure_scratch(&c->bin_rtape, &c->bin_rtape_bytes, recs * dc.n * sizeof(uint32_t)) == PRT_OK;
+        if (binned) {
+            bins.cnt = (uint32_t*)c->bin_cnt;
+            bins.list = (uint32_t*)c->bin_list;
+            bins.list_cap = (int64_t)list_words;
+            bins.chunks = bins.list + std::max<size_t>(list_words, 1);
+            bins.partial = (double*)c->bin_part;
+        }
+    }
+    const GradPlan plan = plan_grad(s->nx, s->ny, s->nz, p->n_slots, p->first_slot, c->n_cu, tape && !binned);
+    TraceArgs a{};
+    a.s = ds;
+    a.st = view_of(p);
+    a.grad = grad;
+    if (binned) {
+        a.trange = (int*)c->bin_trange;
+        a.rtape = (uint32_t*)c->bin_rtape;
+        a.bin_axis = bins.axis;
+        a.bin_layers = bins.layers;
+    }
     {
         TimedScope ts(c, K_PREP);
         // the slabs' reductions write every voxel; otherwise atomics add up on zeros
-        if (!work || !plan.lds) HIPCHK(launch_fill(c->stream, grad, nu, 0.0));
+        if (!work || (!plan.lds && !binned)) HIPCHK(launch_fill(c->stream, grad, nu, 0.0));
         if (!work) return PRT_OK;
+        // empty task ranges and a zeroed gradient for the binned walk
+        if (binned) HIPCHK(launch_grad_bin_init(c->stream, a, bins));
         HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
                                  c->grid_dlt));
         // also sets the tape flag (cleared by launch_equal_flag on a mismatch) and
@@ -1005,14 +1091,10 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
         HIPCHK(launch_grad_prep(c->stream, residual, c->pix, dc, 1.0 / (double)p->n, tape ? c->flag : nullptr,
                                 c->work));
     }
-    TraceArgs a{};
-    a.s = ds;
-    a.st = view_of(p);
     a.bc_t = s->beta_cloud;
     a.grid_tot = c->grid_tot;
     a.grid_dlt = c->grid_dlt;
     a.rho = c->pix;
-    a.grad = grad;
     a.brender = s->max_order;
     a.counters = c->counters;
     a.work = c->work;
@@ -1028,13 +1110,158 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
         TimedScope ts(c, K_GRAD_WEIGHTS);
         HIPCHK(launch_grad_weights(c->stream, a, dc, task_levels(p, p->bmax), c->n_cu));
     }
+    if (binned) {
+        {
+            TimedScope ts(c, K_GRAD_BIN);
+            HIPCHK(launch_grad_bin_lists(c->stream, a, bins,
+                                         (uint32_t*)c->bin_cnt + (int64_t)bins.n_slabs * bins.n_blocks + 1));
+        }
+        {
+            TimedScope ts(c, K_GRAD);
+            HIPCHK(launch_grad_bin_walk(c->stream, a, dc, bins, c->n_cu));
+        }
+        TimedScope ts(c, K_GRAD_REDUCE);
+        HIPCHK(launch_grad_bin_reduce(c->stream, a, bins));
+    }
     if ((rc = ensure_scratch(&c->gpart, &c->gpart_bytes, plan.partial_bytes))) return rc;
     // task counters: zeroed by launch_grad_prep for the first slab, by each
     // slab's reduction for the next (one slab only when there is no reduction)
     for (int i = 0; i < plan.n_slabs; ++i) {
         {
-            TimedScope ts(c, K_GRAD);
-            HIPCHK(launch_grad(c->stream, c->fp64, a, dc, plan, i, c->gpart));
+            TimedScope ts(c, binned ? K_GRAD_RECOMPUTE : K_GRAD);
+            HIPCHK(launch_grad(c->stream, c->fp64, a, dc, plan, i, c->gpart, !binned));
+        }
+        TimedScope ts(c, K_GRAD_REDUCE);
+        HIPCHK(launch_grad_reduce(c->stream, plan, s->nx, s->ny, s->nz, i, c->gpart, grad, c->work,
+                                  binned ? c->flag : nullptr));
+    }
+    return PRT_OK;
+}
+
+// The per-path copy of store p in `order` for the ablation kernels (built
+// on first use): sizes, offsets and records.
+int tpp_copy(prt_ctx c, prt_paths p, int order, TppView* v)
+{
+    auto& t = p->tpp[order];
+    const int64_t n = (int64_t)p->n;
+    v->n = n;
+    if (!t.valid) {
+        int rc;
+        if (t.cap_n < n + 1) {
+            (void)hipFree(t.off);
+            (void)hipFree(t.B);
+            (void)hipFree(t.inv);
+            t.off = nullptr;
+            t.B = nullptr;
+            t.inv = nullptr;
+            t.cap_n = 0;
+            if ((rc = dalloc(&t.off, (size_t)n + 1)) || (rc = dalloc(&t.B, (size_t)n + 1)) ||
+                (rc = dalloc(&t.inv, (size_t)n + 1)))
+                return rc;
+            t.cap_n = n + 1;
+        }
+        if (t.cap_rec < p->n_records) {
+            (void)hipFree(t.rec);
+            t.rec = nullptr;
+            t.cap_rec = 0;
+            if ((rc = dalloc(&t.rec, (size_t)std::max<int64_t>(p->n_records, 1)))) return rc;
+            t.cap_rec = p->n_records;
+        }
+        if ((rc = ensure_scratch(&c->s_hist, &c->s_hist_bytes,
+                                 (size_t)scan_u32_scratch_words(n + 1) * sizeof(int64_t))))
+            return rc;
+        TimedScope ts(c, K_TPP_LAYOUT);
+        const StoreView sv = view_of(p);
+        HIPCHK(launch_tpp_layout(c->stream, sv, n, p->perm, order, t.inv, t.off, t.B, c->s_hist));
+        HIPCHK(launch_tpp_copy(c->stream, sv, n, t.inv, order, t.off, t.rec));
+        t.valid = true;
+    }
+    v->rec = t.rec;
+    v->off = t.off;
+    v->B = t.B;
+    return PRT_OK;
+}
+
+int prt_tpp_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p, int32_t order,
+                   double* images)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    int rc = check_scene(s);
+    if (rc) return rc;
+    if ((rc = check_match(s, p))) return rc;
+    if (!images) return fail(PRT_E_INVALID, "images is NULL");
+    if (order != PRT_ORDER_BY_SIZE && order != PRT_ORDER_BY_ID) return fail(PRT_E_INVALID, "unknown order %d", order);
+    DevCams dc;
+    if ((rc = make_dev_cams(cams, s, &dc))) return rc;
+    DeviceGuard g(c->device);
+    const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
+    if ((rc = ensure_grids(c, nu))) return rc;
+    TppView v{};
+    if ((rc = tpp_copy(c, p, order, &v))) return rc;
+    TraceArgs a{};
+    a.s = make_dev_scene(s);
+    a.st = view_of(p);
+    a.bc_t = s->beta_cloud;
+    a.grid_tot = c->grid_tot;
+    a.grid_dlt = c->grid_dlt;
+    a.img = images;
+    a.brender = s->max_order;
+    a.counters = c->counters;
+    {
+        TimedScope ts(c, K_PREP);
+        HIPCHK(launch_fill(c->stream, images, (int64_t)dc.n * dc.W * dc.H, 0.0));
+        HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
+                                 c->grid_dlt));
+    }
+    {
+        TimedScope ts(c, K_TPP_RENDER);
+        HIPCHK(launch_tpp_render(c->stream, c->fp64, a, dc, v, c->n_cu));
+    }
+    TimedScope ts(c, K_FINALIZE);
+    HIPCHK(launch_render_finalize(c->stream, images, dc, 1.0 / (double)p->n));
+    return PRT_OK;
+}
+
+int prt_tpp_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p, int32_t order,
+                 const double* residual, double* grad)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    int rc = check_scene(s);
+    if (rc) return rc;
+    if ((rc = check_match(s, p))) return rc;
+    if (!residual || !grad) return fail(PRT_E_INVALID, "residual/grad is NULL");
+    if (order != PRT_ORDER_BY_SIZE && order != PRT_ORDER_BY_ID) return fail(PRT_E_INVALID, "unknown order %d", order);
+    DevCams dc;
+    if ((rc = make_dev_cams(cams, s, &dc))) return rc;
+    DeviceGuard g(c->device);
+    const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
+    if ((rc = ensure_grids(c, nu))) return rc;
+    const int64_t npx = (int64_t)dc.n * dc.W * dc.H;
+    if ((rc = ensure_pix(c, npx))) return rc;
+    TppView v{};
+    if ((rc = tpp_copy(c, p, order, &v))) return rc;
+    const GradPlan plan = plan_grad(s->nx, s->ny, s->nz, p->n_slots, 0, c->n_cu, false);
+    if ((rc = ensure_scratch(&c->gpart, &c->gpart_bytes, plan.partial_bytes))) return rc;
+    TraceArgs a{};
+    a.s = make_dev_scene(s);
+    a.st = view_of(p);
+    a.bc_t = s->beta_cloud;
+    a.grid_tot = c->grid_tot;
+    a.grid_dlt = c->grid_dlt;
+    a.rho = c->pix;
+    a.grad = grad;
+    a.counters = c->counters;
+    {
+        TimedScope ts(c, K_PREP);
+        if (!plan.lds) HIPCHK(launch_fill(c->stream, grad, nu, 0.0));
+        HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
+                                 c->grid_dlt));
+        HIPCHK(launch_grad_prep(c->stream, residual, c->pix, dc, 1.0 / (double)p->n, nullptr, c->work));
+    }
+    for (int i = 0; i < plan.n_slabs; ++i) {
+        {
+            TimedScope ts(c, K_TPP_GRAD);
+            HIPCHK(launch_tpp_grad(c->stream, c->fp64, a, dc, v, plan, i, (double*)c->gpart));
         }
         TimedScope ts(c, K_GRAD_REDUCE);
         HIPCHK(launch_grad_reduce(c->stream, plan, s->nx, s->ny, s->nz, i, c->gpart, grad, c->work));

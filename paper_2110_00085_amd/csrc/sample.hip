@@ -398,6 +398,18 @@ __global__ void __launch_bounds__(kWave) sort_scatter_kernel(const K* __restrict
     }
 }
 
+int64_t scan_u32_scratch_words(int64_t n) { return scan_scratch_elems(n); }
+
+hipError_t launch_scan_i64(hipStream_t st, int64_t* a, int64_t n, int64_t* scratch)
+{
+    return scan_exclusive<int64_t>(st, a, n, scratch);
+}
+
+hipError_t launch_scan_u32(hipStream_t st, uint32_t* a, int64_t n, uint32_t* scratch)
+{
+    return scan_exclusive<uint32_t>(st, a, n, scratch);
+}
+
 template <typename K>
 static hipError_t counting_sort(hipStream_t st, const K* key, const int32_t* in, int64_t n, int nbins,
                                 uint32_t* hist, int32_t* out, SortExtra x = SortExtra{})

@@ -9,120 +9,14 @@
 // a stored contribution after the projection (phase function, transmittance,
 // 1/r^2) and the gradient weights are FP32, as they are stored in FP32.
 #include <algorithm>
+#include <cmath>
 
 #include "launch.hpp"
+#include "trace_common.hpp"
 
 namespace prt {
 
-namespace {
-
-struct Vtx {
-    double x, y, z;
-    int v;
-};
-
-__device__ __forceinline__ Vtx load_vtx(const float4* __restrict__ V, int k)
-{
-    const float4 r = V[(int64_t)k * kWave];
-    return Vtx{(double)r.x, (double)r.y, (double)r.z, vox_of(r)};
-}
-
-// Unit direction from a to b and the distance (grid units).
-__device__ __forceinline__ double seg_dir(const Vtx& a, const Vtx& b, double w[3])
-{
-    const double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-    const double L = sqrt(dx * dx + dy * dy + dz * dz);
-    const double inv = L > 0.0 ? 1.0 / L : 0.0;
-    w[0] = dx * inv;
-    w[1] = dy * inv;
-    w[2] = dz * inv;
-    return L;
-}
-
-__device__ __forceinline__ int clamp_vox(int v, int nu) { return min(max(v, 0), nu - 1); }
-
-// Sum of beta(v) * length over the walk from vertex p (voxel p.v) along w
-// for length tmax (grid units); adds the number of pieces to count.
-template <typename Real, bool kBounded = true, typename G>
-__device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx& p, const double w[3], double tmax,
-                                         uint64_t& count)
-{
-    int ix, iy, iz;
-    voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
-    Real acc = (Real)0;
-    uint32_t n = 0;
-    dda_walk_counted<Real, kBounded>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
-                           (Real)w[2], (Real)tmax, n, [&](int v, Real, Real l) {
-                               acc += beta((uint32_t)v) * l;
-                               return true;
-                           });
-    count += n;
-    return acc;
-}
-
-// Calls add(v, scale * length) for every piece of the walk that lies in the
-// slab of z layers [z0, z1), v numbered inside the slab (zero-length pieces
-// add zero).
-template <typename Real, bool kBounded = true, typename A>
-__device__ __forceinline__ void walk_scatter(const DevScene& s, A&& add, const Vtx& p, const double w[3], double tmax,
-                                             double scale, uint64_t& count, int z0, int z1)
-{
-    int ix, iy, iz;
-    voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
-    uint32_t n = 0;
-    dda_walk_slab<Real, kBounded>(s.nx, s.ny, z0, z1, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
-                        (Real)w[2], (Real)tmax, n, [&](int v, Real, Real l) {
-                            add((uint32_t)v, scale * (double)l);
-                            return true;
-                        });
-    count += n;
-}
-
-// Henyey-Greenstein phase function in FP32, 1 + g^2 - 2 g mu written as
-// (1-g)^2 + 2 g (1-mu) (no cancellation near mu = 1); the hardware square
-// root and reciprocal (each within 1 ulp) stand in for the correctly rounded
-// ones, since the FP32 contribution carries ~1e-7 relative error anyway.
-__device__ __forceinline__ float phase_hg_f32_om(const DevScene& s, float one_minus_mu)
-{
-    const float g = (float)s.g;
-    const float d = (1.f - g) * (1.f - g) + 2.f * g * one_minus_mu;
-    return (float)s.hg_num * __builtin_amdgcn_rcpf(d * __builtin_amdgcn_sqrtf(d));
-}
-
-__device__ __forceinline__ float phase_hg_f32(const DevScene& s, float mu) { return phase_hg_f32_om(s, 1.f - mu); }
-
-// Factor of scatter vertex k (1 <= k < b) in the recycled contribution:
-// albedo_ref(x_k) * f_s,t(x_k, mu_k) / f_s,ref(x_k, mu_k).
-__device__ __forceinline__ double vertex_ratio(const DevScene& s, double bct, double bcr, double mu)
-{
-    const double hg = phase_hg(s, mu), ra = phase_rayleigh(mu);
-    const double fst = fs_mix(s, bct, hg, ra), fsr = fs_mix(s, bcr, hg, ra);
-    const double bsr = s.w_c * bcr + s.w_a * s.beta_air, btr = bcr + s.beta_air;
-    return (bsr / btr) * (fst / fsr);
-}
-
-// Counter of this wavefront in a task-counter set.
-__device__ __forceinline__ unsigned int task_counter()
-{
-    return (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) % kTaskCounters;
-}
-
-// Next task for this wavefront from counter c (lane 0 takes it).
-__device__ __forceinline__ unsigned int next_task(unsigned int* work, unsigned int c)
-{
-    unsigned int t = 0;
-    if (threadIdx.x % kWave == 0) t = atomicAdd(work + c * kTaskStride, 1u);
-    return __shfl(t, 0) * kTaskCounters + c;
-}
-
-__device__ __forceinline__ void flush_counts(unsigned long long* c, uint64_t seg, uint64_t le, uint64_t ovh)
-{
-    if (seg) atomicAdd(&c[0], (unsigned long long)seg);
-    if (le) atomicAdd(&c[1], (unsigned long long)le);
-    if (ovh) atomicAdd(&c[3], (unsigned long long)ovh);
-}
-
-}  // namespace
+using namespace trace;
 
 // ------------------------------------------------------------------ render
 
@@ -540,6 +434,7 @@ __global__ void __launch_bounds__(256) grad_prep_kernel(const double* __restrict
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && flag) *flag = 1;
     if (i < 2 * kTaskCounters) work[(i / 2) * kTaskStride + i % 2] = 0u;
+    if (i == 0) work[kBinChunkWord] = 0u;
     const int64_t npix = (int64_t)c.W * c.H;
     if (i >= npix * c.n) return;
     rho[i] = res[i] * pixel_scale(c, i, scale);
@@ -664,6 +559,22 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
         const Vtx p0 = load_vtx(V, b - 1), p1 = load_vtx(V, b);
         const int Bn = (int)a.st.B[slot];
         const bool act = b <= Bn;
+        // binned gradient: layers along the slab axis reached by the walks of
+        // this (batch, b), per camera group and for segment b-1
+        const bool bins = a.trange != nullptr;
+        const int ax = a.bin_axis;
+        const int G = a.groups, cpg = (cams.n + G - 1) / G;
+        const float p1a = (float)(ax == 0 ? p1.x : (ax == 1 ? p1.y : p1.z));
+        int p1i;
+        {
+            int i0, i1, i2;
+            voxel_ijk(clamp_vox(p1.v, nu), s.nx, s.ny, i0, i1, i2);
+            p1i = ax == 0 ? i0 : (ax == 1 ? i1 : i2);
+        }
+        const float nbox[3] = {(float)s.nx, (float)s.ny, (float)s.nz};
+        // ranges of the camera groups (at most 3) and of the segment walk,
+        // updated by selects so that they stay in registers
+        int rlo[4] = {kNoLayer, kNoLayer, kNoLayer, kNoLayer}, rhi[4] = {-1, -1, -1, -1};
         // tape records of kGwCams cameras from d0 on, one group ahead of its
         // arithmetic (a camera index past the last loads the last camera's
         // record, in bounds and without a branch, and is masked below)
@@ -704,6 +615,31 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
                     wf = tt[j].x * (float)rr[j];
                     const float ex = (float)(cams.pos[d][0] - p1.x), ey = (float)(cams.pos[d][1] - p1.y),
                                 ez = (float)(cams.pos[d][2] - p1.z);
+                    uint32_t rpack = 0xffffu;
+                    if (bins && wf != 0.f) {
+                        // the connection runs from x_b to where it leaves the box
+                        // (or reaches the camera): parameter t in [0, 1] along e
+                        const float e[3] = {ex, ey, ez};
+                        const float q[3] = {(float)p1.x, (float)p1.y, (float)p1.z};
+                        float tend = 1.f;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+                            if (e[k] != 0.f) tend = fminf(tend, ((e[k] > 0.f ? nbox[k] : 0.f) - q[k]) / e[k]);
+                        tend = fmaxf(tend, 0.f);
+                        const float ea = ax == 0 ? ex : (ax == 1 ? ey : ez);
+                        int lo = kNoLayer, hi = -1;
+                        layer_span(p1a, p1i, lo, hi);
+                        layer_span(p1a + tend * ea, p1i, lo, hi);
+                        const int gi = d / cpg;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            rlo[k] = gi == k ? min(rlo[k], lo) : rlo[k];
+                            rhi[k] = gi == k ? max(rhi[k], hi) : rhi[k];
+                        }
+                        const int na = ax == 0 ? s.nx : (ax == 1 ? s.ny : s.nz);
+                        rpack = (uint32_t)(max(lo, 0) / a.bin_layers) | (uint32_t)(min(hi, na - 1) / a.bin_layers) << 16;
+                    }
+                    if (bins && act) a.rtape[rec0 * cams.n + lane + (int64_t)(b * cams.n + d) * kWave] = rpack;
                     const float mu = (wf0 * ex + wf1 * ey + wf2 * ez) * rsqrtf(ex * ex + ey * ey + ez * ez);
                     const float hg = phase_hg_f32(s, mu);
                     const float fst = wcb * hg + wab * ray_k * (1.f + mu * mu);
@@ -712,6 +648,35 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
                     ++nle;
                 }
                 if (act) Wp[(int64_t)(b * cams.n + d) * kWave] = wf;
+                if (bins && act && pix < 0) a.rtape[rec0 * cams.n + lane + (int64_t)(b * cams.n + d) * kWave] = 0xffffu;
+            }
+        }
+        if (bins) {
+            int slo = kNoLayer, shi = -1;
+            if (act) {
+                // segment b-1 of the free-flight walk
+                int i0, i1, i2;
+                voxel_ijk(clamp_vox(p0.v, nu), s.nx, s.ny, i0, i1, i2);
+                const float p0a = (float)(ax == 0 ? p0.x : (ax == 1 ? p0.y : p0.z));
+                layer_span(p0a, ax == 0 ? i0 : (ax == 1 ? i1 : i2), slo, shi);
+                layer_span(p1a, p1i, slo, shi);
+            }
+            // wavefront minimum and maximum, then one atomic pair per kind
+            const int nsl = (a.st.n_slots / kWave), kinds = G + 1;
+            const int na = ax == 0 ? s.nx : (ax == 1 ? s.ny : s.nz);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k >= kinds) break;
+                int lo = k == G ? slo : rlo[k], hi = k == G ? shi : rhi[k];
+                for (int o = kWave / 2; o > 0; o >>= 1) {
+                    lo = min(lo, __shfl_xor(lo, o));
+                    hi = max(hi, __shfl_xor(hi, o));
+                }
+                if (lane == 0 && lo <= hi) {
+                    const int64_t t = (int64_t)(nsl - 1 - bt) * kinds + k;
+                    atomicMin(&a.trange[2 * t], max(lo, 0) / a.bin_layers);
+                    atomicMax(&a.trange[2 * t + 1], min(hi, na - 1) / a.bin_layers);
+                }
             }
         }
         if (!act) continue;
@@ -832,6 +797,374 @@ __global__ void __launch_bounds__(kBlock) grad_walk_kernel(TraceArgs a, DevCams 
     }
     flush_counts(a.counters, nseg, 0, 0);
     slab_tally_end<kLds>(tally, partial);
+}
+
+// ------------------------------------------------------- binned gradient
+//
+// The walks on the stored weights again, without repeating every walk once
+// per slab: each gradient task (batch, kind) carries the range of slabs its
+// walks reach (set by the weights kernel); the tasks are listed slab after
+// slab, and one persistent launch takes chunks of that list.  A workgroup
+// tallies the slab of its chunk in LDS in FP64, walking each listed task
+// clipped to the slab, and writes the slab's sums as the chunk's partial; a
+// second kernel adds, for every voxel, the partials of its slab's chunks in
+// chunk order.  Every voxel piece of a walk lies in exactly one slab.
+
+constexpr int kBinChunksPerWg = 16;  // chunks of the list per workgroup (load balance)
+constexpr int kBinMinChunk = 64;    // smallest chunk (each chunk zeroes and writes out a slab)
+constexpr int kBinReduceLoads = 8;
+constexpr int kBinQueue = 128;      // per-wavefront queue of connection walks (power of two, >= 2 * 64)
+
+// trange = empty ranges, grad = 0.
+__global__ void __launch_bounds__(256) grad_bin_init_kernel(int* __restrict__ trange, int64_t n_tasks,
+                                                            double* __restrict__ grad, int64_t nu)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_tasks) {
+        trange[2 * i] = kNoLayer;
+        trange[2 * i + 1] = -1;
+    }
+    if (i < nu) grad[i] = 0.0;
+}
+
+// cnt[s * n_blocks + block] = tasks of the block whose range holds slab s.
+__global__ void __launch_bounds__(kBinTasks) grad_bin_count_kernel(const int* __restrict__ trange, GradBins g,
+                                                                   const int* __restrict__ flag)
+{
+    if (*flag == 0) return;
+    __shared__ unsigned int hist[kMaxBinSlabs];
+    for (int i = threadIdx.x; i < g.n_slabs; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * kBinTasks + threadIdx.x;
+    if (t < g.n_tasks) {
+        const int lo = trange[2 * t], hi = trange[2 * t + 1];
+        for (int s = lo; s <= hi; ++s) atomicAdd(&hist[s], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < g.n_slabs; i += blockDim.x) g.cnt[(int64_t)i * g.n_blocks + blockIdx.x] = hist[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) g.cnt[(int64_t)g.n_slabs * g.n_blocks] = 0u;
+}
+
+// After the scan: every task is written to the list of each slab of its range.
+__global__ void __launch_bounds__(kBinTasks) grad_bin_fill_kernel(const int* __restrict__ trange, GradBins g,
+                                                                  const int* __restrict__ flag)
+{
+    if (*flag == 0) return;
+    __shared__ unsigned int cur[kMaxBinSlabs];
+    for (int i = threadIdx.x; i < g.n_slabs; i += blockDim.x) cur[i] = g.cnt[(int64_t)i * g.n_blocks + blockIdx.x];
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * kBinTasks + threadIdx.x;
+    if (t < g.n_tasks) {
+        const int lo = trange[2 * t], hi = trange[2 * t + 1];
+        for (int s = lo; s <= hi; ++s) {
+            const unsigned int pos = atomicAdd(&cur[s], 1u);
+            if ((int64_t)pos < g.list_cap) g.list[pos] = (uint32_t)t;
+        }
+    }
+}
+
+// One listed task of slab box b: the walks of kind `kind` of batch bt,
+// clipped to the block, added to the LDS tally.
+__device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams& cams, const SubBox& box, int slab,
+                                              double* __restrict__ tally, uint32_t* queue, int64_t bt, int kind,
+                                              uint64_t& nseg)
+{
+    const DevScene& s = a.s;
+    const int nu = s.nx * s.ny * s.nz;
+    const int lane = threadIdx.x % kWave;
+    const int G = a.groups, cpg = (cams.n + G - 1) / G;
+    const int64_t slot = bt * kWave + lane;
+    const int Bn = (int)a.st.B[slot];
+    // (lanes without scatters stay: the connection walks are shared across lanes)
+    if (kind >= G && Bn <= 0) return;
+    auto add = [&](uint32_t v, double x) { atomicAdd(&tally[v], x); };
+    const int64_t rec0 = a.st.batch_off[bt] - a.tape_base;
+    const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
+    const float4* __restrict__ X = a.vaux + rec0 + lane;
+    if (kind < G) {
+        // connections: every lane tests its (scatter, camera) walks against
+        // the slab (range tape), the hits are queued in LDS, and 64 queued
+        // walks at a time are walked, one per lane
+        const int d_lo = kind * cpg, nd = min(cams.n, d_lo + cpg) - d_lo;
+        const uint32_t* __restrict__ Rp = a.rtape + rec0 * cams.n + d_lo * kWave + lane;
+        const float4* __restrict__ Vb = a.st.vtx + a.st.batch_off[bt];
+        const float* __restrict__ Wb = a.wtape + rec0 * cams.n + d_lo * kWave;
+        const uint32_t sl = (uint32_t)slab;
+        uint32_t wq = 0, rq = 0;
+        auto walk_entry = [&](uint32_t e) {
+            const int L = (int)(e & 63u), b = (int)((e >> 6) & 127u), j = (int)(e >> 13);
+            const float4 r = Vb[(int64_t)b * kWave + L];
+            const Vtx p1{(double)r.x, (double)r.y, (double)r.z, vox_of(r)};
+            const double wgt = (double)Wb[(int64_t)(b * cams.n + j) * kWave + L];
+            const int d = d_lo + j;
+            const float ex = (float)(cams.pos[d][0] - p1.x), ey = (float)(cams.pos[d][1] - p1.y),
+                        ez = (float)(cams.pos[d][2] - p1.z);
+            const float d2 = ex * ex + ey * ey + ez * ez;
+            const float id = __builtin_amdgcn_rsqf(d2);
+            const double u[3] = {(double)(ex * id), (double)(ey * id), (double)(ez * id)};
+            const double dist = (double)(d2 * id);
+            if (cams.outside)
+                walk_scatter_box<float, false>(s, add, p1, u, dist, -wgt * s.vk, nseg, box);
+            else
+                walk_scatter_box<float>(s, add, p1, u, dist, -wgt * s.vk, nseg, box);
+        };
+        int bmax = Bn;
+        for (int o = kWave / 2; o > 0; o >>= 1) bmax = max(bmax, __shfl_xor(bmax, o));
+        for (int b = 1; b <= bmax; ++b) {
+            uint32_t rr[kGroupCams];
+#pragma unroll
+            for (int j = 0; j < kGroupCams; ++j)
+                rr[j] = (j < nd && b <= Bn) ? Rp[(int64_t)(b * cams.n + j) * kWave] : 0xffffu;
+#pragma unroll
+            for (int j = 0; j < kGroupCams; ++j) {
+                const bool hit = (rr[j] & 0xffffu) <= sl && sl <= (rr[j] >> 16);
+                const uint64_t m = __ballot(hit);
+                if (hit) {
+                    const uint32_t pos = wq + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    queue[pos & (kBinQueue - 1)] = (uint32_t)lane | (uint32_t)b << 6 | (uint32_t)j << 13;
+                }
+                wq += (uint32_t)__popcll(m);
+                if (wq - rq >= (uint32_t)kWave) {
+                    __builtin_amdgcn_wave_barrier();
+                    walk_entry(queue[(rq + lane) & (kBinQueue - 1)]);
+                    rq += kWave;
+                }
+            }
+            if (kind == 0 && b <= Bn) {
+                const double vert = (double)X[(int64_t)b * kWave].y;
+                const int u = vert != 0.0 ? box_index(box, clamp_vox(vox_of(V[(int64_t)b * kWave]), nu), s.nx, s.ny) : -1;
+                if (u >= 0) add((uint32_t)u, vert);
+            }
+        }
+        if (wq > rq) {
+            __builtin_amdgcn_wave_barrier();
+            if ((uint32_t)lane < wq - rq) walk_entry(queue[(rq + lane) & (kBinQueue - 1)]);
+        }
+    } else {
+        double A = 0.0;
+        Vtx pk1 = load_vtx(V, Bn);
+        for (int k = Bn - 1; k >= 0; --k) {
+            A += (double)X[(int64_t)(k + 1) * kWave].x;
+            const Vtx pk = load_vtx(V, k);
+            double w[3];
+            const double L = seg_dir(pk, pk1, w);
+            if (A != 0.0) {
+                walk_scatter_box<float>(s, add, pk, w, L, -A * s.vk, nseg, box);
+                const int u = k >= 1 ? box_index(box, clamp_vox(pk.v, nu), s.nx, s.ny) : -1;
+                if (u >= 0) add((uint32_t)u, A * (double)X[(int64_t)k * kWave].z);
+            }
+            pk1 = pk;
+        }
+    }
+}
+
+// Chunks of the slab lists: chunk size C = max(kBinMinChunk, total / (chunks
+// per workgroup * workgroups)); slab s holds chunks [chunks[s], chunks[s+1]),
+// chunks[n_slabs] = their number, chunks[n_slabs+1] = C.  One workgroup.
+__global__ void __launch_bounds__(256) grad_bin_chunks_kernel(GradBins g, int n_wg, const int* __restrict__ flag)
+{
+    if (*flag == 0) return;
+    if (threadIdx.x != 0) return;
+    const uint32_t total = g.cnt[(int64_t)g.n_slabs * g.n_blocks];
+    const uint32_t want = (uint32_t)kBinChunksPerWg * (uint32_t)n_wg;
+    const uint32_t C = max((uint32_t)kBinMinChunk, (total + want - 1) / want);
+    uint32_t k = 0;
+    for (int s = 0; s < g.n_slabs; ++s) {
+        g.chunks[s] = k;
+        const uint32_t a0 = g.cnt[(int64_t)s * g.n_blocks];
+        const uint32_t a1 = s + 1 < g.n_slabs ? g.cnt[(int64_t)(s + 1) * g.n_blocks] : total;
+        k += (a1 - a0 + C - 1) / C;
+    }
+    g.chunks[g.n_slabs] = k;
+    g.chunks[g.n_slabs + 1] = C;
+}
+
+// Persistent: a workgroup takes chunk c of slab s, tallies its tasks' walks
+// clipped to the slab in LDS (FP64) and writes the slab's sums to
+// partial[c * slab_voxels + i].
+__global__ void __launch_bounds__(kBlock) grad_bin_walk_kernel(TraceArgs a, DevCams cams, GradBins g)
+{
+    if (*a.tape_flag == 0) return;
+    extern __shared__ unsigned char smem[];
+    double* __restrict__ tally = reinterpret_cast<double*>(smem);
+    __shared__ unsigned int s_chunk, s_item;
+    __shared__ uint32_t wave_queue[kWavesPerBlock][kBinQueue];
+    const DevScene& s = a.s;
+    const int per_layer = g.axis == 0 ? s.ny * s.nz : (g.axis == 1 ? s.nx * s.nz : s.nx * s.ny);
+    const int64_t nb = a.st.n_slots / kWave;
+    const int kinds = a.groups + 1;
+    const uint32_t total = g.cnt[(int64_t)g.n_slabs * g.n_blocks];
+    const uint32_t n_chunks = g.chunks[g.n_slabs];
+    const uint32_t C = g.chunks[g.n_slabs + 1];
+    const int64_t slab_vox = (int64_t)g.layers * per_layer;
+    uint64_t nseg = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_chunk = atomicAdd(a.work + kBinChunkWord, 1u);
+        __syncthreads();
+        const uint32_t c = s_chunk;
+        if (c >= n_chunks) break;
+        // the slab of chunk c: the last slab whose chunks start at or before it
+        int lo = 0, hi = g.n_slabs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (g.chunks[mid] <= c) lo = mid;
+            else hi = mid - 1;
+        }
+        const int sl = lo;
+        const uint32_t a0 = g.cnt[(int64_t)sl * g.n_blocks];
+        const uint32_t a1 = sl + 1 < g.n_slabs ? g.cnt[(int64_t)(sl + 1) * g.n_blocks] : total;
+        const uint32_t i0 = a0 + (c - g.chunks[sl]) * C;
+        const uint32_t i1 = min(a1, i0 + C);
+        const SubBox box = slab_box(s, g.axis, g.layers, sl);
+        const int nsv = (sl * g.layers + g.layers <= (g.axis == 0 ? s.nx : (g.axis == 1 ? s.ny : s.nz))
+                             ? g.layers
+                             : (g.axis == 0 ? s.nx : (g.axis == 1 ? s.ny : s.nz)) - sl * g.layers) *
+                        per_layer;
+        for (int i = threadIdx.x; i < nsv; i += kBlock) tally[i] = 0.0;
+        if (threadIdx.x == 0) s_item = i0;
+        __syncthreads();
+        for (;;) {
+            unsigned int it = 0;
+            if (threadIdx.x % kWave == 0) it = atomicAdd(&s_item, 1u);
+            it = __shfl(it, 0);
+            if (it >= i1) break;
+            const uint32_t t = g.list[it];
+            grad_bin_task(a, cams, box, sl, tally, wave_queue[threadIdx.x / kWave], nb - 1 - (int64_t)(t / kinds),
+                          (int)(t % kinds), nseg);
+        }
+        __syncthreads();
+        double* __restrict__ out = g.partial + (int64_t)c * slab_vox;
+        for (int i = threadIdx.x; i < nsv; i += kBlock) out[i] = tally[i];
+        __syncthreads();
+    }
+    flush_counts(a.counters, nseg, 0, 0);
+}
+
+// grad[v] = sum over the chunks of v's slab, in chunk order, of the
+// partials; one thread per slab voxel (slab after slab).
+__global__ void __launch_bounds__(256) grad_bin_reduce_kernel(GradBins g, int nx, int ny, int nz,
+                                                              double* __restrict__ grad,
+                                                              const int* __restrict__ flag)
+{
+    if (*flag == 0) return;
+    const int per_layer = g.axis == 0 ? ny * nz : (g.axis == 1 ? nx * nz : nx * ny);
+    const int na = g.axis == 0 ? nx : (g.axis == 1 ? ny : nz);
+    const int64_t slab_vox = (int64_t)g.layers * per_layer;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int sl = (int)(q / slab_vox);
+    const int64_t i = q % slab_vox;
+    if (sl >= g.n_slabs) return;
+    const int la = (int)(i / per_layer);
+    if (sl * g.layers + la >= na) return;
+    const int r = (int)(i % per_layer);
+    const int nb = g.axis == 0 ? ny : nx;
+    const int ib = r % nb, ic = r / nb, ia = sl * g.layers + la;
+    // (x, y, z) from the slab axis and the two others in increasing order
+    const int x = g.axis == 0 ? ia : ib;
+    const int y = g.axis == 0 ? ib : (g.axis == 1 ? ia : ic);
+    const int z = g.axis == 2 ? ia : ic;
+    double acc = 0.0;
+    const uint32_t c0 = g.chunks[sl], c1 = g.chunks[sl + 1];
+    for (uint32_t c = c0; c < c1; c += kBinReduceLoads) {
+        double t[kBinReduceLoads];
+#pragma unroll
+        for (uint32_t j = 0; j < kBinReduceLoads; ++j) t[j] = c + j < c1 ? g.partial[(int64_t)(c + j) * slab_vox + i] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kBinReduceLoads; ++j) acc += t[j];
+    }
+    grad[x + (int64_t)nx * (y + (int64_t)ny * z)] = acc;
+}
+
+GradBins choose_grad_bins(const DevScene& s, const DevCams& c, int64_t n_tasks)
+{
+    const int n[3] = {s.nx, s.ny, s.nz};
+    // the slab axis along which the walks move least: the directions from the
+    // box centre to the cameras and the sun's direction, summed per axis
+    double spread[3] = {0.0, 0.0, 0.0};
+    const double ctr[3] = {0.5 * s.nx, 0.5 * s.ny, 0.5 * s.nz};
+    for (int d = 0; d < c.n; ++d) {
+        double e[3], l2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            e[k] = c.pos[d][k] - ctr[k];
+            l2 += e[k] * e[k];
+        }
+        const double il = l2 > 0.0 ? 1.0 / std::sqrt(l2) : 0.0;
+        for (int k = 0; k < 3; ++k) spread[k] += std::fabs(e[k]) * il;
+    }
+    for (int k = 0; k < 3; ++k) spread[k] += std::fabs(s.sun[k]);
+    GradBins g{};
+    g.axis = 0;
+    for (int k = 1; k < 3; ++k)
+        if (spread[k] < spread[g.axis]) g.axis = k;
+    const int ob = g.axis == 0 ? 1 : 0, oc = g.axis == 2 ? 1 : 2;
+    const int64_t layer_bytes = (int64_t)n[ob] * n[oc] * (int64_t)sizeof(double);
+    g.layers = (int)std::max<int64_t>(1, std::min<int64_t>(n[g.axis], (int64_t)kLdsBudget / layer_bytes));
+    g.n_slabs = (n[g.axis] + g.layers - 1) / g.layers;
+    g.n_tasks = n_tasks;
+    g.n_blocks = (n_tasks + kBinTasks - 1) / kBinTasks;
+    return g;
+}
+
+bool grad_bins_fit(const DevScene& s, const GradBins& g)
+{
+    const int n[3] = {s.nx, s.ny, s.nz};
+    const int ob = g.axis == 0 ? 1 : 0, oc = g.axis == 2 ? 1 : 2;
+    return (int64_t)n[ob] * n[oc] * (int64_t)sizeof(double) <= (int64_t)kLdsBudget && g.n_slabs <= kMaxBinSlabs;
+}
+
+hipError_t launch_grad_bin_init(hipStream_t st, const TraceArgs& a, const GradBins& g)
+{
+    const int64_t nu = (int64_t)a.s.nx * a.s.ny * a.s.nz;
+    const int64_t n = std::max<int64_t>(std::max<int64_t>(g.n_tasks, nu), 1);
+    grad_bin_init_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(a.trange, g.n_tasks, a.grad, nu);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_bin_lists(hipStream_t st, const TraceArgs& a, const GradBins& g, uint32_t* scan_scratch)
+{
+    if (g.n_tasks <= 0) return hipSuccess;
+    grad_bin_count_kernel<<<dim3((unsigned)g.n_blocks), dim3(kBinTasks), 0, st>>>(a.trange, g, a.tape_flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_scan_u32(st, g.cnt, (int64_t)g.n_slabs * g.n_blocks + 1, scan_scratch)) != hipSuccess) return e;
+    grad_bin_fill_kernel<<<dim3((unsigned)g.n_blocks), dim3(kBinTasks), 0, st>>>(a.trange, g, a.tape_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_bin_walk(hipStream_t st, const TraceArgs& a, const DevCams& c, const GradBins& g, int n_cu)
+{
+    if (g.n_tasks <= 0) return hipSuccess;
+    hipError_t e;
+    grad_bin_chunks_kernel<<<dim3(1), dim3(256), 0, st>>>(g, n_cu, a.tape_flag);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int n[3] = {a.s.nx, a.s.ny, a.s.nz};
+    const int ob = g.axis == 0 ? 1 : 0, oc = g.axis == 2 ? 1 : 2;
+    const size_t lds = (size_t)g.layers * n[ob] * n[oc] * sizeof(double);
+    if ((e = hipFuncSetAttribute((const void*)grad_bin_walk_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds)) != hipSuccess)
+        return e;
+    grad_bin_walk_kernel<<<dim3(n_cu), dim3(kBlock), lds, st>>>(a, c, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_bin_reduce(hipStream_t st, const TraceArgs& a, const GradBins& g)
+{
+    if (g.n_tasks <= 0) return hipSuccess;
+    const int n[3] = {a.s.nx, a.s.ny, a.s.nz};
+    const int ob = g.axis == 0 ? 1 : 0, oc = g.axis == 2 ? 1 : 2;
+    const int64_t cells = (int64_t)g.n_slabs * g.layers * n[ob] * n[oc];
+    grad_bin_reduce_kernel<<<dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st>>>(g, a.s.nx, a.s.ny, a.s.nz,
+                                                                                       a.grad, a.tape_flag);
+    return hipGetLastError();
+}
+
+size_t grad_bin_partial_bytes(const DevScene& s, const GradBins& g, int n_cu)
+{
+    const int n[3] = {s.nx, s.ny, s.nz};
+    const int ob = g.axis == 0 ? 1 : 0, oc = g.axis == 2 ? 1 : 2;
+    const size_t chunks = (size_t)kBinChunksPerWg * n_cu + g.n_slabs;
+    return chunks * (size_t)g.layers * n[ob] * n[oc] * sizeof(double);
 }
 
 // Recomputing variant (no valid tape, or all-FP64 mode), per path: pass 1
@@ -956,12 +1289,15 @@ constexpr int kReduceLoads = 8;
 __global__ void __launch_bounds__(kReduceChunks * kWave) grad_reduce_kernel(const double* __restrict__ partial,
                                                                            int n_wg, int64_t nv,
                                                                            double* __restrict__ grad,
-                                                                           unsigned int* __restrict__ work)
+                                                                           unsigned int* __restrict__ work,
+                                                                           const int* __restrict__ skip)
 {
     __shared__ double red[kReduceChunks][kWave];
     // zeroes the task counters of the next slab's launch
     if (blockIdx.x == 0 && threadIdx.x < 2 * kTaskCounters)
         work[(threadIdx.x / 2) * kTaskStride + threadIdx.x % 2] = 0u;
+    // the binned walk on the tape has written the gradient
+    if (skip && *skip != 0) return;
     const int lane = threadIdx.x % kWave, c = threadIdx.x / kWave;
     const int64_t v = (int64_t)blockIdx.x * kWave + lane;
     const int cs = (n_wg + kReduceChunks - 1) / kReduceChunks;
@@ -1001,17 +1337,19 @@ static hipError_t launch_persistent(hipStream_t st, Kern k, int n_wg, size_t lds
 // work[0]) and the recomputing kernel (work[1]); exactly one of them does work.
 template <typename Real, bool kLds>
 static hipError_t launch_grad_t(hipStream_t st, const TraceArgs& a, const DevCams& c, const GradPlan& p, int z0,
-                                int z1, double* partial)
+                                int z1, double* partial, bool walk_on_tape)
 {
     const size_t lds = kLds ? (size_t)(z1 - z0) * a.s.nx * a.s.ny * sizeof(double) : 0;
     hipError_t e = hipSuccess;
-    const bool walk = sizeof(Real) == 4 && a.tape_flag && a.tape && a.wtape && a.vaux;
+    const bool tape = sizeof(Real) == 4 && a.tape_flag && a.tape && a.wtape && a.vaux;
+    const bool walk = tape && walk_on_tape;
     if (walk) e = launch_persistent(st, grad_walk_kernel<kLds>, p.n_wg, lds, a, c, z0, z1, partial);
     if (e != hipSuccess) return e;
-    // without the walk kernel the recomputing kernel must run whatever the flag says
+    // without a tape the recomputing kernel must run whatever the flag says;
+    // with one it runs only when the tape does not match beta_t
     TraceArgs b = a;
     b.work = a.work + 1;
-    if (!walk) b.tape_flag = nullptr;
+    if (!tape) b.tape_flag = nullptr;
     return launch_persistent(st, grad_kernel<Real, kLds>, p.n_wg, lds, b, c, z0, z1, partial);
 }
 
@@ -1042,28 +1380,28 @@ void grad_slab(const GradPlan& p, int nz, int i, int* z0, int* z1)
 }
 
 hipError_t launch_grad(hipStream_t st, int fp64, const TraceArgs& a, const DevCams& c, const GradPlan& p, int slab,
-                       void* partial)
+                       void* partial, bool walk_on_tape)
 {
     if (a.st.n_slots - a.st.first_slot <= 0) return hipSuccess;
     int z0, z1;
     grad_slab(p, a.s.nz, slab, &z0, &z1);
     if (fp64) {
-        if (p.lds) return launch_grad_t<double, true>(st, a, c, p, z0, z1, (double*)partial);
-        return launch_grad_t<double, false>(st, a, c, p, z0, z1, nullptr);
+        if (p.lds) return launch_grad_t<double, true>(st, a, c, p, z0, z1, (double*)partial, walk_on_tape);
+        return launch_grad_t<double, false>(st, a, c, p, z0, z1, nullptr, walk_on_tape);
     }
-    if (p.lds) return launch_grad_t<float, true>(st, a, c, p, z0, z1, (double*)partial);
-    return launch_grad_t<float, false>(st, a, c, p, z0, z1, nullptr);
+    if (p.lds) return launch_grad_t<float, true>(st, a, c, p, z0, z1, (double*)partial, walk_on_tape);
+    return launch_grad_t<float, false>(st, a, c, p, z0, z1, nullptr, walk_on_tape);
 }
 
 hipError_t launch_grad_reduce(hipStream_t st, const GradPlan& p, int nx, int ny, int nz, int slab,
-                              const void* partial, double* grad, unsigned int* work)
+                              const void* partial, double* grad, unsigned int* work, const int* skip)
 {
     if (!p.lds) return hipSuccess;
     int z0, z1;
     grad_slab(p, nz, slab, &z0, &z1);
     const int64_t layer = (int64_t)nx * ny, nv = (int64_t)(z1 - z0) * layer;
     grad_reduce_kernel<<<dim3((unsigned)std::max<int64_t>(1, (nv + kWave - 1) / kWave)), dim3(kReduceChunks * kWave),
-                         0, st>>>((const double*)partial, p.n_wg, nv, grad + z0 * layer, work);
+                         0, st>>>((const double*)partial, p.n_wg, nv, grad + z0 * layer, work, skip);
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "prt.h")
 
 PRT_OK, PRT_E_INVALID, PRT_E_NOMEM, PRT_E_CAPACITY, PRT_E_MISMATCH, PRT_E_HIP = 0, -1, -2, -3, -4, -5
 PRT_TRAVERSAL_FP32, PRT_ALL_FP64 = 0, 1
+PRT_ORDER_BY_SIZE, PRT_ORDER_BY_ID = 0, 1
 PRT_MAX_CAMERAS, PRT_MAX_ORDER = 24, 64
 
 
@@ -77,6 +78,8 @@ def lib():
             "prt_paths_destroy": ([_V], None),
             "prt_render": ([_V, C.POINTER(prt_scene), C.POINTER(prt_cameras), _V, _I32, _V], C.c_int),
             "prt_grad": ([_V, C.POINTER(prt_scene), C.POINTER(prt_cameras), _V, _V, _V], C.c_int),
+            "prt_tpp_render": ([_V, C.POINTER(prt_scene), C.POINTER(prt_cameras), _V, _I32, _V], C.c_int),
+            "prt_tpp_grad": ([_V, C.POINTER(prt_scene), C.POINTER(prt_cameras), _V, _I32, _V, _V], C.c_int),
             "prt_reweight": ([_V, C.POINTER(prt_scene), _V, C.POINTER(_D), C.POINTER(_D)], C.c_int),
             "prt_loss": ([_V, _I64, _V, _V, _V, _V], C.c_int),
             "prt_adam": ([_V, _I64, _V, _V, _V, _V, _V, _I32, _D, _D, _D, _D], C.c_int),
@@ -227,6 +230,15 @@ def prt_render(ctx, scene: prt_scene, cams: CamerasHost, paths, max_order_render
 
 def prt_grad(ctx, scene: prt_scene, cams: CamerasHost, paths, residual, grad):
     _check(lib().prt_grad(ctx, C.byref(scene), C.byref(cams.s), paths, _dptr(residual), _dptr(grad)))
+
+
+def prt_tpp_render(ctx, scene: prt_scene, cams: CamerasHost, paths, order: int, images):
+    _check(lib().prt_tpp_render(ctx, C.byref(scene), C.byref(cams.s), paths, int(order), _dptr(images)))
+
+
+def prt_tpp_grad(ctx, scene: prt_scene, cams: CamerasHost, paths, order: int, residual, grad):
+    _check(lib().prt_tpp_grad(ctx, C.byref(scene), C.byref(cams.s), paths, int(order), _dptr(residual),
+                              _dptr(grad)))
 
 
 def prt_reweight(ctx, scene: prt_scene, paths):

@@ -108,13 +108,16 @@ def _workload(name):
         return s, inputs.cloud32_cameras(s), (1 << 15) + 37, 1002
     if name == "slabs40":
         # 40 x 40 x 24 grid: the gradient tally runs in three z slabs of
-        # 10, 10 and 4 layers (FP64 LDS, 12.8 KB per layer)
+        # 10, 10 and 4 layers (FP64 LDS, 12.8 KB per layer), one walk launch
+        # per slab
         s = inputs.random_field((40, 40, 24), voxel_km=0.02, lo=0.0, hi=30.0, seed=40, albedo_cloud=0.99,
                                 g=0.85, max_order=12)
         return s, inputs.arc_cameras(s, [-50.0, -20.0, 0.0, 25.0, 55.0], 32, 32), 20_011, 1040
     if name == "wide96":
-        # 96 x 96 x 12 grid: one 72 KB layer per slab would need 12 slabs, so the
-        # gradient falls back to FP64 atomics on the output
+        # 96 x 96 x 12 grid: one 72 KB z layer per slab would need 12 slabs, so
+        # the tape-driven gradient bins its walks into 7 slabs of 14 y layers
+        # (the last 12) and the recomputing one falls back to FP64 atomics on
+        # the output
         s = inputs.random_field((96, 96, 12), voxel_km=0.02, lo=0.0, hi=25.0, seed=96, albedo_cloud=0.99,
                                 g=0.85, max_order=10)
         return s, inputs.arc_cameras(s, [-40.0, 0.0, 40.0], 24, 24), 6_007, 1096
@@ -264,6 +267,39 @@ def test_render_grad_reweight_match_oracle(env, prec, name):
     mr_ref, ess_ref = oracle.reweight(scene, paths, beta_t=beta_t)
     assert abs(mr - mr_ref) <= tol["rw"] * abs(mr_ref), (mr, mr_ref)
     assert abs(ess - ess_ref) <= tol["rw"] * abs(ess_ref), (ess, ess_ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "incam"])
+def test_thread_per_path_kernels_match_oracle(env, prec, name):
+    """The path-sorting ablation's thread-per-path render and gradient (Sec.
+    5.3) in both path orders, against the oracle on the same stored paths."""
+    torch, P, api = env
+    scene, cams, n, seed = _workload(name)
+    say(f"thread-per-path render/grad {prec} {name} n={n}")
+    paths = oracle.sample(scene, seed, n)
+    beta_t = _perturbed(scene)
+    ctx = api.Context(0, _prec(P, prec))
+    st = _store(api, ctx, torch, scene, paths)
+    ch = P.CamerasHost(cams)
+    bt = _dev(torch, beta_t)
+    sc = P.make_scene(scene, bt)
+    tol = TOL[prec]
+    ref = oracle.render(scene, cams, paths, beta_t=beta_t)
+    res = np.random.default_rng(3).standard_normal(ref.shape) * np.abs(ref).mean()
+    gref = oracle.grad(scene, cams, paths, res, beta_t=beta_t)
+    res_d = torch.as_tensor(res).cuda()
+    img = torch.empty(ch.image_shape, dtype=torch.float64, device="cuda")
+    g = torch.empty((scene.nz, scene.ny, scene.nx), dtype=torch.float64, device="cuda")
+    for order in (P.PRT_ORDER_BY_SIZE, P.PRT_ORDER_BY_ID):
+        for rep in range(2):  # the second call reuses the per-path copy
+            P.prt_tpp_render(ctx.handle, sc, ch, st.handle, order, img)
+            _close(img.cpu().numpy(), ref, tol["img"], f"thread-per-path images, order {order}, call {rep}")
+            P.prt_tpp_grad(ctx.handle, sc, ch, st.handle, order, res_d, g)
+            _close(g.cpu().numpy(), gref, tol["grad"], f"thread-per-path gradient, order {order}, call {rep}")
+    with pytest.raises(P.PrtError) as e:
+        P.prt_tpp_render(ctx.handle, sc, ch, st.handle, 2, img)
+    assert e.value.code == P.PRT_E_INVALID
 
 
 def test_counters_match_oracle(env):
