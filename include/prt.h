@@ -211,6 +211,22 @@ int prt_grad(prt_ctx ctx, const prt_scene* scene, const prt_cameras* cams, prt_p
    Synchronises and reports any pending kernel error. */
 int prt_reweight(prt_ctx ctx, const prt_scene* scene, prt_paths paths, double* mean_r, double* ess);
 
+/* The statistics of prt_reweight without allocating, for callers that cannot
+   allocate device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc): stats is a caller-owned DEVICE buffer of
+   2 doubles, set to {mean r, ess} on the context's stream; the call does not
+   synchronise.  Its scratch (per-workgroup sums of r and r^2 and, for grids
+   whose field beta_t - beta_ref exceeds the LDS, that field) is a fixed
+   device array of PRT_NOALLOC_SCRATCH_BYTES inside the library, one per GPU,
+   held until the process ends; a call needing more returns PRT_E_CAPACITY
+   before launching anything (16 MiB hold the field of 4 Mi voxels with FP32
+   traversal, 2 Mi in the all-FP64 mode).  Every call on one GPU, from any
+   context, uses that GPU's array: calls that overlap on a GPU race.  The
+   result equals prt_reweight's bit for bit.  No device memory is allocated
+   or freed. */
+#define PRT_NOALLOC_SCRATCH_BYTES (16u << 20)
+int prt_reweight_noalloc(prt_ctx ctx, const prt_scene* scene, prt_paths paths, double* stats);
+
 /* Appearance loss (Eq. appearance_loss): residual[i] = images[i] - target[i]
    and *loss = 0.5 sum residual^2 (all device FP64; n elements). */
 int prt_loss(prt_ctx ctx, int64_t n, const double* images, const double* target, double* residual,

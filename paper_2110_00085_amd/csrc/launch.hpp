@@ -141,8 +141,9 @@ struct VertexLevels {
 };
 
 // ---- sampling, sorting, packing (sample.hip)
-// grid_tot = beta_t + beta_air and (if given) grid_dlt = beta_t - beta_ref in
-// the traversal precision; also copy = beta_t and *zero = 0 when given.
+// grid_tot = beta_t + beta_air and grid_dlt = beta_t - beta_ref in the
+// traversal precision (each when given); also copy = beta_t and *zero = 0
+// when given.
 hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const float* bc_r, double beta_air,
                              int64_t nu, void* grid_tot, void* grid_dlt, float* copy = nullptr,
                              unsigned int* zero = nullptr);
@@ -255,6 +256,8 @@ hipError_t launch_grad_bin_reduce(hipStream_t st, const TraceArgs& a, const Grad
 size_t grad_bin_partial_bytes(const DevScene& s, const GradBins& g, int n_cu);
 // Per-workgroup sums of r and r^2 into a.partial[2*wg..]; *n_blocks workgroups.
 hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int n_cu, int64_t* n_blocks);
+// Workgroups launch_reweight uses for a store of n_slots slots.
+int64_t reweight_blocks(int64_t n_slots, int n_cu);
 // flag = 0 if a[i] != b[i] bitwise for some i < n (flag set to 1 beforehand,
 // by launch_grad_prep).
 hipError_t launch_equal_flag(hipStream_t st, const float* a, const float* b, int64_t n, int* flag);
@@ -292,6 +295,10 @@ int64_t loss_blocks(int64_t n);
 // out2[0] = sum of partial[2 i], out2[1] = sum of partial[2 i + 1] over
 // i < n_blocks, in a fixed order (out2 may be pinned host memory).
 hipError_t launch_sum_pairs(hipStream_t st, const double* partial, int64_t n_blocks, double* out2);
+// stats[0] = (sum of partial[2i]) / n_paths, stats[1] = (sum partial[2i])^2 /
+// sum partial[2i+1] (0 when that is 0), sums in launch_sum_pairs' order.
+hipError_t launch_reweight_stats(hipStream_t st, const double* partial, int64_t n_blocks, double n_paths,
+                                 double* stats);
 struct CarveThresholds {
     double t[kMaxCams];
 };

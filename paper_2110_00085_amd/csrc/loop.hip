@@ -98,6 +98,42 @@ hipError_t launch_sum_pairs(hipStream_t st, const double* partial, int64_t n_blo
     return hipGetLastError();
 }
 
+// stats[0] = mean r = (sum r) / n, stats[1] = ess = (sum r)^2 / sum r^2 (0
+// when sum r^2 is 0) from the reweight's per-workgroup pairs, summed in the
+// order of sum_pairs_kernel; one block.
+__global__ void __launch_bounds__(256) reweight_stats_kernel(const double* __restrict__ partial, int64_t nb,
+                                                             double n, double* __restrict__ stats)
+{
+    __shared__ double red[2][256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) {
+        a += partial[2 * i];
+        b += partial[2 * i + 1];
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + o];
+            red[1][threadIdx.x] += red[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double s = red[0][0], s2 = red[1][0];
+        stats[0] = s / n;
+        stats[1] = s2 > 0 ? s * s / s2 : 0.0;
+    }
+}
+
+hipError_t launch_reweight_stats(hipStream_t st, const double* partial, int64_t n_blocks, double n_paths,
+                                 double* stats)
+{
+    reweight_stats_kernel<<<dim3(1), dim3(256), 0, st>>>(partial, n_blocks, n_paths, stats);
+    return hipGetLastError();
+}
+
 // Adam (Kingma & Ba) with bias corrections bc1 = 1 - b1^t, bc2 = 1 - b2^t,
 // then projection onto beta >= 0 and the FP32 copy used by the kernels.
 __global__ void __launch_bounds__(256) adam_kernel(int64_t n, double* __restrict__ beta, float* __restrict__ bf,

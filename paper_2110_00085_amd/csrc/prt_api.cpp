@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/prt.h"
@@ -648,6 +649,42 @@ StoreView view_of(prt_paths p)
 
 }  // namespace
 
+// ------------------------------------------------ no-allocation scratch
+
+// Device scratch of prt_reweight_noalloc: one fixed array per GPU, held until
+// the process ends.  Host code never passes its name to a kernel (on the host
+// it is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device by prt_create with
+// that device current.
+static __device__ __align__(256) unsigned char scratch[PRT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the device is current).
+int lookup_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(PRT_E_CAPACITY, "device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return PRT_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(PRT_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = p;
+    return PRT_OK;
+}
+
+void* scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 // ================================================================== C ABI
 
 extern "C" {
@@ -663,6 +700,8 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out)
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PRT_E_HIP, "no HIP device available");
     if (device < 0 || device >= ndev) return fail(PRT_E_INVALID, "device %d out of range (have %d)", device, ndev);
     DeviceGuard g(device);
+    // the no-allocation entry point's scratch address on this device
+    if (int rc = lookup_scratch(device)) return rc;
     prt_ctx c = new prt_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -1305,6 +1344,42 @@ int prt_reweight(prt_ctx c, const prt_scene* s, prt_paths p, double* mean_r, dou
     const double h[2] = {c->hsum[0], c->hsum[1]};
     *mean_r = h[0] / (double)p->n;
     *ess = h[1] > 0 ? h[0] * h[0] / h[1] : 0.0;
+    return PRT_OK;
+}
+
+int prt_reweight_noalloc(prt_ctx c, const prt_scene* s, prt_paths p, double* stats)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    int rc = check_scene(s);
+    if (rc) return rc;
+    if ((rc = check_match(s, p))) return rc;
+    if (!stats) return fail(PRT_E_INVALID, "stats is NULL");
+    const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
+    // scratch layout: the per-workgroup (sum r, sum r^2) pairs, then (for
+    // grids larger than the LDS) the field beta_t - beta_ref
+    const int64_t nb = reweight_blocks(p->n_slots, c->n_cu);
+    const size_t pair_bytes = ((size_t)nb * 2 * sizeof(double) + 255) / 256 * 256;
+    const bool grid_lds = delta_grid_lds(c->fp64, nu);
+    const size_t need = pair_bytes + (grid_lds ? 0 : (size_t)nu * (c->fp64 ? 8 : 4));
+    if (need > PRT_NOALLOC_SCRATCH_BYTES)
+        return fail(PRT_E_CAPACITY, "reweight needs %zu bytes of scratch, more than the %u available", need,
+                    (unsigned)PRT_NOALLOC_SCRATCH_BYTES);
+    unsigned char* base = (unsigned char*)scratch_of(c->device);
+    if (!base) return fail(PRT_E_HIP, "no scratch address for device %d", c->device);
+    DeviceGuard g(c->device);
+    TraceArgs a{};
+    a.s = make_dev_scene(s);
+    a.st = view_of(p);
+    a.bc_t = s->beta_cloud;
+    a.grid_dlt = grid_lds ? nullptr : base + pair_bytes;
+    a.partial = (double*)base;
+    a.counters = c->counters;
+    if (!grid_lds)
+        HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, nullptr,
+                                 base + pair_bytes));
+    int64_t used = 0;
+    HIPCHK(launch_reweight(c->stream, c->fp64, a, c->n_cu, &used));
+    HIPCHK(launch_reweight_stats(c->stream, a.partial, used, (double)p->n, stats));
     return PRT_OK;
 }
 

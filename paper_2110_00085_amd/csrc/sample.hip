@@ -19,7 +19,7 @@ __global__ void __launch_bounds__(256) prep_grids_kernel(const float* __restrict
     if (zero && i == 0) *zero = 0u;
     if (i >= nu) return;
     const double t = (double)bc_t[i];
-    tot[i] = (Real)(t + beta_air);
+    if (tot) tot[i] = (Real)(t + beta_air);
     if (dlt) dlt[i] = (Real)(t - (double)bc_r[i]);
     if (copy) copy[i] = bc_t[i];
 }

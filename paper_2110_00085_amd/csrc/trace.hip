@@ -1513,11 +1513,16 @@ __global__ void __launch_bounds__(kBlock) reweight_kernel(TraceArgs a)
     }
 }
 
+int64_t reweight_blocks(int64_t n_slots, int n_cu)
+{
+    return std::max<int64_t>(1, std::min<int64_t>((n_slots + kBlock - 1) / kBlock, n_cu));
+}
+
 hipError_t launch_reweight(hipStream_t st, int fp64, const TraceArgs& a, int n_cu, int64_t* n_blocks)
 {
     const size_t grid_bytes = (size_t)a.s.nx * a.s.ny * a.s.nz * (fp64 ? 8 : 4);
     const bool lds = grid_bytes <= kLdsBudget;
-    const int n_wg = (int)std::max<int64_t>(1, std::min<int64_t>((a.st.n_slots + kBlock - 1) / kBlock, n_cu));
+    const int n_wg = (int)reweight_blocks(a.st.n_slots, n_cu);
     *n_blocks = n_wg;
     if (fp64)
         return lds ? launch_delta_kernel(st, reweight_kernel<double, true>, true, grid_bytes, n_wg, a)

@@ -82,6 +82,7 @@ def lib():
             "prt_tpp_grad": ([_V, C.POINTER(prt_scene), C.POINTER(prt_cameras), _V, _I32, _V, _V], C.c_int),
             "prt_reweight": ([_V, C.POINTER(prt_scene), _V, C.POINTER(_D), C.POINTER(_D)], C.c_int),
             "prt_loss": ([_V, _I64, _V, _V, _V, _V], C.c_int),
+            "prt_reweight_noalloc": ([_V, C.POINTER(prt_scene), _V, _V], C.c_int),
             "prt_adam": ([_V, _I64, _V, _V, _V, _V, _V, _I32, _D, _D, _D, _D], C.c_int),
             "prt_space_carve": ([_V, C.POINTER(prt_scene), C.POINTER(prt_cameras), _V, _V, _D, _V, _V], C.c_int),
             "prt_counters": ([_V, C.POINTER(prt_counters_t), C.c_int], C.c_int),
@@ -245,6 +246,13 @@ def prt_reweight(ctx, scene: prt_scene, paths):
     m, e = _D(), _D()
     _check(lib().prt_reweight(ctx, C.byref(scene), paths, C.byref(m), C.byref(e)))
     return m.value, e.value
+
+
+def prt_reweight_noalloc(ctx, scene: prt_scene, paths, stats):
+    """stats: device float64 tensor of 2 elements, set to (mean r, ess)."""
+    if stats.dtype.itemsize != 8 or stats.numel() < 2:
+        raise ValueError("stats must hold 2 float64 values")
+    _check(lib().prt_reweight_noalloc(ctx, C.byref(scene), paths, _dptr(stats)))
 
 
 def prt_loss(ctx, images, target, residual, loss):
