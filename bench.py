@@ -88,19 +88,29 @@ def parse():
                          "LDSBankConflict SQ_INSTS_VALU csv output of a bench run into --valu-json, "
                          "then exit")
     ap.add_argument("--valu-json", default=VALU_JSON, help="where --valu-summary writes its result")
+    ap.add_argument("--counter-summary", metavar="PMC_DIR",
+                    help="print a markdown table of the mean of every counter per hot-path kernel in the "
+                         "rocprofv3 --pmc csv output under PMC_DIR, then exit")
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
                     help="print a markdown table of the kernel_stats.csv that rocprofv3 --kernel-trace --stats "
                          "--output-format csv wrote under TRACE_DIR, then exit")
     ap.add_argument("--reuse-study", action="store_true",
-                    help="reuse against fresh resampling at equal gradient error on --workload (default plume64 "
-                         "for the study): Adam iterations on recycled paths, and at checkpoints the recycled "
-                         "gradient's error and one fresh gradient's error against the mean of 8 fresh gradients")
+                    help="path recycling (new paths every 30 iterations) against fresh paths every iteration on "
+                         "--workload (plume64 when the default is given): loss, epsilon and delta against time")
     ap.add_argument("--sort-ablation", action="store_true",
                     help="path sorting (Sec. 5.3) on --workload: the production kernels against the thread-per-path "
                          "kernels on the same store, with the paths sorted by size and in the order they were drawn")
     ap.add_argument("--ablation-parts", default="render,grad", help="which passes the ablation times")
     ap.add_argument("--ablation-reps", type=int, default=5)
-    ap.add_argument("--study-iters", type=int, default=30)
+    ap.add_argument("--loop", action="store_true",
+                    help="run Alg. 2 on the 32^3 cloud (initial field) towards images of a second seeded field, "
+                         "resampling when |mean r - 1| > 0.2; per-iteration loss, epsilon, delta, mean r, ESS")
+    ap.add_argument("--loop-iters", type=int, default=200)
+    ap.add_argument("--loop-policies", default="drift0.2,period30,ess0.1",
+                    help="resampling policies to run: drift0.2 (|mean r - 1| > 0.2), period30 (also every 30 "
+                         "iterations), ess0.1 (also when ESS < 0.1 N)")
+    ap.add_argument("--study-iters", type=int, default=50)
+    ap.add_argument("--study-lr", type=float, default=1.0, help="Adam step size of the study, 1/km")
     ap.add_argument("--study-paths", type=int, default=0, help="paths per store (default: the workload's)")
     return ap.parse_args()
 
@@ -224,6 +234,27 @@ def valu_summary(valu_dir, occ_dir, out_json, workload):
     _update_json(out_json, workload, {"source_sha256": source_hash(), "kernels": table})
 
 
+def counter_summary(pmc_dir):
+    """Mean over the dispatches of each hot-path kernel of every counter in a
+    rocprofv3 --pmc csv output, as a markdown table."""
+    import csv
+    import glob
+    vals = {}
+    for f in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            for scope, sym in DEVICE_KERNEL.items():
+                k = r["Kernel_Name"]
+                if "prt::" + sym + "<" in k or "prt::" + sym + "(" in k:
+                    vals.setdefault(sym, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({c for v in vals.values() for c in v})
+    print("| kernel | dispatches | " + " | ".join(names) + " |")
+    print("|---|---:|" + "---:|" * len(names))
+    for sym, v in sorted(vals.items()):
+        n = max(len(x) for x in v.values())
+        cells = [f"{sum(v[c]) / len(v[c]):.4g}" if c in v else "" for c in names]
+        print(f"| {sym} | {n} | " + " | ".join(cells) + " |")
+
+
 def trace_summary(trace_dir):
     """Markdown table (kernel, calls, total / average / min / max ms, share)
     of rocprofv3's kernel_stats.csv, kernels by total time."""
@@ -259,100 +290,213 @@ def traffic_for(scope, workload):
 
 
 def reuse_study(args):
-    """Path reuse against fresh resampling at equal gradient error.
+    """Path recycling against fresh paths every iteration (Sec. 6.1, Results:
+    N_r = 30 against N_r = 1 on the plume).
 
-    Adam (lr 0.1 km^-1, beta >= 0) runs on recycled paths from beta^0 (the
-    workload's field) towards images of a second seeded field, resampling
-    only when |mean r - 1| > 0.2.  At checkpoints k the recycled gradient g_k
-    and one gradient g_f from freshly sampled paths at beta_k are compared
-    with g_ref, the mean of 8 further fresh gradients at beta_k:
-    e = ||g - g_ref|| / ||g_ref||.  Iteration times: recycled (render, loss,
-    grad, Adam, reweight) and fresh (the same plus resampling).  A fresh
-    gradient of the recycled one's error needs (e_f / e_k)^2 as many paths,
-    so reuse is faster at equal error by that factor times the fresh
-    iteration time over the recycled one."""
+    Measured images: the workload's field rendered with fresh paths (4x N).
+    Both runs start from the same space-carved field (photo hull at 5 % of
+    each camera's peak, filled with the true field's mean extinction) and run
+    the same Adam iterations (lr --study-lr 1/km) with the same N; one draws new
+    paths every 30 iterations, the other every iteration.  Reported per run:
+    loss, epsilon, delta and wall time per iteration, and the time each run
+    needs to reach the epsilon that the fresh-path run ends with.  At the end,
+    the recycled gradient and one fresh gradient at the recycled run's final
+    field are compared with the mean of 8 fresh gradients, per voxel and
+    summed over 4x4x4 blocks (where the per-voxel Monte Carlo noise averages
+    out), e = ||g - g_ref|| / ||g_ref||."""
     import numpy as np
     import torch
 
     import inputs
     from paper_2110_00085_amd import api, prt as P
-    name = args.workload if args.workload != "cloud32" else "plume64"
+    from paper_2110_00085_amd.loop import Policy, Reconstruction, Stage, space_carved_start
+    name = args.workload if args.workload != "field128" else "plume64"
     make_scene, make_cams, n_paths, seed = inputs.WORKLOADS[name]
     n = args.study_paths or n_paths
     scene = make_scene()
     cams = make_cams(scene)
     ch = P.CamerasHost(cams)
     ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
-    h = ctx.handle
     dev = torch.device("cuda:0")
-    tgt_scene = make_scene(seed=7) if name != "cloud8" else scene.with_beta(scene.beta_cloud * 1.2)
-    st = api.PathStore.sample(ctx, tgt_scene, torch.as_tensor(tgt_scene.beta_cloud).to(dev), seed + 2000, n)
-    target = api.render(ctx, tgt_scene, torch.as_tensor(tgt_scene.beta_cloud).to(dev), ch, st)
+    truth = torch.as_tensor(scene.beta_cloud).to(dev).contiguous()
+    st = api.PathStore.sample(ctx, scene, truth, seed + 5000, min(4 * n, (1 << 31) - 64))
+    measured = api.render(ctx, scene, truth, ch, st)
     st.close()
-    beta32 = torch.as_tensor(scene.beta_cloud).to(dev).contiguous()
-    beta64 = beta32.double()
-    m = torch.zeros_like(beta64)
-    v = torch.zeros_like(beta64)
+    thr = [0.05 * float(measured[d].max()) for d in range(cams.n)]
+    fill = float(scene.beta_cloud[scene.beta_cloud > 0].mean())
+    beta0, mask = space_carved_start(ctx, scene, cams, measured, thr, fill)
+    print(f"[study] {name}: {n} paths, {args.study_iters} iterations, lr {args.study_lr}; space-carved start keeps "
+          f"{int(mask.sum())} of {mask.numel()} voxels at {fill:.2f} 1/km", flush=True)
+    runs = {}
+    for label, period in (("recycled_Nr30", 30), ("fresh_Nr1", 1)):
+        rec = Reconstruction(ctx, scene, cams, measured, beta0, lr=args.study_lr,
+                             policy=Policy(period=period, drift=None), seed=seed + 100, beta_true=truth)
+        recs = rec.run([Stage(factor=1, n_paths=n, max_iters=args.study_iters, window=10 ** 9)])
+        t = np.cumsum([r.seconds for r in recs])
+        runs[label] = {"seconds": t.tolist(), "loss": [r.loss for r in recs], "epsilon": [r.epsilon for r in recs],
+                       "delta": [r.delta for r in recs], "mean_r": [r.mean_r for r in recs],
+                       "resamples": int(sum(r.resampled for r in recs))}
+        print(f"[study] {label}: {t[-1]:.1f} s, loss {recs[0].loss:.4e} -> {recs[-1].loss:.4e}, epsilon "
+              f"{recs[0].epsilon:.4f} -> {recs[-1].epsilon:.4f}, {runs[label]['resamples']} resamples", flush=True)
+        if label == "recycled_Nr30":
+            final = rec
+        else:
+            rec.close()
+    target_eps = runs["fresh_Nr1"]["epsilon"][-1]
+    for label, r in runs.items():
+        hit = [s_ for s_, e in zip(r["seconds"], r["epsilon"]) if e <= target_eps]
+        r["seconds_to_fresh_final_epsilon"] = hit[0] if hit else None
+
+    # gradient errors at the recycled run's final field
     img = torch.empty(ch.image_shape, dtype=torch.float64, device=dev)
     res = torch.empty_like(img)
     loss = torch.empty(1, dtype=torch.float64, device=dev)
-    grad = torch.empty((scene.nz, scene.ny, scene.nx), dtype=torch.float64, device=dev)
-    sc = P.make_scene(scene, beta32)
-    print(f"[study] {name}: {scene.nx}x{scene.ny}x{scene.nz}, {cams.n} cams {cams.width}^2, {n} paths, "
-          f"{args.study_iters} iterations", flush=True)
+    g = torch.empty((scene.nz, scene.ny, scene.nx), dtype=torch.float64, device=dev)
+    b32 = final.beta32
+    sc = P.make_scene(scene, b32)
 
     def grad_on(store):
-        P.prt_render(h, sc, ch, store.handle, scene.max_order, img)
-        P.prt_loss(h, img, target, res, loss)
-        P.prt_grad(h, sc, ch, store.handle, res, grad)
-        return grad.clone()
+        P.prt_render(ctx.handle, sc, ch, store.handle, scene.max_order, img)
+        P.prt_loss(ctx.handle, img, measured, res, loss)
+        P.prt_grad(ctx.handle, sc, ch, store.handle, res, g)
+        return g.clone()
 
-    def fresh_grad(s_):
-        fs = api.PathStore.sample(ctx, scene, beta32, s_, n)
-        g = grad_on(fs)
+    def fresh(s_):
+        fs = api.PathStore.sample(ctx, scene, b32, s_, n)
+        out = grad_on(fs)
         fs.close()
-        return g
+        return out
 
-    store = api.PathStore.sample(ctx, scene, beta32, seed, n)
-    resamples, t_rec, checkpoints, rows = 0, [], {5, 10, 20, args.study_iters}, []
-    for it in range(1, args.study_iters + 1):
+    def blocks(x):
+        k = 4
+        v = x.view(scene.nz // k, k, scene.ny // k, k, scene.nx // k, k)
+        return v.sum(dim=(1, 3, 5))
+
+    g_rec = grad_on(final.store)
+    g_one = fresh(70_000)
+    g_ref = sum(fresh(71_000 + j) for j in range(8)) / 8
+    errs = {}
+    for tag, f in (("voxel", lambda x: x), ("block4", blocks)):
+        nr = float(torch.linalg.vector_norm(f(g_ref)))
+        errs[tag] = {"recycled": float(torch.linalg.vector_norm(f(g_rec) - f(g_ref))) / nr,
+                     "fresh": float(torch.linalg.vector_norm(f(g_one) - f(g_ref))) / nr}
+    final.close()
+    print(json.dumps({"study": "path recycling (N_r = 30) against fresh paths every iteration (N_r = 1)",
+                      "workload": name, "paths": n, "iterations": args.study_iters, "lr": args.study_lr,
+                      "fresh_final_epsilon": target_eps, "runs": runs, "gradient_error_at_end": errs}), flush=True)
+
+
+def loop_run(args):
+    """Alg. 2 on the differentiable-step workload: the 32^3 cloud as the
+    initial field, measured images of a second seeded field (seed 3) rendered
+    with fresh paths (seed 2003, 4x N), Adam lr 0.1 1/km, --loop-iters
+    iterations under each resampling policy of --loop-policies; JSON records
+    (loss, epsilon, delta against the second field, mean r, ESS, resample
+    flag, seconds) every 20 iterations, then a summary line per policy."""
+    import torch
+
+    import inputs
+    from paper_2110_00085_amd import api, prt as P
+    from paper_2110_00085_amd.loop import Policy, Reconstruction, Stage
+    make_scene, make_cams, n_paths, seed = inputs.WORKLOADS["cloud32"]
+    if args.paths:
+        n_paths = args.paths
+    scene = make_scene()
+    cams = make_cams(scene)
+    ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
+    dev = torch.device("cuda:0")
+    truth_scene = scene.with_beta(inputs.gaussian_field_cloud(scene.nx, 3))
+    truth = torch.as_tensor(truth_scene.beta_cloud).to(dev).contiguous()
+    st = api.PathStore.sample(ctx, truth_scene, truth, 2003, 4 * n_paths)
+    measured = api.render(ctx, truth_scene, truth, P.CamerasHost(cams), st)
+    st.close()
+    beta0 = torch.as_tensor(scene.beta_cloud).to(dev).contiguous()
+    policies = {"drift0.2": Policy(period=None, drift=0.2), "period30": Policy(period=30, drift=0.2),
+                "ess0.1": Policy(period=None, drift=0.2, min_ess=0.1)}
+    for label in args.loop_policies.split(","):
+        rec = Reconstruction(ctx, scene, cams, measured, beta0, lr=0.1, policy=policies[label], seed=seed,
+                             beta_true=truth)
+        out = []
+
+        def show(r):
+            d = {"policy": label, "iteration": r.iteration, "loss": r.loss, "epsilon": r.epsilon, "delta": r.delta,
+                 "mean_r": r.mean_r, "ess": r.ess, "resampled": r.resampled, "seconds": r.seconds}
+            out.append(d)
+            if r.iteration % 20 == 0 or r.iteration == 1:
+                print(json.dumps(d), flush=True)
+
+        rec.run([Stage(factor=1, n_paths=n_paths, max_iters=args.loop_iters, window=10 ** 9)], callback=show)
+        rec.close()
+        print(json.dumps({"loop": "Alg. 2 on cloud32", "policy": label, "paths": n_paths, "iterations": len(out),
+                          "resamples": sum(d["resampled"] for d in out), "loss_first": out[0]["loss"],
+                          "loss_last": out[-1]["loss"], "epsilon_first": out[0]["epsilon"],
+                          "epsilon_last": out[-1]["epsilon"], "delta_first": out[0]["delta"],
+                          "delta_last": out[-1]["delta"], "mean_r_min": min(d["mean_r"] for d in out),
+                          "ess_over_n_min": min(d["ess"] for d in out) / n_paths,
+                          "seconds_per_iteration": sum(d["seconds"] for d in out) / len(out)}), flush=True)
+
+
+def sort_ablation(args):
+    """Path sorting (Sec. 5.3, "up to 3x" with 32-thread groups) at wave64.
+
+    On one store of the workload: the production kernels (persistent
+    wavefront tasks over the size-sorted, batch-major store), and the
+    thread-per-path kernels on per-path copies of the same paths in size
+    order and in drawing order.  Each pass is timed over --ablation-reps
+    calls after one untimed call (which also builds the per-path copies)."""
+    import torch
+
+    import inputs
+    from paper_2110_00085_amd import api, prt as P
+    name = args.workload
+    make_scene, make_cams, n_paths, seed = inputs.WORKLOADS[name]
+    if args.paths:
+        n_paths = args.paths
+    scene = make_scene()
+    cams = make_cams(scene)
+    ch = P.CamerasHost(cams)
+    ctx = api.Context(0, P.PRT_ALL_FP64 if args.precision == "fp64" else P.PRT_TRAVERSAL_FP32)
+    h = ctx.handle
+    dev = torch.device("cuda:0")
+    beta = torch.as_tensor(scene.beta_cloud).to(dev).contiguous()
+    st = api.PathStore.sample(ctx, scene, beta, seed, n_paths)
+    sc = P.make_scene(scene, beta)
+    img = api.render(ctx, scene, beta, ch, st)
+    res = (img * 0.05).contiguous()
+    g = torch.empty((scene.nz, scene.ny, scene.nx), dtype=torch.float64, device=dev)
+    parts = args.ablation_parts.split(",")
+    print(f"[ablation] {name}: {n_paths} paths, parts {parts}, {args.ablation_reps} reps", flush=True)
+
+    def timed(fn):
+        fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g = grad_on(store)
-        P.prt_adam(h, beta64, beta32, grad, m, v, it, 0.1)
-        mr, ess = P.prt_reweight(h, sc, store.handle)
-        t_rec.append(time.perf_counter() - t0)
-        if it in checkpoints:
-            # beta has moved on; the recycled gradient at the new beta_k
-            g_k = grad_on(store).double()
-            g_f = fresh_grad(10_000 + it).double()
-            g_ref = sum(fresh_grad(20_000 + 100 * it + j).double() for j in range(8)) / 8
-            nr = float(torch.linalg.vector_norm(g_ref))
-            e_k = float(torch.linalg.vector_norm(g_k - g_ref)) / nr
-            e_f = float(torch.linalg.vector_norm(g_f - g_ref)) / nr
-            rows.append({"iteration": it, "mean_r": mr, "ess": ess, "e_recycled": e_k, "e_fresh": e_f,
-                         "loss": float(loss.item()), "resamples": resamples})
-            print(f"[study] it {it}: loss {loss.item():.4e} mean r {mr:.4f} ess/N {ess / n:.3f} "
-                  f"e_recycled {e_k:.4f} e_fresh {e_f:.4f} resamples {resamples}", flush=True)
-        if abs(mr - 1.0) > 0.2:
-            store.resample(scene, beta32, seed + it, n)
-            resamples += 1
-    # iteration times: recycled (median of the loop) and fresh (with resampling)
-    t_fresh = []
-    for k in range(5):
+        for _ in range(args.ablation_reps):
+            fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        store.resample(scene, beta32, 30_000 + k, n)
-        grad_on(store)
-        P.prt_adam(h, beta64.clone(), beta32.clone(), grad, m.clone(), v.clone(), 1, 0.0)
-        P.prt_reweight(h, sc, store.handle)
-        t_fresh.append(time.perf_counter() - t0)
-    tr, tf = float(np.median(t_rec)), float(np.median(t_fresh))
-    ratio = float(np.mean([(r["e_fresh"] / r["e_recycled"]) ** 2 for r in rows]))
-    print(json.dumps({"study": "reuse vs fresh resampling", "workload": name, "paths": n,
-                      "ms_recycled_iteration": 1e3 * tr, "ms_fresh_iteration": 1e3 * tf,
-                      "paths_factor_equal_error": ratio, "equal_error_speedup_of_reuse": tf * ratio / tr,
-                      "checkpoints": rows}), flush=True)
+        return 1e3 * (time.perf_counter() - t0) / args.ablation_reps
+
+    out = {"study": "path sorting", "workload": name, "paths": n_paths, "precision": args.precision, "ms": {}}
+    for part in parts:
+        if part == "render":
+            runs = {"production": lambda: P.prt_render(h, sc, ch, st.handle, scene.max_order, img),
+                    "thread_per_path_sorted": lambda: P.prt_tpp_render(h, sc, ch, st.handle, P.PRT_ORDER_BY_SIZE, img),
+                    "thread_per_path_unsorted": lambda: P.prt_tpp_render(h, sc, ch, st.handle, P.PRT_ORDER_BY_ID, img)}
+        else:
+            # the production gradient walks on the transmittance tape of the last render
+            P.prt_render(h, sc, ch, st.handle, scene.max_order, img)
+            runs = {"production": lambda: P.prt_grad(h, sc, ch, st.handle, res, g),
+                    "thread_per_path_sorted": lambda: P.prt_tpp_grad(h, sc, ch, st.handle, P.PRT_ORDER_BY_SIZE, res, g),
+                    "thread_per_path_unsorted": lambda: P.prt_tpp_grad(h, sc, ch, st.handle, P.PRT_ORDER_BY_ID, res, g)}
+        for k, fn in runs.items():
+            out["ms"][f"{part}_{k}"] = timed(fn)
+            print(f"[ablation] {part} {k}: {out['ms'][f'{part}_{k}']:.3f} ms", flush=True)
+        m = out["ms"]
+        out[f"{part}_sorting_speedup"] = m[f"{part}_thread_per_path_unsorted"] / m[f"{part}_thread_per_path_sorted"]
+        out[f"{part}_production_vs_unsorted"] = m[f"{part}_thread_per_path_unsorted"] / m[f"{part}_production"]
+    print(json.dumps(out), flush=True)
+    st.close()
+    ctx.close()
 
 
 def run_workload(args, name, steps, warmup, breakdown_steps, recycled_steps, cpu_paths):
@@ -528,79 +672,22 @@ def run_workload(args, name, steps, warmup, breakdown_steps, recycled_steps, cpu
     return out
 
 
-def sort_ablation(args):
-    """Path sorting (Sec. 5.3, "up to 3x" with 32-thread groups) at wave64.
-
-    On one store of the workload: the production kernels (persistent
-    wavefront tasks over the size-sorted, batch-major store), and the
-    thread-per-path kernels on per-path copies of the same paths in size
-    order and in drawing order.  Each pass is timed over --ablation-reps
-    calls after one untimed call (which also builds the per-path copies)."""
-    import torch
-
-    import inputs
-    from paper_2110_00085_amd import api, prt as P
-    name = args.workload
-    make_scene, make_cams, n_paths, seed = inputs.WORKLOADS[name]
-    if args.paths:
-        n_paths = args.paths
-    scene = make_scene()
-    cams = make_cams(scene)
-    ch = P.CamerasHost(cams)
-    ctx = api.Context(0, P.PRT_ALL_FP64 if args.precision == "fp64" else P.PRT_TRAVERSAL_FP32)
-    h = ctx.handle
-    dev = torch.device("cuda:0")
-    beta = torch.as_tensor(scene.beta_cloud).to(dev).contiguous()
-    st = api.PathStore.sample(ctx, scene, beta, seed, n_paths)
-    sc = P.make_scene(scene, beta)
-    img = api.render(ctx, scene, beta, ch, st)
-    res = (img * 0.05).contiguous()
-    g = torch.empty((scene.nz, scene.ny, scene.nx), dtype=torch.float64, device=dev)
-    parts = args.ablation_parts.split(",")
-    print(f"[ablation] {name}: {n_paths} paths, parts {parts}, {args.ablation_reps} reps", flush=True)
-
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.ablation_reps):
-            fn()
-        torch.cuda.synchronize()
-        return 1e3 * (time.perf_counter() - t0) / args.ablation_reps
-
-    out = {"study": "path sorting", "workload": name, "paths": n_paths, "precision": args.precision, "ms": {}}
-    for part in parts:
-        if part == "render":
-            runs = {"production": lambda: P.prt_render(h, sc, ch, st.handle, scene.max_order, img),
-                    "thread_per_path_sorted": lambda: P.prt_tpp_render(h, sc, ch, st.handle, P.PRT_ORDER_BY_SIZE, img),
-                    "thread_per_path_unsorted": lambda: P.prt_tpp_render(h, sc, ch, st.handle, P.PRT_ORDER_BY_ID, img)}
-        else:
-            # the production gradient walks on the transmittance tape of the last render
-            P.prt_render(h, sc, ch, st.handle, scene.max_order, img)
-            runs = {"production": lambda: P.prt_grad(h, sc, ch, st.handle, res, g),
-                    "thread_per_path_sorted": lambda: P.prt_tpp_grad(h, sc, ch, st.handle, P.PRT_ORDER_BY_SIZE, res, g),
-                    "thread_per_path_unsorted": lambda: P.prt_tpp_grad(h, sc, ch, st.handle, P.PRT_ORDER_BY_ID, res, g)}
-        for k, fn in runs.items():
-            out["ms"][f"{part}_{k}"] = timed(fn)
-            print(f"[ablation] {part} {k}: {out['ms'][f'{part}_{k}']:.3f} ms", flush=True)
-        m = out["ms"]
-        out[f"{part}_sorting_speedup"] = m[f"{part}_thread_per_path_unsorted"] / m[f"{part}_thread_per_path_sorted"]
-        out[f"{part}_production_vs_unsorted"] = m[f"{part}_thread_per_path_unsorted"] / m[f"{part}_production"]
-    print(json.dumps(out), flush=True)
-    st.close()
-    ctx.close()
-
-
 def main():
     args = parse()
     if args.sort_ablation:
         sort_ablation(args)
+        return
+    if args.loop:
+        loop_run(args)
         return
     if args.copy_calibration:
         copy_calibration()
         return
     if args.trace_summary:
         trace_summary(args.trace_summary)
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary)
         return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, args.traffic_json, args.workload)

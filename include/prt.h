@@ -273,6 +273,24 @@ int prt_tpp_render(prt_ctx ctx, const prt_scene* scene, const prt_cameras* cams,
 int prt_tpp_grad(prt_ctx ctx, const prt_scene* scene, const prt_cameras* cams, prt_paths paths, int32_t order,
                  const double* residual, double* grad);
 
+/* Coarse-to-fine measurements (Sec. 6.1: the reconstruction starts from
+   down-sampled images and raises the resolution when the loss saturates).
+   images: device FP64 [n][H][W] of the cameras cams (pixel-averaged
+   radiance); coarse: device FP64 [n][H/factor][W/factor], overwritten with
+   the solid-angle-weighted mean of each factor x factor block of pixels,
+   which is the pixel-averaged radiance of the same pinhole camera with focal
+   length f/factor and image sides divided by factor.  H and W must be
+   multiples of factor (PRT_E_INVALID otherwise).  Async. */
+int prt_downsample_images(prt_ctx ctx, const prt_cameras* cams, const double* images, int32_t factor,
+                          double* coarse);
+
+/* Reconstruction errors of Sec. 6: errors[0] = epsilon = ||b* - b||_1 /
+   ||b*||_1 (relative L1 distance) and errors[1] = delta = (||b*||_1 -
+   ||b||_1) / ||b*||_1 (relative mass bias) of the estimate beta_est (device
+   FP64 [n]) against the true field beta_true (device FP32 [n]); errors is a
+   device FP64 [2].  Sums in a fixed order.  Async. */
+int prt_volume_errors(prt_ctx ctx, int64_t n, const double* beta_est, const float* beta_true, double* errors);
+
 /* ----------------------------------------------------------- telemetry */
 
 /* Read (and optionally reset) the work counters.  Synchronises. */

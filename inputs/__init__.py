@@ -98,6 +98,16 @@ def cameras_at(positions_km, targets_km, width: int, height: int, f_px: float) -
     return Cameras(n, width, height, np.array(pos), np.array(rot), np.full(n, float(f_px)))
 
 
+def coarse_cameras(cams: Cameras, factor: int) -> Cameras:
+    """The same pinhole cameras with images `factor` times smaller per side
+    (focal length and image sides divided by `factor`), so that coarse pixel
+    (r, c) covers fine pixels factor*r .. factor*r + factor - 1 (same for c)."""
+    if cams.width % factor or cams.height % factor:
+        raise ValueError("image sides must be multiples of the factor")
+    return Cameras(cams.n, cams.width // factor, cams.height // factor, cams.pos, cams.rot,
+                   np.asarray(cams.f_px, np.float64) / factor)
+
+
 # ------------------------------------------------------------ fields
 
 def _centre_dist(nx, ny, nz):

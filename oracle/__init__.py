@@ -333,6 +333,34 @@ def loss_and_residual(images, target):
     return 0.5 * float((res * res).sum()), res
 
 
+def downsample_images(cams, images, factor: int) -> np.ndarray:
+    """Measurements at a coarser resolution (Sec. 6.1, coarse to fine): with
+    images as pixel-averaged radiance (tally / Omega_p), coarse pixel P, the
+    union of factor x factor fine pixels p, holds the average of the radiance
+    over its solid angle, sum_p Omega_p I_p / sum_p Omega_p.  Cameras keep
+    their pinhole; the coarse camera has focal length f / factor."""
+    img = np.asarray(images, np.float64)
+    n, H, W = img.shape
+    k = int(factor)
+    out = np.zeros((n, H // k, W // k))
+    for d in range(n):
+        om = pixel_solid_angles(float(cams.f_px[d]), W, H)
+        num = (om * img[d]).reshape(H // k, k, W // k, k).sum(axis=(1, 3))
+        den = om.reshape(H // k, k, W // k, k).sum(axis=(1, 3))
+        out[d] = num / den
+    return out
+
+
+def volume_errors(beta_est, beta_true):
+    """Reconstruction errors of Sec. 6: relative L1 distance
+    epsilon = ||b* - b||_1 / ||b*||_1 and relative mass bias
+    delta = (||b*||_1 - ||b||_1) / ||b*||_1 (b* the true field)."""
+    b = np.asarray(beta_est, np.float64).ravel()
+    t = np.asarray(beta_true, np.float64).ravel()
+    nt = np.abs(t).sum()
+    return float(np.abs(t - b).sum() / nt), float((nt - np.abs(b).sum()) / nt)
+
+
 def adam_step(beta, grad_, m, v, t: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
     """One Adam step (Kingma & Ba, Alg. 1), then projection onto beta >= 0.
     Returns new (beta, m, v); arrays are FP64."""

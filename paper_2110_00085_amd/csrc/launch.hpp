@@ -306,6 +306,14 @@ struct CarveThresholds {
 // below its threshold; beta[v] (when given) = fill where kept, else 0.
 hipError_t launch_space_carve(hipStream_t st, int nx, int ny, int nz, double vk, const DevCams& c,
                               const CarveThresholds& t, const double* img, float fill, uint8_t* mask, float* beta);
+// coarse[d][R][C] = solid-angle-weighted mean of fine pixels
+// (factor R + i, factor C + j), i, j < factor; c describes the fine cameras.
+hipError_t launch_downsample(hipStream_t st, const DevCams& c, int factor, const double* fine, double* coarse);
+// out[0] = epsilon, out[1] = delta of the estimate against the true field;
+// partial holds 3 * volume_error_blocks(n) doubles.
+int64_t volume_error_blocks(int64_t n);
+hipError_t launch_volume_errors(hipStream_t st, int64_t n, const double* est, const float* truth, double* partial,
+                                double* out);
 hipError_t launch_adam(hipStream_t st, int64_t n, double* beta, float* beta_f32, const double* grad, double* m,
                        double* v, double lr, double b1, double b2, double eps, double bc1, double bc2);
 

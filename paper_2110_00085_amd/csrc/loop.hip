@@ -184,6 +184,114 @@ __global__ void __launch_bounds__(256) space_carve_kernel(int nx, int ny, int nz
     if (beta) beta[v] = keep ? fill : 0.f;
 }
 
+// Down-sampling of pixel-averaged images by `factor` per side: coarse pixel
+// (R, C) of camera d gets sum_p Omega_p I_p / sum_p Omega_p over the fine
+// pixels p = (factor R + i, factor C + j), Omega_p the fine pixels' exact
+// solid angles (focal length f of the fine camera).  One thread per coarse
+// pixel.
+__device__ __forceinline__ double solid_angle_px(double f, int W, int H, int row, int col)
+{
+    auto F = [f](double x, double y) { return atan(x * y / (f * sqrt(x * x + y * y + f * f))); };
+    const double x1 = col - 0.5 * W, x2 = x1 + 1.0, y1 = row - 0.5 * H, y2 = y1 + 1.0;
+    return F(x2, y2) - F(x1, y2) - F(x2, y1) + F(x1, y1);
+}
+
+__global__ void __launch_bounds__(256) downsample_kernel(DevCams c, int factor, const double* __restrict__ fine,
+                                                         double* __restrict__ coarse)
+{
+    const int Wc = c.W / factor, Hc = c.H / factor;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)c.n * Wc * Hc) return;
+    const int d = (int)(i / ((int64_t)Wc * Hc));
+    const int rem = (int)(i % ((int64_t)Wc * Hc));
+    const int R = rem / Wc, Cc = rem % Wc;
+    double num = 0.0, den = 0.0;
+    for (int a = 0; a < factor; ++a)
+        for (int b = 0; b < factor; ++b) {
+            const int row = R * factor + a, col = Cc * factor + b;
+            const double om = solid_angle_px(c.f[d], c.W, c.H, row, col);
+            num += om * fine[((int64_t)d * c.H + row) * c.W + col];
+            den += om;
+        }
+    coarse[i] = num / den;
+}
+
+hipError_t launch_downsample(hipStream_t st, const DevCams& c, int factor, const double* fine, double* coarse)
+{
+    const int64_t n = (int64_t)c.n * (c.W / factor) * (c.H / factor);
+    if (n <= 0) return hipSuccess;
+    downsample_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(c, factor, fine, coarse);
+    return hipGetLastError();
+}
+
+// Sec. 6 error measures: per-block sums of |t - b|, |t| and |b| (t the true
+// field, b the estimate), then one block adds them in a fixed order and
+// writes epsilon = sum|t - b| / sum|t| and delta = (sum|t| - sum|b|) / sum|t|.
+constexpr int kErrItems = 4096;
+
+__global__ void __launch_bounds__(256) volume_error_sums_kernel(int64_t n, const double* __restrict__ est,
+                                                                const float* __restrict__ truth,
+                                                                double* __restrict__ partial)
+{
+    __shared__ double red[3][256];
+    const int64_t base = (int64_t)blockIdx.x * kErrItems;
+    double a = 0.0, t = 0.0, b = 0.0;
+    for (int j = threadIdx.x; j < kErrItems; j += blockDim.x) {
+        const int64_t i = base + j;
+        if (i < n) {
+            const double x = est[i], y = (double)truth[i];
+            a += fabs(y - x);
+            t += fabs(y);
+            b += fabs(x);
+        }
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = t;
+    red[2][threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) partial[3 * blockIdx.x + k] = red[k][0];
+}
+
+__global__ void __launch_bounds__(256) volume_errors_kernel(const double* __restrict__ partial, int64_t nb,
+                                                            double* __restrict__ out)
+{
+    __shared__ double red[3][256];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < nb; i += blockDim.x)
+        for (int k = 0; k < 3; ++k) s[k] += partial[3 * i + k];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double a = red[0][0], t = red[1][0], b = red[2][0];
+        out[0] = a / t;
+        out[1] = (t - b) / t;
+    }
+}
+
+int64_t volume_error_blocks(int64_t n) { return (n + kErrItems - 1) / kErrItems; }
+
+hipError_t launch_volume_errors(hipStream_t st, int64_t n, const double* est, const float* truth, double* partial,
+                                double* out)
+{
+    const int64_t nb = volume_error_blocks(n);
+    volume_error_sums_kernel<<<dim3((unsigned)nb), dim3(256), 0, st>>>(n, est, truth, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    volume_errors_kernel<<<dim3(1), dim3(256), 0, st>>>(partial, nb, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_space_carve(hipStream_t st, int nx, int ny, int nz, double vk, const DevCams& c,
                               const CarveThresholds& t, const double* img, float fill, uint8_t* mask, float* beta)
 {

@@ -1409,6 +1409,39 @@ int prt_adam(prt_ctx c, int64_t n, double* beta, float* beta_f32, const double* 
     return PRT_OK;
 }
 
+int prt_downsample_images(prt_ctx c, const prt_cameras* cams, const double* images, int32_t factor, double* coarse)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    if (!images || !coarse) return fail(PRT_E_INVALID, "images/coarse is NULL");
+    if (factor < 1) return fail(PRT_E_INVALID, "factor must be >= 1");
+    if (!cams || cams->n < 1 || cams->n > kMaxCams || cams->width < 1 || cams->height < 1 || !cams->f_px)
+        return fail(PRT_E_INVALID, "bad cameras");
+    if (cams->width % factor || cams->height % factor)
+        return fail(PRT_E_INVALID, "image sides %dx%d are not multiples of %d", cams->width, cams->height, factor);
+    DevCams dc{};
+    dc.n = cams->n;
+    dc.W = cams->width;
+    dc.H = cams->height;
+    for (int d = 0; d < dc.n; ++d) {
+        if (!std::isfinite(cams->f_px[d]) || !(cams->f_px[d] > 0)) return fail(PRT_E_INVALID, "bad focal length");
+        dc.f[d] = cams->f_px[d];
+    }
+    DeviceGuard g(c->device);
+    HIPCHK(launch_downsample(c->stream, dc, factor, images, coarse));
+    return PRT_OK;
+}
+
+int prt_volume_errors(prt_ctx c, int64_t n, const double* beta_est, const float* beta_true, double* errors)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    if (n < 1 || !beta_est || !beta_true || !errors) return fail(PRT_E_INVALID, "bad volume-error arguments");
+    DeviceGuard g(c->device);
+    int rc = ensure_part(c, 3 * volume_error_blocks(n));
+    if (rc) return rc;
+    HIPCHK(launch_volume_errors(c->stream, n, beta_est, beta_true, c->part, errors));
+    return PRT_OK;
+}
+
 int prt_space_carve(prt_ctx c, const prt_scene* s, const prt_cameras* cams, const double* images,
                     const double* threshold, double fill_value, uint8_t* mask, float* beta_out)
 {

@@ -84,6 +84,8 @@ def lib():
             "prt_loss": ([_V, _I64, _V, _V, _V, _V], C.c_int),
             "prt_reweight_noalloc": ([_V, C.POINTER(prt_scene), _V, _V], C.c_int),
             "prt_adam": ([_V, _I64, _V, _V, _V, _V, _V, _I32, _D, _D, _D, _D], C.c_int),
+            "prt_downsample_images": ([_V, C.POINTER(prt_cameras), _V, _I32, _V], C.c_int),
+            "prt_volume_errors": ([_V, _I64, _V, _V, _V], C.c_int),
             "prt_space_carve": ([_V, C.POINTER(prt_scene), C.POINTER(prt_cameras), _V, _V, _D, _V, _V], C.c_int),
             "prt_counters": ([_V, C.POINTER(prt_counters_t), C.c_int], C.c_int),
             "prt_enable_timing": ([_V, C.c_int], C.c_int),
@@ -263,6 +265,17 @@ def prt_adam(ctx, beta, beta_f32, grad, m, v, t: int, lr: float, b1: float = 0.9
              eps: float = 1e-8):
     _check(lib().prt_adam(ctx, beta.numel(), _dptr(beta), _dptr(beta_f32), _dptr(grad), _dptr(m), _dptr(v),
                           int(t), lr, b1, b2, eps))
+
+
+def prt_downsample_images(ctx, cams: CamerasHost, images, factor: int, coarse):
+    _check(lib().prt_downsample_images(ctx, C.byref(cams.s), _dptr(images), int(factor), _dptr(coarse)))
+
+
+def prt_volume_errors(ctx, beta_est, beta_true, errors):
+    """errors: device float64 tensor of 2, set to (epsilon, delta)."""
+    if beta_est.numel() != beta_true.numel():
+        raise ValueError("fields differ in size")
+    _check(lib().prt_volume_errors(ctx, beta_est.numel(), _dptr(beta_est), _dptr(beta_true), _dptr(errors)))
 
 
 def prt_space_carve(ctx, scene: prt_scene, cams: CamerasHost, images, threshold, fill_value: float, mask,
