@@ -305,6 +305,148 @@ __device__ __forceinline__ Real dda_walk_counted(int nx, int ny, int nz, Real px
                                      pieces, f);
 }
 
+// Sum of value(voxel) * length over the pieces of the walk of
+// dda_walk_counted, t in [0, tmax] (unbounded without kBounded), with U
+// pieces formed before their U values are fetched: a lane then has U loads
+// in flight, which hides the latency of a grid in global memory.  The pieces
+// and the order of the additions are those of the plain walk (a step past the
+// end of the walk repeats the last voxel with length 0 and adds nothing), so
+// the sum equals the plain walk's bit for bit; pieces are counted as there.
+template <int U, typename Real, bool kBounded, typename G>
+__device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy, int iz,
+                                        Real wx, Real wy, Real wz, Real tmax, uint32_t& pieces, G&& value)
+{
+    int sx, sy, sz;
+    Real ivx, ivy, ivz;
+    if (!dda_dir(wx, wy, wz, sx, sy, sz, ivx, ivy, ivz)) return (Real)0;
+    constexpr int kGuard = (1 << 9) | (1 << 19) | (1 << 29);
+    Real t = (Real)0;
+    Real tnx = dda_first_face(sx, ix, px, ivx, t), tny = dda_first_face(sy, iy, py, ivy, t),
+         tnz = dda_first_face(sz, iz, pz, ivz, t);
+    const Real dtx = (Real)sx * ivx, dty = (Real)sy * ivy, dtz = (Real)sz * ivz;
+    const int rx = sx > 0 ? nx - 1 - ix : ix;
+    const int ry = sy > 0 ? ny - 1 - iy : iy;
+    const int rz = sz > 0 ? nz - 1 - iz : iz;
+    int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
+    const int dvx = sx, dvy = sy * nx, dvz = sz * nx * ny;
+    int v = ix + nx * (iy + ny * iz);
+    bool alive = true;
+    uint32_t n = 0;
+    Real acc = (Real)0;
+    for (;;) {
+        int vv[U];
+        Real ll[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const Real tn = fmin(tnx, fmin(tny, tnz));
+            const bool go = !kBounded || tn < tmax;
+            const Real te = kBounded ? (go ? tn : tmax) : tn;
+            vv[k] = v;
+            ll[k] = alive ? te - t : (Real)0;
+            n += alive ? 1u : 0u;
+            const bool bx = tnx == tn;
+            const bool by = !bx && tny == tn;
+            const bool bz = !bx && !by;
+            const int Rn = R - (bx ? 1 : (by ? 1 << 10 : 1 << 20));
+            const bool next = alive && (!kBounded || go) && (Rn & kGuard) == kGuard;
+            // the last piece's voxel stays: no step leaves the box
+            R = next ? Rn : R;
+            v = next ? v + (bx ? dvx : (by ? dvy : dvz)) : v;
+            t = next ? te : t;
+            tnx = next && bx ? tnx + dtx : tnx;
+            tny = next && by ? tny + dty : tny;
+            tnz = next && bz ? tnz + dtz : tnz;
+            alive = next;
+        }
+        Real bb[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) bb[k] = value((uint32_t)vv[k]);
+#pragma unroll
+        for (int k = 0; k < U; ++k) acc += bb[k] * ll[k];
+        if (!alive) break;
+    }
+    pieces += n;
+    return acc;
+}
+
+// The free flight of the sampler: the walk of dda_walk (unbounded, to the box
+// exit) accumulating value(voxel) * length until the optical depth tau is
+// passed, with U pieces formed before their U values are fetched (as
+// dda_sum).  Returns the voxel of the piece in which the accumulated depth
+// first exceeds tau (strictly: tau < acc + value * length), setting *acc to
+// the depth before that piece and *t0 to the piece's start, or -1 when the
+// ray leaves the box first, setting *t0 to the exit parameter.  The pieces,
+// the order of the additions and the comparisons are those of a dda_walk
+// functor doing the same, so both give the same result.
+template <int U, typename Real, typename G>
+__device__ __forceinline__ int dda_first_hit(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy, int iz,
+                                             Real wx, Real wy, Real wz, Real tau, G&& value, Real* acc_out,
+                                             Real* t0_out)
+{
+    int sx, sy, sz;
+    Real ivx, ivy, ivz;
+    *acc_out = (Real)0;
+    *t0_out = (Real)0;
+    if (!dda_dir(wx, wy, wz, sx, sy, sz, ivx, ivy, ivz)) return -1;
+    constexpr int kGuard = (1 << 9) | (1 << 19) | (1 << 29);
+    Real t = (Real)0;
+    Real tnx = dda_first_face(sx, ix, px, ivx, t), tny = dda_first_face(sy, iy, py, ivy, t),
+         tnz = dda_first_face(sz, iz, pz, ivz, t);
+    const Real dtx = (Real)sx * ivx, dty = (Real)sy * ivy, dtz = (Real)sz * ivz;
+    const int rx = sx > 0 ? nx - 1 - ix : ix;
+    const int ry = sy > 0 ? ny - 1 - iy : iy;
+    const int rz = sz > 0 ? nz - 1 - iz : iz;
+    int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
+    const int dvx = sx, dvy = sy * nx, dvz = sz * nx * ny;
+    int v = ix + nx * (iy + ny * iz);
+    bool alive = true;
+    Real acc = (Real)0;
+    for (;;) {
+        int vv[U];
+        Real ll[U], ts[U];
+        bool live[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const Real tn = fmin(tnx, fmin(tny, tnz));
+            vv[k] = v;
+            ts[k] = t;
+            ll[k] = tn - t;
+            live[k] = alive;
+            const bool bx = tnx == tn;
+            const bool by = !bx && tny == tn;
+            const bool bz = !bx && !by;
+            const int Rn = R - (bx ? 1 : (by ? 1 << 10 : 1 << 20));
+            const bool next = alive && (Rn & kGuard) == kGuard;
+            // the exit parameter advances with the last piece; its voxel stays
+            t = alive ? tn : t;
+            R = next ? Rn : R;
+            v = next ? v + (bx ? dvx : (by ? dvy : dvz)) : v;
+            tnx = next && bx ? tnx + dtx : tnx;
+            tny = next && by ? tny + dty : tny;
+            tnz = next && bz ? tnz + dtz : tnz;
+            alive = next;
+        }
+        Real bb[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) bb[k] = value((uint32_t)vv[k]);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (!live[k]) break;
+            const Real dt = bb[k] * ll[k];
+            if (tau < acc + dt) {
+                *acc_out = acc;
+                *t0_out = ts[k];
+                return vv[k];
+            }
+            acc += dt;
+        }
+        if (!alive) break;
+    }
+    *acc_out = acc;
+    *t0_out = t;
+    return -1;
+}
+
 // The part of that walk inside the slab of z layers [z0, z1) (pieces counted
 // as in dda_walk_counted): the pieces
 // are those of the whole-grid walk that fall in the slab, with voxels

@@ -45,6 +45,7 @@ hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const 
 constexpr int kSampleBlock = 1024;
 constexpr size_t kSampleLds = 128 * 1024;
 constexpr int kSampleBlocksPerCU = 2;
+constexpr int kSampleLoads = 4;  // free-flight pieces formed before their grid loads (grid in global memory)
 
 // A uniform of (0,1) in the event precision, still below 1: in FP32 the
 // largest uniforms round to 1.0f, which would give a free flight of zero
@@ -161,20 +162,28 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
         if (!active) continue;
         // one event: the free flight to the next scatter or out of the box
         const Real taur = (Real)tau;
-        Real acc = (Real)0, thit = (Real)0;
+        Real acc = (Real)0, thit = (Real)0, tend = (Real)0;
         int hit = -1;
-        const Real tend = dda_walk<Real>(
-            s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy, iz, (Real)w[0], (Real)w[1], (Real)w[2],
-            [&](int vv, Real t0, Real l) {
-                const Real dt = gt[vv] * l;  // zero for an empty voxel or a zero-length piece
-                if (taur < acc + dt) {
-                    hit = vv;
-                    thit = t0;
-                    return false;
-                }
-                acc += dt;
-                return true;
-            });
+        if constexpr (kGridLds) {
+            tend = dda_walk<Real>(
+                s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy, iz, (Real)w[0], (Real)w[1], (Real)w[2],
+                [&](int vv, Real t0, Real l) {
+                    const Real dt = gt[vv] * l;  // zero for an empty voxel or a zero-length piece
+                    if (taur < acc + dt) {
+                        hit = vv;
+                        thit = t0;
+                        return false;
+                    }
+                    acc += dt;
+                    return true;
+                });
+        } else {
+            // the grid in global memory: kSampleLoads pieces per batch of loads
+            hit = dda_first_hit<kSampleLoads, Real>(s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy, iz,
+                                                    (Real)w[0], (Real)w[1], (Real)w[2], taur,
+                                                    [&](uint32_t vv) { return gt[vv]; }, &acc, &thit);
+            tend = thit;
+        }
         // the division that places the scatter inside its voxel stays out of the loop
         if (hit >= 0) thit += (taur - acc) / gt[hit];
         bool done;

@@ -30,6 +30,7 @@ constexpr size_t kLdsBudget = 128 * 1024;       // grids
 constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs when each slab recomputes the weights
 constexpr int64_t kMaxTapeGradSlabs = 64;       // LDS gradient slabs when the weights come from the tape
 constexpr size_t kTapeImageLds = 64 * 1024;     // FP64 image of one camera, images formed from the tape
+constexpr int kWalkLoads = 4;                   // pieces formed before their grid loads, grids in global memory
 
 // The field beta_t - beta_ref for a persistent workgroup: formed in LDS from
 // beta_t and beta_ref (kGridLds), else the one prepared in global memory.
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(kBlock) render_prefix_kernel(TraceArgs a, Vert
         double w[3];
         const double L = seg_dir(p0, p1, w);
         // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
-        const Real dt = walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, nseg);
+        const Real dt = walk_sum<Real, true, kGridLds ? 1 : kWalkLoads>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, nseg);
         double q = exp(-(double)dt * s.vk);
         if (b == 1) {
             q *= s.w0;
@@ -212,8 +213,9 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                     const float fst = wcb * hg + wab * ray_k * (1.f + muf * muf);
                     // with every camera outside the box the walk ends at the box
                     // boundary, before the camera, so it needs no length bound
-                    const Real tc = cams.outside ? walk_sum<Real, false>(s, beta_tot, p1, u, d2 * id, nseg)
-                                                 : walk_sum<Real>(s, beta_tot, p1, u, d2 * id, nseg);
+                    const Real tc = cams.outside
+                                        ? walk_sum<Real, false, kGridLds ? 1 : kWalkLoads>(s, beta_tot, p1, u, d2 * id, nseg)
+                                        : walk_sum<Real, true, kGridLds ? 1 : kWalkLoads>(s, beta_tot, p1, u, d2 * id, nseg);
                     c = base * (double)(fst * expf(-(float)tc * vkf) * (float)(r2scale * id * id));
                 } else {
                     const double dist2 = ex * ex + ey * ey + ez * ez;
@@ -222,8 +224,9 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                     const double u[3] = {ex * id, ey * id, ez * id};
                     const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
                     const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
-                    const Real tc = cams.outside ? walk_sum<Real, false>(s, beta_tot, p1, u, dist, nseg)
-                                                 : walk_sum<Real>(s, beta_tot, p1, u, dist, nseg);
+                    const Real tc = cams.outside
+                                        ? walk_sum<Real, false, kGridLds ? 1 : kWalkLoads>(s, beta_tot, p1, u, dist, nseg)
+                                        : walk_sum<Real, true, kGridLds ? 1 : kWalkLoads>(s, beta_tot, p1, u, dist, nseg);
                     c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
                 }
                 if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = make_float2((float)c, __int_as_float(pix));
@@ -1214,7 +1217,7 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
             const Vtx p1 = load_vtx(V, b);
             double w[3];
             const double L = seg_dir(p0, p1, w);
-            const Real dt = walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, novh);
+            const Real dt = walk_sum<Real, true, kWalkLoads>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, novh);
             P *= exp(-(double)dt * s.vk);
             if (b >= 2) {
                 const int v = clamp_vox(p0.v, nu);
@@ -1238,7 +1241,7 @@ __global__ void __launch_bounds__(kBlock) grad_kernel(TraceArgs a, DevCams cams,
                 const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
                 const double hg = phase_hg(s, mu);
                 const double fst = fs_mix(s, bct, hg, phase_rayleigh(mu));
-                const Real tc = walk_sum<Real>(s, [&](uint32_t v) { return gtot[v]; }, p1, u, dist, cseg);
+                const Real tc = walk_sum<Real, true, kWalkLoads>(s, [&](uint32_t v) { return gtot[v]; }, p1, u, dist, cseg);
                 const double c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
                 const double wgt = c * rho;
                 Rb += wgt;
@@ -1459,7 +1462,7 @@ __global__ void __launch_bounds__(kBlock) reweight_kernel(TraceArgs a)
             const Vtx p1 = load_vtx(V, k + 1);
             double w[3];
             const double L = seg_dir(p0, p1, w);
-            lr -= (double)walk_sum<Real>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, cnt) * s.vk;
+            lr -= (double)walk_sum<Real, true, kGridLds ? 1 : kWalkLoads>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, cnt) * s.vk;
             if (k >= 1) {
                 // scatter k (it has the successor k+1): extinction ratio and
                 // direction-pdf ratio f_s,t bs_ref / (f_s,ref bs_t)

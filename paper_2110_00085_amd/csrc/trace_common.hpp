@@ -36,13 +36,22 @@ __device__ __forceinline__ double seg_dir(const Vtx& a, const Vtx& b, double w[3
 __device__ __forceinline__ int clamp_vox(int v, int nu) { return min(max(v, 0), nu - 1); }
 
 // Sum of beta(v) * length over the walk from vertex p (voxel p.v) along w
-// for length tmax (grid units); adds the number of pieces to count.
-template <typename Real, bool kBounded = true, typename G>
+// for length tmax (grid units); adds the number of pieces to count.  With
+// U > 1 the walk forms U pieces before fetching their values (for grids in
+// global memory; same sum).
+template <typename Real, bool kBounded = true, int U = 1, typename G>
 __device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx& p, const double w[3], double tmax,
                                          uint64_t& count)
 {
     int ix, iy, iz;
     voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
+    if constexpr (U > 1) {
+        uint32_t n = 0;
+        const Real acc = dda_sum<U, Real, kBounded>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz,
+                                                    (Real)w[0], (Real)w[1], (Real)w[2], (Real)tmax, n, beta);
+        count += n;
+        return acc;
+    }
     Real acc = (Real)0;
     uint32_t n = 0;
     dda_walk_counted<Real, kBounded>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
