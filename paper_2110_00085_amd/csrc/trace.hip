@@ -31,6 +31,7 @@ constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs when each 
 constexpr int64_t kMaxTapeGradSlabs = 64;       // LDS gradient slabs when the weights come from the tape
 constexpr size_t kTapeImageLds = 64 * 1024;     // FP64 image of one camera, images formed from the tape
 constexpr int kWalkLoads = 4;                   // pieces formed before their grid loads, grids in global memory
+constexpr int kRenderWalkLoads = 8;             // the same for the render's connection walks
 
 // The field beta_t - beta_ref for a persistent workgroup: formed in LDS from
 // beta_t and beta_ref (kGridLds), else the one prepared in global memory.
@@ -214,8 +215,8 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                     // with every camera outside the box the walk ends at the box
                     // boundary, before the camera, so it needs no length bound
                     const Real tc = cams.outside
-                                        ? walk_sum<Real, false, kGridLds ? 1 : kWalkLoads>(s, beta_tot, p1, u, d2 * id, nseg)
-                                        : walk_sum<Real, true, kGridLds ? 1 : kWalkLoads>(s, beta_tot, p1, u, d2 * id, nseg);
+                                        ? walk_sum<Real, false, kGridLds ? 1 : kRenderWalkLoads>(s, beta_tot, p1, u, d2 * id, nseg)
+                                        : walk_sum<Real, true, kGridLds ? 1 : kRenderWalkLoads>(s, beta_tot, p1, u, d2 * id, nseg);
                     c = base * (double)(fst * expf(-(float)tc * vkf) * (float)(r2scale * id * id));
                 } else {
                     const double dist2 = ex * ex + ey * ey + ez * ez;
@@ -225,8 +226,8 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                     const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
                     const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
                     const Real tc = cams.outside
-                                        ? walk_sum<Real, false, kGridLds ? 1 : kWalkLoads>(s, beta_tot, p1, u, dist, nseg)
-                                        : walk_sum<Real, true, kGridLds ? 1 : kWalkLoads>(s, beta_tot, p1, u, dist, nseg);
+                                        ? walk_sum<Real, false, kGridLds ? 1 : kRenderWalkLoads>(s, beta_tot, p1, u, dist, nseg)
+                                        : walk_sum<Real, true, kGridLds ? 1 : kRenderWalkLoads>(s, beta_tot, p1, u, dist, nseg);
                     c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
                 }
                 if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = make_float2((float)c, __int_as_float(pix));
