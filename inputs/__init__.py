@@ -12,6 +12,11 @@ with the paper's shapes (Sec. 6.1, Table scene_settings):
 - ``field128``   128x128x64 grid, 20 m voxels, ten log-normal ellipsoid blobs
                  (stands in for the LES cloud field, 79x84x27).
 
+- ``smallpaint``  reflectometry box (Sec. 6.2): a unit box, one large sphere
+                 with the unknown Phong BRDF, 14 small diffuse spheres, a
+                 point light and one 60x60 camera (stands in for the
+                 Smallpaint scene).
+
 Air: constant 0.01 1/km, albedo 1, Rayleigh.  Sun at 30 deg zenith, F0 = 1.
 Cameras sit on an arc in the x-z plane, look at the box centre with +y up, at
 distance 2.5 x the box's bounding radius, field of view 2 asin(1/2.5).
@@ -200,6 +205,86 @@ def target_images(shape, mean_value: float, seed: int = 11) -> np.ndarray:
     """Random target images I_gt = U(0,1) * 2 * mean_value."""
     rng = np.random.default_rng(seed)
     return rng.uniform(0.0, 1.0, shape) * 2.0 * mean_value
+
+
+# ------------------------------------------------------------ reflectometry
+
+@dataclass
+class SurfaceScene:
+    """Closed box [0, box]^3 with diffuse walls and spheres; sphere `phong`
+    carries the unknown BRDF.  Walls in the order x=0, x=box, y=0, y=box, z=0,
+    z=box.  An isotropic point light of radiant intensity `intensity` sits at
+    `light`.  Paths keep at most `max_order` surface vertices."""
+    box: float
+    wall_albedo: np.ndarray     # [6]
+    light: np.ndarray           # [3]
+    intensity: float
+    centers: np.ndarray         # [n][3]
+    radii: np.ndarray           # [n]
+    albedo: np.ndarray          # [n] (the Phong sphere's entry is unused)
+    phong: int
+    max_order: int = 10
+
+    @property
+    def n_spheres(self) -> int:
+        return int(len(self.radii))
+
+
+def smallpaint(seed: int = 7, max_order: int = 10) -> SurfaceScene:
+    """Stand-in for the Smallpaint box of the reflectometry test: a unit box,
+    a large sphere of radius 0.2 at its centre (the unknown BRDF) and 14 small
+    diffuse spheres (radius 0.04-0.07, albedo 0.4-0.9) placed at seeded random
+    positions that keep clear of each other, the walls, the light, and the
+    lines from the camera and from the light to the large sphere; the light
+    hangs under the ceiling."""
+    rng = np.random.default_rng(seed)
+    centre = np.array([0.5, 0.42, 0.6])
+    light = np.array([0.5, 0.92, 0.45])
+    cam = np.array([0.5, 0.5, 0.03])
+    centers, radii = [centre], [0.2]
+
+    def seg_dist(c, a, b):
+        t = np.clip(np.dot(c - a, b - a) / np.dot(b - a, b - a), 0.0, 1.0)
+        return np.linalg.norm(c - (a + t * (b - a)))
+
+    while len(radii) < 15:
+        r = rng.uniform(0.04, 0.07)
+        c = rng.uniform(r + 0.02, 1.0 - r - 0.02, 3)
+        c[2] = max(c[2], 0.2)
+        if all(np.linalg.norm(c - c2) > r + r2 + 0.02 for c2, r2 in zip(centers, radii)) and \
+                seg_dist(c, cam, centre) > r + 0.2 and seg_dist(c, light, centre) > r + 0.2 and \
+                np.linalg.norm(c - light) > r + 0.05:
+            centers.append(c)
+            radii.append(r)
+    albedo = np.concatenate([[0.0], rng.uniform(0.4, 0.9, 14)])
+    return SurfaceScene(1.0, np.array([0.75, 0.75, 0.8, 0.8, 0.6, 0.8]), light, 1.0, np.array(centers),
+                        np.array(radii), albedo, 0, max_order)
+
+
+def smallpaint_camera(scene: SurfaceScene, width: int = 60) -> Cameras:
+    """One pinhole camera inside the box near the front wall, looking at the
+    large sphere, 60 degree field of view."""
+    f_px = 0.5 * width / np.tan(np.deg2rad(30.0))
+    return cameras_at([[0.5, 0.5, 0.03]], [[0.5, 0.42, 0.6]], width, width, f_px)
+
+
+def surface_box(spheres=(), phong: int = -1, wall_albedo=0.7, light=(0.5, 0.85, 0.5), max_order: int = 10,
+                intensity: float = 1.0) -> SurfaceScene:
+    """Unit box with the given spheres [(centre, radius, albedo), ...];
+    `phong` names the sphere with the unknown BRDF (-1: none)."""
+    c = np.array([s[0] for s in spheres], np.float64).reshape(-1, 3)
+    r = np.array([s[1] for s in spheres], np.float64)
+    a = np.array([s[2] for s in spheres], np.float64)
+    wa = np.full(6, wall_albedo, np.float64) if np.isscalar(wall_albedo) else np.asarray(wall_albedo, np.float64)
+    return SurfaceScene(1.0, wa, np.asarray(light, np.float64), intensity, c, r, a, phong, max_order)
+
+
+# reflectometry workload registry: name -> (scene factory, camera factory,
+# paths, seed, true (kappa_s, gamma)); Sec. 6.2: one 60x60 camera, 1.8e6
+# paths, truth kappa_s = 0.7, gamma = 50
+SURFACE_WORKLOADS = {
+    "smallpaint60": (smallpaint, smallpaint_camera, 1_800_000, 2001, (0.7, 50.0)),
+}
 
 
 # workload registry: name -> (scene factory, camera factory, paths, seed)

@@ -4,8 +4,10 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product path (the HIP library and
 its Python binding) never imports, links or runs anything here.
 
-The numerics live in ``prt_oracle.c`` (plain C, FP64, OpenMP over paths with
-thread-private tallies reduced in a fixed order); this module only builds it
+The numerics live in ``prt_oracle.c`` and, for the reflectometry workload,
+``surface_oracle.c`` (plain C, FP64, OpenMP over paths with thread-private
+tallies reduced in a fixed order; Python wrappers of the latter in
+``oracle.surface``); this module only builds them
 with gcc, declares the ctypes signatures and converts numpy arrays.  Each C
 function cites the passage of the paper it follows.  Loss and Adam (plain
 definitions, Eq. appearance_loss and Kingma & Ba's update) are written in numpy
@@ -22,6 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "prt_oracle.c")
+_SRC_SURFACE = os.path.join(_HERE, "surface_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libprt_oracle.so")
 _lib = None
 
@@ -31,7 +34,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, _SRC, _SRC_SURFACE, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
