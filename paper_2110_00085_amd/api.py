@@ -14,7 +14,7 @@ import torch
 
 from . import prt as P
 
-_live_stores: "weakref.WeakSet[PathStore]" = weakref.WeakSet()
+_live_stores: "weakref.WeakSet" = weakref.WeakSet()
 _live_contexts: "weakref.WeakSet[Context]" = weakref.WeakSet()
 
 
@@ -79,6 +79,69 @@ class PathStore:
     def close(self):
         if self.handle is not None:
             P.prt_paths_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SurfacePaths:
+    """Owning handle of a reflectometry path store (include/prt_surface.h):
+    paths drawn at theta_ref in a box of spheres, with their tape for the
+    cameras they were drawn for."""
+
+    def __init__(self, ctx: Context, handle, scene, cams):
+        self.ctx = ctx
+        self.handle = handle
+        self.scene = P.SurfaceSceneHost(scene)
+        self.cams = P.CamerasHost(cams) if not isinstance(cams, P.CamerasHost) else cams
+        _live_stores.add(self)
+
+    @classmethod
+    def sample(cls, ctx: Context, scene, cams, theta_ref, seed: int, n_paths: int) -> "SurfacePaths":
+        sh, ch = P.SurfaceSceneHost(scene), P.CamerasHost(cams)
+        return cls(ctx, P.prt_surface_sample(ctx.handle, sh, ch, theta_ref, seed, n_paths), scene, ch)
+
+    @classmethod
+    def from_host(cls, ctx: Context, scene, cams, theta_ref, B, pos, sid) -> "SurfacePaths":
+        sh, ch = P.SurfaceSceneHost(scene), P.CamerasHost(cams)
+        return cls(ctx, P.prt_surface_import(ctx.handle, sh, ch, theta_ref, B, pos, sid), scene, ch)
+
+    def resample(self, theta_ref, seed: int, n_paths: int) -> "SurfacePaths":
+        P.prt_surface_resample(self.ctx.handle, self.handle, self.scene, self.cams, theta_ref, seed, n_paths)
+        return self
+
+    @property
+    def n(self) -> int:
+        return P.prt_surface_info(self.handle)[0]
+
+    def export(self):
+        return P.prt_surface_export(self.ctx.handle, self.handle)
+
+    def render(self, theta, images=None):
+        if images is None:
+            images = torch.empty(self.cams.image_shape, dtype=torch.float64, device=theta.device)
+        P.prt_surface_render(self.ctx.handle, self.handle, theta, images)
+        return images
+
+    def grad(self, theta, residual, out=None):
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=theta.device)
+        P.prt_surface_grad(self.ctx.handle, self.handle, theta, residual.contiguous(), out)
+        return out
+
+    def reweight(self, theta, out=None):
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=theta.device)
+        P.prt_surface_reweight(self.ctx.handle, self.handle, theta, out)
+        return out
+
+    def close(self):
+        if self.handle is not None:
+            P.prt_surface_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libprt.so")
 ARCH = os.environ.get("PRT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["sample.hip", "trace.hip", "ablation.hip", "loop.hip", "prt_api.cpp"]
+SOURCES = ["sample.hip", "trace.hip", "ablation.hip", "loop.hip", "surface.hip", "prt_api.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-x", "hip",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]

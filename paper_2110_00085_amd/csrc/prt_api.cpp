@@ -11,7 +11,9 @@
 #include <vector>
 
 #include "../../include/prt.h"
+#include "../../include/prt_surface.h"
 #include "launch.hpp"
+#include "surface.hpp"
 
 using namespace prt;
 
@@ -39,13 +41,15 @@ int fail(int code, const char* fmt, ...)
 enum KernelId {
     K_SAMPLE = 0, K_SORT, K_PACK, K_PREP, K_RENDER, K_FINALIZE, K_GRAD, K_REWEIGHT, K_LOSS, K_ADAM,
     K_RENDER_REDUCE, K_GRAD_REDUCE, K_GRAD_WEIGHTS, K_RENDER_PREFIX, K_GRAD_BIN, K_GRAD_RECOMPUTE, K_TPP_LAYOUT,
-    K_TPP_RENDER, K_TPP_GRAD, K_COUNT
+    K_TPP_RENDER, K_TPP_GRAD, K_SURF_SAMPLE, K_SURF_TAPE, K_SURF_RENDER, K_SURF_GRAD, K_SURF_REWEIGHT,
+    K_SURF_ADAM, K_COUNT
 };
 const char* kKernelNames[K_COUNT] = {"sample", "sort",          "pack",        "prep",         "render",
                                      "render_finalize", "grad",  "reweight",    "loss",         "adam",
                                      "render_reduce",   "grad_reduce", "grad_weights", "render_prefix",
                                      "grad_bin",        "grad_recompute", "tpp_layout",   "tpp_render",
-                                     "tpp_grad"};
+                                     "tpp_grad",        "surf_sample", "surf_tape",    "surf_render",
+                                     "surf_grad",       "surf_reweight", "surf_adam"};
 
 struct Timed {
     int id;
@@ -159,6 +163,26 @@ struct prt_paths_s {
         int64_t cap_rec = 0, cap_n = 0;
         bool valid = false;
     } tpp[2];
+};
+
+// Reflectometry store: paths as rows per vertex order, their tape, the
+// scene (spheres on the device), the cameras and theta_ref.
+struct prt_surface_paths_s {
+    int device = 0;
+    int64_t n = 0, cap = 0;          // paths, paths the buffers hold
+    int M = 0, n_cams = 0, cap_cams = 0;
+    int32_t* B = nullptr;
+    double4* pos = nullptr;
+    int32_t* sid = nullptr;
+    double2* tv = nullptr;
+    double2* tc = nullptr;
+    int32_t* pix = nullptr;
+    double* theta_ref = nullptr;     // device [2]
+    double* sph = nullptr;           // device [kMaxSpheres][5]
+    double* part = nullptr;          // render partial images / gradient and reweight pairs
+    size_t part_n = 0;
+    SurfScene scene{};
+    DevCams cams{};
 };
 
 namespace {
@@ -1524,5 +1548,389 @@ int prt_kernel_times(prt_ctx c, double* total_ms, int64_t* launches, int n, int 
 }
 
 const char* prt_kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "unknown"; }
+
+}  // extern "C"
+
+// ------------------------------------------------------ reflectometry
+
+namespace {
+
+bool inside_box(const double* x, double L) { return x[0] > 0 && x[0] < L && x[1] > 0 && x[1] < L && x[2] > 0 && x[2] < L; }
+
+bool outside_spheres(const prt_surface_scene* s, const double* x)
+{
+    for (int k = 0; k < s->n_spheres; ++k) {
+        const double* c = s->center + 3 * k;
+        const double d2 = (x[0] - c[0]) * (x[0] - c[0]) + (x[1] - c[1]) * (x[1] - c[1]) + (x[2] - c[2]) * (x[2] - c[2]);
+        if (!(d2 > s->radius[k] * s->radius[k])) return false;
+    }
+    return true;
+}
+
+int check_surface_scene(const prt_surface_scene* s)
+{
+    if (!s) return fail(PRT_E_INVALID, "surface scene is NULL");
+    if (!(s->box > 0) || !std::isfinite(s->box)) return fail(PRT_E_INVALID, "box must be finite and > 0");
+    if (s->n_spheres < 0 || s->n_spheres > PRT_SURFACE_MAX_SPHERES)
+        return fail(PRT_E_CAPACITY, "sphere count %d outside [0, %d]", s->n_spheres, PRT_SURFACE_MAX_SPHERES);
+    if (s->phong < -1 || s->phong >= s->n_spheres) return fail(PRT_E_INVALID, "phong index %d out of range", s->phong);
+    if (s->max_order < 1 || s->max_order > PRT_MAX_ORDER)
+        return fail(PRT_E_CAPACITY, "max_order %d outside [1, %d]", s->max_order, PRT_MAX_ORDER);
+    for (int k = 0; k < 6; ++k)
+        if (!(s->wall_albedo[k] >= 0 && s->wall_albedo[k] <= 1)) return fail(PRT_E_INVALID, "wall albedo outside [0, 1]");
+    if (!(s->intensity > 0) || !std::isfinite(s->intensity)) return fail(PRT_E_INVALID, "intensity must be finite and > 0");
+    if (s->n_spheres > 0 && (!s->center || !s->radius || !s->albedo))
+        return fail(PRT_E_INVALID, "sphere arrays must be non-NULL");
+    for (int k = 0; k < s->n_spheres; ++k) {
+        const double* c = s->center + 3 * k;
+        const double r = s->radius[k];
+        if (!finite_all({c[0], c[1], c[2], r}) || !(r > 0)) return fail(PRT_E_INVALID, "sphere %d: bad centre/radius", k);
+        for (int a = 0; a < 3; ++a)
+            if (!(c[a] - r >= 0 && c[a] + r <= s->box)) return fail(PRT_E_INVALID, "sphere %d leaves the box", k);
+        if (!(s->albedo[k] >= 0 && s->albedo[k] <= 1)) return fail(PRT_E_INVALID, "sphere %d: albedo outside [0, 1]", k);
+    }
+    if (!finite_all({s->light[0], s->light[1], s->light[2]}) || !inside_box(s->light, s->box) ||
+        !outside_spheres(s, s->light))
+        return fail(PRT_E_INVALID, "the light must lie strictly inside the box and outside every sphere");
+    return PRT_OK;
+}
+
+int check_theta_ref(const double* t)
+{
+    if (!t) return fail(PRT_E_INVALID, "theta_ref is NULL");
+    if (!(t[0] >= 0 && t[0] < 1)) return fail(PRT_E_INVALID, "theta_ref kappa_s must lie in [0, 1)");
+    if (!(t[1] >= 0 && t[1] <= 1e4)) return fail(PRT_E_INVALID, "theta_ref gamma must lie in [0, 1e4]");
+    return PRT_OK;
+}
+
+int make_surface_cams(const prt_cameras* c, const prt_surface_scene* s, DevCams* out)
+{
+    if (!c) return fail(PRT_E_INVALID, "cameras is NULL");
+    if (c->n < 1 || c->n > PRT_MAX_CAMERAS) return fail(PRT_E_CAPACITY, "camera count %d outside [1, %d]", c->n, PRT_MAX_CAMERAS);
+    if (c->width < 1 || c->height < 1 || c->width > 16384 || c->height > 16384)
+        return fail(PRT_E_INVALID, "image size must be in [1, 16384]");
+    if (!c->pos || !c->rot || !c->f_px) return fail(PRT_E_INVALID, "camera arrays must be non-NULL");
+    std::memset(out, 0, sizeof *out);
+    out->n = c->n;
+    out->W = c->width;
+    out->H = c->height;
+    for (int d = 0; d < c->n; ++d) {
+        const double* q = c->pos + 3 * d;
+        if (!finite_all({q[0], q[1], q[2]}) || !inside_box(q, s->box) || !outside_spheres(s, q))
+            return fail(PRT_E_INVALID, "camera %d must lie strictly inside the box and outside every sphere", d);
+        for (int k = 0; k < 3; ++k) out->pos[d][k] = q[k];
+        for (int k = 0; k < 9; ++k) {
+            if (!std::isfinite(c->rot[9 * d + k])) return fail(PRT_E_INVALID, "non-finite camera rotation");
+            out->rot[d][k] = c->rot[9 * d + k];
+        }
+        if (!(c->f_px[d] > 0) || !std::isfinite(c->f_px[d])) return fail(PRT_E_INVALID, "focal length must be > 0");
+        out->f[d] = c->f_px[d];
+    }
+    return PRT_OK;
+}
+
+void free_surface(prt_surface_paths p)
+{
+    if (!p) return;
+    DeviceGuard g(p->device);
+    (void)hipDeviceSynchronize();
+    for (void* q : {(void*)p->B, (void*)p->pos, (void*)p->sid, (void*)p->tv, (void*)p->tc, (void*)p->pix,
+                    (void*)p->theta_ref, (void*)p->sph, (void*)p->part})
+        (void)hipFree(q);
+    delete p;
+}
+
+SurfStore view_of(prt_surface_paths p)
+{
+    SurfStore v{};
+    v.n = p->n;
+    v.B = p->B;
+    v.pos = p->pos;
+    v.sid = p->sid;
+    v.tv = p->tv;
+    v.tc = p->tc;
+    v.pix = p->pix;
+    v.theta_ref = p->theta_ref;
+    return v;
+}
+
+// Buffers for n paths of the scene's order and the cameras (reused when
+// large enough), the scene's spheres and theta_ref (host) on the device.
+int surface_prepare(prt_ctx c, prt_surface_paths p, const prt_surface_scene* s, const DevCams& dc,
+                    const double* theta_ref, int64_t n)
+{
+    const int M = s->max_order;
+    // earlier calls on the stream may still read the buffers and theta_ref
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (n > p->cap || M > p->M || dc.n > p->cap_cams || !p->B) {
+        for (void** q : {(void**)&p->B, (void**)&p->pos, (void**)&p->sid, (void**)&p->tv, (void**)&p->tc,
+                         (void**)&p->pix}) {
+            (void)hipFree(*q);
+            *q = nullptr;
+        }
+        const int64_t cap = std::max<int64_t>(n, p->cap);
+        const int Mc = std::max(M, p->M), nc = std::max(dc.n, p->cap_cams);
+        const size_t rows = (size_t)Mc * (size_t)cap, crows = rows * (size_t)nc;
+        int rc;
+        if ((rc = dalloc(&p->B, (size_t)cap)) || (rc = dalloc(&p->pos, rows)) || (rc = dalloc(&p->sid, rows)) ||
+            (rc = dalloc(&p->tv, rows)) || (rc = dalloc(&p->tc, crows)) || (rc = dalloc(&p->pix, crows))) {
+            p->cap = 0;
+            return rc;
+        }
+        p->cap = cap;
+        p->M = Mc;
+        p->cap_cams = nc;
+    }
+    int rc;
+    if (!p->theta_ref && (rc = dalloc(&p->theta_ref, 2))) return rc;
+    if (!p->sph && (rc = dalloc(&p->sph, (size_t)5 * kMaxSpheres))) return rc;
+    double h[5 * kMaxSpheres];
+    for (int k = 0; k < s->n_spheres; ++k) {
+        for (int a = 0; a < 3; ++a) h[5 * k + a] = s->center[3 * k + a];
+        h[5 * k + 3] = s->radius[k];
+        h[5 * k + 4] = s->albedo[k];
+    }
+    // (synchronous copies of host arrays that the caller may free on return)
+    HIPCHK(hipMemcpy(p->theta_ref, theta_ref, 2 * sizeof(double), hipMemcpyHostToDevice));
+    if (s->n_spheres > 0) HIPCHK(hipMemcpy(p->sph, h, (size_t)5 * s->n_spheres * sizeof(double), hipMemcpyHostToDevice));
+    p->n = n;
+    p->M = M;
+    p->n_cams = dc.n;
+    p->cams = dc;
+    SurfScene& d = p->scene;
+    d.box = s->box;
+    for (int k = 0; k < 6; ++k) d.wall_albedo[k] = s->wall_albedo[k];
+    for (int k = 0; k < 3; ++k) d.light[k] = s->light[k];
+    d.intensity = s->intensity;
+    d.n_spheres = s->n_spheres;
+    d.phong = s->phong;
+    d.max_order = M;
+    d.sph = p->sph;
+    return PRT_OK;
+}
+
+// The rows of the store use M = the scene's max_order as stride: a store
+// whose buffers were sized for a larger order keeps M rows per order anyway.
+int surface_draw(prt_ctx c, prt_surface_paths p, uint64_t seed)
+{
+    {
+        TimedScope ts(c, K_SURF_SAMPLE);
+        HIPCHK(launch_surf_sample(c->stream, p->scene, view_of(p), seed, 0, c->n_cu));
+    }
+    TimedScope ts(c, K_SURF_TAPE);
+    HIPCHK(launch_surf_tape(c->stream, p->scene, p->cams, view_of(p), c->n_cu));
+    return PRT_OK;
+}
+
+int ensure_surface_part(prt_surface_paths p, size_t n)
+{
+    if (p->part_n >= n) return PRT_OK;
+    (void)hipFree(p->part);
+    p->part = nullptr;
+    p->part_n = 0;
+    int rc = dalloc(&p->part, n);
+    if (rc == PRT_OK) p->part_n = n;
+    return rc;
+}
+
+int check_surface_call(prt_ctx c, prt_surface_paths p)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    if (!p) return fail(PRT_E_INVALID, "paths is NULL");
+    if (p->device != c->device) return fail(PRT_E_MISMATCH, "store and context are on different devices");
+    return PRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int prt_surface_sample(prt_ctx c, const prt_surface_scene* s, const prt_cameras* cams, const double* theta_ref,
+                       uint64_t seed, int64_t n_paths, prt_surface_paths* out)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    if (!out) return fail(PRT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    prt_surface_paths p = new prt_surface_paths_s();
+    p->device = c->device;
+    int rc = prt_surface_resample(c, p, s, cams, theta_ref, seed, n_paths);
+    if (rc) {
+        free_surface(p);
+        return rc;
+    }
+    *out = p;
+    return PRT_OK;
+}
+
+int prt_surface_resample(prt_ctx c, prt_surface_paths p, const prt_surface_scene* s, const prt_cameras* cams,
+                         const double* theta_ref, uint64_t seed, int64_t n_paths)
+{
+    int rc = check_surface_call(c, p);
+    if (rc || (rc = check_surface_scene(s)) || (rc = check_theta_ref(theta_ref))) return rc;
+    if (n_paths < 1 || n_paths > ((int64_t)1 << 40)) return fail(PRT_E_INVALID, "n_paths must be in [1, 2^40]");
+    DevCams dc;
+    if ((rc = make_surface_cams(cams, s, &dc))) return rc;
+    DeviceGuard g(c->device);
+    if ((rc = surface_prepare(c, p, s, dc, theta_ref, n_paths))) return rc;
+    return surface_draw(c, p, seed);
+}
+
+int prt_surface_import(prt_ctx c, const prt_surface_scene* s, const prt_cameras* cams, const double* theta_ref,
+                       int64_t n_paths, const int32_t* B, const double* pos, const int32_t* sid,
+                       prt_surface_paths* out)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    if (!out) return fail(PRT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc;
+    if ((rc = check_surface_scene(s)) || (rc = check_theta_ref(theta_ref))) return rc;
+    if (n_paths < 1 || n_paths > ((int64_t)1 << 34)) return fail(PRT_E_INVALID, "n_paths must be in [1, 2^34]");
+    if (!B || !pos || !sid) return fail(PRT_E_INVALID, "path arrays must be non-NULL");
+    const int M = s->max_order;
+    const int n_ids = 6 + s->n_spheres;
+    for (int64_t i = 0; i < n_paths; ++i) {
+        if (B[i] < 0 || B[i] > M) return fail(PRT_E_INVALID, "path %lld: B outside [0, max_order]", (long long)i);
+        for (int b = 0; b < B[i]; ++b) {
+            const int32_t id = sid[i * M + b];
+            const double* x = pos + (i * M + b) * 3;
+            if (id < 0 || id >= n_ids || !finite_all({x[0], x[1], x[2]}))
+                return fail(PRT_E_INVALID, "path %lld vertex %d: bad surface id or position", (long long)i, b);
+        }
+    }
+    DevCams dc;
+    if ((rc = make_surface_cams(cams, s, &dc))) return rc;
+    DeviceGuard g(c->device);
+    prt_surface_paths p = new prt_surface_paths_s();
+    p->device = c->device;
+    if ((rc = surface_prepare(c, p, s, dc, theta_ref, n_paths))) {
+        free_surface(p);
+        return rc;
+    }
+    // rows per vertex order on the host, then one copy each
+    std::vector<int32_t> hsid((size_t)M * n_paths, -1);
+    std::vector<double4> hpos((size_t)M * n_paths);
+    for (int64_t i = 0; i < n_paths; ++i)
+        for (int b = 0; b < M; ++b) {
+            const size_t r = (size_t)b * n_paths + i;
+            if (b < B[i]) {
+                const double* x = pos + (i * M + b) * 3;
+                hpos[r] = make_double4(x[0], x[1], x[2], 0.0);
+                hsid[r] = sid[i * M + b];
+            } else {
+                hpos[r] = make_double4(0.0, 0.0, 0.0, 0.0);
+            }
+        }
+    if (hipMemcpy(p->B, B, (size_t)n_paths * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->pos, hpos.data(), hpos.size() * sizeof(double4), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->sid, hsid.data(), hsid.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        free_surface(p);
+        return fail(PRT_E_HIP, "copy of the imported paths failed");
+    }
+    {
+        TimedScope ts(c, K_SURF_TAPE);
+        hipError_t e = launch_surf_tape(c->stream, p->scene, p->cams, view_of(p), c->n_cu);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            free_surface(p);
+            return fail(PRT_E_HIP, "surface tape: %s", hipGetErrorString(e));
+        }
+    }
+    *out = p;
+    return PRT_OK;
+}
+
+int prt_surface_export(prt_ctx c, prt_surface_paths p, int32_t* B, double* pos, int32_t* sid)
+{
+    int rc = check_surface_call(c, p);
+    if (rc) return rc;
+    if (!B || !pos || !sid) return fail(PRT_E_INVALID, "output arrays must be non-NULL");
+    DeviceGuard g(c->device);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t n = p->n;
+    const int M = p->M;
+    std::vector<double4> hpos((size_t)M * n);
+    std::vector<int32_t> hsid((size_t)M * n);
+    HIPCHK(hipMemcpy(B, p->B, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hpos.data(), p->pos, hpos.size() * sizeof(double4), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hsid.data(), p->sid, hsid.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i)
+        for (int b = 0; b < M; ++b) {
+            const size_t r = (size_t)b * n + i;
+            double* x = pos + (i * M + b) * 3;
+            const bool in = b < B[i];
+            x[0] = in ? hpos[r].x : 0.0;
+            x[1] = in ? hpos[r].y : 0.0;
+            x[2] = in ? hpos[r].z : 0.0;
+            sid[i * M + b] = in ? hsid[r] : -1;
+        }
+    return PRT_OK;
+}
+
+int prt_surface_info(prt_surface_paths p, int64_t* n_paths, int32_t* max_order)
+{
+    if (!p) return fail(PRT_E_INVALID, "paths is NULL");
+    if (n_paths) *n_paths = p->n;
+    if (max_order) *max_order = p->M;
+    return PRT_OK;
+}
+
+int prt_surface_render(prt_ctx c, prt_surface_paths p, const double* theta, double* images)
+{
+    int rc = check_surface_call(c, p);
+    if (rc) return rc;
+    if (!theta || !images) return fail(PRT_E_INVALID, "theta/images is NULL");
+    DeviceGuard g(c->device);
+    const int npx = p->cams.W * p->cams.H;
+    const int np = surf_render_parts(p->n, p->n_cams, npx, c->n_cu);
+    if ((rc = ensure_surface_part(p, std::max<size_t>((size_t)np * p->n_cams * npx, 2 * (size_t)surf_pair_blocks(p->n, c->n_cu)))))
+        return rc;
+    const double w0 = 4.0 * kPi * p->scene.intensity / (double)p->n;
+    TimedScope ts(c, K_SURF_RENDER);
+    HIPCHK(launch_surf_render(c->stream, view_of(p), p->n_cams, npx, w0, theta, images, p->part, c->n_cu));
+    return PRT_OK;
+}
+
+int prt_surface_grad(prt_ctx c, prt_surface_paths p, const double* theta, const double* residual, double* grad)
+{
+    int rc = check_surface_call(c, p);
+    if (rc) return rc;
+    if (!theta || !residual || !grad) return fail(PRT_E_INVALID, "theta/residual/grad is NULL");
+    DeviceGuard g(c->device);
+    const int npx = p->cams.W * p->cams.H;
+    if ((rc = ensure_surface_part(p, 2 * (size_t)surf_pair_blocks(p->n, c->n_cu)))) return rc;
+    const double w0 = 4.0 * kPi * p->scene.intensity / (double)p->n;
+    TimedScope ts(c, K_SURF_GRAD);
+    HIPCHK(launch_surf_grad(c->stream, view_of(p), p->n_cams, npx, w0, theta, residual, p->part, grad, c->n_cu));
+    return PRT_OK;
+}
+
+int prt_surface_reweight(prt_ctx c, prt_surface_paths p, const double* theta, double* stats)
+{
+    int rc = check_surface_call(c, p);
+    if (rc) return rc;
+    if (!theta || !stats) return fail(PRT_E_INVALID, "theta/stats is NULL");
+    DeviceGuard g(c->device);
+    if ((rc = ensure_surface_part(p, 2 * (size_t)surf_pair_blocks(p->n, c->n_cu)))) return rc;
+    TimedScope ts(c, K_SURF_REWEIGHT);
+    HIPCHK(launch_surf_reweight(c->stream, view_of(p), theta, p->part, stats, c->n_cu));
+    return PRT_OK;
+}
+
+int prt_surface_adam(prt_ctx c, double* theta, const double* grad, double* m, double* v, int32_t t, double lr_kappa,
+                     double lr_gamma, double b1, double b2, double eps)
+{
+    if (!c) return fail(PRT_E_INVALID, "ctx is NULL");
+    if (!theta || !grad || !m || !v) return fail(PRT_E_INVALID, "bad adam arguments");
+    if (t < 1 || !finite_all({lr_kappa, lr_gamma, b1, b2, eps}) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) ||
+        !(eps > 0) || lr_kappa < 0 || lr_gamma < 0)
+        return fail(PRT_E_INVALID, "bad adam hyper-parameters");
+    DeviceGuard g(c->device);
+    TimedScope ts(c, K_SURF_ADAM);
+    HIPCHK(launch_surf_adam(c->stream, theta, grad, m, v, lr_kappa, lr_gamma, b1, b2, eps, 1.0 - std::pow(b1, t),
+                            1.0 - std::pow(b2, t)));
+    return PRT_OK;
+}
+
+void prt_surface_destroy(prt_surface_paths p) { free_surface(p); }
 
 }  // extern "C"

@@ -195,3 +195,113 @@ def space_carved_start(ctx: api.Context, scene, cams, measured: torch.Tensor, th
     P.prt_space_carve(ctx.handle, P.make_scene(scene, dummy), P.CamerasHost(cams), measured.contiguous(),
                       threshold, fill_value, mask, beta)
     return beta, mask
+
+
+# ------------------------------------------------------------ reflectometry
+
+@dataclass
+class SurfaceRecord:
+    iteration: int
+    loss: float
+    mean_r: float
+    ess: float
+    resampled: bool
+    seconds: float
+    theta: tuple
+    epsilon: float | None = None
+    delta: float | None = None
+
+
+def param_errors(theta, truth):
+    """Sec. 6's error measures on the parameter vector (kappa_s, gamma):
+    epsilon = sum |est - true| / sum |true|, delta = (sum est - sum true) /
+    sum true."""
+    e = [float(x) for x in theta]
+    t = [float(x) for x in truth]
+    st = sum(abs(x) for x in t)
+    return sum(abs(a - b) for a, b in zip(e, t)) / st, (sum(e) - sum(t)) / st
+
+
+# largest kappa_s the draws use: at kappa_ref = 1 no diffuse direction could
+# be drawn, and recycled estimates at kappa_s < 1 would miss them
+KAPPA_REF_MAX = 0.999
+
+
+class SurfaceReconstruction:
+    """Alg. 2 for the reflectometry workload (Sec. 6.2): theta = (kappa_s,
+    gamma) of the unknown sphere lives on the device with its Adam moments;
+    each iteration renders the recycled images, the loss and residual, the
+    gradient in theta, one Adam step (per-parameter step sizes, box
+    projection) and the correction-factor statistics at the new theta; the
+    policy decides when to draw new paths at the current theta (Alg. 2's N_r
+    or the drift / ESS triggers)."""
+
+    def __init__(self, ctx: api.Context, scene, cams, measured: torch.Tensor, theta0, n_paths: int,
+                 lr=(0.03, 3.0), policy: Policy | None = None, seed: int = 1, theta_true=None):
+        self.ctx, self.scene, self.cams = ctx, scene, cams
+        self.measured = measured.to(torch.float64).contiguous()
+        dev = self.measured.device
+        self.theta = torch.tensor([float(x) for x in theta0], dtype=torch.float64, device=dev)
+        self.m = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.v = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.grad = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.stats = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.img = torch.empty_like(self.measured)
+        self.res = torch.empty_like(self.measured)
+        self.n_paths, self.lr = int(n_paths), (float(lr[0]), float(lr[1]))
+        self.policy = policy if policy is not None else Policy(period=30, drift=None)
+        self.seed, self.theta_true = seed, theta_true
+        self.t = 0
+        self.t_ref = 0
+        self.mean_r = self.ess_fraction = None
+        self.store = None
+        self.records: list = []
+
+    def theta_host(self):
+        return tuple(float(x) for x in self.theta.cpu())
+
+    def close(self):
+        if self.store is not None:
+            self.store.close()
+            self.store = None
+
+    def step(self) -> SurfaceRecord:
+        h = self.ctx.handle
+        t0 = time.perf_counter()
+        resampled = False
+        if self.store is None or self.policy.resample(self.t, self.t_ref, self.mean_r, self.ess_fraction):
+            k, g = self.theta_host()
+            ref = (min(k, KAPPA_REF_MAX), g)
+            if self.store is None:
+                self.store = api.SurfacePaths.sample(self.ctx, self.scene, self.cams, ref, self.seed + self.t,
+                                                     self.n_paths)
+            else:
+                self.store.resample(ref, self.seed + self.t, self.n_paths)
+            self.t_ref = self.t
+            resampled = True
+        self.t += 1
+        P.prt_surface_render(h, self.store.handle, self.theta, self.img)
+        P.prt_loss(h, self.img, self.measured, self.res, self.loss)
+        P.prt_surface_grad(h, self.store.handle, self.theta, self.res, self.grad)
+        P.prt_surface_adam(h, self.theta, self.grad, self.m, self.v, self.t, *self.lr)
+        P.prt_surface_reweight(h, self.store.handle, self.theta, self.stats)
+        mean_r, ess = (float(x) for x in self.stats.cpu())
+        self.mean_r, self.ess_fraction = mean_r, ess / self.n_paths
+        theta = self.theta_host()
+        eps = dlt = None
+        if self.theta_true is not None:
+            eps, dlt = param_errors(theta, self.theta_true)
+        rec = SurfaceRecord(self.t, float(self.loss.item()), mean_r, ess, resampled, time.perf_counter() - t0, theta,
+                            eps, dlt)
+        self.records.append(rec)
+        return rec
+
+    def run(self, iters: int, callback=None, stop_epsilon: float | None = None):
+        for _ in range(iters):
+            rec = self.step()
+            if callback:
+                callback(rec)
+            if stop_epsilon is not None and rec.epsilon is not None and rec.epsilon <= stop_epsilon:
+                break
+        return self.records

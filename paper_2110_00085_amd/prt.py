@@ -41,6 +41,13 @@ class prt_cameras(C.Structure):
                 ("pos", C.c_void_p), ("rot", C.c_void_p), ("f_px", C.c_void_p)]
 
 
+class prt_surface_scene(C.Structure):
+    _fields_ = [("box", C.c_double), ("wall_albedo", C.c_double * 6), ("light", C.c_double * 3),
+                ("intensity", C.c_double), ("n_spheres", C.c_int32), ("phong", C.c_int32),
+                ("max_order", C.c_int32), ("pad", C.c_int32), ("center", C.c_void_p), ("radius", C.c_void_p),
+                ("albedo", C.c_void_p)]
+
+
 class prt_counters_t(C.Structure):
     _fields_ = [("voxel_segments", C.c_uint64), ("local_estimates", C.c_uint64), ("paths", C.c_uint64),
                 ("overhead_segments", C.c_uint64)]
@@ -92,6 +99,19 @@ def lib():
             "prt_enable_timing_mask": ([_V, C.c_uint32], C.c_int),
             "prt_kernel_times": ([_V, _V, _V, C.c_int, C.c_int], C.c_int),
             "prt_kernel_name": ([C.c_int], C.c_char_p),
+            "prt_surface_sample": ([_V, C.POINTER(prt_surface_scene), C.POINTER(prt_cameras), _V, _U64, _I64,
+                                    C.POINTER(_V)], C.c_int),
+            "prt_surface_resample": ([_V, _V, C.POINTER(prt_surface_scene), C.POINTER(prt_cameras), _V, _U64, _I64],
+                                     C.c_int),
+            "prt_surface_import": ([_V, C.POINTER(prt_surface_scene), C.POINTER(prt_cameras), _V, _I64, _V, _V, _V,
+                                    C.POINTER(_V)], C.c_int),
+            "prt_surface_export": ([_V, _V, _V, _V, _V], C.c_int),
+            "prt_surface_info": ([_V, C.POINTER(_I64), C.POINTER(_I32)], C.c_int),
+            "prt_surface_render": ([_V, _V, _V, _V], C.c_int),
+            "prt_surface_grad": ([_V, _V, _V, _V, _V], C.c_int),
+            "prt_surface_reweight": ([_V, _V, _V, _V], C.c_int),
+            "prt_surface_adam": ([_V, _V, _V, _V, _V, _I32, _D, _D, _D, _D, _D], C.c_int),
+            "prt_surface_destroy": ([_V], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -146,6 +166,21 @@ class CamerasHost:
     @property
     def image_shape(self):
         return (self.n, self.height, self.width)
+
+
+class SurfaceSceneHost:
+    """prt_surface_scene with its host sphere arrays kept alive, from an
+    object with the attributes of inputs.SurfaceScene."""
+
+    def __init__(self, scene):
+        self.c = np.ascontiguousarray(np.asarray(scene.centers, np.float64).reshape(-1, 3))
+        self.r = np.ascontiguousarray(scene.radii, np.float64)
+        self.a = np.ascontiguousarray(scene.albedo, np.float64)
+        self.max_order = int(scene.max_order)
+        wa = (C.c_double * 6)(*[float(x) for x in np.asarray(scene.wall_albedo, np.float64)])
+        li = (C.c_double * 3)(*[float(x) for x in np.asarray(scene.light, np.float64)])
+        self.s = prt_surface_scene(float(scene.box), wa, li, float(scene.intensity), len(self.r), int(scene.phong),
+                                   self.max_order, 0, _hptr(self.c).value, _hptr(self.r).value, _hptr(self.a).value)
 
 
 # ---------------------------------------------------------- entry points
@@ -320,11 +355,95 @@ def prt_kernel_name(i: int) -> str:
     return lib().prt_kernel_name(i).decode()
 
 
+# ---------------------------------------------------- reflectometry (prt_surface.h)
+
+def _theta_host(theta) -> np.ndarray:
+    t = np.ascontiguousarray(np.asarray(theta, np.float64).ravel())
+    if t.size != 2:
+        raise ValueError("theta_ref must hold (kappa_s, gamma)")
+    return t
+
+
+def _pair(t, what: str):
+    if t.dtype.itemsize != 8 or t.numel() < 2 or not t.is_cuda:
+        raise ValueError(f"{what} must be a device float64 tensor of 2 elements")
+    return _dptr(t)
+
+
+def prt_surface_sample(ctx, scene: SurfaceSceneHost, cams: CamerasHost, theta_ref, seed: int, n_paths: int):
+    t = _theta_host(theta_ref)
+    h = _V()
+    _check(lib().prt_surface_sample(ctx, C.byref(scene.s), C.byref(cams.s), _hptr(t), seed, int(n_paths),
+                                    C.byref(h)))
+    return h
+
+
+def prt_surface_resample(ctx, paths, scene: SurfaceSceneHost, cams: CamerasHost, theta_ref, seed: int,
+                         n_paths: int):
+    t = _theta_host(theta_ref)
+    _check(lib().prt_surface_resample(ctx, paths, C.byref(scene.s), C.byref(cams.s), _hptr(t), seed,
+                                      int(n_paths)))
+
+
+def prt_surface_import(ctx, scene: SurfaceSceneHost, cams: CamerasHost, theta_ref, B, pos, sid):
+    """B [n], pos [n][M][3], sid [n][M] host arrays (M = max_order)."""
+    t = _theta_host(theta_ref)
+    B = np.ascontiguousarray(B, np.int32)
+    n, M = len(B), scene.max_order
+    pos = np.ascontiguousarray(pos, np.float64).reshape(n, M, 3)
+    sid = np.ascontiguousarray(sid, np.int32).reshape(n, M)
+    h = _V()
+    _check(lib().prt_surface_import(ctx, C.byref(scene.s), C.byref(cams.s), _hptr(t), n, _hptr(B), _hptr(pos),
+                                    _hptr(sid), C.byref(h)))
+    return h
+
+
+def prt_surface_info(paths):
+    n, m = _I64(), _I32()
+    _check(lib().prt_surface_info(paths, C.byref(n), C.byref(m)))
+    return int(n.value), int(m.value)
+
+
+def prt_surface_export(ctx, paths):
+    """(B [n], pos [n][M][3], sid [n][M]) as numpy arrays."""
+    n, M = prt_surface_info(paths)
+    B = np.zeros(n, np.int32)
+    pos = np.zeros((n, M, 3), np.float64)
+    sid = np.zeros((n, M), np.int32)
+    _check(lib().prt_surface_export(ctx, paths, _hptr(B), _hptr(pos), _hptr(sid)))
+    return B, pos, sid
+
+
+def prt_surface_render(ctx, paths, theta, images):
+    _check(lib().prt_surface_render(ctx, paths, _pair(theta, "theta"), _dptr(images)))
+
+
+def prt_surface_grad(ctx, paths, theta, residual, grad):
+    _check(lib().prt_surface_grad(ctx, paths, _pair(theta, "theta"), _dptr(residual), _pair(grad, "grad")))
+
+
+def prt_surface_reweight(ctx, paths, theta, stats):
+    _check(lib().prt_surface_reweight(ctx, paths, _pair(theta, "theta"), _pair(stats, "stats")))
+
+
+def prt_surface_adam(ctx, theta, grad, m, v, t: int, lr_kappa: float, lr_gamma: float, b1: float = 0.9,
+                     b2: float = 0.999, eps: float = 1e-8):
+    _check(lib().prt_surface_adam(ctx, _pair(theta, "theta"), _pair(grad, "grad"), _pair(m, "m"), _pair(v, "v"),
+                                  int(t), lr_kappa, lr_gamma, b1, b2, eps))
+
+
+def prt_surface_destroy(paths):
+    lib().prt_surface_destroy(paths)
+
+
 def header_entry_points() -> list[str]:
-    """Names of the functions declared in include/prt.h."""
+    """Names of the functions declared in include/*.h."""
+    import glob
     import re
-    src = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(prt_\w+)\s*\(", src, re.M)))
+    names = set()
+    for h in glob.glob(os.path.join(os.path.dirname(HEADER), "*.h")):
+        names |= set(re.findall(r"^\s*(?:int|void|const char\*)\s+(prt_\w+)\s*\(", open(h).read(), re.M))
+    return sorted(names)
 
 
 def prt_last_error() -> str:

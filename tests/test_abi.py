@@ -48,6 +48,14 @@ def test_null_arguments_are_rejected_before_any_device_work(P):
     assert L.prt_paths_info(None, None) == P.PRT_E_INVALID
     L.prt_paths_destroy(None)
     L.prt_destroy(None)
+    # reflectometry calls (prt_surface.h)
+    assert L.prt_surface_render(None, None, None, None) == P.PRT_E_INVALID
+    assert L.prt_surface_grad(None, None, None, None, None) == P.PRT_E_INVALID
+    assert L.prt_surface_reweight(None, None, None, None) == P.PRT_E_INVALID
+    assert L.prt_surface_adam(None, None, None, None, None, 1, 0.1, 0.1, 0.9, 0.999, 1e-8) == P.PRT_E_INVALID
+    assert L.prt_surface_info(None, None, None) == P.PRT_E_INVALID
+    assert L.prt_surface_sample(None, None, None, None, 0, 1, None) == P.PRT_E_INVALID
+    L.prt_surface_destroy(None)
 
 
 def test_create_without_gpu_fails_cleanly(P):
