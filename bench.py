@@ -109,6 +109,14 @@ def parse():
     ap.add_argument("--loop-policies", default="drift0.2,period30,ess0.1",
                     help="resampling policies to run: drift0.2 (|mean r - 1| > 0.2), period30 (also every 30 "
                          "iterations), ess0.1 (also when ESS < 0.1 N)")
+    ap.add_argument("--surface", action="store_true",
+                    help="reflectometry workload (Sec. 6.2, smallpaint60): time full steps (resample + render + "
+                         "loss + gradient + Adam + reweight) and print their JSON line")
+    ap.add_argument("--surface-loop", action="store_true",
+                    help="reflectometry Alg. 2 from (0.3, 15) to the truth (0.7, 50): time to epsilon <= 1%% with "
+                         "resampling every N_r iterations, for each N_r of --surface-nr")
+    ap.add_argument("--surface-nr", default="30,1", help="resampling periods N_r of --surface-loop")
+    ap.add_argument("--surface-iters", type=int, default=400, help="iteration cap of --surface-loop")
     ap.add_argument("--study-iters", type=int, default=50)
     ap.add_argument("--study-lr", type=float, default=1.0, help="Adam step size of the study, 1/km")
     ap.add_argument("--study-paths", type=int, default=0, help="paths per store (default: the workload's)")
@@ -703,6 +711,15 @@ def main():
     if args.reuse_study:
         reuse_study(args)
         return
+    if args.surface:
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps(surface_bench(args)), flush=True)
+        return
+    if args.surface_loop:
+        surface_loop(args)
+        return
     if args.gpus != 1:
         print("bench.py: the hot path runs on one GPU; --gpus must be 1 (sharding paths over GPUs is not "
               "implemented)", file=sys.stderr)
@@ -723,6 +740,193 @@ def main():
     if secondary:
         out["secondary"] = secondary
     print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------ reflectometry
+
+SURFACE_START = (0.3, 15.0)
+SURFACE_LR = (0.02, 2.0)
+
+
+def _surface_setup(ctx, n_meas_factor: int = 4):
+    """smallpaint60 scene, camera and measured images (rendered at the truth
+    with fresh paths, 4 x N of them, seed + 1000)."""
+    import torch
+
+    import inputs
+    from paper_2110_00085_amd import api
+    make, make_cam, n, seed, truth = inputs.SURFACE_WORKLOADS["smallpaint60"]
+    scene = make()
+    cams = make_cam(scene)
+    th = torch.tensor(truth, dtype=torch.float64, device="cuda")
+    meas = torch.zeros((cams.n, cams.height, cams.width), dtype=torch.float64, device="cuda")
+    for k in range(n_meas_factor):
+        st = api.SurfacePaths.sample(ctx, scene, cams, truth, seed + 1000 + k, n)
+        meas += st.render(th)
+        st.close()
+    meas /= n_meas_factor
+    return scene, cams, n, seed, truth, meas
+
+
+def surface_bench(args):
+    """Full Alg. 2 steps of the reflectometry workload: resample at the
+    current theta (sample + tape), recycled render, loss, gradient, Adam,
+    correction factors.  The dominant kernel is timed with HIP events on the
+    library's stream over the timed steps."""
+    import torch
+
+    from paper_2110_00085_amd import api, prt as P
+    ctx = api.Context(0)
+    h = ctx.handle
+    scene, cams, n, seed, truth, meas = _surface_setup(ctx)
+    theta = torch.tensor(SURFACE_START, dtype=torch.float64, device="cuda")
+    m = torch.zeros(2, dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(m)
+    g = torch.zeros_like(m)
+    stats = torch.zeros_like(m)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    img = torch.empty_like(meas)
+    res = torch.empty_like(meas)
+    st = api.SurfacePaths.sample(ctx, scene, cams, SURFACE_START, seed, n)
+    state = {"t": 0}
+
+    def iterate():
+        state["t"] += 1
+        P.prt_surface_render(h, st.handle, theta, img)
+        P.prt_loss(h, img, meas, res, loss)
+        P.prt_surface_grad(h, st.handle, theta, res, g)
+        P.prt_surface_adam(h, theta, g, m, v, state["t"], *SURFACE_LR)
+        P.prt_surface_reweight(h, st.handle, theta, stats)
+
+    def full_step():
+        # theta_ref of the draw: the current theta (read back, as the loop does)
+        k, gm = (float(x) for x in theta.cpu())
+        st.resample((min(k, 0.999), gm), seed + state["t"], n)
+        iterate()
+
+    for _ in range(args.warmup):
+        full_step()
+    torch.cuda.synchronize()
+    # breakdown over a few steps, every kernel timed
+    P.prt_enable_timing(h, True)
+    P.prt_kernel_times(h, reset=True)
+    nb = max(1, min(args.steps, 5))
+    for _ in range(nb):
+        full_step()
+    kb = P.prt_kernel_times(h, reset=True)
+    kms = {k: x[0] / nb for k, x in kb.items() if x[1] and k.startswith("surf") or (x[1] and k == "loss")}
+    dom = max((k for k in kms if k.startswith("surf")), key=lambda k: kms[k])
+    P.prt_enable_timing_mask(h, [dom])
+    P.prt_kernel_times(h, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        full_step()
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    kt = P.prt_kernel_times(h, reset=True)
+    P.prt_enable_timing(h, False)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        iterate()
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    B, _, _ = st.export()
+    nverts = int(B.sum())
+    dom_ms = kt[dom][0] / max(kt[dom][1], 1)
+    # algorithmic bytes of the tape passes: per vertex the drawn-direction
+    # record (16 B) and per camera the pixel (4 B) and record (16 B), plus B
+    # per path; the draw writes positions (32 B) and surface ids (4 B)
+    per_vertex = 16 + cams.n * 20
+    alg = {"surf_render": nverts * per_vertex + 4 * n, "surf_grad": nverts * per_vertex + 4 * n,
+           "surf_reweight": nverts * 16 + 4 * n}
+    roof = {"kernel": dom, "avg_launch_ms": dom_ms, "traffic": None}
+    if dom in alg:
+        gbs = alg[dom] / (dom_ms * 1e-3) / 1e9
+        roof.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": alg[dom]})
+    else:
+        roof.update({"bound": "alu", "achieved": None, "peak": 78.6, "unit": "TFLOP/s", "frac": None})
+    render_gbs = alg["surf_render"] / (kms["surf_render"] * 1e-3) / 1e9
+    out = {
+        "metric": "paths/s (forward+backward)", "value": n / (t_full / args.steps), "unit": "paths/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_full / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"smallpaint60: reflectometry box, 15 spheres (one Phong), 1 camera 60x60, {n} paths, "
+                               f"{scene.max_order} bounces, step = resample+tape+render+loss+grad+adam+reweight",
+                   "paths": n},
+        "recycled_ms_per_step": 1e3 * t_rec / args.steps,
+        "vertices": nverts,
+        "kernel_ms_per_step": kms,
+        "render_hbm_gbs": render_gbs,
+        "theta_after": [float(x) for x in theta.cpu()],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = surface_cpu_baseline(scene, cams, meas.cpu().numpy(), seed, n)
+    st.close()
+    ctx.close()
+    return out
+
+
+def surface_cpu_baseline(scene, cams, meas, seed, n_total, n_cpu: int = 200_000):
+    """The FP64 oracle doing one full reflectometry step (sample, render,
+    loss, gradient, Adam, correction factors) on the first n_cpu paths."""
+    import numpy as np
+
+    import oracle
+    import oracle.surface as OS
+    if not os.path.exists(os.path.join(ROOT, "oracle", "libprt_oracle.so")):
+        oracle.build()
+    t0 = time.perf_counter()
+    paths = OS.sample(scene, SURFACE_START, seed, n_cpu)
+    img = OS.render(scene, cams, paths, SURFACE_START)
+    g = OS.grad(scene, cams, paths, img - meas, SURFACE_START)
+    th, _, _ = OS.adam_step(SURFACE_START, g, np.zeros(2), np.zeros(2), 1, np.array(SURFACE_LR))
+    th[0] = min(th[0], 0.999)
+    OS.reweight(scene, paths, th)
+    dt = time.perf_counter() - t0
+    return {"value": n_cpu / dt, "unit": "paths/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one full step on the first {n_cpu} of the {n_total} paths, FP64, {dt:.1f} s; rate "
+                      f"extrapolated to the whole workload (paths are independent)"}
+
+
+def surface_loop(args):
+    """Alg. 2 on smallpaint60 from (0.3, 15) towards the truth (0.7, 50):
+    wall time until the parameter error epsilon (Sec. 6) reaches 1 %, for
+    each resampling period N_r (the paper reports 31 s to 1 % with N_r = 30
+    on its GPU, and that N_r = 30 converges faster than N_r = 1)."""
+    import torch
+
+    from paper_2110_00085_amd import api
+    from paper_2110_00085_amd.loop import Policy, SurfaceReconstruction
+    ctx = api.Context(0)
+    scene, cams, n, seed, truth, meas = _surface_setup(ctx)
+    for nr in (int(x) for x in args.surface_nr.split(",")):
+        rec = SurfaceReconstruction(ctx, scene, cams, meas, SURFACE_START, n, lr=SURFACE_LR,
+                                    policy=Policy(period=nr, drift=None), seed=seed, theta_true=truth)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hit = None
+
+        def show(r):
+            nonlocal hit
+            if hit is None and r.epsilon <= 0.01:
+                hit = (r.iteration, time.perf_counter() - t0)
+            if r.iteration % 25 == 0 or r.iteration == 1:
+                print(json.dumps({"N_r": nr, "iteration": r.iteration, "theta": r.theta, "epsilon": r.epsilon,
+                                  "loss": r.loss, "mean_r": r.mean_r, "ess_over_n": r.ess / n,
+                                  "resampled": r.resampled}), flush=True)
+
+        recs = rec.run(args.surface_iters, callback=show, stop_epsilon=0.01)
+        total = time.perf_counter() - t0
+        print(json.dumps({"surface_loop": "smallpaint60", "N_r": nr, "paths": n, "iterations": len(recs),
+                          "resamples": sum(r.resampled for r in recs), "theta_last": recs[-1].theta,
+                          "epsilon_last": recs[-1].epsilon, "iterations_to_1pct": hit[0] if hit else None,
+                          "seconds_to_1pct": hit[1] if hit else None, "seconds_total": total,
+                          "seconds_per_iteration": total / len(recs)}), flush=True)
+        rec.close()
+    ctx.close()
 
 
 def oracle_step_seconds(scene, cams, target, seed, n_cpu):
