@@ -54,6 +54,8 @@ DEVICE_KERNEL = {"grad": "grad_bin_walk_kernel", "render": "render_kernel", "sam
 # (one FP32 or FP64 FMA per lane per clock without packed math).
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_GBS = 8000.0
+# dense FP64 vector peak of MI355X (TFLOP/s)
+FP64_PEAK_TFLOPS = 78.6
 # algorithmic VALU lane-operations per unit of work: the arithmetic of one
 # voxel piece of a walk and of one local estimate (projection, phase
 # functions, weight), as the kernels perform it
@@ -841,12 +843,21 @@ def surface_bench(args):
     alg = {"surf_render": nverts * per_vertex + 4 * n, "surf_grad": nverts * per_vertex + 4 * n,
            "surf_reweight": nverts * 16 + 4 * n}
     roof = {"kernel": dom, "avg_launch_ms": dom_ms, "traffic": None}
+    tests, _ = P.prt_surface_work(h, st.handle)
     if dom in alg:
         gbs = alg[dom] / (dom_ms * 1e-3) / 1e9
         roof.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": alg[dom]})
+    elif dom == "surf_sample":
+        # the draw's algorithmic FP64 work: 17 flops per ray-sphere test
+        # (offset 3, dot product with the direction 5, squared distance minus
+        # r^2 7, discriminant 2), tests counted by the kernel
+        tf = 17.0 * tests / (dom_ms * 1e-3) / 1e12
+        roof.update({"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tf / FP64_PEAK_TFLOPS, "sphere_tests_per_launch": tests,
+                     "flops_per_launch": 17.0 * tests})
     else:
-        roof.update({"bound": "alu", "achieved": None, "peak": 78.6, "unit": "TFLOP/s", "frac": None})
+        roof.update({"bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None})
     render_gbs = alg["surf_render"] / (kms["surf_render"] * 1e-3) / 1e9
     out = {
         "metric": "paths/s (forward+backward)", "value": n / (t_full / args.steps), "unit": "paths/s", "n_gpus": 1,

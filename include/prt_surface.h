@@ -97,6 +97,12 @@ int prt_surface_export(prt_ctx ctx, prt_surface_paths paths, int32_t* B, double*
 /* Number of paths and max_order of a store. */
 int prt_surface_info(prt_surface_paths paths, int64_t* n_paths, int32_t* max_order);
 
+/* Work of the store's last draw (zero for an imported store): ray-sphere
+   tests (n_spheres per nearest-surface query of a traced ray and per
+   occlusion query of a camera connection in the image) and stored vertices.
+   Synchronises. */
+int prt_surface_work(prt_ctx ctx, prt_surface_paths paths, uint64_t* sphere_tests, uint64_t* vertices);
+
 /* Recycled images F(theta | theta_ref) (Eq. forward_simualtion_recycling):
    images (device FP64 [n_cams][H][W]) are overwritten. */
 int prt_surface_render(prt_ctx ctx, prt_surface_paths paths, const double* theta, double* images);

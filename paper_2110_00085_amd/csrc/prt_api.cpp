@@ -179,6 +179,9 @@ struct prt_surface_paths_s {
     int32_t* pix = nullptr;
     double* theta_ref = nullptr;     // device [2]
     double* sph = nullptr;           // device [kMaxSpheres][5]
+    double* omega = nullptr;         // pixel solid angles [n_cams][W*H]
+    int64_t cap_omega = 0;
+    unsigned long long* work = nullptr;  // [2] sphere tests and vertices of the last draw
     double* part = nullptr;          // render partial images / gradient and reweight pairs
     size_t part_n = 0;
     SurfScene scene{};
@@ -1635,7 +1638,7 @@ void free_surface(prt_surface_paths p)
     DeviceGuard g(p->device);
     (void)hipDeviceSynchronize();
     for (void* q : {(void*)p->B, (void*)p->pos, (void*)p->sid, (void*)p->tv, (void*)p->tc, (void*)p->pix,
-                    (void*)p->theta_ref, (void*)p->sph, (void*)p->part})
+                    (void*)p->theta_ref, (void*)p->sph, (void*)p->part, (void*)p->omega, (void*)p->work})
         (void)hipFree(q);
     delete p;
 }
@@ -1651,6 +1654,8 @@ SurfStore view_of(prt_surface_paths p)
     v.tc = p->tc;
     v.pix = p->pix;
     v.theta_ref = p->theta_ref;
+    v.omega = p->omega;
+    v.work = p->work;
     return v;
 }
 
@@ -1693,6 +1698,10 @@ int surface_prepare(prt_ctx c, prt_surface_paths p, const prt_surface_scene* s, 
     // (synchronous copies of host arrays that the caller may free on return)
     HIPCHK(hipMemcpy(p->theta_ref, theta_ref, 2 * sizeof(double), hipMemcpyHostToDevice));
     if (s->n_spheres > 0) HIPCHK(hipMemcpy(p->sph, h, (size_t)5 * s->n_spheres * sizeof(double), hipMemcpyHostToDevice));
+    if ((rc = grow(&p->omega, &p->cap_omega, (int64_t)dc.n * dc.W * dc.H))) return rc;
+    if (!p->work && (rc = dalloc(&p->work, 2))) return rc;
+    HIPCHK(hipMemsetAsync(p->work, 0, 2 * sizeof(unsigned long long), c->stream));
+    HIPCHK(launch_surf_omega(c->stream, dc, p->omega));
     p->n = n;
     p->M = M;
     p->n_cams = dc.n;
@@ -1713,12 +1722,8 @@ int surface_prepare(prt_ctx c, prt_surface_paths p, const prt_surface_scene* s, 
 // whose buffers were sized for a larger order keeps M rows per order anyway.
 int surface_draw(prt_ctx c, prt_surface_paths p, uint64_t seed)
 {
-    {
-        TimedScope ts(c, K_SURF_SAMPLE);
-        HIPCHK(launch_surf_sample(c->stream, p->scene, view_of(p), seed, 0, c->n_cu));
-    }
-    TimedScope ts(c, K_SURF_TAPE);
-    HIPCHK(launch_surf_tape(c->stream, p->scene, p->cams, view_of(p), c->n_cu));
+    TimedScope ts(c, K_SURF_SAMPLE);
+    HIPCHK(launch_surf_draw(c->stream, p->scene, p->cams, view_of(p), seed, 0, c->n_cu));
     return PRT_OK;
 }
 
@@ -1871,6 +1876,19 @@ int prt_surface_info(prt_surface_paths p, int64_t* n_paths, int32_t* max_order)
     if (!p) return fail(PRT_E_INVALID, "paths is NULL");
     if (n_paths) *n_paths = p->n;
     if (max_order) *max_order = p->M;
+    return PRT_OK;
+}
+
+int prt_surface_work(prt_ctx c, prt_surface_paths p, uint64_t* sphere_tests, uint64_t* vertices)
+{
+    int rc = check_surface_call(c, p);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    unsigned long long h[2] = {0, 0};
+    HIPCHK(hipMemcpy(h, p->work, sizeof h, hipMemcpyDeviceToHost));
+    if (sphere_tests) *sphere_tests = h[0];
+    if (vertices) *vertices = h[1];
     return PRT_OK;
 }
 

@@ -35,20 +35,30 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3])
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-// Sphere k entered from outside along p + t w: smallest t > 0, or +inf.
-__device__ __forceinline__ double sphere_entry(const double* sph, int k, const double p[3], const double w[3])
+// Ray p + t w against sphere k (p outside it): b = (p - c).w and the
+// discriminant disc = b^2 - (|p - c|^2 - r^2); the ray enters the sphere
+// ahead (at -b - sqrt(disc) > 0) when disc >= 0 and b < 0.
+__device__ __forceinline__ void sphere_terms(const double* sph, int k, const double p[3], const double w[3], double& b,
+                                             double& disc)
 {
     const double ox = p[0] - sph[5 * k], oy = p[1] - sph[5 * k + 1], oz = p[2] - sph[5 * k + 2];
     const double r = sph[5 * k + 3];
-    const double b = ox * w[0] + oy * w[1] + oz * w[2];
-    const double disc = b * b - (ox * ox + oy * oy + oz * oz - r * r);
-    if (disc < 0.0) return INFINITY;
-    const double t = -b - sqrt(disc);
-    return t > 0.0 ? t : INFINITY;
+    b = ox * w[0] + oy * w[1] + oz * w[2];
+    disc = b * b - (ox * ox + oy * oy + oz * oz - r * r);
+}
+
+// Does the entry -b - sqrt(disc) lie in (0, tmax)?  Decided without the
+// square root: sqrt(disc) > -b - tmax holds outright when -b < tmax, else it
+// is disc > (b + tmax)^2.
+__device__ __forceinline__ bool enters_before(double b, double disc, double tmax)
+{
+    const double e = b + tmax;
+    return disc >= 0.0 && b < 0.0 && (e > 0.0 || disc > e * e);
 }
 
 // Nearest surface along p + t w, skipping surface `skip` (walls 0..5, then
-// spheres): id (or -1) and its t.
+// spheres): id (or -1) and its t.  A sphere's entry point (the square root)
+// is formed only when it comes before the nearest surface found so far.
 __device__ __forceinline__ int nearest_surface(const SurfScene& s, const double* sph, const double p[3],
                                                const double w[3], int skip, double& t_best)
 {
@@ -65,15 +75,34 @@ __device__ __forceinline__ int nearest_surface(const SurfScene& s, const double*
             id = wall;
         }
     }
+#pragma unroll 2
     for (int k = 0; k < s.n_spheres; ++k) {
-        if (6 + k == skip) continue;
-        const double t = sphere_entry(sph, k, p, w);
-        if (t < t_best) {
-            t_best = t;
-            id = 6 + k;
+        double b, disc;
+        sphere_terms(sph, k, p, w, b, disc);
+        if (6 + k != skip && enters_before(b, disc, t_best)) {
+            const double t = -b - sqrt(disc);
+            if (t > 0.0 && t < t_best) {
+                t_best = t;
+                id = 6 + k;
+            }
         }
     }
     return id;
+}
+
+// Is the segment from x (on surface sid) to a point at distance dist along
+// w cut by another sphere?
+__device__ __forceinline__ bool occluded(const SurfScene& s, const double* sph, int sid, const double x[3],
+                                         const double w[3], double dist)
+{
+    bool hit = false;
+#pragma unroll 2
+    for (int k = 0; k < s.n_spheres; ++k) {
+        double b, disc;
+        sphere_terms(sph, k, x, w, b, disc);
+        hit = hit || (6 + k != sid && enters_before(b, disc, dist));
+    }
+    return hit;
 }
 
 // Inward wall normal, outward sphere normal.
@@ -150,11 +179,23 @@ struct PhongTerms {
         ra = (1.0 - theta_ref[0]) / kPiD;
         rb = theta_ref[0] * (rgamma + 1.0) / (2.0 * kPiD);
     }
-    __device__ __forceinline__ double lobe(double c) const { return c > 0.0 ? pow(c, gamma) : 0.0; }
-    __device__ __forceinline__ double f(double c) const { return fa + fb * lobe(c); }
-    __device__ __forceinline__ double pdf_ref(double nc, double c) const
+    // c^gamma (0 for c <= 0) as exp(gamma log c), with lc = log c (0 for c <= 0)
+    __device__ __forceinline__ double lobe_log(double c, double& lc) const
     {
-        return ra * fmax(nc, 0.0) + (c > 0.0 ? rb * pow(c, rgamma) : 0.0);
+        lc = c > 0.0 ? log(c) : 0.0;
+        return c > 0.0 ? exp(gamma * lc) : 0.0;
+    }
+    __device__ __forceinline__ double f(double c) const
+    {
+        double lc;
+        return fa + fb * lobe_log(c, lc);
+    }
+    // f(c) nc / pdf_ref(nc, c): the continuation weight of a drawn direction
+    __device__ __forceinline__ double carry(double c, double nc) const
+    {
+        const double lc = c > 0.0 ? log(c) : 0.0;
+        const double l = c > 0.0 ? exp(gamma * lc) : 0.0, lr = c > 0.0 ? exp(rgamma * lc) : 0.0;
+        return (fa + fb * l) * nc / (ra * fmax(nc, 0.0) + rb * lr);
     }
 };
 
@@ -175,63 +216,70 @@ __device__ __forceinline__ double block_sum(double x, double* lds)
 
 }  // namespace
 
-// Forward path tracing from the light at theta_ref (Sec. 3.4 with surfaces):
-// uniform direction from the light, then at each vertex a cosine-weighted
-// draw (diffuse) or the mixture of a cosine-weighted and a Phong-lobe draw
-// (unknown sphere; a lobe draw below the surface ends the path).  One lane
-// per path, FP64.
-__global__ void __launch_bounds__(kSurfBlock) surf_sample_kernel(SurfScene s, SurfStore st, uint64_t seed,
-                                                                  uint64_t first_id)
+// Pixel solid angles of every camera, once per draw: omega[d * npx + p].
+__global__ void surf_omega_kernel(DevCams c, double* omega)
 {
-    __shared__ double lsph[5 * kMaxSpheres];
-    const double* sph = load_spheres(s, lsph);
-    const double kr = st.theta_ref[0], ge = 1.0 / (st.theta_ref[1] + 1.0);
-    const int M = s.max_order;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < st.n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t id = first_id + (uint64_t)i;
-        double u[4];
-        uniforms4(seed, id, 0u, u);
-        const double mu0 = 1.0 - 2.0 * u[0], st0 = sqrt(fmax(0.0, 1.0 - mu0 * mu0));
-        double sp, cp;
-        sincos(2.0 * kPiD * u[1], &sp, &cp);
-        double w[3] = {st0 * cp, st0 * sp, mu0};
-        double p[3] = {s.light[0], s.light[1], s.light[2]};
-        int skip = -1, b = 0;
-        while (b < M) {
-            double t;
-            const int hid = nearest_surface(s, sph, p, w, skip, t);
-            if (hid < 0 || !isfinite(t)) break;
-            double x[3] = {p[0] + t * w[0], p[1] + t * w[1], p[2] + t * w[2]};
-            if (hid < 6) x[hid >> 1] = (hid & 1) ? s.box : 0.0;
-            st.pos[(int64_t)b * st.n + i] = make_double4(x[0], x[1], x[2], 0.0);
-            st.sid[(int64_t)b * st.n + i] = hid;
-            ++b;
-            if (b == M) break;
-            uniforms4(seed, id, (uint32_t)b, u);
-            double n[3];
-            surface_normal(sph, hid, x, n);
-            double wn[3];
-            if (is_phong(s, hid) && u[0] < kr) {
-                double r[3];
-                mirror_dir(w, n, r);
-                scatter_direction(r, pow(u[1], ge), 2.0 * kPiD * u[2], wn);
-                if (!(dot3(n, wn) > 0.0)) break;
-            } else {
-                scatter_direction(n, sqrt(u[1]), 2.0 * kPiD * u[2], wn);
-            }
-            p[0] = x[0];
-            p[1] = x[1];
-            p[2] = x[2];
-            w[0] = wn[0];
-            w[1] = wn[1];
-            w[2] = wn[2];
-            skip = hid;
-        }
-        st.B[i] = b;
-    }
+    const int npx = c.W * c.H;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= c.n * npx) return;
+    const int d = k / npx, p = k % npx;
+    omega[k] = pixel_omega(c.f[d], c.W, c.H, p / c.W, p % c.W);
 }
 
-// The theta-independent tape of every stored vertex (see the file comment).
+namespace {
+
+// The per-camera records of vertex b of path i at x (surface sid, normal n_,
+// mirror direction r): pixel (or -1 when the camera does not see x) and
+// {geometric factor, cosine of the camera direction to r}; a diffuse
+// vertex's factor includes rho/pi.  Returns the number of occlusion queries.
+__device__ __forceinline__ int camera_records(const SurfScene& s, const double* sph, const DevCams& c,
+                                              const SurfStore& st, int b, int64_t i, const double x[3], int sid,
+                                              const double n_[3], const double r[3], bool ph, double rho)
+{
+    const int64_t n = st.n;
+    const int npx = c.W * c.H;
+    int queries = 0;
+    for (int d = 0; d < c.n; ++d) {
+        const int64_t e = ((int64_t)b * c.n + d) * n + i;
+        int pix = project(c, d, x[0], x[1], x[2], 1.0);
+        double2 tc = make_double2(0.0, 0.0);
+        if (pix >= 0) {
+            double wc[3], dist;
+            unit_to(x, c.pos[d], wc, dist);
+            const double cn = dot3(n_, wc);
+            queries += cn > 0.0;
+            if (cn > 0.0 && !occluded(s, sph, sid, x, wc, dist)) {
+                const double geo = cn / (dist * dist) / st.omega[d * npx + pix];
+                tc = ph ? make_double2(geo, dot3(r, wc)) : make_double2(geo * rho / kPiD, 0.0);
+            } else {
+                pix = -1;
+            }
+        }
+        st.tc[e] = tc;
+        st.pix[e] = pix;
+    }
+    return queries;
+}
+
+// Drawn-direction record of a vertex: {cos to the mirror direction, cos to
+// the normal} of the direction to the next vertex at the unknown sphere,
+// {rho, -1} at a diffuse surface; the unknown sphere's last vertex (no next
+// vertex) gets {0, 0}: its flag still selects its BRDF for the local
+// estimates.
+__device__ __forceinline__ double2 direction_record(bool ph, double rho, bool has_next, const double x[3],
+                                                    const double y[3], const double n_[3], const double r[3])
+{
+    if (!ph) return make_double2(rho, -1.0);
+    if (!has_next) return make_double2(0.0, 0.0);
+    double w_out[3], len;
+    unit_to(x, y, w_out, len);
+    return make_double2(dot3(r, w_out), dot3(n_, w_out));
+}
+
+}  // namespace
+
+// The theta-independent tape of every stored vertex (see the file comment),
+// from the stored positions (imported stores).
 __global__ void __launch_bounds__(kSurfBlock) surf_tape_kernel(SurfScene s, DevCams c, SurfStore st)
 {
     __shared__ double lsph[5 * kMaxSpheres];
@@ -251,44 +299,109 @@ __global__ void __launch_bounds__(kSurfBlock) surf_tape_kernel(SurfScene s, DevC
             double r[3];
             mirror_dir(w_in, n_, r);
             const double rho = ph ? 0.0 : albedo_of(s, sph, sid);
-            // (the unknown sphere keeps a non-negative normal cosine even at
-            // a path's last vertex, which has no drawn direction: the flag
-            // selects its BRDF for the local estimates)
-            double2 tv = make_double2(rho, ph ? 0.0 : -1.0);
-            if (b + 1 < Bn) {
-                q = st.pos[(int64_t)(b + 1) * n + i];
-                const double y[3] = {q.x, q.y, q.z};
-                double w_out[3];
-                unit_to(x, y, w_out, len);
-                if (ph) tv = make_double2(dot3(r, w_out), dot3(n_, w_out));
-            }
-            st.tv[(int64_t)b * n + i] = tv;
-            for (int d = 0; d < c.n; ++d) {
-                const int64_t e = ((int64_t)b * c.n + d) * n + i;
-                int pix = project(c, d, x[0], x[1], x[2], 1.0);
-                double2 tc = make_double2(0.0, 0.0);
-                if (pix >= 0) {
-                    double wc[3], dist;
-                    unit_to(x, c.pos[d], wc, dist);
-                    const double cn = dot3(n_, wc);
-                    bool vis = cn > 0.0;
-                    for (int k = 0; k < s.n_spheres && vis; ++k)
-                        if (6 + k != sid && sphere_entry(sph, k, x, wc) < dist) vis = false;
-                    if (vis) {
-                        const double geo =
-                            cn / (dist * dist) / pixel_omega(c.f[d], c.W, c.H, pix / c.W, pix % c.W);
-                        tc = ph ? make_double2(geo, dot3(r, wc)) : make_double2(geo * rho / kPiD, 0.0);
-                    } else {
-                        pix = -1;
-                    }
-                }
-                st.tc[e] = tc;
-                st.pix[e] = pix;
-            }
+            const bool has_next = b + 1 < Bn;
+            if (has_next) q = st.pos[(int64_t)(b + 1) * n + i];
+            const double y[3] = {q.x, q.y, q.z};
+            st.tv[(int64_t)b * n + i] = direction_record(ph, rho, has_next, x, y, n_, r);
+            camera_records(s, sph, c, st, b, i, x, sid, n_, r, ph, rho);
             prev[0] = x[0];
             prev[1] = x[1];
             prev[2] = x[2];
         }
+    }
+}
+
+// Forward path tracing from the light at theta_ref (Sec. 3.4 with surfaces)
+// and the tape in one pass, one lane per path, FP64: a uniform direction from
+// the light, then at each vertex a cosine-weighted draw (diffuse) or the
+// mixture of a cosine-weighted and a Phong-lobe draw (unknown sphere; a lobe
+// draw below the surface ends the path).  Each vertex's camera records are
+// formed when it is found and its drawn-direction record when the next
+// vertex is found, from the positions as surf_tape_kernel forms them, so that
+// a store and an import of its exported paths hold the same tape.
+__global__ void __launch_bounds__(kSurfBlock) surf_draw_kernel(SurfScene s, DevCams c, SurfStore st, uint64_t seed,
+                                                                uint64_t first_id)
+{
+    __shared__ double lsph[5 * kMaxSpheres];
+    const double* sph = load_spheres(s, lsph);
+    const double kr = st.theta_ref[0], ge = 1.0 / (st.theta_ref[1] + 1.0);
+    const int M = s.max_order;
+    const int64_t n = st.n;
+    unsigned long long queries = 0, verts = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t id = first_id + (uint64_t)i;
+        double u[4];
+        uniforms4(seed, id, 0u, u);
+        const double mu0 = 1.0 - 2.0 * u[0], st0 = sqrt(fmax(0.0, 1.0 - mu0 * mu0));
+        double sp, cp;
+        sincos(2.0 * kPiD * u[1], &sp, &cp);
+        double w[3] = {st0 * cp, st0 * sp, mu0};
+        double p[3] = {s.light[0], s.light[1], s.light[2]};
+        // the previous vertex, whose drawn-direction record waits for this one
+        double xp[3] = {0.0, 0.0, 0.0}, np_[3] = {0.0, 0.0, 0.0}, rp[3] = {0.0, 0.0, 0.0};
+        bool php = false;
+        double rhop = 0.0;
+        int skip = -1, b = 0;
+        while (b < M) {
+            double t;
+            const int hid = nearest_surface(s, sph, p, w, skip, t);
+            ++queries;
+            if (hid < 0 || !isfinite(t)) break;
+            double x[3] = {p[0] + t * w[0], p[1] + t * w[1], p[2] + t * w[2]};
+            if (hid < 6) x[hid >> 1] = (hid & 1) ? s.box : 0.0;
+            st.pos[(int64_t)b * n + i] = make_double4(x[0], x[1], x[2], 0.0);
+            st.sid[(int64_t)b * n + i] = hid;
+            if (b > 0) st.tv[(int64_t)(b - 1) * n + i] = direction_record(php, rhop, true, xp, x, np_, rp);
+            // tape of this vertex: normal, arriving direction from the
+            // positions, mirror direction, camera records
+            const bool ph = is_phong(s, hid);
+            const double rho = ph ? 0.0 : albedo_of(s, sph, hid);
+            double n_[3], w_in[3], len, r[3];
+            surface_normal(sph, hid, x, n_);
+            unit_to(p, x, w_in, len);
+            mirror_dir(w_in, n_, r);
+            queries += camera_records(s, sph, c, st, b, i, x, hid, n_, r, ph, rho);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                xp[a] = x[a];
+                np_[a] = n_[a];
+                rp[a] = r[a];
+            }
+            php = ph;
+            rhop = rho;
+            ++b;
+            if (b == M) break;
+            uniforms4(seed, id, (uint32_t)b, u);
+            double wn[3];
+            if (ph && u[0] < kr) {
+                double rr[3];
+                mirror_dir(w, n_, rr);
+                scatter_direction(rr, pow(u[1], ge), 2.0 * kPiD * u[2], wn);
+                if (!(dot3(n_, wn) > 0.0)) break;
+            } else {
+                scatter_direction(n_, sqrt(u[1]), 2.0 * kPiD * u[2], wn);
+            }
+            p[0] = x[0];
+            p[1] = x[1];
+            p[2] = x[2];
+            w[0] = wn[0];
+            w[1] = wn[1];
+            w[2] = wn[2];
+            skip = hid;
+        }
+        if (b > 0) st.tv[(int64_t)(b - 1) * n + i] = direction_record(php, rhop, false, xp, xp, np_, rp);
+        st.B[i] = b;
+        verts += (unsigned long long)b;
+    }
+    // work of the draw: one nearest-surface query per traced ray and one
+    // occlusion query per in-image camera connection, n_spheres tests each
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        queries += __shfl_xor(queries, o);
+        verts += __shfl_xor(verts, o);
+    }
+    if (threadIdx.x % kWave == 0 && st.work) {
+        atomicAdd(&st.work[0], queries * (unsigned long long)s.n_spheres);
+        atomicAdd(&st.work[1], verts);
     }
 }
 
@@ -328,7 +441,7 @@ __global__ void __launch_bounds__(kSurfBlock) surf_render_kernel(SurfStore st, i
                 else
                     atomicAdd(&out[(int64_t)d * npx + pix], v);
             }
-            if (b + 1 < Bn) w *= ph ? P.f(tv.x) * tv.y / P.pdf_ref(tv.y, tv.x) : tv.x;
+            if (b + 1 < Bn) w *= ph ? P.carry(tv.x, tv.y) : tv.x;
         }
     }
     if (kLds) {
@@ -360,13 +473,7 @@ __global__ void __launch_bounds__(kSurfBlock) surf_grad_kernel(SurfStore st, int
     __shared__ double red[kSurfBlock / kWave];
     PhongTerms P;
     P.init(theta, st.theta_ref);
-    const double ig = P.kappa / (2.0 * kPiD);
-    // d f / d kappa, d f / d gamma at cosine c (with c^gamma given)
-    auto dlog = [&](double c, double f, double& dk, double& dg) {
-        const double l = P.lobe(c);
-        dk = (-1.0 / kPiD + (P.gamma + 2.0) / (2.0 * kPiD) * l) / f;
-        dg = c > 0.0 ? ig * l * (1.0 + (P.gamma + 2.0) * log(c)) / f : 0.0;
-    };
+    const double dka = -1.0 / kPiD, dkb = (P.gamma + 2.0) / (2.0 * kPiD), dgb = P.kappa / (2.0 * kPiD);
     double g0 = 0.0, g1 = 0.0;
     const int64_t n = st.n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -382,12 +489,13 @@ __global__ void __launch_bounds__(kSurfBlock) surf_grad_kernel(SurfStore st, int
                 const double2 tc = st.tc[e];
                 const double r = res[(int64_t)d * npx + pix];
                 if (ph) {
-                    const double f = P.f(tc.y);
-                    double dk, dg;
-                    dlog(tc.y, f, dk, dg);
-                    const double v = r * w * f * tc.x;
-                    g0 += v * (s0 + dk);
-                    g1 += v * (s1 + dg);
+                    // f, d f / d kappa, d f / d gamma at the camera cosine
+                    double lc;
+                    const double l = P.lobe_log(tc.y, lc);
+                    const double f = P.fa + P.fb * l;
+                    const double v = r * w * tc.x;
+                    g0 += v * (f * s0 + dka + dkb * l);
+                    g1 += v * (f * s1 + dgb * l * (1.0 + (P.gamma + 2.0) * lc));
                 } else {
                     const double v = r * w * tc.x;
                     g0 += v * s0;
@@ -396,12 +504,14 @@ __global__ void __launch_bounds__(kSurfBlock) surf_grad_kernel(SurfStore st, int
             }
             if (b + 1 < Bn) {
                 if (ph) {
-                    const double f = P.f(tv.x);
-                    double dk, dg;
-                    dlog(tv.x, f, dk, dg);
-                    s0 += dk;
-                    s1 += dg;
-                    w *= f * tv.y / P.pdf_ref(tv.y, tv.x);
+                    const double c = tv.x, nc = tv.y;
+                    const double lc = c > 0.0 ? log(c) : 0.0;
+                    const double l = c > 0.0 ? exp(P.gamma * lc) : 0.0, lr = c > 0.0 ? exp(P.rgamma * lc) : 0.0;
+                    const double f = P.fa + P.fb * l;
+                    const double fi = 1.0 / f;
+                    s0 += (dka + dkb * l) * fi;
+                    s1 += dgb * l * (1.0 + (P.gamma + 2.0) * lc) * fi;
+                    w *= f * nc / (P.ra * fmax(nc, 0.0) + P.rb * lr);
                 } else {
                     w *= tv.x;
                 }
@@ -422,10 +532,9 @@ __global__ void __launch_bounds__(kSurfBlock) surf_grad_kernel(SurfStore st, int
 __global__ void __launch_bounds__(kSurfBlock) surf_reweight_kernel(SurfStore st, const double* theta, double* part)
 {
     __shared__ double red[kSurfBlock / kWave];
-    const double ka = theta[0], ga = theta[1];
-    const double ta = (1.0 - ka) / kPiD, tb = ka * (ga + 1.0) / (2.0 * kPiD);
     PhongTerms P;
     P.init(theta, st.theta_ref);
+    const double ta = (1.0 - P.kappa) / kPiD, tb = P.kappa * (P.gamma + 1.0) / (2.0 * kPiD);
     double s1 = 0.0, s2 = 0.0;
     const int64_t n = st.n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -434,8 +543,10 @@ __global__ void __launch_bounds__(kSurfBlock) surf_reweight_kernel(SurfStore st,
         for (int b = 0; b + 1 < Bn; ++b) {
             const double2 tv = st.tv[(int64_t)b * n + i];
             if (tv.y < 0.0) continue;
-            const double pt = ta * fmax(tv.y, 0.0) + (tv.x > 0.0 ? tb * pow(tv.x, ga) : 0.0);
-            lr += log(pt) - log(P.pdf_ref(tv.y, tv.x));
+            const double c = tv.x, nc = fmax(tv.y, 0.0);
+            const double lc = c > 0.0 ? log(c) : 0.0;
+            const double l = c > 0.0 ? exp(P.gamma * lc) : 0.0, lrf = c > 0.0 ? exp(P.rgamma * lc) : 0.0;
+            lr += log((ta * nc + tb * l) / (P.ra * nc + P.rb * lrf));
         }
         const double r = exp(lr);
         s1 += r;
@@ -494,11 +605,18 @@ static unsigned surf_blocks(int64_t n, int n_cu, int per_cu)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)n_cu * per_cu));
 }
 
-hipError_t launch_surf_sample(hipStream_t stream, const SurfScene& s, const SurfStore& st, uint64_t seed,
-                              uint64_t first_id, int n_cu)
+hipError_t launch_surf_omega(hipStream_t stream, const DevCams& c, double* omega)
+{
+    const int k = c.n * c.W * c.H;
+    surf_omega_kernel<<<(k + 255) / 256, 256, 0, stream>>>(c, omega);
+    return hipGetLastError();
+}
+
+hipError_t launch_surf_draw(hipStream_t stream, const SurfScene& s, const DevCams& c, const SurfStore& st,
+                            uint64_t seed, uint64_t first_id, int n_cu)
 {
     if (st.n == 0) return hipSuccess;
-    surf_sample_kernel<<<surf_blocks(st.n, n_cu, 8), kSurfBlock, 0, stream>>>(s, st, seed, first_id);
+    surf_draw_kernel<<<surf_blocks(st.n, n_cu, 8), kSurfBlock, 0, stream>>>(s, c, st, seed, first_id);
     return hipGetLastError();
 }
 
@@ -512,7 +630,7 @@ hipError_t launch_surf_tape(hipStream_t stream, const SurfScene& s, const DevCam
 int surf_render_parts(int64_t n, int n_cams, int npx, int n_cu)
 {
     if ((int64_t)n_cams * npx * (int64_t)sizeof(double) > kSurfImageLds) return 0;
-    return (int)surf_blocks(n, n_cu, 2);
+    return (int)surf_blocks(n, n_cu, 4);
 }
 
 hipError_t launch_surf_render(hipStream_t stream, const SurfStore& st, int n_cams, int npx, double w0,

@@ -30,10 +30,16 @@ struct SurfStore {
     double2* tc;              // [M][n_cams][n] {geometric factor, cos of camera direction to mirror}
     int32_t* pix;             // [M][n_cams][n] pixel or -1
     const double* theta_ref;  // device [2]
+    const double* omega;      // [n_cams][W*H] pixel solid angles
+    unsigned long long* work; // [2]: ray-sphere tests and vertices of the last draw
 };
 
-hipError_t launch_surf_sample(hipStream_t stream, const SurfScene& s, const SurfStore& st, uint64_t seed,
-                              uint64_t first_id, int n_cu);
+// omega[d][p] = solid angle of pixel p of camera d
+hipError_t launch_surf_omega(hipStream_t stream, const DevCams& c, double* omega);
+// Draw st.n paths (ids first_id ..) at st.theta_ref with their tape.
+hipError_t launch_surf_draw(hipStream_t stream, const SurfScene& s, const DevCams& c, const SurfStore& st,
+                            uint64_t seed, uint64_t first_id, int n_cu);
+// The tape of the stored positions.
 hipError_t launch_surf_tape(hipStream_t stream, const SurfScene& s, const DevCams& c, const SurfStore& st, int n_cu);
 // Number of per-workgroup partial images the render writes (0: the images
 // exceed the LDS and the render adds into the output with FP64 atomics).

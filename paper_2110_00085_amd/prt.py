@@ -107,6 +107,7 @@ def lib():
                                     C.POINTER(_V)], C.c_int),
             "prt_surface_export": ([_V, _V, _V, _V, _V], C.c_int),
             "prt_surface_info": ([_V, C.POINTER(_I64), C.POINTER(_I32)], C.c_int),
+            "prt_surface_work": ([_V, _V, C.POINTER(_U64), C.POINTER(_U64)], C.c_int),
             "prt_surface_render": ([_V, _V, _V, _V], C.c_int),
             "prt_surface_grad": ([_V, _V, _V, _V, _V], C.c_int),
             "prt_surface_reweight": ([_V, _V, _V, _V], C.c_int),
@@ -412,6 +413,13 @@ def prt_surface_export(ctx, paths):
     sid = np.zeros((n, M), np.int32)
     _check(lib().prt_surface_export(ctx, paths, _hptr(B), _hptr(pos), _hptr(sid)))
     return B, pos, sid
+
+
+def prt_surface_work(ctx, paths):
+    """(ray-sphere tests, vertices) of the store's last draw."""
+    t, v = _U64(), _U64()
+    _check(lib().prt_surface_work(ctx, paths, C.byref(t), C.byref(v)))
+    return int(t.value), int(v.value)
 
 
 def prt_surface_render(ctx, paths, theta, images):

@@ -162,6 +162,28 @@ def test_surface_full_workload(env):
     st.close()
 
 
+def test_surface_draw_tape_equals_import_tape(env):
+    """A drawn store forms its tape while drawing; importing its exported
+    paths forms the tape from the positions alone.  Both describe the same
+    paths, so render, gradient and correction factors agree to the summation
+    order of the FP64 tallies."""
+    torch, P, api, ctx = env
+    scene, cams, n, ref, tt = _case("smallpaint16")
+    a = api.SurfacePaths.sample(ctx, scene, cams, ref, 123, n)
+    B, pos, sid = a.export()
+    b = api.SurfacePaths.from_host(ctx, scene, cams, ref, B, pos, sid)
+    th = torch.tensor(tt, dtype=torch.float64, device="cuda")
+    ia, ib = a.render(th).cpu().numpy(), b.render(th).cpu().numpy()
+    _close_img(ia, ib, 1e-13, "drawn vs imported tape")
+    res = torch.tensor(ia - ia.mean(), device="cuda")
+    ga, gb = a.grad(th, res).cpu().numpy(), b.grad(th, res).cpu().numpy()
+    assert np.all(np.abs(ga - gb) <= 1e-12 * np.abs(gb).max()), (ga, gb)
+    ra, rb = a.reweight(th).cpu().numpy(), b.reweight(th).cpu().numpy()
+    assert np.all(np.abs(ra - rb) <= 1e-12 * np.abs(rb)), (ra, rb)
+    a.close()
+    b.close()
+
+
 def test_surface_adam_matches_oracle(env):
     torch, P, api, ctx = env
     rng = np.random.default_rng(3)
