@@ -452,13 +452,40 @@ __global__ void __launch_bounds__(kSurfBlock) surf_render_kernel(SurfStore st, i
 }
 
 // out[k] = sum over the partial images in workgroup order.
-__global__ void surf_image_reduce_kernel(const double* __restrict__ part, int n_part, int ni, double* __restrict__ out)
+// out[k] = sum over the partial images of pixel k in a fixed order: a block
+// holds 16 pixels x 16 partial segments; each thread sums its segment's
+// partials (8 loads in flight, added in order), then the 16 segment sums of a
+// pixel are added in segment order.
+constexpr int kRedPix = 16, kRedSeg = 16;
+
+__global__ void __launch_bounds__(kRedPix * kRedSeg) surf_image_reduce_kernel(const double* __restrict__ part,
+                                                                              int n_part, int ni,
+                                                                              double* __restrict__ out)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ni) return;
+    __shared__ double seg[kRedSeg][kRedPix];
+    const int px = threadIdx.x % kRedPix, sg = threadIdx.x / kRedPix;
+    const int k = blockIdx.x * kRedPix + px;
+    const int per = (n_part + kRedSeg - 1) / kRedSeg;
+    const int j0 = sg * per, j1 = min(n_part, j0 + per);
     double acc = 0.0;
-    for (int j = 0; j < n_part; ++j) acc += part[(int64_t)j * ni + k];
-    out[k] = acc;
+    if (k < ni) {
+        int j = j0;
+        for (; j + 8 <= j1; j += 8) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(j + q) * ni + k];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += v[q];
+        }
+        for (; j < j1; ++j) acc += part[(int64_t)j * ni + k];
+    }
+    seg[sg][px] = acc;
+    __syncthreads();
+    if (sg == 0 && k < ni) {
+        double t = 0.0;
+        for (int q = 0; q < kRedSeg; ++q) t += seg[q][px];
+        out[k] = t;
+    }
 }
 
 // Loss gradient in (kappa_s, gamma) (Eq. loss_gradient with Eq.
@@ -562,13 +589,29 @@ __global__ void __launch_bounds__(kSurfBlock) surf_reweight_kernel(SurfStore st,
 
 // out[0..1] = sums of the pairs part[2j], part[2j+1] over j < n in order
 // (gradient); with stats set, out = {sum/n_paths, sum^2 / sum of squares}.
-__global__ void surf_pairs_kernel(const double* __restrict__ part, int n, double n_paths, int stats, double* out)
+// out[0..1] = sums of the pairs part[2j], part[2j+1] over j < n in a fixed
+// order (each of 256 threads sums a contiguous range, then the 256 range sums
+// are added in thread order); with stats set, out = {sum/n_paths, sum^2 / sum
+// of squares}.
+__global__ void __launch_bounds__(256) surf_pairs_kernel(const double* __restrict__ part, int n, double n_paths,
+                                                         int stats, double* out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double sa[256], sb[256];
+    const int per = (n + 255) / 256;
+    const int j0 = threadIdx.x * per, j1 = min(n, j0 + per);
     double a = 0.0, b = 0.0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = j0; j < j1; ++j) {
         a += part[2 * j];
         b += part[2 * j + 1];
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    a = b = 0.0;
+    for (int t = 0; t < 256; ++t) {
+        a += sa[t];
+        b += sb[t];
     }
     if (stats) {
         out[0] = a / n_paths;
@@ -643,7 +686,7 @@ hipError_t launch_surf_render(hipStream_t stream, const SurfStore& st, int n_cam
                                                                                           part);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        surf_image_reduce_kernel<<<(ni + 255) / 256, 256, 0, stream>>>(part, np, ni, img);
+        surf_image_reduce_kernel<<<(ni + kRedPix - 1) / kRedPix, kRedPix * kRedSeg, 0, stream>>>(part, np, ni, img);
         return hipGetLastError();
     }
     hipError_t e = launch_fill(stream, img, ni, 0.0);
@@ -662,7 +705,7 @@ hipError_t launch_surf_grad(hipStream_t stream, const SurfStore& st, int n_cams,
     surf_grad_kernel<<<nb, kSurfBlock, 0, stream>>>(st, n_cams, npx, w0, theta, res, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    surf_pairs_kernel<<<1, 64, 0, stream>>>(part, nb, 0.0, 0, grad);
+    surf_pairs_kernel<<<1, 256, 0, stream>>>(part, nb, 0.0, 0, grad);
     return hipGetLastError();
 }
 
@@ -673,7 +716,7 @@ hipError_t launch_surf_reweight(hipStream_t stream, const SurfStore& st, const d
     surf_reweight_kernel<<<nb, kSurfBlock, 0, stream>>>(st, theta, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    surf_pairs_kernel<<<1, 64, 0, stream>>>(part, nb, (double)st.n, 1, stats);
+    surf_pairs_kernel<<<1, 256, 0, stream>>>(part, nb, (double)st.n, 1, stats);
     return hipGetLastError();
 }
 
