@@ -222,3 +222,45 @@ def test_surface_loop_recovers_brdf(env):
     say(f"  theta {rec.theta_host()} eps {eps:.4f} after {len(recs)} iterations")
     assert eps < 0.10
     rec.close()
+
+
+def test_surface_argument_errors(env):
+    """Invalid scenes, cameras, theta_ref and path arrays are rejected before
+    any device work, with PRT_E_INVALID / PRT_E_CAPACITY and a message."""
+    torch, P, api, ctx = env
+    import dataclasses
+    scene = inputs.smallpaint(max_order=4)
+    cams = inputs.smallpaint_camera(scene, 8)
+    sh, ch = P.SurfaceSceneHost(scene), P.CamerasHost(cams)
+
+    def code(fn):
+        with pytest.raises(P.PrtError) as e:
+            fn()
+        return e.value.code
+
+    h = ctx.handle
+    assert code(lambda: P.prt_surface_sample(h, sh, ch, (1.0, 10.0), 1, 100)) == P.PRT_E_INVALID
+    assert code(lambda: P.prt_surface_sample(h, sh, ch, (0.5, -1.0), 1, 100)) == P.PRT_E_INVALID
+    assert code(lambda: P.prt_surface_sample(h, sh, ch, (0.5, 10.0), 1, 0)) == P.PRT_E_INVALID
+    bad_light = P.SurfaceSceneHost(dataclasses.replace(scene, light=np.array([0.5, 1.2, 0.5])))
+    assert code(lambda: P.prt_surface_sample(h, bad_light, ch, (0.5, 10.0), 1, 100)) == P.PRT_E_INVALID
+    in_sphere = P.SurfaceSceneHost(dataclasses.replace(scene, light=scene.centers[0].copy()))
+    assert code(lambda: P.prt_surface_sample(h, in_sphere, ch, (0.5, 10.0), 1, 100)) == P.PRT_E_INVALID
+    c2 = scene.centers.copy()
+    c2[1] = [0.99, 0.5, 0.5]
+    leaves = P.SurfaceSceneHost(dataclasses.replace(scene, centers=c2))
+    assert code(lambda: P.prt_surface_sample(h, leaves, ch, (0.5, 10.0), 1, 100)) == P.PRT_E_INVALID
+    deep = P.SurfaceSceneHost(dataclasses.replace(scene, max_order=P.PRT_MAX_ORDER + 1))
+    assert code(lambda: P.prt_surface_sample(h, deep, ch, (0.5, 10.0), 1, 100)) == P.PRT_E_CAPACITY
+    cam_in = inputs.cameras_at([scene.centers[0]], [[0.5, 0.5, 0.9]], 8, 8, 6.0)
+    assert code(lambda: P.prt_surface_sample(h, sh, P.CamerasHost(cam_in), (0.5, 10.0), 1, 100)) == P.PRT_E_INVALID
+    M = scene.max_order
+    B = np.array([2, 1], np.int32)
+    pos = np.full((2, M, 3), 0.5)
+    sid = np.zeros((2, M), np.int32)
+    sid[0, 1] = 6 + scene.n_spheres          # no such surface
+    assert code(lambda: P.prt_surface_import(h, sh, ch, (0.5, 10.0), B, pos, sid)) == P.PRT_E_INVALID
+    B[0] = M + 1
+    sid[0, 1] = 0
+    assert code(lambda: P.prt_surface_import(h, sh, ch, (0.5, 10.0), B, pos, sid)) == P.PRT_E_INVALID
+    assert "theta_ref" in P.prt_last_error() or "B outside" in P.prt_last_error()
