@@ -106,6 +106,10 @@ struct TraceArgs {
     // and, per connection, its own slab range lo | hi << 16 in the tape's
     // layout (0xffff when the connection has no weight)
     uint32_t* rtape;
+    // and, per row of 64 records (tape row r = record / 64) and camera group
+    // g, the union of that row's connection ranges at brange[r * groups + g]
+    // (0xffff when the row has no weighted connection in the group)
+    uint32_t* brange;
 };
 
 // Slabs of the binned gradient: layers of the grid along `axis`, `layers`

@@ -83,6 +83,8 @@ struct prt_ctx_s {
     size_t bin_part_bytes = 0;
     void* bin_rtape = nullptr;  // per-connection slab ranges (tape layout)
     size_t bin_rtape_bytes = 0;
+    void* bin_brange = nullptr; // per (row of 64 records, camera group) slab ranges
+    size_t bin_brange_bytes = 0;
     size_t rpart_bytes = 0;
     // sampling / sorting temporaries (grow-only)
     void* s_tmp = nullptr;
@@ -789,6 +791,7 @@ void prt_destroy(prt_ctx c)
     (void)hipFree(c->bin_list);
     (void)hipFree(c->bin_part);
     (void)hipFree(c->bin_rtape);
+    (void)hipFree(c->bin_brange);
     (void)hipFree(c->pb);
     (void)hipFree(c->s_tmp);
     (void)hipFree(c->s_keys);
@@ -1123,7 +1126,9 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
                  ensure_scratch(&c->bin_list, &c->bin_list_bytes,
                                 (std::max<size_t>(list_words, 1) + bins.n_slabs + 2) * sizeof(uint32_t)) == PRT_OK &&
                  ensure_scratch(&c->bin_part, &c->bin_part_bytes, grad_bin_partial_bytes(ds, bins, c->n_cu)) == PRT_OK &&
-                 ensure_scratch(&c->bin_rtape, &c->bin_rtape_bytes, recs * dc.n * sizeof(uint32_t)) == PRT_OK;
+                 ensure_scratch(&c->bin_rtape, &c->bin_rtape_bytes, recs * dc.n * sizeof(uint32_t)) == PRT_OK &&
+                 ensure_scratch(&c->bin_brange, &c->bin_brange_bytes,
+                                (recs / kWave + 1) * (size_t)(kinds - 1) * sizeof(uint32_t)) == PRT_OK;
         if (binned) {
             bins.cnt = (uint32_t*)c->bin_cnt;
             bins.list = (uint32_t*)c->bin_list;
@@ -1140,6 +1145,7 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
     if (binned) {
         a.trange = (int*)c->bin_trange;
         a.rtape = (uint32_t*)c->bin_rtape;
+        a.brange = (uint32_t*)c->bin_brange;
         a.bin_axis = bins.axis;
         a.bin_layers = bins.layers;
     }

@@ -681,6 +681,11 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
                     atomicMin(&a.trange[2 * t], max(lo, 0) / a.bin_layers);
                     atomicMax(&a.trange[2 * t + 1], min(hi, na - 1) / a.bin_layers);
                 }
+                if (lane == 0 && k < G)
+                    a.brange[((rec0 >> 6) + b) * G + k] =
+                        lo <= hi ? (uint32_t)(max(lo, 0) / a.bin_layers) |
+                                       (uint32_t)(min(hi, na - 1) / a.bin_layers) << 16
+                                 : 0xffffu;
             }
         }
         if (!act) continue;
@@ -914,7 +919,13 @@ __device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams&
         };
         int bmax = Bn;
         for (int o = kWave / 2; o > 0; o >>= 1) bmax = max(bmax, __shfl_xor(bmax, o));
+        // the union of a row's ranges skips rows without a walk in this slab
+        // (their vertex terms are zero too: a vertex term comes with a
+        // weighted connection, whose range holds the vertex's own layer)
+        const uint32_t* __restrict__ BR = a.brange + (rec0 >> 6) * G + kind;
         for (int b = 1; b <= bmax; ++b) {
+            const uint32_t br = BR[(int64_t)b * G];
+            if (sl < (br & 0xffffu) || sl > (br >> 16)) continue;
             uint32_t rr[kGroupCams];
 #pragma unroll
             for (int j = 0; j < kGroupCams; ++j)
