@@ -180,8 +180,8 @@ struct prt_surface_paths_s {
     double2* tc = nullptr;
     int32_t* pix = nullptr;
     double* theta_ref = nullptr;     // device [2]
-    double* sph = nullptr;           // device [kMaxSpheres][5]
-    double* omega = nullptr;         // pixel solid angles [n_cams][W*H]
+    double* sph = nullptr;           // device [kMaxSpheres][kSphStride]
+    double* omega = nullptr;         // reciprocal pixel solid angles [n_cams][W*H]
     int64_t cap_omega = 0;
     unsigned long long* work = nullptr;  // [2] sphere tests and vertices of the last draw
     double* part = nullptr;          // render partial images / gradient and reweight pairs
@@ -1694,16 +1694,18 @@ int surface_prepare(prt_ctx c, prt_surface_paths p, const prt_surface_scene* s, 
     }
     int rc;
     if (!p->theta_ref && (rc = dalloc(&p->theta_ref, 2))) return rc;
-    if (!p->sph && (rc = dalloc(&p->sph, (size_t)5 * kMaxSpheres))) return rc;
-    double h[5 * kMaxSpheres];
+    if (!p->sph && (rc = dalloc(&p->sph, (size_t)kSphStride * kMaxSpheres))) return rc;
+    double h[kSphStride * kMaxSpheres];
     for (int k = 0; k < s->n_spheres; ++k) {
-        for (int a = 0; a < 3; ++a) h[5 * k + a] = s->center[3 * k + a];
-        h[5 * k + 3] = s->radius[k];
-        h[5 * k + 4] = s->albedo[k];
+        for (int a = 0; a < 3; ++a) h[kSphStride * k + a] = s->center[3 * k + a];
+        h[kSphStride * k + 3] = s->radius[k];
+        h[kSphStride * k + 4] = s->albedo[k];
+        h[kSphStride * k + 5] = 1.0 / s->radius[k];
     }
     // (synchronous copies of host arrays that the caller may free on return)
     HIPCHK(hipMemcpy(p->theta_ref, theta_ref, 2 * sizeof(double), hipMemcpyHostToDevice));
-    if (s->n_spheres > 0) HIPCHK(hipMemcpy(p->sph, h, (size_t)5 * s->n_spheres * sizeof(double), hipMemcpyHostToDevice));
+    if (s->n_spheres > 0)
+        HIPCHK(hipMemcpy(p->sph, h, (size_t)kSphStride * s->n_spheres * sizeof(double), hipMemcpyHostToDevice));
     if ((rc = grow(&p->omega, &p->cap_omega, (int64_t)dc.n * dc.W * dc.H))) return rc;
     if (!p->work && (rc = dalloc(&p->work, 2))) return rc;
     HIPCHK(hipMemsetAsync(p->work, 0, 2 * sizeof(unsigned long long), c->stream));

@@ -41,8 +41,8 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3])
 __device__ __forceinline__ void sphere_terms(const double* sph, int k, const double p[3], const double w[3], double& b,
                                              double& disc)
 {
-    const double ox = p[0] - sph[5 * k], oy = p[1] - sph[5 * k + 1], oz = p[2] - sph[5 * k + 2];
-    const double r = sph[5 * k + 3];
+    const double ox = p[0] - sph[kSphStride * k], oy = p[1] - sph[kSphStride * k + 1], oz = p[2] - sph[kSphStride * k + 2];
+    const double r = sph[kSphStride * k + 3];
     b = ox * w[0] + oy * w[1] + oz * w[2];
     disc = b * b - (ox * ox + oy * oy + oz * oz - r * r);
 }
@@ -114,10 +114,10 @@ __device__ __forceinline__ void surface_normal(const double* sph, int sid, const
         return;
     }
     const int k = sid - 6;
-    const double ir = 1.0 / sph[5 * k + 3];
-    n[0] = (x[0] - sph[5 * k]) * ir;
-    n[1] = (x[1] - sph[5 * k + 1]) * ir;
-    n[2] = (x[2] - sph[5 * k + 2]) * ir;
+    const double ir = sph[kSphStride * k + 5];
+    n[0] = (x[0] - sph[kSphStride * k]) * ir;
+    n[1] = (x[1] - sph[kSphStride * k + 1]) * ir;
+    n[2] = (x[2] - sph[kSphStride * k + 2]) * ir;
 }
 
 __device__ __forceinline__ void mirror_dir(const double w[3], const double n[3], double r[3])
@@ -128,14 +128,20 @@ __device__ __forceinline__ void mirror_dir(const double w[3], const double n[3],
     r[2] = w[2] - c * n[2];
 }
 
-__device__ __forceinline__ void unit_to(const double a[3], const double b[3], double w[3], double& len)
+__device__ __forceinline__ void unit_to(const double a[3], const double b[3], double w[3], double& len, double& il)
 {
     const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
     len = sqrt(dx * dx + dy * dy + dz * dz);
-    const double il = 1.0 / len;
+    il = 1.0 / len;
     w[0] = dx * il;
     w[1] = dy * il;
     w[2] = dz * il;
+}
+
+__device__ __forceinline__ void unit_to(const double a[3], const double b[3], double w[3], double& len)
+{
+    double il;
+    unit_to(a, b, w, len, il);
 }
 
 // Does surface sid carry the unknown BRDF?  (phong < 0: no sphere does)
@@ -143,7 +149,7 @@ __device__ __forceinline__ bool is_phong(const SurfScene& s, int sid) { return s
 
 __device__ __forceinline__ double albedo_of(const SurfScene& s, const double* sph, int sid)
 {
-    return sid < 6 ? s.wall_albedo[sid] : sph[5 * (sid - 6) + 4];
+    return sid < 6 ? s.wall_albedo[sid] : sph[kSphStride * (sid - 6) + 4];
 }
 
 // Exact solid angle of pixel (row, col) of a pinhole camera with focal length
@@ -159,7 +165,7 @@ __device__ __forceinline__ double pixel_omega(double f, int W, int H, int row, i
 // The spheres (centre, radius, albedo) into LDS, shared by the workgroup.
 __device__ __forceinline__ const double* load_spheres(const SurfScene& s, double* lds)
 {
-    for (int i = threadIdx.x; i < 5 * s.n_spheres; i += blockDim.x) lds[i] = s.sph[i];
+    for (int i = threadIdx.x; i < kSphStride * s.n_spheres; i += blockDim.x) lds[i] = s.sph[i];
     __syncthreads();
     return lds;
 }
@@ -216,14 +222,15 @@ __device__ __forceinline__ double block_sum(double x, double* lds)
 
 }  // namespace
 
-// Pixel solid angles of every camera, once per draw: omega[d * npx + p].
+// Reciprocal pixel solid angles of every camera, once per draw:
+// omega[d * npx + p] = 1 / Omega.
 __global__ void surf_omega_kernel(DevCams c, double* omega)
 {
     const int npx = c.W * c.H;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= c.n * npx) return;
     const int d = k / npx, p = k % npx;
-    omega[k] = pixel_omega(c.f[d], c.W, c.H, p / c.W, p % c.W);
+    omega[k] = 1.0 / pixel_omega(c.f[d], c.W, c.H, p / c.W, p % c.W);
 }
 
 namespace {
@@ -244,12 +251,12 @@ __device__ __forceinline__ int camera_records(const SurfScene& s, const double* 
         int pix = project(c, d, x[0], x[1], x[2], 1.0);
         double2 tc = make_double2(0.0, 0.0);
         if (pix >= 0) {
-            double wc[3], dist;
-            unit_to(x, c.pos[d], wc, dist);
+            double wc[3], dist, idist;
+            unit_to(x, c.pos[d], wc, dist, idist);
             const double cn = dot3(n_, wc);
             queries += cn > 0.0;
             if (cn > 0.0 && !occluded(s, sph, sid, x, wc, dist)) {
-                const double geo = cn / (dist * dist) / st.omega[d * npx + pix];
+                const double geo = cn * (idist * idist) * st.omega[d * npx + pix];
                 tc = ph ? make_double2(geo, dot3(r, wc)) : make_double2(geo * rho / kPiD, 0.0);
             } else {
                 pix = -1;
@@ -282,7 +289,7 @@ __device__ __forceinline__ double2 direction_record(bool ph, double rho, bool ha
 // from the stored positions (imported stores).
 __global__ void __launch_bounds__(kSurfBlock) surf_tape_kernel(SurfScene s, DevCams c, SurfStore st)
 {
-    __shared__ double lsph[5 * kMaxSpheres];
+    __shared__ double lsph[kSphStride * kMaxSpheres];
     const double* sph = load_spheres(s, lsph);
     const int64_t n = st.n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -322,7 +329,7 @@ __global__ void __launch_bounds__(kSurfBlock) surf_tape_kernel(SurfScene s, DevC
 __global__ void __launch_bounds__(kSurfBlock) surf_draw_kernel(SurfScene s, DevCams c, SurfStore st, uint64_t seed,
                                                                 uint64_t first_id)
 {
-    __shared__ double lsph[5 * kMaxSpheres];
+    __shared__ double lsph[kSphStride * kMaxSpheres];
     const double* sph = load_spheres(s, lsph);
     const double kr = st.theta_ref[0], ge = 1.0 / (st.theta_ref[1] + 1.0);
     const int M = s.max_order;

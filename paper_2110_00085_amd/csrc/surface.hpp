@@ -8,6 +8,8 @@
 namespace prt {
 
 constexpr int kMaxSpheres = 64;
+// per sphere in the device table: centre (3), radius, albedo, 1 / radius
+constexpr int kSphStride = 6;
 // largest set of images tallied in one workgroup's LDS (FP64)
 constexpr int64_t kSurfImageLds = 64 * 1024;
 
@@ -17,7 +19,7 @@ struct SurfScene {
     double light[3];
     double intensity;         // radiant intensity of the point light
     int n_spheres, phong, max_order;
-    const double* sph;        // device [n_spheres][5]: centre, radius, albedo
+    const double* sph;        // device [n_spheres][kSphStride]
 };
 
 // Device view of a store of surface paths (rows of n paths per vertex order).
@@ -30,11 +32,11 @@ struct SurfStore {
     double2* tc;              // [M][n_cams][n] {geometric factor, cos of camera direction to mirror}
     int32_t* pix;             // [M][n_cams][n] pixel or -1
     const double* theta_ref;  // device [2]
-    const double* omega;      // [n_cams][W*H] pixel solid angles
+    const double* omega;      // [n_cams][W*H] reciprocal pixel solid angles
     unsigned long long* work; // [2]: ray-sphere tests and vertices of the last draw
 };
 
-// omega[d][p] = solid angle of pixel p of camera d
+// omega[d][p] = 1 / solid angle of pixel p of camera d
 hipError_t launch_surf_omega(hipStream_t stream, const DevCams& c, double* omega);
 // Draw st.n paths (ids first_id ..) at st.theta_ref with their tape.
 hipError_t launch_surf_draw(hipStream_t stream, const SurfScene& s, const DevCams& c, const SurfStore& st,
