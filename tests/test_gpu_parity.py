@@ -121,6 +121,20 @@ def _workload(name):
         s = inputs.random_field((96, 96, 12), voxel_km=0.02, lo=0.0, hi=25.0, seed=96, albedo_cloud=0.99,
                                 g=0.85, max_order=10)
         return s, inputs.arc_cameras(s, [-40.0, 0.0, 40.0], 24, 24), 6_007, 1096
+    if name == "sparse64":
+        # 64 x 64 x 32 grid (512 KB, walked in global memory) holding four
+        # cloud blobs in clear air: the render's connection walks cross the
+        # cloud-free bricks of 8^3 voxels in one step each
+        rng = np.random.default_rng(64)
+        nx, ny, nz = 64, 64, 32
+        z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+        inside = np.zeros((nz, ny, nx), bool)
+        for _ in range(4):
+            cx, cy, cz, r = rng.uniform(12, 52), rng.uniform(12, 52), rng.uniform(8, 24), rng.uniform(4, 9)
+            inside |= ((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2) <= r * r
+        beta = np.where(inside, rng.lognormal(3.0, 0.6, (nz, ny, nx)), 0.0).astype(np.float32)
+        s = inputs.Scene(nx, ny, nz, 0.02, beta, albedo_cloud=0.99, g=0.85, max_order=12)
+        return s, inputs.arc_cameras(s, [-45.0, 0.0, 30.0], 32, 32), 20_003, 1064
     if name == "manycams":
         # 20 cameras of 48 x 48: the FP32 image partials (184 KB) exceed the LDS,
         # so renders of fewer orders (no tape) fall back to FP64 atomics on the
@@ -227,7 +241,7 @@ def test_sample_fp32_close_to_oracle(env, name):
 # ---------------------------------------------- render / grad / reweight
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "slabs40", "wide96", "manycams", "incam"])
+@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "slabs40", "wide96", "sparse64", "manycams", "incam"])
 def test_render_grad_reweight_match_oracle(env, prec, name):
     torch, P, api = env
     scene, cams, n, seed = _workload(name)
