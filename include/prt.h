@@ -126,13 +126,21 @@ int prt_create(int device, void* hip_stream, int precision, prt_ctx* out);
 void prt_destroy(prt_ctx ctx);
 int prt_set_stream(prt_ctx ctx, void* hip_stream);
 /* Largest temporary, in bytes, that prt_sample / prt_resample may allocate to
-   draw the paths in one pass (n_paths * (max_order + 2) vertex records of
-   16 bytes, held until the paths are sorted).  A resample that would need
-   more draws every path twice from its Philox stream: first only its size
-   and sort key, then, once the sort (Sec. 5.3) has fixed its place, its
-   vertices straight into the store.  Both give the same store; the second
-   pass checks every path's size against the first and fails with PRT_E_HIP
-   otherwise.  Default 8 GiB; 0 always takes two passes. */
+   draw the paths in one pass (kept by the context for later draws).  A draw
+   takes, in this order of preference: whole rows of max_order + 2 vertex
+   records of 16 bytes per path; rows of 2 records per path (entry and exit:
+   all a path without a scatter needs) plus a pool of blocks of max_order
+   records for the paths that scatter, sized from the store's previous draw
+   with a margin (a new store takes all the limit leaves and needs room for
+   a quarter of its paths), cut to what the limit leaves, and claimed by the
+   sampler's wavefronts as they go, with 4 bytes per path for the block
+   index; or, when neither fits (the pool does not hold the estimate), or
+   the pool runs out, two passes per path
+   from its Philox stream: first only its size and sort key, then, once the
+   sort (Sec. 5.3) has fixed its place, its vertices straight into the store.
+   All give the same store; the second pass checks every path's size against
+   the first and fails with PRT_E_HIP otherwise.  Default 40 GiB; 0 always
+   takes two passes. */
 int prt_set_sample_scratch_limit(prt_ctx ctx, uint64_t bytes);
 /* Thread-local text of the last error (never NULL). */
 const char* prt_last_error(void);

@@ -36,7 +36,18 @@ struct SampleArgs {
     const void* grid_tot;  // Real[N_u]: beta_c + beta_air
     uint64_t seed;
     int64_t n;
-    float4* tmp;           // [n][max_order+2] records, or null
+    float4* tmp;           // [n][tmp_rows] records, or null
+    // Short temporary rows (tmp_rows < max_order+2): a path's records from
+    // tmp_rows on go to a block of the overflow pool (max_order+2-tmp_rows
+    // records at ovf[ovf_slot[id] * that]); wavefronts claim blocks in chunks
+    // from *ovf_next (a block count), and a path that finds the ovf_cap
+    // blocks used up sets *ovf_full and stores no more.
+    int tmp_rows;
+    float4* ovf;
+    int64_t ovf_cap;
+    unsigned long long* ovf_next;
+    int32_t* ovf_slot;
+    int* ovf_full;
     float4* vtx;           // packed store records, or null
     const int64_t* batch_off;
     const int32_t* inv;    // path id -> sorted slot
@@ -162,9 +173,13 @@ hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint
 int64_t sort_scratch_words(int64_t n, int nbins);
 // scratch: the sort's scratch (sort_scratch_words(64 * nb, ...) words) may be reused.
 hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, int64_t* batch_off, void* scratch);
+// Record k of the path in slot i: tmp[(tmp_off ? tmp_off[id] : id * tmp_stride) + k],
+// or, with an overflow pool and k >= tmp_stride,
+// ovf[ovf_slot[id] * ovf_block + k - tmp_stride].
 hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, const int64_t* tmp_off,
                        int64_t tmp_stride, const uint8_t* nv, const int64_t* batch_off, int64_t n,
-                       int64_t n_slots, float4* vtx);
+                       int64_t n_slots, float4* vtx, const float4* ovf = nullptr, const int32_t* ovf_slot = nullptr,
+                       int ovf_block = 0);
 // meta[0] = batch_off[nb] (records), meta[1] = first slot with B > 0 (n if
 // none), meta[2] = batch_off of that slot's batch (records of B = 0 batches),
 // meta[kMetaFirstGe + k] = first slot with B >= k (n if none), k = 1..kMaxOrder.

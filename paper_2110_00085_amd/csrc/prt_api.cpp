@@ -57,6 +57,7 @@ struct Timed {
 };
 
 constexpr int kMismatchWord = 6;
+constexpr int kOvfFullWord = 7;
 
 }  // namespace
 
@@ -89,6 +90,8 @@ struct prt_ctx_s {
     // sampling / sorting temporaries (grow-only)
     void* s_tmp = nullptr;
     size_t s_tmp_bytes = 0;
+    void* s_ovf = nullptr;      // overflow block counter (16 bytes), then a block per path id
+    size_t s_ovf_bytes = 0;
     void* s_keys = nullptr;     // tB and tnv
     size_t s_keys_bytes = 0;
     void* s_hist = nullptr;
@@ -97,7 +100,7 @@ struct prt_ctx_s {
     void* s_perm = nullptr;     // permutation after the sort's first pass, then id -> slot
     size_t s_perm_bytes = 0;
     // largest one-pass sampling temporary; larger resamples take two passes
-    uint64_t sample_tmp_limit = (uint64_t)8 << 30;
+    uint64_t sample_tmp_limit = (uint64_t)40 << 30;
     size_t s_off_bytes = 0;
     // pinned host words the kernels write directly (read after a stream sync):
     // the store's meta words after packing (words 0-2 and kMetaFirstGe on),
@@ -518,17 +521,26 @@ int layout_store(prt_ctx c, prt_paths p, const uint8_t* tB, const uint8_t* tnv, 
 // Sort temporary paths (rows of tmp addressed by tmp_off, CSR, or by
 // id * tmp_stride) into the store.
 int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_off, int64_t tmp_stride,
-                const uint8_t* tB, const uint8_t* tnv, const uint16_t* tC)
+                const uint8_t* tB, const uint8_t* tnv, const uint16_t* tC, const float4* ovf = nullptr,
+                const int32_t* ovf_slot = nullptr, int ovf_block = 0)
 {
     int rc;
     if ((rc = layout_store(c, p, tB, tnv, tC, nullptr))) return rc;
     const int64_t n = (int64_t)p->n;
     {
         TimedScope ts(c, K_PACK);
-        HIPCHK(launch_pack(c->stream, p->perm, tmp, tmp_off, tmp_stride, p->nv, p->batch_off, n, p->n_slots, p->vtx));
+        HIPCHK(launch_pack(c->stream, p->perm, tmp, tmp_off, tmp_stride, p->nv, p->batch_off, n, p->n_slots, p->vtx,
+                           ovf, ovf_slot, ovf_block));
     }
     return PRT_OK;
 }
+
+// Records per path in the short rows of a one-pass draw that does not fit
+// whole rows: an entry and an exit, all a path without a scatter needs.
+constexpr int kShortRows = 2;
+// Overflow blocks a wavefront claims at a time (as the sampler's chunk): a
+// wavefront leaves fewer than this many unused.
+constexpr int64_t kOvfChunk = 16;
 
 // Samples n paths into p (allocated or reused) under scene->beta_cloud.  When
 // the one-pass temporary (max_order+2 records per path) would exceed the
@@ -540,12 +552,37 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
     const int64_t stride = s->max_order + 2;
     const bool one_pass = (uint64_t)n * (uint64_t)stride * sizeof(float4) <= c->sample_tmp_limit;
+    // otherwise short rows and an overflow pool of blocks of `per` records.
+    // A refill estimates its scattering paths from the store's previous draw
+    // (scaled to n) and takes a quarter more plus the chunks the sampler's
+    // wavefronts (1024 threads per workgroup, at most two workgroups per CU)
+    // may leave unused; a new store assumes a quarter of its paths scatter
+    // and takes as many blocks as the limit leaves.  Either is cut to what
+    // the limit leaves and used when it still holds the estimate.
+    const int64_t per = stride - kShortRows;
+    int64_t ovf_blocks = 0;
+    bool compact = false;
+    const uint64_t rows_bytes = (uint64_t)n * (kShortRows * sizeof(float4) + sizeof(int32_t));
+    if (!one_pass && per > 0 && rows_bytes < c->sample_tmp_limit) {
+        const bool refill = p->n_records > 0 && p->n > 0 && p->first_slot <= (int64_t)p->n;
+        const int64_t est =
+            refill ? (int64_t)((double)((int64_t)p->n - p->first_slot) / (double)p->n * (double)n) : n / 4;
+        const int64_t waves = std::min<int64_t>((n + 1023) / 1024, (int64_t)c->n_cu * 2) * (1024 / kWave);
+        const int64_t fit = (int64_t)((c->sample_tmp_limit - rows_bytes) / ((uint64_t)per * sizeof(float4)));
+        ovf_blocks = std::min<int64_t>(std::min<int64_t>(n, refill ? est + est / 4 + kOvfChunk * waves : n), fit);
+        compact = ovf_blocks >= est && ovf_blocks > 0 && ovf_blocks < ((int64_t)1 << 31);
+    }
     int rc;
     // earlier work may still read the store's or the context's buffers
     HIPCHK(hipDeviceSynchronize());
     if ((rc = ensure_grids(c, nu))) return rc;
     if ((rc = grow(&p->beta_ref, &p->cap_nu, nu))) return rc;
     if (one_pass && (rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes, (size_t)n * stride * sizeof(float4)))) return rc;
+    if (compact &&
+        ((rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes,
+                              ((size_t)n * kShortRows + (size_t)ovf_blocks * per) * sizeof(float4))) ||
+         (rc = ensure_scratch(&c->s_ovf, &c->s_ovf_bytes, (size_t)n * sizeof(int32_t) + 16))))
+        return rc;
     if ((rc = ensure_scratch(&c->s_keys, &c->s_keys_bytes, 4 * (size_t)n))) return rc;
     p->n = (uint64_t)n;
     p->seed = seed;
@@ -570,7 +607,18 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     a.grid_tot = c->grid_tot;
     a.seed = seed;
     a.n = n;
-    a.tmp = one_pass ? (float4*)c->s_tmp : nullptr;
+    a.tmp = (one_pass || compact) ? (float4*)c->s_tmp : nullptr;
+    a.tmp_rows = compact ? kShortRows : (int)stride;
+    a.ovf = compact ? (float4*)c->s_tmp + (size_t)n * kShortRows : nullptr;
+    a.ovf_cap = compact ? ovf_blocks : 0;
+    a.ovf_next = compact ? (unsigned long long*)c->s_ovf : nullptr;
+    a.ovf_slot = compact ? (int32_t*)((unsigned char*)c->s_ovf + 16) : nullptr;
+    a.ovf_full = compact ? (int*)(c->dmeta + kOvfFullWord) : nullptr;
+    volatile int* ovf_full = (volatile int*)(c->hmeta + kOvfFullWord);
+    if (compact) {
+        *ovf_full = 0;
+        HIPCHK(hipMemsetAsync(c->s_ovf, 0, 16, c->stream));
+    }
     a.vtx = nullptr;
     a.batch_off = nullptr;
     a.inv = nullptr;
@@ -584,6 +632,14 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
         HIPCHK(launch_sample(c->stream, c->fp64, a, c->n_cu));
     }
     if (one_pass) return build_store(c, p, (const float4*)c->s_tmp, nullptr, stride, tB, tnv, tC);
+    if (compact) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (*ovf_full == 0)
+            return build_store(c, p, (const float4*)c->s_tmp, nullptr, kShortRows, tB, tnv, tC, a.ovf, a.ovf_slot,
+                               (int)per);
+        // the pool ran out: the sizes and keys are complete, so the second
+        // pass of the two-pass draw finishes the store
+    }
     int32_t* inv = nullptr;
     if ((rc = layout_store(c, p, tB, tnv, tC, &inv))) return rc;
     // second pass: padding rows are zero, the sampler writes every path's records
@@ -591,6 +647,13 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     *mismatch = 0;
     HIPCHK(hipMemsetAsync(p->vtx, 0, (size_t)p->n_records * sizeof(float4), c->stream));
     HIPCHK(hipMemsetAsync(c->work + 2, 0, sizeof(unsigned int), c->stream));
+    a.tmp = nullptr;
+    a.tmp_rows = (int)stride;
+    a.ovf = nullptr;
+    a.ovf_cap = 0;
+    a.ovf_next = nullptr;
+    a.ovf_slot = nullptr;
+    a.ovf_full = nullptr;
     a.vtx = p->vtx;
     a.batch_off = p->batch_off;
     a.inv = inv;
@@ -794,6 +857,7 @@ void prt_destroy(prt_ctx c)
     (void)hipFree(c->bin_brange);
     (void)hipFree(c->pb);
     (void)hipFree(c->s_tmp);
+    (void)hipFree(c->s_ovf);
     (void)hipFree(c->s_keys);
     (void)hipFree(c->s_hist);
     (void)hipFree(c->s_off);

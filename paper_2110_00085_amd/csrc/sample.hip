@@ -90,6 +90,19 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
     const int stride = s.max_order + 2;
     const int lane = threadIdx.x % kWave;
     const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;  // lanes under this one
+    // short temporary rows: records from R on go to an overflow block, taken
+    // from the wavefront's chunk of blocks [chunk[w][0], chunk[w][1])
+    const bool compact = a.tmp && a.tmp_rows < stride;
+    const int R = compact ? a.tmp_rows : stride;
+    const int per = stride - R;
+    constexpr int kChunkBlocks = 16;
+    __shared__ unsigned long long chunk[kSampleBlock / kWave][2];
+    if (lane == 0) {
+        chunk[threadIdx.x / kWave][0] = 0;
+        chunk[threadIdx.x / kWave][1] = 0;
+    }
+    __syncthreads();
+    int64_t oblk = -1;  // this path's overflow block (-2: none left)
     // path state and event arithmetic in the traversal precision
     using E = Real;
     int64_t id = 0;
@@ -124,8 +137,9 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
             if (!active && rank < take) {
                 // start path nid at the source
                 id = nid;
+                oblk = -1;
                 if (a.tmp) {
-                    out = a.tmp + id * stride;
+                    out = a.tmp + id * R;
                     ostr = 1;
                 } else if (a.vtx) {
                     const int64_t sl = a.inv[id];
@@ -186,9 +200,59 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
         }
         // the division that places the scatter inside its voxel stays out of the loop
         if (hit >= 0) thit += (taur - acc) / gt[hit];
+        // this event writes record nv: past the short row it goes to the
+        // path's overflow block, taken now from the wavefront's chunk
+        if (compact) {
+            const bool need = nv == R && oblk == -1;
+            const uint64_t m = __ballot(need);
+            if (m) {
+                // the first `old` lanes (in lane order) take the rest of the
+                // chunk, the others the start of a new chunk claimed for them
+                const int lead = __ffsll((unsigned long long)m) - 1;
+                const unsigned long long cnt = (unsigned long long)__popcll(m);
+                unsigned long long base = 0, old = 0, fresh = 0;
+                if (lane == lead) {
+                    const int w = threadIdx.x / kWave;
+                    unsigned long long c0 = chunk[w][0], c1 = chunk[w][1];
+                    base = c0;
+                    old = min(cnt, c1 - c0);
+                    c0 += old;
+                    if (old < cnt) {
+                        const unsigned long long take = max(cnt - old, (unsigned long long)kChunkBlocks);
+                        fresh = atomicAdd(a.ovf_next, take);
+                        c0 = fresh + (cnt - old);
+                        c1 = fresh + take;
+                    }
+                    chunk[w][0] = c0;
+                    chunk[w][1] = c1;
+                }
+                base = __shfl(base, lead);
+                old = __shfl(old, lead);
+                fresh = __shfl(fresh, lead);
+                if (need) {
+                    const unsigned long long r = (unsigned long long)__popcll(m & below);
+                    const unsigned long long blk = r < old ? base + r : fresh + (r - old);
+                    if ((int64_t)blk < a.ovf_cap) {
+                        oblk = (int64_t)blk;
+                        a.ovf_slot[id] = (int32_t)blk;
+                    } else {
+                        oblk = -2;
+                        *a.ovf_full = 1;
+                    }
+                }
+            }
+        }
+        // record k of the path: the short row, the overflow block, the store
+        auto put = [&](int k, float4 r) {
+            if (k < R) {
+                if (out) out[k * ostr] = r;
+            } else if (oblk >= 0) {
+                a.ovf[oblk * per + (k - R)] = r;
+            }
+        };
         bool done;
         if (hit < 0) {
-            if (out) out[nv * ostr] = vrec(x + tend * w[0], y + tend * w[1], z + tend * w[2], -1);
+            put(nv, vrec(x + tend * w[0], y + tend * w[1], z + tend * w[2], -1));
             ++nv;
             done = true;
         } else {
@@ -196,7 +260,7 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
             y = y + thit * w[1];
             z = z + thit * w[2];
             ++b;
-            if (out) out[nv * ostr] = vrec(x, y, z, hit);
+            put(nv, vrec(x, y, z, hit));
             ++nv;
             if (b == 1) v0 = hit;  // the sort key follows the first scatter
             done = b >= s.max_order;
@@ -497,7 +561,9 @@ __global__ void __launch_bounds__(256) pack_kernel(const int32_t* __restrict__ p
                                                    const int64_t* __restrict__ tmp_off, int64_t tmp_stride,
                                                    const uint8_t* __restrict__ nv,
                                                    const int64_t* __restrict__ batch_off, int64_t n,
-                                                   int64_t n_slots, float4* __restrict__ vtx)
+                                                   int64_t n_slots, float4* __restrict__ vtx,
+                                                   const float4* __restrict__ ovf, const int32_t* __restrict__ ovf_slot,
+                                                   int ovf_block)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_slots) return;
@@ -506,15 +572,20 @@ __global__ void __launch_bounds__(256) pack_kernel(const int32_t* __restrict__ p
     float4* dst = vtx + batch_off[b] + lane;
     const int cnt = i < n ? (int)nv[i] : 0;
     const float4* src = nullptr;
+    const float4* src2 = nullptr;  // records from tmp_stride on (overflow pool)
     if (i < n) {
         const int64_t id = perm[i];
         src = tmp + (tmp_off ? tmp_off[id] : id * tmp_stride);
+        if (ovf && cnt > tmp_stride) src2 = ovf + (int64_t)ovf_slot[id] * ovf_block;
     }
     // kPackLoads records of the path in flight at a time
     for (int64_t k0 = 0; k0 < rows; k0 += kPackLoads) {
         float4 r[kPackLoads];
 #pragma unroll
-        for (int j = 0; j < kPackLoads; ++j) r[j] = k0 + j < cnt ? src[k0 + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int j = 0; j < kPackLoads; ++j) {
+            const int64_t k = k0 + j;
+            r[j] = k < cnt ? (src2 && k >= tmp_stride ? src2[k - tmp_stride] : src[k]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
 #pragma unroll
         for (int j = 0; j < kPackLoads; ++j)
             if (k0 + j < rows) dst[(k0 + j) * kWave] = r[j];
@@ -523,10 +594,10 @@ __global__ void __launch_bounds__(256) pack_kernel(const int32_t* __restrict__ p
 
 hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, const int64_t* tmp_off,
                        int64_t tmp_stride, const uint8_t* nv, const int64_t* batch_off, int64_t n, int64_t n_slots,
-                       float4* vtx)
+                       float4* vtx, const float4* ovf, const int32_t* ovf_slot, int ovf_block)
 {
-    pack_kernel<<<dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, st>>>(perm, tmp, tmp_off, tmp_stride, nv,
-                                                                              batch_off, n, n_slots, vtx);
+    pack_kernel<<<dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, st>>>(
+        perm, tmp, tmp_off, tmp_stride, nv, batch_off, n, n_slots, vtx, ovf, ovf_slot, ovf_block);
     return hipGetLastError();
 }
 

@@ -219,6 +219,53 @@ def test_two_pass_resample_equals_one_pass(env, prec):
             assert np.array_equal(x, y), name
 
 
+def _sample_launches(P, ctx):
+    return P.prt_kernel_times(ctx.handle, reset=True)["sample"][1]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_compact_draw_equals_one_pass(env, prec):
+    """With a temporary limit just under whole rows, a draw writes short rows
+    plus an overflow pool in one sampler launch; the store equals the one-pass
+    store bit for bit.  A refill whose pool, sized from a nearly empty field's
+    draw, runs out finishes with the second pass of the two-pass draw (two
+    launches) and still gives the same store."""
+    torch, P, api = env
+    say(f"compact draw {prec}")
+    for name in ("cloud8", "cloud32mid"):
+        scene, _, n, seed = _workload(name)
+        bd = _dev(torch, scene.beta_cloud)
+        thin = _dev(torch, scene.beta_cloud * 1e-3)
+        one = api.Context(0, _prec(P, prec))
+        cmp_ = api.Context(0, _prec(P, prec))
+        P.prt_set_sample_scratch_limit(cmp_.handle, n * (scene.max_order + 2) * 16 - 1)
+        P.prt_enable_timing(cmp_.handle, True)
+        a = api.PathStore.sample(one, scene, bd, seed, n)
+        b = api.PathStore.sample(cmp_, scene, bd, seed, n)
+        assert _sample_launches(P, cmp_) == 1, name
+        for x, y in zip(a.export(), b.export()):
+            assert np.array_equal(x, y), name
+        assert np.array_equal(P.prt_paths_permutation(one.handle, a.handle),
+                              P.prt_paths_permutation(cmp_.handle, b.handle))
+        # a larger refill, its pool sized from this store's draw
+        a.resample(scene, bd, seed + 1, n + 5)
+        b.resample(scene, bd, seed + 1, n + 5)
+        assert _sample_launches(P, cmp_) == 1, name
+        for x, y in zip(a.export(), b.export()):
+            assert np.array_equal(x, y), name
+        if name == "cloud8":
+            # about 35% of cloud8's paths scatter, more than the pool that a
+            # draw in a field a thousand times thinner leaves room for
+            a.resample(scene, thin, seed + 2, n)
+            b.resample(scene, thin, seed + 2, n)
+            _sample_launches(P, cmp_)
+            a.resample(scene, bd, seed + 3, n)
+            b.resample(scene, bd, seed + 3, n)
+            assert _sample_launches(P, cmp_) == 2, name
+            for x, y in zip(a.export(), b.export()):
+                assert np.array_equal(x, y), name
+
+
 @pytest.mark.parametrize("name", ["cloud8", "cloud32mid"])
 def test_sample_fp32_close_to_oracle(env, name):
     torch, P, api = env
