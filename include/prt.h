@@ -129,12 +129,12 @@ int prt_set_stream(prt_ctx ctx, void* hip_stream);
    draw the paths in one pass (kept by the context for later draws).  A draw
    takes, in this order of preference: whole rows of max_order + 2 vertex
    records of 16 bytes per path; rows of 2 records per path (entry and exit:
-   all a path without a scatter needs) plus a pool of blocks of max_order
-   records for the paths that scatter, sized from the store's previous draw
-   with a margin (a new store takes all the limit leaves and needs room for
-   a quarter of its paths), cut to what the limit leaves, and claimed by the
-   sampler's wavefronts as they go, with 4 bytes per path for the block
-   index; or, when neither fits (the pool does not hold the estimate), or
+   all a path without a scatter needs) plus a pool of 128-byte segments of 7
+   records that the sampler's wavefronts claim as paths grow, chained per
+   path, with 4 bytes per path for its first segment -- the pool sized from
+   the store's previous draw with a margin (a new store takes a segment for
+   half of its paths and needs room for a quarter), cut to what the limit
+   leaves; or, when neither fits (the pool does not hold the estimate), or
    the pool runs out, two passes per path
    from its Philox stream: first only its size and sort key, then, once the
    sort (Sec. 5.3) has fixed its place, its vertices straight into the store.

@@ -30,6 +30,9 @@ struct StoreView {
 // sort keys).  The second pass draws the same paths again from the same
 // Philox streams with the same code; it checks each path's size against the
 // first pass's and sets *mismatch otherwise.
+// Overflow segment of a short-row draw: 128 bytes, one cache line.
+constexpr int kSegRecords = 8;
+
 struct SampleArgs {
     DevScene s;
     const float* beta_c;   // cloud field the paths are drawn from
@@ -38,11 +41,14 @@ struct SampleArgs {
     int64_t n;
     float4* tmp;           // [n][tmp_rows] records, or null
     // Short temporary rows (tmp_rows < max_order+2): a path's records from
-    // tmp_rows on go to a block of the overflow pool (max_order+2-tmp_rows
-    // records at ovf[ovf_slot[id] * that]); wavefronts claim blocks in chunks
-    // from *ovf_next (a block count), and a path that finds the ovf_cap
-    // blocks used up sets *ovf_full and stores no more.
+    // tmp_rows on go to a chain of segments of the overflow pool
+    // (kSegRecords float4 each: kSegRecords-1 records, then the next
+    // segment's index as an int in .x); the first segment's index is
+    // ovf_slot[id].  Wavefronts claim segments in chunks of ovf_chunk from
+    // *ovf_next (a segment count); a path that finds the ovf_cap segments
+    // used up sets *ovf_full and stores no more.
     int tmp_rows;
+    int ovf_chunk;
     float4* ovf;
     int64_t ovf_cap;
     unsigned long long* ovf_next;
@@ -174,12 +180,11 @@ int64_t sort_scratch_words(int64_t n, int nbins);
 // scratch: the sort's scratch (sort_scratch_words(64 * nb, ...) words) may be reused.
 hipError_t launch_batch_offsets(hipStream_t st, const uint8_t* nv, int64_t nb, int64_t* batch_off, void* scratch);
 // Record k of the path in slot i: tmp[(tmp_off ? tmp_off[id] : id * tmp_stride) + k],
-// or, with an overflow pool and k >= tmp_stride,
-// ovf[ovf_slot[id] * ovf_block + k - tmp_stride].
+// or, with an overflow pool and k >= tmp_stride, record (k - tmp_stride) of
+// the chain of segments that starts at ovf_slot[id] (SampleArgs).
 hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, const int64_t* tmp_off,
                        int64_t tmp_stride, const uint8_t* nv, const int64_t* batch_off, int64_t n,
-                       int64_t n_slots, float4* vtx, const float4* ovf = nullptr, const int32_t* ovf_slot = nullptr,
-                       int ovf_block = 0);
+                       int64_t n_slots, float4* vtx, const float4* ovf = nullptr, const int32_t* ovf_slot = nullptr);
 // meta[0] = batch_off[nb] (records), meta[1] = first slot with B > 0 (n if
 // none), meta[2] = batch_off of that slot's batch (records of B = 0 batches),
 // meta[kMetaFirstGe + k] = first slot with B >= k (n if none), k = 1..kMaxOrder.

@@ -90,7 +90,7 @@ struct prt_ctx_s {
     // sampling / sorting temporaries (grow-only)
     void* s_tmp = nullptr;
     size_t s_tmp_bytes = 0;
-    void* s_ovf = nullptr;      // overflow block counter (16 bytes), then a block per path id
+    void* s_ovf = nullptr;      // overflow segment counter (16 bytes), then a first segment per path id
     size_t s_ovf_bytes = 0;
     void* s_keys = nullptr;     // tB and tnv
     size_t s_keys_bytes = 0;
@@ -522,7 +522,7 @@ int layout_store(prt_ctx c, prt_paths p, const uint8_t* tB, const uint8_t* tnv, 
 // id * tmp_stride) into the store.
 int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_off, int64_t tmp_stride,
                 const uint8_t* tB, const uint8_t* tnv, const uint16_t* tC, const float4* ovf = nullptr,
-                const int32_t* ovf_slot = nullptr, int ovf_block = 0)
+                const int32_t* ovf_slot = nullptr)
 {
     int rc;
     if ((rc = layout_store(c, p, tB, tnv, tC, nullptr))) return rc;
@@ -530,7 +530,7 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
     {
         TimedScope ts(c, K_PACK);
         HIPCHK(launch_pack(c->stream, p->perm, tmp, tmp_off, tmp_stride, p->nv, p->batch_off, n, p->n_slots, p->vtx,
-                           ovf, ovf_slot, ovf_block));
+                           ovf, ovf_slot));
     }
     return PRT_OK;
 }
@@ -538,39 +538,52 @@ int build_store(prt_ctx c, prt_paths p, const float4* tmp, const int64_t* tmp_of
 // Records per path in the short rows of a one-pass draw that does not fit
 // whole rows: an entry and an exit, all a path without a scatter needs.
 constexpr int kShortRows = 2;
-// Overflow blocks a wavefront claims at a time (as the sampler's chunk): a
-// wavefront leaves fewer than this many unused.
-constexpr int64_t kOvfChunk = 16;
+// Overflow segments a wavefront claims at a time: about a sixteenth of its
+// share of the estimate, within these bounds (a wavefront leaves fewer than a
+// chunk unused; small chunks make the shared counter's atomics contend).
+constexpr int64_t kOvfChunkMin = 16, kOvfChunkMax = 256;
 
 // Samples n paths into p (allocated or reused) under scene->beta_cloud.  When
 // the one-pass temporary (max_order+2 records per path) would exceed the
-// context's limit, every path is drawn twice: first only its size and sort
-// key, then, once the sort has fixed its slot, its vertices straight into the
-// store.
+// context's limit, the paths are drawn once into short rows and a pool of
+// overflow segments; when that does not fit either, or the pool runs out,
+// every path is drawn twice: first only its size and sort key, then, once
+// the sort has fixed its slot, its vertices straight into the store.
 int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_paths p)
 {
     const int64_t nu = (int64_t)s->nx * s->ny * s->nz;
     const int64_t stride = s->max_order + 2;
     const bool one_pass = (uint64_t)n * (uint64_t)stride * sizeof(float4) <= c->sample_tmp_limit;
-    // otherwise short rows and an overflow pool of blocks of `per` records.
-    // A refill estimates its scattering paths from the store's previous draw
-    // (scaled to n) and takes a quarter more plus the chunks the sampler's
-    // wavefronts (1024 threads per workgroup, at most two workgroups per CU)
-    // may leave unused; a new store assumes a quarter of its paths scatter
-    // and takes as many blocks as the limit leaves.  Either is cut to what
+    // otherwise short rows and an overflow pool of segments of kSegRecords - 1
+    // records (and a link).  A refill estimates the segments from the
+    // store's previous draw (a path of B scatters stores at most B records
+    // past its short row, so it takes one segment for each of B >= 1, 8,
+    // 15, ...; counted per batch from the sorted store's first batch with
+    // B >= k and scaled to n) and takes a quarter more plus the
+    // chunks the sampler's wavefronts (1024 threads per workgroup, at most two
+    // workgroups per CU) may leave unused; a new store assumes a quarter of
+    // its paths need a segment and takes twice that.  Either is cut to what
     // the limit leaves and used when it still holds the estimate.
-    const int64_t per = stride - kShortRows;
-    int64_t ovf_blocks = 0;
+    const int64_t seg_rec = kSegRecords - 1;
+    const int64_t rows_recs = ((int64_t)n * kShortRows + kSegRecords - 1) / kSegRecords * kSegRecords;
+    int64_t ovf_segs = 0;
+    int ovf_chunk = (int)kOvfChunkMin;
     bool compact = false;
-    const uint64_t rows_bytes = (uint64_t)n * (kShortRows * sizeof(float4) + sizeof(int32_t));
-    if (!one_pass && per > 0 && rows_bytes < c->sample_tmp_limit) {
+    const uint64_t rows_bytes = (uint64_t)rows_recs * sizeof(float4) + (uint64_t)n * sizeof(int32_t);
+    if (!one_pass && stride > kShortRows && rows_bytes < c->sample_tmp_limit) {
         const bool refill = p->n_records > 0 && p->n > 0 && p->first_slot <= (int64_t)p->n;
-        const int64_t est =
-            refill ? (int64_t)((double)((int64_t)p->n - p->first_slot) / (double)p->n * (double)n) : n / 4;
+        int64_t est = n / 4;
+        if (refill) {
+            double segs = 0;
+            for (int k = 1; k <= p->bmax; k += (int)seg_rec)
+                segs += (double)std::max<int64_t>((int64_t)p->n - (int64_t)p->first_batch_ge[k] * kWave, 0);
+            est = (int64_t)(segs / (double)p->n * (double)n);
+        }
         const int64_t waves = std::min<int64_t>((n + 1023) / 1024, (int64_t)c->n_cu * 2) * (1024 / kWave);
-        const int64_t fit = (int64_t)((c->sample_tmp_limit - rows_bytes) / ((uint64_t)per * sizeof(float4)));
-        ovf_blocks = std::min<int64_t>(std::min<int64_t>(n, refill ? est + est / 4 + kOvfChunk * waves : n), fit);
-        compact = ovf_blocks >= est && ovf_blocks > 0 && ovf_blocks < ((int64_t)1 << 31);
+        ovf_chunk = (int)std::min<int64_t>(std::max<int64_t>(est / (16 * waves), kOvfChunkMin), kOvfChunkMax);
+        const int64_t fit = (int64_t)((c->sample_tmp_limit - rows_bytes) / (kSegRecords * sizeof(float4)));
+        ovf_segs = std::min<int64_t>(refill ? est + est / 4 + ovf_chunk * waves : 2 * est + ovf_chunk * waves, fit);
+        compact = ovf_segs >= est && ovf_segs > 0 && ovf_segs < ((int64_t)1 << 31);
     }
     int rc;
     // earlier work may still read the store's or the context's buffers
@@ -580,7 +593,7 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     if (one_pass && (rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes, (size_t)n * stride * sizeof(float4)))) return rc;
     if (compact &&
         ((rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes,
-                              ((size_t)n * kShortRows + (size_t)ovf_blocks * per) * sizeof(float4))) ||
+                              ((size_t)rows_recs + (size_t)ovf_segs * kSegRecords) * sizeof(float4))) ||
          (rc = ensure_scratch(&c->s_ovf, &c->s_ovf_bytes, (size_t)n * sizeof(int32_t) + 16))))
         return rc;
     if ((rc = ensure_scratch(&c->s_keys, &c->s_keys_bytes, 4 * (size_t)n))) return rc;
@@ -609,8 +622,9 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     a.n = n;
     a.tmp = (one_pass || compact) ? (float4*)c->s_tmp : nullptr;
     a.tmp_rows = compact ? kShortRows : (int)stride;
-    a.ovf = compact ? (float4*)c->s_tmp + (size_t)n * kShortRows : nullptr;
-    a.ovf_cap = compact ? ovf_blocks : 0;
+    a.ovf = compact ? (float4*)c->s_tmp + rows_recs : nullptr;
+    a.ovf_cap = compact ? ovf_segs : 0;
+    a.ovf_chunk = ovf_chunk;
     a.ovf_next = compact ? (unsigned long long*)c->s_ovf : nullptr;
     a.ovf_slot = compact ? (int32_t*)((unsigned char*)c->s_ovf + 16) : nullptr;
     a.ovf_full = compact ? (int*)(c->dmeta + kOvfFullWord) : nullptr;
@@ -635,8 +649,7 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     if (compact) {
         HIPCHK(hipStreamSynchronize(c->stream));
         if (*ovf_full == 0)
-            return build_store(c, p, (const float4*)c->s_tmp, nullptr, kShortRows, tB, tnv, tC, a.ovf, a.ovf_slot,
-                               (int)per);
+            return build_store(c, p, (const float4*)c->s_tmp, nullptr, kShortRows, tB, tnv, tC, a.ovf, a.ovf_slot);
         // the pool ran out: the sizes and keys are complete, so the second
         // pass of the two-pass draw finishes the store
     }
@@ -651,6 +664,7 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     a.tmp_rows = (int)stride;
     a.ovf = nullptr;
     a.ovf_cap = 0;
+    a.ovf_chunk = 0;
     a.ovf_next = nullptr;
     a.ovf_slot = nullptr;
     a.ovf_full = nullptr;

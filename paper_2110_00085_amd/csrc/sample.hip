@@ -90,19 +90,18 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
     const int stride = s.max_order + 2;
     const int lane = threadIdx.x % kWave;
     const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;  // lanes under this one
-    // short temporary rows: records from R on go to an overflow block, taken
-    // from the wavefront's chunk of blocks [chunk[w][0], chunk[w][1])
+    // short temporary rows: records from R on go to a chain of overflow
+    // segments, taken from the wavefront's chunk [chunk[w][0], chunk[w][1])
     const bool compact = a.tmp && a.tmp_rows < stride;
     const int R = compact ? a.tmp_rows : stride;
-    const int per = stride - R;
-    constexpr int kChunkBlocks = 16;
+    constexpr int kSegRec = kSegRecords - 1;  // records per segment
     __shared__ unsigned long long chunk[kSampleBlock / kWave][2];
     if (lane == 0) {
         chunk[threadIdx.x / kWave][0] = 0;
         chunk[threadIdx.x / kWave][1] = 0;
     }
     __syncthreads();
-    int64_t oblk = -1;  // this path's overflow block (-2: none left)
+    int64_t oseg = -1;  // this path's current overflow segment (-2: none left)
     // path state and event arithmetic in the traversal precision
     using E = Real;
     int64_t id = 0;
@@ -137,7 +136,7 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
             if (!active && rank < take) {
                 // start path nid at the source
                 id = nid;
-                oblk = -1;
+                oseg = -1;
                 if (a.tmp) {
                     out = a.tmp + id * R;
                     ostr = 1;
@@ -201,9 +200,11 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
         // the division that places the scatter inside its voxel stays out of the loop
         if (hit >= 0) thit += (taur - acc) / gt[hit];
         // this event writes record nv: past the short row it goes to the
-        // path's overflow block, taken now from the wavefront's chunk
+        // path's overflow segment, a new one taken now from the wavefront's
+        // chunk when the current one is full
         if (compact) {
-            const bool need = nv == R && oblk == -1;
+            const int j = nv - R;
+            const bool need = j >= 0 && oseg != -2 && j % kSegRec == 0;
             const uint64_t m = __ballot(need);
             if (m) {
                 // the first `old` lanes (in lane order) take the rest of the
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
                     old = min(cnt, c1 - c0);
                     c0 += old;
                     if (old < cnt) {
-                        const unsigned long long take = max(cnt - old, (unsigned long long)kChunkBlocks);
+                        const unsigned long long take = max(cnt - old, (unsigned long long)a.ovf_chunk);
                         fresh = atomicAdd(a.ovf_next, take);
                         c0 = fresh + (cnt - old);
                         c1 = fresh + take;
@@ -233,21 +234,24 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
                     const unsigned long long r = (unsigned long long)__popcll(m & below);
                     const unsigned long long blk = r < old ? base + r : fresh + (r - old);
                     if ((int64_t)blk < a.ovf_cap) {
-                        oblk = (int64_t)blk;
-                        a.ovf_slot[id] = (int32_t)blk;
+                        if (j == 0)
+                            a.ovf_slot[id] = (int32_t)blk;
+                        else
+                            a.ovf[oseg * kSegRecords + kSegRec] = make_float4(__int_as_float((int)blk), 0.f, 0.f, 0.f);
+                        oseg = (int64_t)blk;
                     } else {
-                        oblk = -2;
+                        oseg = -2;
                         *a.ovf_full = 1;
                     }
                 }
             }
         }
-        // record k of the path: the short row, the overflow block, the store
+        // record k of the path: the short row, the overflow segment, the store
         auto put = [&](int k, float4 r) {
             if (k < R) {
                 if (out) out[k * ostr] = r;
-            } else if (oblk >= 0) {
-                a.ovf[oblk * per + (k - R)] = r;
+            } else if (oseg >= 0) {
+                a.ovf[oseg * kSegRecords + (k - R) % kSegRec] = r;
             }
         };
         bool done;
@@ -562,8 +566,7 @@ __global__ void __launch_bounds__(256) pack_kernel(const int32_t* __restrict__ p
                                                    const uint8_t* __restrict__ nv,
                                                    const int64_t* __restrict__ batch_off, int64_t n,
                                                    int64_t n_slots, float4* __restrict__ vtx,
-                                                   const float4* __restrict__ ovf, const int32_t* __restrict__ ovf_slot,
-                                                   int ovf_block)
+                                                   const float4* __restrict__ ovf, const int32_t* __restrict__ ovf_slot)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_slots) return;
@@ -571,33 +574,51 @@ __global__ void __launch_bounds__(256) pack_kernel(const int32_t* __restrict__ p
     const int64_t rows = (batch_off[b + 1] - batch_off[b]) / kWave;
     float4* dst = vtx + batch_off[b] + lane;
     const int cnt = i < n ? (int)nv[i] : 0;
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     const float4* src = nullptr;
-    const float4* src2 = nullptr;  // records from tmp_stride on (overflow pool)
+    int64_t id = 0;
     if (i < n) {
-        const int64_t id = perm[i];
+        id = perm[i];
         src = tmp + (tmp_off ? tmp_off[id] : id * tmp_stride);
-        if (ovf && cnt > tmp_stride) src2 = ovf + (int64_t)ovf_slot[id] * ovf_block;
     }
-    // kPackLoads records of the path in flight at a time
-    for (int64_t k0 = 0; k0 < rows; k0 += kPackLoads) {
-        float4 r[kPackLoads];
+    if (!ovf) {
+        // whole rows: kPackLoads records of the path in flight at a time
+        for (int64_t k0 = 0; k0 < rows; k0 += kPackLoads) {
+            float4 r[kPackLoads];
 #pragma unroll
-        for (int j = 0; j < kPackLoads; ++j) {
-            const int64_t k = k0 + j;
-            r[j] = k < cnt ? (src2 && k >= tmp_stride ? src2[k - tmp_stride] : src[k]) : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int j = 0; j < kPackLoads; ++j) {
+                const int64_t k = k0 + j;
+                r[j] = k < cnt ? src[k] : zero;
+            }
+#pragma unroll
+            for (int j = 0; j < kPackLoads; ++j)
+                if (k0 + j < rows) dst[(k0 + j) * kWave] = r[j];
         }
+        return;
+    }
+    // short row, then one overflow segment at a time (its records and its
+    // link in flight together)
+    for (int64_t k = 0; k < tmp_stride && k < rows; ++k) dst[k * kWave] = k < cnt ? src[k] : zero;
+    constexpr int kSegRec = kSegRecords - 1;
+    const float4* seg = cnt > tmp_stride ? ovf + (int64_t)ovf_slot[id] * kSegRecords : nullptr;
+    for (int64_t k0 = tmp_stride; k0 < rows; k0 += kSegRec) {
+        float4 r[kSegRecords];
 #pragma unroll
-        for (int j = 0; j < kPackLoads; ++j)
+        for (int j = 0; j < kSegRecords; ++j) r[j] = seg && k0 + j < cnt ? seg[j] : zero;
+#pragma unroll
+        for (int j = 0; j < kSegRec; ++j)
             if (k0 + j < rows) dst[(k0 + j) * kWave] = r[j];
+        // the link is set when the path has a record past this segment
+        seg = seg && k0 + kSegRec < cnt ? ovf + (int64_t)__float_as_int(r[kSegRec].x) * kSegRecords : nullptr;
     }
 }
 
 hipError_t launch_pack(hipStream_t st, const int32_t* perm, const float4* tmp, const int64_t* tmp_off,
                        int64_t tmp_stride, const uint8_t* nv, const int64_t* batch_off, int64_t n, int64_t n_slots,
-                       float4* vtx, const float4* ovf, const int32_t* ovf_slot, int ovf_block)
+                       float4* vtx, const float4* ovf, const int32_t* ovf_slot)
 {
     pack_kernel<<<dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, st>>>(
-        perm, tmp, tmp_off, tmp_stride, nv, batch_off, n, n_slots, vtx, ovf, ovf_slot, ovf_block);
+        perm, tmp, tmp_off, tmp_stride, nv, batch_off, n, n_slots, vtx, ovf, ovf_slot);
     return hipGetLastError();
 }
 
