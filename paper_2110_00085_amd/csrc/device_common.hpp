@@ -25,6 +25,7 @@ struct DevScene {
     double a_top, a_x, a_y; // projected areas of the lit faces [km^2]
     double w0;              // source weight F0 * projected box area
     double x_face, y_face;  // grid coordinate of the lit x / y face
+    double inv_nx, inv_nxy; // 1 / nx and 1 / (nx * ny), for voxel_ijk
 };
 
 // Cameras with positions converted to grid units.
@@ -503,21 +504,21 @@ __device__ __forceinline__ void dda_walk_box(const SubBox& b, Real px, Real py, 
     const bool inside = ix >= b.lo[0] && ix < b.hi[0] && iy >= b.lo[1] && iy < b.hi[1] && iz >= b.lo[2] &&
                         iz < b.hi[2];
     if (!inside) {
-        // slab clipping of the ray against the block
+        // slab clipping of the ray against the block (selects, no branches:
+        // an axis the ray does not move along only has to hold the start)
         Real tn = (Real)0, tf = kBounded ? tmax : (Real)INFINITY;
         const int s[3] = {sx, sy, sz}, i[3] = {ix, iy, iz};
         const Real p[3] = {px, py, pz}, iv[3] = {ivx, ivy, ivz};
+        bool miss = false;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            if (s[a] == 0) {
-                if (i[a] < b.lo[a] || i[a] >= b.hi[a]) return;
-            } else {
-                const Real t1 = ((Real)b.lo[a] - p[a]) * iv[a], t2 = ((Real)b.hi[a] - p[a]) * iv[a];
-                tn = fmax(tn, fmin(t1, t2));
-                tf = fmin(tf, fmax(t1, t2));
-            }
+            const Real t1 = ((Real)b.lo[a] - p[a]) * iv[a], t2 = ((Real)b.hi[a] - p[a]) * iv[a];
+            const bool still = s[a] == 0;
+            miss = miss || (still && (i[a] < b.lo[a] || i[a] >= b.hi[a]));
+            tn = still ? tn : fmax(tn, fmin(t1, t2));
+            tf = still ? tf : fmin(tf, fmax(t1, t2));
         }
-        if (!(tn < tf)) return;
+        if (miss || !(tn < tf)) return;
         t = tn;
         ix = min(max((int)floor(px + t * wx), b.lo[0]), b.hi[0] - 1);
         iy = min(max((int)floor(py + t * wy), b.lo[1]), b.hi[1] - 1);
@@ -558,6 +559,19 @@ __device__ __forceinline__ void voxel_ijk(int v, int nx, int ny, int& ix, int& i
     const int r = v / nx;
     iy = r % ny;
     iz = r / ny;
+}
+
+// The same from the scene's reciprocals: floor((v + 1/2) / d) computed as
+// ((double)v + 0.5) * (1/d) is exact for 0 <= v < 2^31 and d <= 2^18 (the
+// rounding errors stay below 2^-20 while the quotient lies at least 1/(2d)
+// from an integer), and takes a few FP64 operations instead of an integer
+// division each.
+__device__ __forceinline__ void voxel_ijk(const DevScene& s, int v, int& ix, int& iy, int& iz)
+{
+    iz = (int)floor(((double)v + 0.5) * s.inv_nxy);
+    const int r = v - iz * (s.nx * s.ny);
+    iy = (int)floor(((double)r + 0.5) * s.inv_nx);
+    ix = r - iy * s.nx;
 }
 
 __device__ __forceinline__ int vox_of(const float4& r) { return __float_as_int(r.w); }

@@ -300,6 +300,8 @@ DevScene make_dev_scene(const prt_scene* s)
     d.w0 = s->sun_flux * (d.a_top + d.a_x + d.a_y);
     d.x_face = d.sun[0] > 0 ? 0.0 : (double)s->nx;
     d.y_face = d.sun[1] > 0 ? 0.0 : (double)s->ny;
+    d.inv_nx = 1.0 / (double)s->nx;
+    d.inv_nxy = 1.0 / ((double)s->nx * (double)s->ny);
     return d;
 }
 

@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
             if (b == 1) v0 = hit;  // the sort key follows the first scatter
             done = b >= s.max_order;
             if (!done) {
-                voxel_ijk(hit, s.nx, s.ny, ix, iy, iz);
+                voxel_ijk(s, hit, ix, iy, iz);
                 uniforms4(a.seed, (uint64_t)id, (uint32_t)b, u);
                 // the particle choice is taken in FP64 in both precisions
                 const double bsc = s.w_c * (double)a.beta_c[hit];

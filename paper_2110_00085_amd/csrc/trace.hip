@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
         int p1i;
         {
             int i0, i1, i2;
-            voxel_ijk(clamp_vox(p1.v, nu), s.nx, s.ny, i0, i1, i2);
+            voxel_ijk(s, clamp_vox(p1.v, nu), i0, i1, i2);
             p1i = ax == 0 ? i0 : (ax == 1 ? i1 : i2);
         }
         const float nbox[3] = {(float)s.nx, (float)s.ny, (float)s.nz};
@@ -660,7 +660,7 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
             if (act) {
                 // segment b-1 of the free-flight walk
                 int i0, i1, i2;
-                voxel_ijk(clamp_vox(p0.v, nu), s.nx, s.ny, i0, i1, i2);
+                voxel_ijk(s, clamp_vox(p0.v, nu), i0, i1, i2);
                 const float p0a = (float)(ax == 0 ? p0.x : (ax == 1 ? p0.y : p0.z));
                 layer_span(p0a, ax == 0 ? i0 : (ax == 1 ? i1 : i2), slo, shi);
                 layer_span(p1a, p1i, slo, shi);
@@ -874,9 +874,9 @@ __global__ void __launch_bounds__(kBinTasks) grad_bin_fill_kernel(const int* __r
 
 // One listed task of slab box b: the walks of kind `kind` of batch bt,
 // clipped to the block, added to the LDS tally.
-__device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams& cams, const SubBox& box, int slab,
-                                              double* __restrict__ tally, uint32_t* queue, int64_t bt, int kind,
-                                              uint64_t& nseg)
+__device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams& cams, const double* cpos,
+                                              const SubBox& box, int slab, double* __restrict__ tally,
+                                              uint32_t* queue, int64_t bt, int kind, uint64_t& nseg)
 {
     const DevScene& s = a.s;
     const int nu = s.nx * s.ny * s.nz;
@@ -900,22 +900,23 @@ __device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams&
         const float* __restrict__ Wb = a.wtape + rec0 * cams.n + d_lo * kWave;
         const uint32_t sl = (uint32_t)slab;
         uint32_t wq = 0, rq = 0;
+        // (the camera positions come from LDS: lanes index them by their own
+        // queued camera)
         auto walk_entry = [&](uint32_t e) {
             const int L = (int)(e & 63u), b = (int)((e >> 6) & 127u), j = (int)(e >> 13);
             const float4 r = Vb[(int64_t)b * kWave + L];
-            const Vtx p1{(double)r.x, (double)r.y, (double)r.z, vox_of(r)};
             const double wgt = (double)Wb[(int64_t)(b * cams.n + j) * kWave + L];
-            const int d = d_lo + j;
-            const float ex = (float)(cams.pos[d][0] - p1.x), ey = (float)(cams.pos[d][1] - p1.y),
-                        ez = (float)(cams.pos[d][2] - p1.z);
+            const double* c = cpos + 3 * (d_lo + j);
+            const float ex = (float)(c[0] - (double)r.x), ey = (float)(c[1] - (double)r.y),
+                        ez = (float)(c[2] - (double)r.z);
             const float d2 = ex * ex + ey * ey + ez * ez;
             const float id = __builtin_amdgcn_rsqf(d2);
-            const double u[3] = {(double)(ex * id), (double)(ey * id), (double)(ez * id)};
-            const double dist = (double)(d2 * id);
             if (cams.outside)
-                walk_scatter_box<float, false>(s, add, p1, u, dist, -wgt * s.vk, nseg, box);
+                walk_scatter_box_f<false>(s, add, r.x, r.y, r.z, vox_of(r), ex * id, ey * id, ez * id, d2 * id,
+                                          -wgt * s.vk, nseg, box);
             else
-                walk_scatter_box<float>(s, add, p1, u, dist, -wgt * s.vk, nseg, box);
+                walk_scatter_box_f(s, add, r.x, r.y, r.z, vox_of(r), ex * id, ey * id, ez * id, d2 * id, -wgt * s.vk,
+                                   nseg, box);
         };
         int bmax = Bn;
         for (int o = kWave / 2; o > 0; o >>= 1) bmax = max(bmax, __shfl_xor(bmax, o));
@@ -948,7 +949,7 @@ __device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams&
             }
             if (kind == 0 && b <= Bn) {
                 const double vert = (double)X[(int64_t)b * kWave].y;
-                const int u = vert != 0.0 ? box_index(box, clamp_vox(vox_of(V[(int64_t)b * kWave]), nu), s.nx, s.ny) : -1;
+                const int u = vert != 0.0 ? box_index(box, clamp_vox(vox_of(V[(int64_t)b * kWave]), nu), s) : -1;
                 if (u >= 0) add((uint32_t)u, vert);
             }
         }
@@ -966,7 +967,7 @@ __device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams&
             const double L = seg_dir(pk, pk1, w);
             if (A != 0.0) {
                 walk_scatter_box<float>(s, add, pk, w, L, -A * s.vk, nseg, box);
-                const int u = k >= 1 ? box_index(box, clamp_vox(pk.v, nu), s.nx, s.ny) : -1;
+                const int u = k >= 1 ? box_index(box, clamp_vox(pk.v, nu), s) : -1;
                 if (u >= 0) add((uint32_t)u, A * (double)X[(int64_t)k * kWave].z);
             }
             pk1 = pk;
@@ -1005,6 +1006,8 @@ __global__ void __launch_bounds__(kBlock) grad_bin_walk_kernel(TraceArgs a, DevC
     double* __restrict__ tally = reinterpret_cast<double*>(smem);
     __shared__ unsigned int s_chunk, s_item;
     __shared__ uint32_t wave_queue[kWavesPerBlock][kBinQueue];
+    __shared__ double cpos[3 * kMaxCams];
+    for (int i = threadIdx.x; i < 3 * cams.n; i += kBlock) cpos[i] = cams.pos[i / 3][i % 3];
     const DevScene& s = a.s;
     const int per_layer = g.axis == 0 ? s.ny * s.nz : (g.axis == 1 ? s.nx * s.nz : s.nx * s.ny);
     const int64_t nb = a.st.n_slots / kWave;
@@ -1045,8 +1048,8 @@ __global__ void __launch_bounds__(kBlock) grad_bin_walk_kernel(TraceArgs a, DevC
             it = __shfl(it, 0);
             if (it >= i1) break;
             const uint32_t t = g.list[it];
-            grad_bin_task(a, cams, box, sl, tally, wave_queue[threadIdx.x / kWave], nb - 1 - (int64_t)(t / kinds),
-                          (int)(t % kinds), nseg);
+            grad_bin_task(a, cams, cpos, box, sl, tally, wave_queue[threadIdx.x / kWave],
+                          nb - 1 - (int64_t)(t / kinds), (int)(t % kinds), nseg);
         }
         __syncthreads();
         double* __restrict__ out = g.partial + (int64_t)c * slab_vox;

@@ -44,7 +44,7 @@ __device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx&
                                          uint64_t& count)
 {
     int ix, iy, iz;
-    voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
+    voxel_ijk(s, clamp_vox(p.v, s.nx * s.ny * s.nz), ix, iy, iz);
     if constexpr (U > 1) {
         uint32_t n = 0;
         const Real acc = dda_sum<U, Real, kBounded>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz,
@@ -71,7 +71,7 @@ __device__ __forceinline__ void walk_scatter(const DevScene& s, A&& add, const V
                                              double scale, uint64_t& count, int z0, int z1)
 {
     int ix, iy, iz;
-    voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
+    voxel_ijk(s, clamp_vox(p.v, s.nx * s.ny * s.nz), ix, iy, iz);
     uint32_t n = 0;
     dda_walk_slab<Real, kBounded>(s.nx, s.ny, z0, z1, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1],
                         (Real)w[2], (Real)tmax, n, [&](int v, Real, Real l) {
@@ -88,13 +88,30 @@ __device__ __forceinline__ void walk_scatter_box(const DevScene& s, A&& add, con
                                                  double tmax, double scale, uint64_t& count, const SubBox& b)
 {
     int ix, iy, iz;
-    voxel_ijk(clamp_vox(p.v, s.nx * s.ny * s.nz), s.nx, s.ny, ix, iy, iz);
+    voxel_ijk(s, clamp_vox(p.v, s.nx * s.ny * s.nz), ix, iy, iz);
     uint32_t n = 0;
     dda_walk_box<Real, kBounded>(b, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy, iz, (Real)w[0], (Real)w[1], (Real)w[2],
                                  (Real)tmax, n, [&](int v, Real, Real l) {
                                      add((uint32_t)v, scale * (double)l);
                                      return true;
                                  });
+    count += n;
+}
+
+// As walk_scatter_box for an FP32 walk given in floats: from point (px,py,pz)
+// in voxel v along the unit direction (wx,wy,wz) up to tmax.
+template <bool kBounded = true, typename A>
+__device__ __forceinline__ void walk_scatter_box_f(const DevScene& s, A&& add, float px, float py, float pz, int v,
+                                                   float wx, float wy, float wz, float tmax, double scale,
+                                                   uint64_t& count, const SubBox& b)
+{
+    int ix, iy, iz;
+    voxel_ijk(s, clamp_vox(v, s.nx * s.ny * s.nz), ix, iy, iz);
+    uint32_t n = 0;
+    dda_walk_box<float, kBounded>(b, px, py, pz, ix, iy, iz, wx, wy, wz, tmax, n, [&](int u, float, float l) {
+        add((uint32_t)u, scale * (double)l);
+        return true;
+    });
     count += n;
 }
 
@@ -120,10 +137,10 @@ __device__ __forceinline__ SubBox slab_box(const DevScene& s, int axis, int laye
 }
 
 // Index of grid voxel v inside block b, or -1 outside it.
-__device__ __forceinline__ int box_index(const SubBox& b, int v, int nx, int ny)
+__device__ __forceinline__ int box_index(const SubBox& b, int v, const DevScene& s)
 {
     int i[3];
-    voxel_ijk(v, nx, ny, i[0], i[1], i[2]);
+    voxel_ijk(s, v, i[0], i[1], i[2]);
     int u = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
