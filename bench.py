@@ -801,9 +801,9 @@ def surface_bench(args):
         P.prt_surface_reweight(h, st.handle, theta, stats)
 
     def full_step():
-        # theta_ref of the draw: the current theta (read back, as the loop does)
-        k, gm = (float(x) for x in theta.cpu())
-        st.resample((min(k, 0.999), gm), seed + state["t"], n)
+        # theta_ref of the draw: the current theta, read by the draw on the
+        # device (kappa_s clamped to 0.999 there)
+        st.resample(theta, seed + state["t"], n)
         iterate()
 
     for _ in range(args.warmup):

@@ -34,7 +34,8 @@
  *  - theta of the render, gradient, reweight and Adam calls is a DEVICE
  *    array of 2 doubles {kappa_s, gamma}, so a loop of render, loss,
  *    gradient and Adam runs without host round trips; theta_ref of a draw is
- *    a HOST array (it is validated).
+ *    a HOST array (it is validated), or a DEVICE array for
+ *    prt_surface_resample_device (it is clamped).
  */
 #ifndef PRT_SURFACE_H
 #define PRT_SURFACE_H
@@ -79,9 +80,19 @@ int prt_surface_sample(prt_ctx ctx, const prt_surface_scene* scene, const prt_ca
 
 /* The same draw into an existing store (Alg. 2, resampling every N_r
    iterations): buffers are reused when large enough; theta_ref (HOST) is
-   copied. */
+   passed to the draw by value. */
 int prt_surface_resample(prt_ctx ctx, prt_surface_paths paths, const prt_surface_scene* scene,
                          const prt_cameras* cams, const double* theta_ref, uint64_t seed, int64_t n_paths);
+
+/* As prt_surface_resample with theta_ref a DEVICE array of 2 doubles (as
+   theta of the render calls), read when the draw runs and clamped to the
+   drawable range kappa_s in [0, 0.999], gamma in [0, 1e4] (NaN counts as
+   0): the loop of Alg. 2 can redraw at its current theta without a host
+   round trip.  The store keeps the clamped value.  Asynchronous when the
+   scene's spheres and the cameras are those of the store's previous draw
+   and its buffers are large enough; otherwise it synchronises first. */
+int prt_surface_resample_device(prt_ctx ctx, prt_surface_paths paths, const prt_surface_scene* scene,
+                                const prt_cameras* cams, const double* theta_ref, uint64_t seed, int64_t n_paths);
 
 /* A store from HOST paths: B[n] vertex counts in [0, max_order], pos[n][M][3]
    and sid[n][M] (M = max_order; entries past B[i] ignored), drawn at the

@@ -111,7 +111,13 @@ class SurfacePaths:
         return cls(ctx, P.prt_surface_import(ctx.handle, sh, ch, theta_ref, B, pos, sid), scene, ch)
 
     def resample(self, theta_ref, seed: int, n_paths: int) -> "SurfacePaths":
-        P.prt_surface_resample(self.ctx.handle, self.handle, self.scene, self.cams, theta_ref, seed, n_paths)
+        """theta_ref: host pair, or a device float64 tensor (read by the draw,
+        clamped to kappa_s <= 0.999, 0 <= gamma <= 1e4)."""
+        if hasattr(theta_ref, "is_cuda") and theta_ref.is_cuda:
+            P.prt_surface_resample_device(self.ctx.handle, self.handle, self.scene, self.cams, theta_ref, seed,
+                                          n_paths)
+        else:
+            P.prt_surface_resample(self.ctx.handle, self.handle, self.scene, self.cams, theta_ref, seed, n_paths)
         return self
 
     @property

@@ -184,8 +184,11 @@ struct prt_surface_paths_s {
     int32_t* pix = nullptr;
     double* theta_ref = nullptr;     // device [2]
     double* sph = nullptr;           // device [kMaxSpheres][kSphStride]
+    double sph_host[kSphStride * kMaxSpheres] = {};  // what sph holds (n_sph of them)
+    int n_sph = -1;
     double* omega = nullptr;         // reciprocal pixel solid angles [n_cams][W*H]
     int64_t cap_omega = 0;
+    bool omega_valid = false;        // omega belongs to `cams`
     unsigned long long* work = nullptr;  // [2] sphere tests and vertices of the last draw
     double* part = nullptr;          // render partial images / gradient and reweight pairs
     size_t part_n = 0;
@@ -1745,15 +1748,41 @@ SurfStore view_of(prt_surface_paths p)
     return v;
 }
 
+bool same_cams(const DevCams& a, const DevCams& b)
+{
+    if (a.n != b.n || a.W != b.W || a.H != b.H || a.outside != b.outside) return false;
+    for (int d = 0; d < a.n; ++d) {
+        if (a.f[d] != b.f[d]) return false;
+        for (int k = 0; k < 3; ++k)
+            if (a.pos[d][k] != b.pos[d][k]) return false;
+        for (int k = 0; k < 9; ++k)
+            if (a.rot[d][k] != b.rot[d][k]) return false;
+    }
+    return true;
+}
+
 // Buffers for n paths of the scene's order and the cameras (reused when
-// large enough), the scene's spheres and theta_ref (host) on the device.
-int surface_prepare(prt_ctx c, prt_surface_paths p, const prt_surface_scene* s, const DevCams& dc,
-                    const double* theta_ref, int64_t n)
+// large enough), and the scene's spheres and the cameras' pixel solid angles
+// on the device (uploaded or recomputed only when they change, so that a
+// redraw of the same scene costs no host round trip).
+int surface_prepare(prt_ctx c, prt_surface_paths p, const prt_surface_scene* s, const DevCams& dc, int64_t n)
 {
     const int M = s->max_order;
-    // earlier calls on the stream may still read the buffers and theta_ref
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (n > p->cap || M > p->M || dc.n > p->cap_cams || !p->B) {
+    double h[kSphStride * kMaxSpheres];
+    for (int k = 0; k < s->n_spheres; ++k) {
+        for (int a = 0; a < 3; ++a) h[kSphStride * k + a] = s->center[3 * k + a];
+        h[kSphStride * k + 3] = s->radius[k];
+        h[kSphStride * k + 4] = s->albedo[k];
+        h[kSphStride * k + 5] = 1.0 / s->radius[k];
+    }
+    const size_t sph_bytes = (size_t)kSphStride * s->n_spheres * sizeof(double);
+    const bool grow_rows = n > p->cap || M > p->M || dc.n > p->cap_cams || !p->B;
+    const bool new_sph = !p->sph || p->n_sph != s->n_spheres || std::memcmp(p->sph_host, h, sph_bytes) != 0;
+    const int64_t npx = (int64_t)dc.n * dc.W * dc.H;
+    const bool new_cams = !p->omega_valid || npx > p->cap_omega || !same_cams(p->cams, dc);
+    // earlier calls on the stream may still read the buffers being replaced
+    if (grow_rows || new_sph || new_cams) HIPCHK(hipStreamSynchronize(c->stream));
+    if (grow_rows) {
         for (void** q : {(void**)&p->B, (void**)&p->pos, (void**)&p->sid, (void**)&p->tv, (void**)&p->tc,
                          (void**)&p->pix}) {
             (void)hipFree(*q);
@@ -1775,21 +1804,21 @@ int surface_prepare(prt_ctx c, prt_surface_paths p, const prt_surface_scene* s, 
     int rc;
     if (!p->theta_ref && (rc = dalloc(&p->theta_ref, 2))) return rc;
     if (!p->sph && (rc = dalloc(&p->sph, (size_t)kSphStride * kMaxSpheres))) return rc;
-    double h[kSphStride * kMaxSpheres];
-    for (int k = 0; k < s->n_spheres; ++k) {
-        for (int a = 0; a < 3; ++a) h[kSphStride * k + a] = s->center[3 * k + a];
-        h[kSphStride * k + 3] = s->radius[k];
-        h[kSphStride * k + 4] = s->albedo[k];
-        h[kSphStride * k + 5] = 1.0 / s->radius[k];
+    if (new_sph) {
+        // (a synchronous copy of a host array that the caller may free on return)
+        p->n_sph = -1;
+        if (s->n_spheres > 0) HIPCHK(hipMemcpy(p->sph, h, sph_bytes, hipMemcpyHostToDevice));
+        std::memcpy(p->sph_host, h, sph_bytes);
+        p->n_sph = s->n_spheres;
     }
-    // (synchronous copies of host arrays that the caller may free on return)
-    HIPCHK(hipMemcpy(p->theta_ref, theta_ref, 2 * sizeof(double), hipMemcpyHostToDevice));
-    if (s->n_spheres > 0)
-        HIPCHK(hipMemcpy(p->sph, h, (size_t)kSphStride * s->n_spheres * sizeof(double), hipMemcpyHostToDevice));
-    if ((rc = grow(&p->omega, &p->cap_omega, (int64_t)dc.n * dc.W * dc.H))) return rc;
+    if (new_cams) {
+        p->omega_valid = false;
+        if ((rc = grow(&p->omega, &p->cap_omega, npx))) return rc;
+        HIPCHK(launch_surf_omega(c->stream, dc, p->omega));
+        p->omega_valid = true;
+    }
     if (!p->work && (rc = dalloc(&p->work, 2))) return rc;
     HIPCHK(hipMemsetAsync(p->work, 0, 2 * sizeof(unsigned long long), c->stream));
-    HIPCHK(launch_surf_omega(c->stream, dc, p->omega));
     p->n = n;
     p->M = M;
     p->n_cams = dc.n;
@@ -1808,10 +1837,10 @@ int surface_prepare(prt_ctx c, prt_surface_paths p, const prt_surface_scene* s, 
 
 // The rows of the store use M = the scene's max_order as stride: a store
 // whose buffers were sized for a larger order keeps M rows per order anyway.
-int surface_draw(prt_ctx c, prt_surface_paths p, uint64_t seed)
+int surface_draw(prt_ctx c, prt_surface_paths p, uint64_t seed, const DrawTheta& th)
 {
     TimedScope ts(c, K_SURF_SAMPLE);
-    HIPCHK(launch_surf_draw(c->stream, p->scene, p->cams, view_of(p), seed, 0, c->n_cu));
+    HIPCHK(launch_surf_draw(c->stream, p->scene, p->cams, view_of(p), seed, 0, th, c->n_cu));
     return PRT_OK;
 }
 
@@ -1864,8 +1893,22 @@ int prt_surface_resample(prt_ctx c, prt_surface_paths p, const prt_surface_scene
     DevCams dc;
     if ((rc = make_surface_cams(cams, s, &dc))) return rc;
     DeviceGuard g(c->device);
-    if ((rc = surface_prepare(c, p, s, dc, theta_ref, n_paths))) return rc;
-    return surface_draw(c, p, seed);
+    if ((rc = surface_prepare(c, p, s, dc, n_paths))) return rc;
+    return surface_draw(c, p, seed, DrawTheta{theta_ref[0], theta_ref[1], nullptr});
+}
+
+int prt_surface_resample_device(prt_ctx c, prt_surface_paths p, const prt_surface_scene* s,
+                                const prt_cameras* cams, const double* theta_ref, uint64_t seed, int64_t n_paths)
+{
+    int rc = check_surface_call(c, p);
+    if (rc || (rc = check_surface_scene(s))) return rc;
+    if (!theta_ref) return fail(PRT_E_INVALID, "theta_ref is NULL");
+    if (n_paths < 1 || n_paths > ((int64_t)1 << 40)) return fail(PRT_E_INVALID, "n_paths must be in [1, 2^40]");
+    DevCams dc;
+    if ((rc = make_surface_cams(cams, s, &dc))) return rc;
+    DeviceGuard g(c->device);
+    if ((rc = surface_prepare(c, p, s, dc, n_paths))) return rc;
+    return surface_draw(c, p, seed, DrawTheta{0.0, 0.0, theta_ref});
 }
 
 int prt_surface_import(prt_ctx c, const prt_surface_scene* s, const prt_cameras* cams, const double* theta_ref,
@@ -1895,7 +1938,9 @@ int prt_surface_import(prt_ctx c, const prt_surface_scene* s, const prt_cameras*
     DeviceGuard g(c->device);
     prt_surface_paths p = new prt_surface_paths_s();
     p->device = c->device;
-    if ((rc = surface_prepare(c, p, s, dc, theta_ref, n_paths))) {
+    if ((rc = surface_prepare(c, p, s, dc, n_paths)) ||
+        (hipMemcpy(p->theta_ref, theta_ref, 2 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess &&
+         (rc = fail(PRT_E_HIP, "copy of theta_ref failed")))) {
         free_surface(p);
         return rc;
     }

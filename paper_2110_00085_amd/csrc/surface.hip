@@ -327,11 +327,22 @@ __global__ void __launch_bounds__(kSurfBlock) surf_tape_kernel(SurfScene s, DevC
 // vertex is found, from the positions as surf_tape_kernel forms them, so that
 // a store and an import of its exported paths hold the same tape.
 __global__ void __launch_bounds__(kSurfBlock) surf_draw_kernel(SurfScene s, DevCams c, SurfStore st, uint64_t seed,
-                                                                uint64_t first_id)
+                                                                uint64_t first_id, DrawTheta th)
 {
     __shared__ double lsph[kSphStride * kMaxSpheres];
     const double* sph = load_spheres(s, lsph);
-    const double kr = st.theta_ref[0], ge = 1.0 / (st.theta_ref[1] + 1.0);
+    // theta_ref: given, or read from the device and clamped to the drawable
+    // range; the first thread keeps it in the store for the later kernels
+    double kr = th.kappa, gr = th.gamma;
+    if (th.src) {
+        kr = fmin(fmax(th.src[0], 0.0), kKappaRefMax);
+        gr = fmin(fmax(th.src[1], 0.0), kGammaRefMax);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st.theta_ref[0] = kr;
+        st.theta_ref[1] = gr;
+    }
+    const double ge = 1.0 / (gr + 1.0);
     const int M = s.max_order;
     const int64_t n = st.n;
     unsigned long long queries = 0, verts = 0;
@@ -663,10 +674,10 @@ hipError_t launch_surf_omega(hipStream_t stream, const DevCams& c, double* omega
 }
 
 hipError_t launch_surf_draw(hipStream_t stream, const SurfScene& s, const DevCams& c, const SurfStore& st,
-                            uint64_t seed, uint64_t first_id, int n_cu)
+                            uint64_t seed, uint64_t first_id, const DrawTheta& th, int n_cu)
 {
     if (st.n == 0) return hipSuccess;
-    surf_draw_kernel<<<surf_blocks(st.n, n_cu, 8), kSurfBlock, 0, stream>>>(s, c, st, seed, first_id);
+    surf_draw_kernel<<<surf_blocks(st.n, n_cu, 8), kSurfBlock, 0, stream>>>(s, c, st, seed, first_id, th);
     return hipGetLastError();
 }
 

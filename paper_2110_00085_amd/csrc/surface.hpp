@@ -31,16 +31,30 @@ struct SurfStore {
     double2* tv;              // [M][n] drawn direction: {cos to mirror, cos to normal}, diffuse {rho, -1}
     double2* tc;              // [M][n_cams][n] {geometric factor, cos of camera direction to mirror}
     int32_t* pix;             // [M][n_cams][n] pixel or -1
-    const double* theta_ref;  // device [2]
+    double* theta_ref;        // device [2] (written by the draw)
     const double* omega;      // [n_cams][W*H] reciprocal pixel solid angles
     unsigned long long* work; // [2]: ray-sphere tests and vertices of the last draw
 };
 
+// Largest theta_ref a draw takes: at kappa_s = 1 the diffuse part would never
+// be drawn, so recycled estimates at kappa_s < 1 would miss it.
+constexpr double kKappaRefMax = 0.999;
+constexpr double kGammaRefMax = 1e4;
+
+// theta_ref of a draw: {kappa, gamma} as given, or, when src is set, the
+// device pair src[0..1] read by the draw and clamped to [0, kKappaRefMax] x
+// [0, kGammaRefMax].
+struct DrawTheta {
+    double kappa, gamma;
+    const double* src;
+};
+
 // omega[d][p] = 1 / solid angle of pixel p of camera d
 hipError_t launch_surf_omega(hipStream_t stream, const DevCams& c, double* omega);
-// Draw st.n paths (ids first_id ..) at st.theta_ref with their tape.
+// Draw st.n paths (ids first_id ..) at theta_ref with their tape, and store
+// theta_ref at st.theta_ref.
 hipError_t launch_surf_draw(hipStream_t stream, const SurfScene& s, const DevCams& c, const SurfStore& st,
-                            uint64_t seed, uint64_t first_id, int n_cu);
+                            uint64_t seed, uint64_t first_id, const DrawTheta& th, int n_cu);
 // The tape of the stored positions.
 hipError_t launch_surf_tape(hipStream_t stream, const SurfScene& s, const DevCams& c, const SurfStore& st, int n_cu);
 // Number of per-workgroup partial images the render writes (0: the images

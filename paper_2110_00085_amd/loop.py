@@ -271,13 +271,15 @@ class SurfaceReconstruction:
         t0 = time.perf_counter()
         resampled = False
         if self.store is None or self.policy.resample(self.t, self.t_ref, self.mean_r, self.ess_fraction):
-            k, g = self.theta_host()
-            ref = (min(k, KAPPA_REF_MAX), g)
             if self.store is None:
+                k, g = self.theta_host()
+                ref = (min(k, KAPPA_REF_MAX), g)
                 self.store = api.SurfacePaths.sample(self.ctx, self.scene, self.cams, ref, self.seed + self.t,
                                                      self.n_paths)
             else:
-                self.store.resample(ref, self.seed + self.t, self.n_paths)
+                # at the current theta on the device (the draw clamps kappa_s
+                # to KAPPA_REF_MAX itself)
+                self.store.resample(self.theta, self.seed + self.t, self.n_paths)
             self.t_ref = self.t
             resampled = True
         self.t += 1

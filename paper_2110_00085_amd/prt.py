@@ -103,6 +103,8 @@ def lib():
                                     C.POINTER(_V)], C.c_int),
             "prt_surface_resample": ([_V, _V, C.POINTER(prt_surface_scene), C.POINTER(prt_cameras), _V, _U64, _I64],
                                      C.c_int),
+            "prt_surface_resample_device": ([_V, _V, C.POINTER(prt_surface_scene), C.POINTER(prt_cameras), _V, _U64,
+                                             _I64], C.c_int),
             "prt_surface_import": ([_V, C.POINTER(prt_surface_scene), C.POINTER(prt_cameras), _V, _I64, _V, _V, _V,
                                     C.POINTER(_V)], C.c_int),
             "prt_surface_export": ([_V, _V, _V, _V, _V], C.c_int),
@@ -384,6 +386,13 @@ def prt_surface_resample(ctx, paths, scene: SurfaceSceneHost, cams: CamerasHost,
     t = _theta_host(theta_ref)
     _check(lib().prt_surface_resample(ctx, paths, C.byref(scene.s), C.byref(cams.s), _hptr(t), seed,
                                       int(n_paths)))
+
+
+def prt_surface_resample_device(ctx, paths, scene: SurfaceSceneHost, cams: CamerasHost, theta_ref, seed: int,
+                                n_paths: int):
+    """theta_ref: device float64 tensor of 2 elements (clamped by the draw)."""
+    _check(lib().prt_surface_resample_device(ctx, paths, C.byref(scene.s), C.byref(cams.s),
+                                             _pair(theta_ref, "theta_ref"), seed, int(n_paths)))
 
 
 def prt_surface_import(ctx, scene: SurfaceSceneHost, cams: CamerasHost, theta_ref, B, pos, sid):

@@ -55,6 +55,8 @@ def test_null_arguments_are_rejected_before_any_device_work(P):
     assert L.prt_surface_adam(None, None, None, None, None, 1, 0.1, 0.1, 0.9, 0.999, 1e-8) == P.PRT_E_INVALID
     assert L.prt_surface_info(None, None, None) == P.PRT_E_INVALID
     assert L.prt_surface_sample(None, None, None, None, 0, 1, None) == P.PRT_E_INVALID
+    assert L.prt_surface_resample(None, None, None, None, None, 0, 1) == P.PRT_E_INVALID
+    assert L.prt_surface_resample_device(None, None, None, None, None, 0, 1) == P.PRT_E_INVALID
     L.prt_surface_destroy(None)
 
 

@@ -16,6 +16,8 @@ against the FP64 oracle (oracle/surface_oracle.c).
 - the Alg. 2 loop recovers (kappa_s, gamma) from measurements the oracle
   rendered.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -182,6 +184,53 @@ def test_surface_draw_tape_equals_import_tape(env):
     assert np.all(np.abs(ra - rb) <= 1e-12 * np.abs(rb)), (ra, rb)
     a.close()
     b.close()
+
+
+def test_surface_redraws_and_device_theta(env):
+    """Redraws into one store: at a device theta_ref (read and clamped by the
+    draw) the store equals a draw at the same host theta_ref, bit for bit,
+    and renders alike; theta_ref beyond the drawable range is clamped to
+    (0.999, 1e4); a redraw that keeps the store's spheres and cameras (which
+    it does not upload or recompute again) and one after the scene and the
+    cameras changed both equal a draw into a new store."""
+    torch, P, api, ctx = env
+    scene, cams, n, ref, tt = _case("smallpaint16")
+    th = torch.tensor(tt, dtype=torch.float64, device="cuda")
+    store = api.SurfacePaths.sample(ctx, scene, cams, ref, 7, n)
+
+    def same(a, b, what):
+        for x, y in zip(a.export(), b.export()):
+            assert np.array_equal(x, y), what
+        # (equal paths: the images differ by the order of the LDS image tallies)
+        _close_img(a.render(th).cpu().numpy(), b.render(th).cpu().numpy(), 1e-13, what)
+
+    for k, (host, dev) in enumerate([((0.55, 25.0), (0.55, 25.0)), ((0.999, 1e4), (1.0, 2e4)),
+                                     ((0.0, 0.0), (-0.5, -3.0))]):
+        store.resample(torch.tensor(dev, dtype=torch.float64, device="cuda"), 11 + k, n)
+        fresh = api.SurfacePaths.sample(ctx, scene, cams, host, 11 + k, n)
+        same(store, fresh, f"device theta_ref {dev}")
+        fresh.close()
+    # another scene (one sphere moved) and other cameras, then back
+    moved = scene.centers.copy()
+    moved[3, 0] += 0.01
+    s2 = dataclasses.replace(scene, centers=moved)
+    c2 = inputs.smallpaint_camera(s2, 20)
+    for sc, cm in [(s2, c2), (scene, cams)]:
+        store2 = api.SurfacePaths.sample(ctx, sc, cm, ref, 5, n)
+        store2.resample(ref, 21, n)
+        store2.resample(ref, 23, n)
+        fresh = api.SurfacePaths.sample(ctx, sc, cm, ref, 23, n)
+        for x, y in zip(store2.export(), fresh.export()):
+            assert np.array_equal(x, y)
+        _close_img(store2.render(th).cpu().numpy(), fresh.render(th).cpu().numpy(), 1e-13, "redraw")
+        fresh.close()
+        store2.close()
+    # one store across the change of scene and cameras
+    store.resample(ref, 31, n)
+    fresh = api.SurfacePaths.sample(ctx, scene, cams, ref, 31, n)
+    same(store, fresh, "same scene again")
+    fresh.close()
+    store.close()
 
 
 def test_surface_adam_matches_oracle(env):
