@@ -313,7 +313,18 @@ __device__ __forceinline__ Real dda_walk_counted(int nx, int ny, int nz, Real px
 // and the order of the additions are those of the plain walk (a step past the
 // end of the walk repeats the last voxel with length 0 and adds nothing), so
 // the sum equals the plain walk's bit for bit; pieces are counted as there.
-template <int U, typename Real, bool kBounded, typename G>
+//
+// kTileZ: value() takes voxel indices of the z-tiled layout (tile_index):
+// a step along z moves by one inside a tile of kTileZ layers and by a tile
+// row between tiles.
+constexpr int kTileZ = 4;
+
+__host__ __device__ inline int64_t tile_index(int ix, int iy, int iz, int nx, int ny)
+{
+    return (((int64_t)(iz / kTileZ) * ny + iy) * nx + ix) * kTileZ + iz % kTileZ;
+}
+
+template <int U, typename Real, bool kBounded, bool kTiled = false, typename G>
 __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy, int iz,
                                         Real wx, Real wy, Real wz, Real tmax, uint32_t& pieces, G&& value)
 {
@@ -329,8 +340,13 @@ __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py
     const int ry = sy > 0 ? ny - 1 - iy : iy;
     const int rz = sz > 0 ? nz - 1 - iz : iz;
     int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
-    const int dvx = sx, dvy = sy * nx, dvz = sz * nx * ny;
-    int v = ix + nx * (iy + ny * iz);
+    const int dvx = kTiled ? sx * kTileZ : sx, dvy = kTiled ? sy * nx * kTileZ : sy * nx;
+    // a z step inside a tile, and one onto the next tile (the same as the
+    // first without tiles)
+    const int dz_in = kTiled ? sz : sz * nx * ny, dz_out = kTiled ? sz * (nx * ny * kTileZ - (kTileZ - 1)) : dz_in;
+    // z steps left before the tile boundary in the walk's direction
+    int zl = kTiled ? (sz > 0 ? kTileZ - 1 - iz % kTileZ : iz % kTileZ) : 1;
+    int v = kTiled ? (int)tile_index(ix, iy, iz, nx, ny) : ix + nx * (iy + ny * iz);
     bool alive = true;
     uint32_t n = 0;
     Real acc = (Real)0;
@@ -352,6 +368,8 @@ __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py
             const bool next = alive && (!kBounded || go) && (Rn & kGuard) == kGuard;
             // the last piece's voxel stays: no step leaves the box
             R = next ? Rn : R;
+            const int dvz = kTiled && zl == 0 ? dz_out : dz_in;
+            if (kTiled) zl = next && bz ? (zl == 0 ? kTileZ - 1 : zl - 1) : zl;
             v = next ? v + (bx ? dvx : (by ? dvy : dvz)) : v;
             t = next ? te : t;
             tnx = next && bx ? tnx + dtx : tnx;

@@ -79,6 +79,7 @@ struct TraceArgs {
     const float* bc_t;        // current cloud field
     const void* grid_tot;     // Real[N_u]: beta_t + beta_air
     const void* grid_dlt;     // Real[N_u]: beta_t - beta_ref
+    const void* grid_tile;    // grid_tot in the z-tiled layout (tile_index), for the render's walks
     double* img;              // render: raw tallies [n][H][W]
     const double* rho;        // grad: residual / (N Omega_p) [n][H][W]
     double* grad;             // grad: [N_u]
@@ -164,10 +165,11 @@ struct VertexLevels {
 // ---- sampling, sorting, packing (sample.hip)
 // grid_tot = beta_t + beta_air and grid_dlt = beta_t - beta_ref in the
 // traversal precision (each when given); also copy = beta_t and *zero = 0
-// when given.
+// when given, and grid_tot in the z-tiled layout of an nx x ny grid
+// (tile_index) into tile when given.
 hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const float* bc_r, double beta_air,
                              int64_t nu, void* grid_tot, void* grid_dlt, float* copy = nullptr,
-                             unsigned int* zero = nullptr);
+                             unsigned int* zero = nullptr, void* tile = nullptr, int nx = 0, int ny = 0);
 hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu);
 // Stable sort of the paths by (size B, spatial key): perm[sorted position] =
 // path id, B[position] = size, nv[position] = tnv[path id] for positions < n

@@ -114,6 +114,8 @@ struct prt_ctx_s {
     void* grid_tot = nullptr;
     void* grid_dlt = nullptr;
     size_t grid_bytes = 0;
+    void* grid_tile = nullptr;  // grid_tot in the z-tiled layout (render walks over a grid in global memory)
+    size_t tile_bytes = 0;
     double* pix = nullptr;      // rho scratch
     size_t pix_n = 0;
     double* part = nullptr;     // reduction partials
@@ -384,6 +386,19 @@ int ensure_grids(prt_ctx c, int64_t nu)
     if (hipMalloc(&c->grid_tot, need) != hipSuccess || hipMalloc(&c->grid_dlt, need) != hipSuccess)
         return fail(PRT_E_NOMEM, "grid scratch allocation failed");
     c->grid_bytes = need;
+    return PRT_OK;
+}
+
+// The render's z-tiled copy of grid_tot (whole tiles of kTileZ layers).
+int ensure_tile(prt_ctx c, int nx, int ny, int nz)
+{
+    const size_t need = (size_t)((nz + kTileZ - 1) / kTileZ) * kTileZ * nx * ny * (c->fp64 ? 8 : 4);
+    if (c->tile_bytes >= need) return PRT_OK;
+    (void)hipFree(c->grid_tile);
+    c->grid_tile = nullptr;
+    c->tile_bytes = 0;
+    if (hipMalloc(&c->grid_tile, need) != hipSuccess) return fail(PRT_E_NOMEM, "grid scratch allocation failed");
+    c->tile_bytes = need;
     return PRT_OK;
 }
 
@@ -863,6 +878,7 @@ void prt_destroy(prt_ctx c)
     for (auto e : c->pool) (void)hipEventDestroy(e);
     (void)hipFree(c->grid_tot);
     (void)hipFree(c->grid_dlt);
+    (void)hipFree(c->grid_tile);
     (void)hipFree(c->pix);
     (void)hipFree(c->gpart);
     (void)hipFree(c->rpart);
@@ -1125,6 +1141,8 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
         p->tape_scene = a.s;
     }
     const RenderPlan plan = plan_render(c->fp64, nu, dc, a.tape != nullptr, p->n_slots, p->first_slot, c->n_cu);
+    if (work && !plan.grid_lds && (rc = ensure_tile(c, s->nx, s->ny, s->nz))) return rc;
+    a.grid_tile = plan.grid_lds ? nullptr : c->grid_tile;
     {
         TimedScope ts(c, K_PREP);
         // the reductions write every pixel; otherwise tallies add up on zeros
@@ -1132,7 +1150,8 @@ int prt_render(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths
         // kernels that hold a grid in LDS form it there from the fields
         if (work && (!plan.grid_lds || !delta_grid_lds(c->fp64, nu)))
             HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, p->beta_ref, s->beta_air, nu, c->grid_tot,
-                                     c->grid_dlt));
+                                     c->grid_dlt, nullptr, nullptr, plan.grid_lds ? nullptr : c->grid_tile, s->nx,
+                                     s->ny));
     }
     if ((rc = ensure_scratch(&c->rpart, &c->rpart_bytes, plan.partial_bytes))) return rc;
     if (work) {

@@ -13,7 +13,8 @@ __global__ void __launch_bounds__(256) prep_grids_kernel(const float* __restrict
                                                          const float* __restrict__ bc_r, double beta_air,
                                                          int64_t nu, Real* __restrict__ tot,
                                                          Real* __restrict__ dlt, float* __restrict__ copy,
-                                                         unsigned int* __restrict__ zero)
+                                                         unsigned int* __restrict__ zero, Real* __restrict__ tile,
+                                                         int nx, int ny)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (zero && i == 0) *zero = 0u;
@@ -22,18 +23,23 @@ __global__ void __launch_bounds__(256) prep_grids_kernel(const float* __restrict
     if (tot) tot[i] = (Real)(t + beta_air);
     if (dlt) dlt[i] = (Real)(t - (double)bc_r[i]);
     if (copy) copy[i] = bc_t[i];
+    if (tile) {
+        const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((int64_t)nx * ny));
+        tile[tile_index(ix, iy, iz, nx, ny)] = (Real)(t + beta_air);
+    }
 }
 
 hipError_t launch_prep_grids(hipStream_t st, int fp64, const float* bc_t, const float* bc_r, double beta_air,
-                             int64_t nu, void* grid_tot, void* grid_dlt, float* copy, unsigned int* zero)
+                             int64_t nu, void* grid_tot, void* grid_dlt, float* copy, unsigned int* zero, void* tile,
+                             int nx, int ny)
 {
     const int64_t blocks = (nu + 255) / 256;
     if (fp64)
         prep_grids_kernel<double><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(
-            bc_t, bc_r, beta_air, nu, (double*)grid_tot, (double*)grid_dlt, copy, zero);
+            bc_t, bc_r, beta_air, nu, (double*)grid_tot, (double*)grid_dlt, copy, zero, (double*)tile, nx, ny);
     else
         prep_grids_kernel<float><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(
-            bc_t, bc_r, beta_air, nu, (float*)grid_tot, (float*)grid_dlt, copy, zero);
+            bc_t, bc_r, beta_air, nu, (float*)grid_tot, (float*)grid_dlt, copy, zero, (float*)tile, nx, ny);
     return hipGetLastError();
 }
 

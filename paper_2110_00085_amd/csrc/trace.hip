@@ -156,12 +156,14 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
     const int nu = s.nx * s.ny * s.nz;
     const int npix = cams.W * cams.H;
     Real* __restrict__ sgrid = reinterpret_cast<Real*>(smem);
-    const Real* __restrict__ gtot = (const Real*)a.grid_tot;
+    // a grid in global memory is walked in its z-tiled copy: a walk's next
+    // pieces share cache lines along z as well as x
+    const Real* __restrict__ gtile = (const Real*)a.grid_tile;
     if (kGridLds) {
         lds_fill(sgrid, nu, [&](int i) { return (Real)((double)a.bc_t[i] + s.beta_air); });
         __syncthreads();
     }
-    auto beta_tot = [&](uint32_t v) -> Real { return kGridLds ? sgrid[v] : gtot[v]; };
+    auto beta_tot = [&](uint32_t v) -> Real { return kGridLds ? sgrid[v] : gtile[v]; };
     const double r2scale = 1.0 / (s.vk * s.vk);
     const float vkf = (float)s.vk, wc_f = (float)s.w_c;
     const float wab = (float)(s.w_a * s.beta_air), ray_k = (float)(3.0 / (16.0 * kPi));
@@ -215,8 +217,8 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                     // with every camera outside the box the walk ends at the box
                     // boundary, before the camera, so it needs no length bound
                     const Real tc = cams.outside
-                                        ? walk_sum<Real, false, kGridLds ? 1 : kRenderWalkLoads>(s, beta_tot, p1, u, d2 * id, nseg)
-                                        : walk_sum<Real, true, kGridLds ? 1 : kRenderWalkLoads>(s, beta_tot, p1, u, d2 * id, nseg);
+                                        ? walk_sum<Real, false, kGridLds ? 1 : kRenderWalkLoads, !kGridLds>(s, beta_tot, p1, u, d2 * id, nseg)
+                                        : walk_sum<Real, true, kGridLds ? 1 : kRenderWalkLoads, !kGridLds>(s, beta_tot, p1, u, d2 * id, nseg);
                     c = base * (double)(fst * expf(-(float)tc * vkf) * (float)(r2scale * id * id));
                 } else {
                     const double dist2 = ex * ex + ey * ey + ez * ez;
@@ -226,8 +228,8 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                     const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
                     const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
                     const Real tc = cams.outside
-                                        ? walk_sum<Real, false, kGridLds ? 1 : kRenderWalkLoads>(s, beta_tot, p1, u, dist, nseg)
-                                        : walk_sum<Real, true, kGridLds ? 1 : kRenderWalkLoads>(s, beta_tot, p1, u, dist, nseg);
+                                        ? walk_sum<Real, false, kGridLds ? 1 : kRenderWalkLoads, !kGridLds>(s, beta_tot, p1, u, dist, nseg)
+                                        : walk_sum<Real, true, kGridLds ? 1 : kRenderWalkLoads, !kGridLds>(s, beta_tot, p1, u, dist, nseg);
                     c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
                 }
                 if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = make_float2((float)c, __int_as_float(pix));
