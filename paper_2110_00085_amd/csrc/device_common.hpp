@@ -25,7 +25,7 @@ struct DevScene {
     double a_top, a_x, a_y; // projected areas of the lit faces [km^2]
     double w0;              // source weight F0 * projected box area
     double x_face, y_face;  // grid coordinate of the lit x / y face
-    double inv_nx, inv_nxy; // 1 / nx and 1 / (nx * ny), for voxel_ijk
+    double inv_nx, inv_ny, inv_nxy; // 1 / nx, 1 / ny and 1 / (nx * ny), for voxel_ijk
 };
 
 // Cameras with positions converted to grid units.
@@ -324,6 +324,43 @@ __host__ __device__ inline int64_t tile_index(int ix, int iy, int iz, int nx, in
     return (((int64_t)(iz / kTileZ) * ny + iy) * nx + ix) * kTileZ + iz % kTileZ;
 }
 
+// Linear voxel index (ix + nx (iy + ny iz)) of z-tiled index t; the
+// divisions by nx and ny as in voxel_ijk.
+__device__ __forceinline__ int tile_to_linear(int t, int nx, int ny, double inv_nx, double inv_ny)
+{
+    const int r = t / kTileZ;  // ((iz / kTileZ) * ny + iy) * nx + ix
+    const int row = (int)floor(((double)r + 0.5) * inv_nx);
+    const int ix = r - row * nx;
+    const int tz = (int)floor(((double)row + 0.5) * inv_ny);
+    const int iy = row - tz * ny;
+    return ix + nx * (iy + ny * (tz * kTileZ + t % kTileZ));
+}
+
+// Voxel index of a walk, stepped with the walk: linear, or z-tiled.
+template <bool kTiled>
+struct WalkIndex {
+    int v, dvx, dvy, dz_in, dz_out;
+    int zl;  // z steps left before the tile boundary in the walk's direction
+    __device__ __forceinline__ WalkIndex(int nx, int ny, int ix, int iy, int iz, int sx, int sy, int sz)
+    {
+        dvx = kTiled ? sx * kTileZ : sx;
+        dvy = kTiled ? sy * nx * kTileZ : sy * nx;
+        // a z step inside a tile, and one onto the next tile (the same as the
+        // first without tiles)
+        dz_in = kTiled ? sz : sz * nx * ny;
+        dz_out = kTiled ? sz * (nx * ny * kTileZ - (kTileZ - 1)) : dz_in;
+        zl = kTiled ? (sz > 0 ? kTileZ - 1 - iz % kTileZ : iz % kTileZ) : 1;
+        v = kTiled ? (int)tile_index(ix, iy, iz, nx, ny) : ix + nx * (iy + ny * iz);
+    }
+    // the step along x, y or z (one of bx, by, bz), taken when `next`
+    __device__ __forceinline__ void step(bool next, bool bx, bool by, bool bz)
+    {
+        const int dvz = kTiled && zl == 0 ? dz_out : dz_in;
+        if (kTiled) zl = next && bz ? (zl == 0 ? kTileZ - 1 : zl - 1) : zl;
+        v = next ? v + (bx ? dvx : (by ? dvy : dvz)) : v;
+    }
+};
+
 template <int U, typename Real, bool kBounded, bool kTiled = false, typename G>
 __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy, int iz,
                                         Real wx, Real wy, Real wz, Real tmax, uint32_t& pieces, G&& value)
@@ -340,13 +377,7 @@ __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py
     const int ry = sy > 0 ? ny - 1 - iy : iy;
     const int rz = sz > 0 ? nz - 1 - iz : iz;
     int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
-    const int dvx = kTiled ? sx * kTileZ : sx, dvy = kTiled ? sy * nx * kTileZ : sy * nx;
-    // a z step inside a tile, and one onto the next tile (the same as the
-    // first without tiles)
-    const int dz_in = kTiled ? sz : sz * nx * ny, dz_out = kTiled ? sz * (nx * ny * kTileZ - (kTileZ - 1)) : dz_in;
-    // z steps left before the tile boundary in the walk's direction
-    int zl = kTiled ? (sz > 0 ? kTileZ - 1 - iz % kTileZ : iz % kTileZ) : 1;
-    int v = kTiled ? (int)tile_index(ix, iy, iz, nx, ny) : ix + nx * (iy + ny * iz);
+    WalkIndex<kTiled> vi(nx, ny, ix, iy, iz, sx, sy, sz);
     bool alive = true;
     uint32_t n = 0;
     Real acc = (Real)0;
@@ -358,7 +389,7 @@ __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py
             const Real tn = fmin(tnx, fmin(tny, tnz));
             const bool go = !kBounded || tn < tmax;
             const Real te = kBounded ? (go ? tn : tmax) : tn;
-            vv[k] = v;
+            vv[k] = vi.v;
             ll[k] = alive ? te - t : (Real)0;
             n += alive ? 1u : 0u;
             const bool bx = tnx == tn;
@@ -368,9 +399,7 @@ __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py
             const bool next = alive && (!kBounded || go) && (Rn & kGuard) == kGuard;
             // the last piece's voxel stays: no step leaves the box
             R = next ? Rn : R;
-            const int dvz = kTiled && zl == 0 ? dz_out : dz_in;
-            if (kTiled) zl = next && bz ? (zl == 0 ? kTileZ - 1 : zl - 1) : zl;
-            v = next ? v + (bx ? dvx : (by ? dvy : dvz)) : v;
+            vi.step(next, bx, by, bz);
             t = next ? te : t;
             tnx = next && bx ? tnx + dtx : tnx;
             tny = next && by ? tny + dty : tny;
@@ -396,8 +425,9 @@ __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py
 // the depth before that piece and *t0 to the piece's start, or -1 when the
 // ray leaves the box first, setting *t0 to the exit parameter.  The pieces,
 // the order of the additions and the comparisons are those of a dda_walk
-// functor doing the same, so both give the same result.
-template <int U, typename Real, typename G>
+// functor doing the same, so both give the same result.  kTiled: voxel
+// indices (value's argument and the result) of the z-tiled layout.
+template <int U, typename Real, bool kTiled = false, typename G>
 __device__ __forceinline__ int dda_first_hit(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy, int iz,
                                              Real wx, Real wy, Real wz, Real tau, G&& value, Real* acc_out,
                                              Real* t0_out)
@@ -416,8 +446,7 @@ __device__ __forceinline__ int dda_first_hit(int nx, int ny, int nz, Real px, Re
     const int ry = sy > 0 ? ny - 1 - iy : iy;
     const int rz = sz > 0 ? nz - 1 - iz : iz;
     int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
-    const int dvx = sx, dvy = sy * nx, dvz = sz * nx * ny;
-    int v = ix + nx * (iy + ny * iz);
+    WalkIndex<kTiled> vi(nx, ny, ix, iy, iz, sx, sy, sz);
     bool alive = true;
     Real acc = (Real)0;
     for (;;) {
@@ -427,7 +456,7 @@ __device__ __forceinline__ int dda_first_hit(int nx, int ny, int nz, Real px, Re
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const Real tn = fmin(tnx, fmin(tny, tnz));
-            vv[k] = v;
+            vv[k] = vi.v;
             ts[k] = t;
             ll[k] = tn - t;
             live[k] = alive;
@@ -439,7 +468,7 @@ __device__ __forceinline__ int dda_first_hit(int nx, int ny, int nz, Real px, Re
             // the exit parameter advances with the last piece; its voxel stays
             t = alive ? tn : t;
             R = next ? Rn : R;
-            v = next ? v + (bx ? dvx : (by ? dvy : dvz)) : v;
+            vi.step(next, bx, by, bz);
             tnx = next && bx ? tnx + dtx : tnx;
             tny = next && by ? tny + dty : tny;
             tnz = next && bz ? tnz + dtz : tnz;

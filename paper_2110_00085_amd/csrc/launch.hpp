@@ -37,6 +37,7 @@ struct SampleArgs {
     DevScene s;
     const float* beta_c;   // cloud field the paths are drawn from
     const void* grid_tot;  // Real[N_u]: beta_c + beta_air
+    const void* grid_tile; // the same in the z-tiled layout (walked when the grid is read from global memory)
     uint64_t seed;
     int64_t n;
     float4* tmp;           // [n][tmp_rows] records, or null

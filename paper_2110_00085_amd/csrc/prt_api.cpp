@@ -306,6 +306,7 @@ DevScene make_dev_scene(const prt_scene* s)
     d.x_face = d.sun[0] > 0 ? 0.0 : (double)s->nx;
     d.y_face = d.sun[1] > 0 ? 0.0 : (double)s->ny;
     d.inv_nx = 1.0 / (double)s->nx;
+    d.inv_ny = 1.0 / (double)s->ny;
     d.inv_nxy = 1.0 / ((double)s->nx * (double)s->ny);
     return d;
 }
@@ -608,7 +609,7 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     int rc;
     // earlier work may still read the store's or the context's buffers
     HIPCHK(hipDeviceSynchronize());
-    if ((rc = ensure_grids(c, nu))) return rc;
+    if ((rc = ensure_grids(c, nu)) || (rc = ensure_tile(c, s->nx, s->ny, s->nz))) return rc;
     if ((rc = grow(&p->beta_ref, &p->cap_nu, nu))) return rc;
     if (one_pass && (rc = ensure_scratch(&c->s_tmp, &c->s_tmp_bytes, (size_t)n * stride * sizeof(float4)))) return rc;
     if (compact &&
@@ -631,13 +632,15 @@ int fill_sampled(prt_ctx c, const prt_scene* s, uint64_t seed, int64_t n, prt_pa
     {
         // the reference snapshot beta_ref = beta_t, the sampler's grid and its id counter
         TimedScope ts(c, K_PREP);
+        // (and its z-tiled copy, walked when the grid does not fit the LDS)
         HIPCHK(launch_prep_grids(c->stream, c->fp64, s->beta_cloud, nullptr, s->beta_air, nu, c->grid_tot, nullptr,
-                                 p->beta_ref, c->work + 2));
+                                 p->beta_ref, c->work + 2, c->grid_tile, s->nx, s->ny));
     }
     SampleArgs a;
     a.s = make_dev_scene(s);
     a.beta_c = p->beta_ref;
     a.grid_tot = c->grid_tot;
+    a.grid_tile = c->grid_tile;
     a.seed = seed;
     a.n = n;
     a.tmp = (one_pass || compact) ? (float4*)c->s_tmp : nullptr;

@@ -197,14 +197,20 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
                     return true;
                 });
         } else {
-            // the grid in global memory: kSampleLoads pieces per batch of loads
-            hit = dda_first_hit<kSampleLoads, Real>(s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy, iz,
-                                                    (Real)w[0], (Real)w[1], (Real)w[2], taur,
-                                                    [&](uint32_t vv) { return gt[vv]; }, &acc, &thit);
+            // the grid in global memory, z-tiled: kSampleLoads pieces per
+            // batch of loads; the hit's tiled index becomes a linear one
+            const Real* __restrict__ gtl = (const Real*)a.grid_tile;
+            const int ht = dda_first_hit<kSampleLoads, Real, true>(s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy,
+                                                                   iz, (Real)w[0], (Real)w[1], (Real)w[2], taur,
+                                                                   [&](uint32_t vv) { return gtl[vv]; }, &acc, &thit);
             tend = thit;
+            if (ht >= 0) {
+                thit += (taur - acc) / gtl[ht];
+                hit = tile_to_linear(ht, s.nx, s.ny, s.inv_nx, s.inv_ny);
+            }
         }
         // the division that places the scatter inside its voxel stays out of the loop
-        if (hit >= 0) thit += (taur - acc) / gt[hit];
+        if (kGridLds && hit >= 0) thit += (taur - acc) / gt[hit];
         // this event writes record nv: past the short row it goes to the
         // path's overflow segment, a new one taken now from the wavefront's
         // chunk when the current one is full
