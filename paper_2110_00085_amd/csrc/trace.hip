@@ -31,7 +31,7 @@ constexpr int64_t kMaxGradSlabs = 8;            // LDS gradient slabs when each 
 constexpr int64_t kMaxTapeGradSlabs = 64;       // LDS gradient slabs when the weights come from the tape
 constexpr size_t kTapeImageLds = 64 * 1024;     // FP64 image of one camera, images formed from the tape
 constexpr int kWalkLoads = 4;                   // pieces formed before their grid loads, grids in global memory
-constexpr int kRenderWalkLoads = 12;            // the same for the render's connection walks
+constexpr int kRenderWalkLoads = 4;             // the same for the render's connection walks
 
 // The field beta_t - beta_ref for a persistent workgroup: formed in LDS from
 // beta_t and beta_ref (kGridLds), else the one prepared in global memory.
