@@ -349,6 +349,10 @@ struct WalkIndex {
         // first without tiles)
         dz_in = kTiled ? sz : sz * nx * ny;
         dz_out = kTiled ? sz * (nx * ny * kTileZ - (kTileZ - 1)) : dz_in;
+        // opaque to the compiler: it would otherwise fold the step's choice
+        // between sz and sz * X into a multiplication by a chosen factor
+        // (a quarter-rate integer multiply per step, in a branch)
+        if (kTiled) asm volatile("" : "+v"(dz_in), "+v"(dz_out));
         zl = kTiled ? (sz > 0 ? kTileZ - 1 - iz % kTileZ : iz % kTileZ) : 1;
         v = kTiled ? (int)tile_index(ix, iy, iz, nx, ny) : ix + nx * (iy + ny * iz);
     }
