@@ -960,14 +960,22 @@ __device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams&
             if ((uint32_t)lane < wq - rq) walk_entry(queue[(rq + lane) & (kBinQueue - 1)]);
         }
     } else {
+        // a segment whose bounding box (widened by a voxel: a walk starts in
+        // its stored voxel, which rounding can put next to the position's)
+        // misses the block has no piece in it, and its start vertex no term:
+        // both are skipped before the direction is formed
+        auto near = [&](double lo, double hi, int a) { return hi >= (double)box.lo[a] - 1.0 && lo <= (double)box.hi[a] + 1.0; };
         double A = 0.0;
         Vtx pk1 = load_vtx(V, Bn);
         for (int k = Bn - 1; k >= 0; --k) {
             A += (double)X[(int64_t)(k + 1) * kWave].x;
             const Vtx pk = load_vtx(V, k);
-            double w[3];
-            const double L = seg_dir(pk, pk1, w);
-            if (A != 0.0) {
+            const bool seg_near = near(fmin(pk.x, pk1.x), fmax(pk.x, pk1.x), 0) &&
+                                  near(fmin(pk.y, pk1.y), fmax(pk.y, pk1.y), 1) &&
+                                  near(fmin(pk.z, pk1.z), fmax(pk.z, pk1.z), 2);
+            if (A != 0.0 && seg_near) {
+                double w[3];
+                const double L = seg_dir(pk, pk1, w);
                 walk_scatter_box<float>(s, add, pk, w, L, -A * s.vk, nseg, box);
                 const int u = k >= 1 ? box_index(box, clamp_vox(pk.v, nu), s) : -1;
                 if (u >= 0) add((uint32_t)u, A * (double)X[(int64_t)k * kWave].z);
