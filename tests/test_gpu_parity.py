@@ -5,6 +5,8 @@ drawn by the oracle and imported into the library.
 Tolerances: FP32 traversal mode -- images 1e-5, gradients 1e-4 relative (L2),
 correction-factor statistics 1e-5; all-FP64 mode -- 1e-9 (only the
 summation order of the FP64 atomics and libm ulps differ)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -135,6 +137,15 @@ def _workload(name):
         beta = np.where(inside, rng.lognormal(3.0, 0.6, (nz, ny, nx)), 0.0).astype(np.float32)
         s = inputs.Scene(nx, ny, nz, 0.02, beta, albedo_cloud=0.99, g=0.85, max_order=12)
         return s, inputs.arc_cameras(s, [-45.0, 0.0, 30.0], 32, 32), 20_003, 1064
+    if name == "ragged_z":
+        # 64 x 48 x 13 grid (160 KB in FP32: sampled and rendered from the
+        # z-tiled copy in global memory; 13 layers: the copy ends in a partial
+        # tile of one layer) with the sun off the vertical so that free
+        # flights and connections cross tile boundaries in both z directions
+        s = inputs.random_field((64, 48, 13), voxel_km=0.02, lo=0.0, hi=35.0, seed=13, albedo_cloud=0.99, g=0.85,
+                                max_order=10)
+        s = dataclasses.replace(s, sun_zenith_deg=35.0, sun_azimuth_deg=20.0)
+        return s, inputs.arc_cameras(s, [-50.0, -10.0, 35.0], 24, 20), 12_007, 1013
     if name == "manycams":
         # 20 cameras of 48 x 48: the FP32 image partials (184 KB) exceed the LDS,
         # so renders of fewer orders (no tape) fall back to FP64 atomics on the
@@ -155,10 +166,13 @@ def _workload(name):
 
 # ---------------------------------------------------------------- sampling
 
-def test_sample_fp64_matches_oracle(env):
+@pytest.mark.parametrize("name", ["cloud8", "ragged_z"])
+def test_sample_fp64_matches_oracle(env, name):
+    """All-FP64 draws reproduce the oracle's paths: on cloud8 from the grid in
+    LDS, on ragged_z from the z-tiled copy in global memory."""
     torch, P, api = env
-    scene, _, n, seed = _workload("cloud8")
-    say(f"sample fp64 cloud8 n={n}")
+    scene, _, n, seed = _workload(name)
+    say(f"sample fp64 {name} n={n}")
     ctx = api.Context(0, P.PRT_ALL_FP64)
     st = api.PathStore.sample(ctx, scene, _dev(torch, scene.beta_cloud), seed, n)
     off, xyz, vox, B, br = st.export()
@@ -169,7 +183,7 @@ def test_sample_fp64_matches_oracle(env):
     for i in np.nonzero(same)[0][::7]:
         a, b = xyz[off[i]:off[i + 1]], ref.xyz[ref.off[i]:ref.off[i + 1]]
         assert a.shape == b.shape
-        assert np.abs(a.astype(float) - b).max() <= 2e-6 * 8, i
+        assert np.abs(a.astype(float) - b).max() <= 2e-6 * max(scene.nx, scene.ny, scene.nz), i
         assert np.array_equal(vox[off[i]:off[i + 1]], ref.vox[ref.off[i]:ref.off[i + 1]])
     _check_sort(P.prt_paths_permutation(ctx.handle, st.handle), scene, off, vox, B)
 
@@ -272,7 +286,7 @@ def test_compact_draw_equals_one_pass(env, prec):
                 assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("name", ["cloud8", "cloud32mid"])
+@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "ragged_z"])
 def test_sample_fp32_close_to_oracle(env, name):
     torch, P, api = env
     scene, _, n, seed = _workload(name)
@@ -294,7 +308,8 @@ def test_sample_fp32_close_to_oracle(env, name):
 # ---------------------------------------------- render / grad / reweight
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "slabs40", "wide96", "sparse64", "manycams", "incam"])
+@pytest.mark.parametrize("name", ["cloud8", "cloud32mid", "slabs40", "wide96", "sparse64", "ragged_z", "manycams",
+                                  "incam"])
 def test_render_grad_reweight_match_oracle(env, prec, name):
     torch, P, api = env
     scene, cams, n, seed = _workload(name)
