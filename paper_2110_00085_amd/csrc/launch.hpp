@@ -122,9 +122,10 @@ struct TraceArgs {
     // weights kernel when non-null.
     int* trange;
     int bin_axis, bin_layers;  // slab axis and layers per slab of those ranges
-    // and, per connection, its own slab range lo | hi << 16 in the tape's
-    // layout (0xffff when the connection has no weight)
-    uint32_t* rtape;
+    // and, per connection, its own slab range lo | hi << 8 in the tape's
+    // layout (0xffff when the connection has no weight: lo = 255 exceeds
+    // every slab)
+    uint16_t* rtape;
     // and, per row of 64 records (tape row r = record / 64) and camera group
     // g, the union of that row's connection ranges at brange[r * groups + g]
     // (0xffff when the row has no weighted connection in the group)
@@ -148,7 +149,9 @@ struct GradBins {
     double* partial;     // per chunk: the slab's sums
 };
 constexpr int kBinTasks = 1024;
-constexpr int kMaxBinSlabs = 512;  // slabs the binning kernels count per block
+// slabs the binning kernels count per block; a connection's slab range
+// packs two slab indices into 8 bits each
+constexpr int kMaxBinSlabs = 255;
 constexpr int kBinChunkWord = 3;  // chunk counter of the binned walk: word 3 of the task-counter set
 
 // Per-vertex task levels of the render prefix and the gradient weights: one

@@ -1231,7 +1231,7 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
                  ensure_scratch(&c->bin_list, &c->bin_list_bytes,
                                 (std::max<size_t>(list_words, 1) + bins.n_slabs + 2) * sizeof(uint32_t)) == PRT_OK &&
                  ensure_scratch(&c->bin_part, &c->bin_part_bytes, grad_bin_partial_bytes(ds, bins, c->n_cu)) == PRT_OK &&
-                 ensure_scratch(&c->bin_rtape, &c->bin_rtape_bytes, recs * dc.n * sizeof(uint32_t)) == PRT_OK &&
+                 ensure_scratch(&c->bin_rtape, &c->bin_rtape_bytes, recs * dc.n * sizeof(uint16_t)) == PRT_OK &&
                  ensure_scratch(&c->bin_brange, &c->bin_brange_bytes,
                                 (recs / kWave + 1) * (size_t)(kinds - 1) * sizeof(uint32_t)) == PRT_OK;
         if (binned) {
@@ -1249,7 +1249,7 @@ int prt_grad(prt_ctx c, const prt_scene* s, const prt_cameras* cams, prt_paths p
     a.grad = grad;
     if (binned) {
         a.trange = (int*)c->bin_trange;
-        a.rtape = (uint32_t*)c->bin_rtape;
+        a.rtape = (uint16_t*)c->bin_rtape;
         a.brange = (uint32_t*)c->bin_brange;
         a.bin_axis = bins.axis;
         a.bin_layers = bins.layers;

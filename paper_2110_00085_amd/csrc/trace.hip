@@ -621,7 +621,8 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
                     wf = tt[j].x * (float)rr[j];
                     const float ex = (float)(cams.pos[d][0] - p1.x), ey = (float)(cams.pos[d][1] - p1.y),
                                 ez = (float)(cams.pos[d][2] - p1.z);
-                    uint32_t rpack = 0xffffu;
+                    static_assert(kMaxBinSlabs <= 255, "slab ranges pack two 8-bit slab indices");
+                    uint16_t rpack = 0xffffu;
                     if (bins && wf != 0.f) {
                         // the connection runs from x_b to where it leaves the box
                         // (or reaches the camera): parameter t in [0, 1] along e
@@ -643,7 +644,7 @@ __global__ void __launch_bounds__(kGwBlock) grad_weights_kernel(TraceArgs a, Dev
                             rhi[k] = gi == k ? max(rhi[k], hi) : rhi[k];
                         }
                         const int na = ax == 0 ? s.nx : (ax == 1 ? s.ny : s.nz);
-                        rpack = (uint32_t)(max(lo, 0) / a.bin_layers) | (uint32_t)(min(hi, na - 1) / a.bin_layers) << 16;
+                        rpack = (uint16_t)((max(lo, 0) / a.bin_layers) | (min(hi, na - 1) / a.bin_layers) << 8);
                     }
                     if (bins && act) a.rtape[rec0 * cams.n + lane + (int64_t)(b * cams.n + d) * kWave] = rpack;
                     const float mu = (wf0 * ex + wf1 * ey + wf2 * ez) * rsqrtf(ex * ex + ey * ey + ez * ez);
@@ -897,7 +898,7 @@ __device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams&
         // the slab (range tape), the hits are queued in LDS, and 64 queued
         // walks at a time are walked, one per lane
         const int d_lo = kind * cpg, nd = min(cams.n, d_lo + cpg) - d_lo;
-        const uint32_t* __restrict__ Rp = a.rtape + rec0 * cams.n + d_lo * kWave + lane;
+        const uint16_t* __restrict__ Rp = a.rtape + rec0 * cams.n + d_lo * kWave + lane;
         const float4* __restrict__ Vb = a.st.vtx + a.st.batch_off[bt];
         const float* __restrict__ Wb = a.wtape + rec0 * cams.n + d_lo * kWave;
         const uint32_t sl = (uint32_t)slab;
@@ -932,10 +933,10 @@ __device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams&
             uint32_t rr[kGroupCams];
 #pragma unroll
             for (int j = 0; j < kGroupCams; ++j)
-                rr[j] = (j < nd && b <= Bn) ? Rp[(int64_t)(b * cams.n + j) * kWave] : 0xffffu;
+                rr[j] = (j < nd && b <= Bn) ? (uint32_t)Rp[(int64_t)(b * cams.n + j) * kWave] : 0xffffu;
 #pragma unroll
             for (int j = 0; j < kGroupCams; ++j) {
-                const bool hit = (rr[j] & 0xffffu) <= sl && sl <= (rr[j] >> 16);
+                const bool hit = (rr[j] & 0xffu) <= sl && sl <= (rr[j] >> 8);
                 const uint64_t m = __ballot(hit);
                 if (hit) {
                     const uint32_t pos = wq + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
