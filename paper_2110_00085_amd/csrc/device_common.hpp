@@ -544,9 +544,11 @@ struct SubBox {
 // enters it where the ray meets the block (if it does before tmax); the
 // entry voxel is taken from the entry point, so a piece next to the entry can
 // differ from the whole-grid walk by rounding only.
+// (v0 is added to every voxel index the functor sees.)
 template <typename Real, bool kBounded = true, typename F>
 __device__ __forceinline__ void dda_walk_box(const SubBox& b, Real px, Real py, Real pz, int ix, int iy, int iz,
-                                             Real wx, Real wy, Real wz, Real tmax, uint32_t& pieces, F&& f)
+                                             Real wx, Real wy, Real wz, Real tmax, uint32_t& pieces, F&& f,
+                                             int v0 = 0)
 {
     int sx, sy, sz;
     Real ivx, ivy, ivz;
@@ -579,7 +581,7 @@ __device__ __forceinline__ void dda_walk_box(const SubBox& b, Real px, Real py, 
     const int ry = sy > 0 ? b.hi[1] - 1 - iy : iy - b.lo[1];
     const int rz = sz > 0 ? b.hi[2] - 1 - iz : iz - b.lo[2];
     const int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
-    const int v = (ix - b.lo[0]) * b.st[0] + (iy - b.lo[1]) * b.st[1] + (iz - b.lo[2]) * b.st[2];
+    const int v = v0 + (ix - b.lo[0]) * b.st[0] + (iy - b.lo[1]) * b.st[1] + (iz - b.lo[2]) * b.st[2];
     dda_loop<Real, kBounded>(R, v, sx * b.st[0], sy * b.st[1], sz * b.st[2], dda_first_face(sx, ix, px, ivx, t),
                              dda_first_face(sy, iy, py, ivy, t), dda_first_face(sz, iz, pz, ivz, t),
                              (Real)sx * ivx, (Real)sy * ivy, (Real)sz * ivz, t, tmax, pieces, f);

@@ -890,6 +890,7 @@ __device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams&
     // (lanes without scatters stay: the connection walks are shared across lanes)
     if (kind >= G && Bn <= 0) return;
     auto add = [&](uint32_t v, double x) { atomicAdd(&tally[v], x); };
+    const LdsTally lt(tally, box);
     const int64_t rec0 = a.st.batch_off[bt] - a.tape_base;
     const float4* __restrict__ V = a.st.vtx + a.st.batch_off[bt] + lane;
     const float4* __restrict__ X = a.vaux + rec0 + lane;
@@ -915,11 +916,11 @@ __device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams&
             const float d2 = ex * ex + ey * ey + ez * ez;
             const float id = __builtin_amdgcn_rsqf(d2);
             if (cams.outside)
-                walk_scatter_box_f<false>(s, add, r.x, r.y, r.z, vox_of(r), ex * id, ey * id, ez * id, d2 * id,
-                                          -wgt * s.vk, nseg, box);
+                walk_tally_box_f<false>(s, lt, r.x, r.y, r.z, vox_of(r), ex * id, ey * id, ez * id, d2 * id,
+                                        -wgt * s.vk, nseg);
             else
-                walk_scatter_box_f(s, add, r.x, r.y, r.z, vox_of(r), ex * id, ey * id, ez * id, d2 * id, -wgt * s.vk,
-                                   nseg, box);
+                walk_tally_box_f(s, lt, r.x, r.y, r.z, vox_of(r), ex * id, ey * id, ez * id, d2 * id, -wgt * s.vk,
+                                 nseg);
         };
         int bmax = Bn;
         for (int o = kWave / 2; o > 0; o >>= 1) bmax = max(bmax, __shfl_xor(bmax, o));
@@ -977,7 +978,8 @@ __device__ __forceinline__ void grad_bin_task(const TraceArgs& a, const DevCams&
             if (A != 0.0 && seg_near) {
                 double w[3];
                 const double L = seg_dir(pk, pk1, w);
-                walk_scatter_box<float>(s, add, pk, w, L, -A * s.vk, nseg, box);
+                walk_tally_box_f(s, lt, (float)pk.x, (float)pk.y, (float)pk.z, pk.v, (float)w[0], (float)w[1],
+                                 (float)w[2], (float)L, -A * s.vk, nseg);
                 const int u = k >= 1 ? box_index(box, clamp_vox(pk.v, nu), s) : -1;
                 if (u >= 0) add((uint32_t)u, A * (double)X[(int64_t)k * kWave].z);
             }

@@ -117,6 +117,45 @@ __device__ __forceinline__ void walk_scatter_box_f(const DevScene& s, A&& add, f
     count += n;
 }
 
+// An FP64 tally in LDS addressed in bytes: walks over it step the byte
+// address itself (strides times 8 from the tally's start), which saves the
+// index-to-address arithmetic of every piece.
+typedef __attribute__((address_space(3))) double lds_double;
+
+struct LdsTally {
+    uint32_t base;  // byte address of element 0
+    SubBox box;     // the block, with strides in bytes
+    __device__ __forceinline__ LdsTally(double* tally, const SubBox& b) : box(b)
+    {
+        base = (uint32_t)(uintptr_t)(lds_double*)tally;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) box.st[k] = b.st[k] * (int)sizeof(double);
+    }
+    __device__ __forceinline__ static void add_at(uint32_t addr, double x)
+    {
+        __hip_atomic_fetch_add((lds_double*)(uintptr_t)addr, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+};
+
+// As walk_scatter_box_f, adding scale * length into the LDS tally t.
+template <bool kBounded = true>
+__device__ __forceinline__ void walk_tally_box_f(const DevScene& s, const LdsTally& t, float px, float py, float pz,
+                                                 int v, float wx, float wy, float wz, float tmax, double scale,
+                                                 uint64_t& count)
+{
+    int ix, iy, iz;
+    voxel_ijk(s, clamp_vox(v, s.nx * s.ny * s.nz), ix, iy, iz);
+    uint32_t n = 0;
+    dda_walk_box<float, kBounded>(
+        t.box, px, py, pz, ix, iy, iz, wx, wy, wz, tmax, n,
+        [&](int a, float, float l) {
+            LdsTally::add_at((uint32_t)a, scale * (double)l);
+            return true;
+        },
+        (int)t.base);
+    count += n;
+}
+
 // Slab `slab` of the binned gradient as a block of the grid, numbered with
 // the slab axis slowest (its voxels are contiguous in the slab tally).
 // (selects rather than indexing by the runtime axis, so that the block stays
