@@ -336,25 +336,26 @@ __device__ __forceinline__ int tile_to_linear(int t, int nx, int ny, double inv_
     return ix + nx * (iy + ny * (tz * kTileZ + t % kTileZ));
 }
 
-// Voxel index of a walk, stepped with the walk: linear, or z-tiled.
-template <bool kTiled>
+// Voxel index of a walk, stepped with the walk: linear, or z-tiled; times
+// kScale (e.g. the element size, so that the walk steps a byte offset).
+template <bool kTiled, int kScale = 1>
 struct WalkIndex {
     int v, dvx, dvy, dz_in, dz_out;
     int zl;  // z steps left before the tile boundary in the walk's direction
     __device__ __forceinline__ WalkIndex(int nx, int ny, int ix, int iy, int iz, int sx, int sy, int sz)
     {
-        dvx = kTiled ? sx * kTileZ : sx;
-        dvy = kTiled ? sy * nx * kTileZ : sy * nx;
+        dvx = kScale * (kTiled ? sx * kTileZ : sx);
+        dvy = kScale * (kTiled ? sy * nx * kTileZ : sy * nx);
         // a z step inside a tile, and one onto the next tile (the same as the
         // first without tiles)
-        dz_in = kTiled ? sz : sz * nx * ny;
-        dz_out = kTiled ? sz * (nx * ny * kTileZ - (kTileZ - 1)) : dz_in;
+        dz_in = kScale * (kTiled ? sz : sz * nx * ny);
+        dz_out = kTiled ? kScale * sz * (nx * ny * kTileZ - (kTileZ - 1)) : dz_in;
         // opaque to the compiler: it would otherwise fold the step's choice
         // between sz and sz * X into a multiplication by a chosen factor
         // (a quarter-rate integer multiply per step, in a branch)
         if (kTiled) asm volatile("" : "+v"(dz_in), "+v"(dz_out));
         zl = kTiled ? (sz > 0 ? kTileZ - 1 - iz % kTileZ : iz % kTileZ) : 1;
-        v = kTiled ? (int)tile_index(ix, iy, iz, nx, ny) : ix + nx * (iy + ny * iz);
+        v = kScale * (kTiled ? (int)tile_index(ix, iy, iz, nx, ny) : ix + nx * (iy + ny * iz));
     }
     // the step along x, y or z (one of bx, by, bz), taken when `next`
     __device__ __forceinline__ void step(bool next, bool bx, bool by, bool bz)
@@ -365,7 +366,9 @@ struct WalkIndex {
     }
 };
 
-template <int U, typename Real, bool kBounded, bool kTiled = false, typename G>
+// kScale: value() takes the voxel index times kScale (sizeof(Real): a byte
+// offset into the grid).
+template <int U, typename Real, bool kBounded, bool kTiled = false, int kScale = 1, typename G>
 __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy, int iz,
                                         Real wx, Real wy, Real wz, Real tmax, uint32_t& pieces, G&& value)
 {
@@ -381,7 +384,7 @@ __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py
     const int ry = sy > 0 ? ny - 1 - iy : iy;
     const int rz = sz > 0 ? nz - 1 - iz : iz;
     int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
-    WalkIndex<kTiled> vi(nx, ny, ix, iy, iz, sx, sy, sz);
+    WalkIndex<kTiled, kScale> vi(nx, ny, ix, iy, iz, sx, sy, sz);
     bool alive = true;
     uint32_t n = 0;
     Real acc = (Real)0;

@@ -163,7 +163,25 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
         lds_fill(sgrid, nu, [&](int i) { return (Real)((double)a.bc_t[i] + s.beta_air); });
         __syncthreads();
     }
-    auto beta_tot = [&](uint32_t v) -> Real { return kGridLds ? sgrid[v] : gtile[v]; };
+    auto beta_tot = [&](uint32_t v) -> Real { return sgrid[v]; };
+    // (the tiled copy is walked in byte offsets: no index arithmetic per piece)
+    auto beta_tile = [&](uint32_t off) -> Real {
+        return *reinterpret_cast<const Real*>(reinterpret_cast<const unsigned char*>(gtile) + off);
+    };
+    uint64_t nseg = 0, nle = 0;
+    // the connection's optical depth (in grid units) from p1 along u up to tm;
+    // with every camera outside the box the walk ends at the box boundary,
+    // before the camera, so it needs no length bound
+    auto walk_conn = [&](const Vtx& p1, const double u[3], double tm) -> Real {
+        if constexpr (kGridLds) {
+            return cams.outside ? walk_sum<Real, false>(s, beta_tot, p1, u, tm, nseg)
+                                : walk_sum<Real, true>(s, beta_tot, p1, u, tm, nseg);
+        } else {
+            return cams.outside
+                       ? walk_sum<Real, false, kRenderWalkLoads, true, (int)sizeof(Real)>(s, beta_tile, p1, u, tm, nseg)
+                       : walk_sum<Real, true, kRenderWalkLoads, true, (int)sizeof(Real)>(s, beta_tile, p1, u, tm, nseg);
+        }
+    };
     const double r2scale = 1.0 / (s.vk * s.vk);
     const float vkf = (float)s.vk, wc_f = (float)s.w_c;
     const float wab = (float)(s.w_a * s.beta_air), ray_k = (float)(3.0 / (16.0 * kPi));
@@ -171,7 +189,6 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
     const int64_t nb = a.st.n_slots / kWave;
     const int G = a.groups, cpg = (cams.n + G - 1) / G;
     const unsigned int n_tasks = (unsigned int)(nb - a.st.first_slot / kWave) * (unsigned int)G;
-    uint64_t nseg = 0, nle = 0;
     const unsigned int tc = task_counter();
     for (unsigned int task = next_task(a.work, tc); task < n_tasks; task = next_task(a.work, tc)) {
         const int64_t bt = nb - 1 - (int64_t)(task / G);
@@ -214,11 +231,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                     const float muf = (float)mu;
                     const float hg = phase_hg_f32_om(s, (float)(1.0 - mu));
                     const float fst = wcb * hg + wab * ray_k * (1.f + muf * muf);
-                    // with every camera outside the box the walk ends at the box
-                    // boundary, before the camera, so it needs no length bound
-                    const Real tc = cams.outside
-                                        ? walk_sum<Real, false, kGridLds ? 1 : kRenderWalkLoads, !kGridLds>(s, beta_tot, p1, u, d2 * id, nseg)
-                                        : walk_sum<Real, true, kGridLds ? 1 : kRenderWalkLoads, !kGridLds>(s, beta_tot, p1, u, d2 * id, nseg);
+                    const Real tc = walk_conn(p1, u, d2 * id);
                     c = base * (double)(fst * expf(-(float)tc * vkf) * (float)(r2scale * id * id));
                 } else {
                     const double dist2 = ex * ex + ey * ey + ez * ez;
@@ -227,9 +240,7 @@ __global__ void __launch_bounds__(kBlock) render_kernel(TraceArgs a, DevCams cam
                     const double u[3] = {ex * id, ey * id, ez * id};
                     const double mu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
                     const double fst = fs_mix(s, bct, phase_hg(s, mu), phase_rayleigh(mu));
-                    const Real tc = cams.outside
-                                        ? walk_sum<Real, false, kGridLds ? 1 : kRenderWalkLoads, !kGridLds>(s, beta_tot, p1, u, dist, nseg)
-                                        : walk_sum<Real, true, kGridLds ? 1 : kRenderWalkLoads, !kGridLds>(s, beta_tot, p1, u, dist, nseg);
+                    const Real tc = walk_conn(p1, u, dist);
                     c = base * fst * exp(-(double)tc * s.vk) * (r2scale / dist2);
                 }
                 if (kTape) T[(int64_t)(b * cams.n + d) * kWave] = make_float2((float)c, __int_as_float(pix));

@@ -39,16 +39,16 @@ __device__ __forceinline__ int clamp_vox(int v, int nu) { return min(max(v, 0), 
 // for length tmax (grid units); adds the number of pieces to count.  With
 // U > 1 the walk forms U pieces before fetching their values (for grids in
 // global memory; same sum).
-template <typename Real, bool kBounded = true, int U = 1, bool kTiled = false, typename G>
+template <typename Real, bool kBounded = true, int U = 1, bool kTiled = false, int kScale = 1, typename G>
 __device__ __forceinline__ Real walk_sum(const DevScene& s, G&& beta, const Vtx& p, const double w[3], double tmax,
                                          uint64_t& count)
 {
     int ix, iy, iz;
     voxel_ijk(s, clamp_vox(p.v, s.nx * s.ny * s.nz), ix, iy, iz);
-    static_assert(!kTiled || U > 1, "the z-tiled layout is walked by dda_sum");
+    static_assert((!kTiled && kScale == 1) || U > 1, "the z-tiled layout and byte offsets are walked by dda_sum");
     if constexpr (U > 1) {
         uint32_t n = 0;
-        const Real acc = dda_sum<U, Real, kBounded, kTiled>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy,
+        const Real acc = dda_sum<U, Real, kBounded, kTiled, kScale>(s.nx, s.ny, s.nz, (Real)p.x, (Real)p.y, (Real)p.z, ix, iy,
                                                             iz, (Real)w[0], (Real)w[1], (Real)w[2], (Real)tmax, n,
                                                             beta);
         count += n;
