@@ -433,8 +433,9 @@ __device__ __forceinline__ Real dda_sum(int nx, int ny, int nz, Real px, Real py
 // ray leaves the box first, setting *t0 to the exit parameter.  The pieces,
 // the order of the additions and the comparisons are those of a dda_walk
 // functor doing the same, so both give the same result.  kTiled: voxel
-// indices (value's argument and the result) of the z-tiled layout.
-template <int U, typename Real, bool kTiled = false, typename G>
+// indices (value's argument and the result) of the z-tiled layout; both
+// times kScale (sizeof(Real): byte offsets).
+template <int U, typename Real, bool kTiled = false, int kScale = 1, typename G>
 __device__ __forceinline__ int dda_first_hit(int nx, int ny, int nz, Real px, Real py, Real pz, int ix, int iy, int iz,
                                              Real wx, Real wy, Real wz, Real tau, G&& value, Real* acc_out,
                                              Real* t0_out)
@@ -453,7 +454,7 @@ __device__ __forceinline__ int dda_first_hit(int nx, int ny, int nz, Real px, Re
     const int ry = sy > 0 ? ny - 1 - iy : iy;
     const int rz = sz > 0 ? nz - 1 - iz : iz;
     int R = (rx + 512) | (ry + 512) << 10 | (rz + 512) << 20;
-    WalkIndex<kTiled> vi(nx, ny, ix, iy, iz, sx, sy, sz);
+    WalkIndex<kTiled, kScale> vi(nx, ny, ix, iy, iz, sx, sy, sz);
     bool alive = true;
     Real acc = (Real)0;
     for (;;) {

@@ -205,16 +205,18 @@ __global__ void __launch_bounds__(kSampleBlock) sample_kernel(SampleArgs a)
                     return true;
                 });
         } else {
-            // the grid in global memory, z-tiled: sample_loads pieces per
-            // batch of loads; the hit's tiled index becomes a linear one
-            const Real* __restrict__ gtl = (const Real*)a.grid_tile;
-            const int ht = dda_first_hit<sample_loads<Real>(), Real, true>(s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy,
-                                                                   iz, (Real)w[0], (Real)w[1], (Real)w[2], taur,
-                                                                   [&](uint32_t vv) { return gtl[vv]; }, &acc, &thit);
+            // the grid in global memory, z-tiled and walked in byte offsets:
+            // sample_loads pieces per batch of loads; the hit's tiled index
+            // becomes a linear one
+            const unsigned char* __restrict__ gtl = (const unsigned char*)a.grid_tile;
+            auto at = [&](uint32_t off) { return *reinterpret_cast<const Real*>(gtl + off); };
+            const int ht = dda_first_hit<sample_loads<Real>(), Real, true, (int)sizeof(Real)>(
+                s.nx, s.ny, s.nz, (Real)x, (Real)y, (Real)z, ix, iy, iz, (Real)w[0], (Real)w[1], (Real)w[2], taur, at,
+                &acc, &thit);
             tend = thit;
             if (ht >= 0) {
-                thit += (taur - acc) / gtl[ht];
-                hit = tile_to_linear(ht, s.nx, s.ny, s.inv_nx, s.inv_ny);
+                thit += (taur - acc) / at((uint32_t)ht);
+                hit = tile_to_linear(ht / (int)sizeof(Real), s.nx, s.ny, s.inv_nx, s.inv_ny);
             }
         }
         // the division that places the scatter inside its voxel stays out of the loop
