@@ -48,6 +48,22 @@ __device__ __forceinline__ const Real* delta_grid(const TraceArgs& a, unsigned c
 
 bool delta_grid_lds(int fp64, int64_t nu) { return (size_t)nu * (fp64 ? 8 : 4) <= kLdsBudget; }
 
+// Sum of the delta grid gd (from delta_grid) times length along a free-flight
+// segment: one piece at a time in LDS, else kWalkLoads pieces per batch of
+// loads from global memory, walked in byte offsets.
+template <typename Real, bool kGridLds>
+__device__ __forceinline__ Real delta_walk(const DevScene& s, const Real* gd, const Vtx& p0, const double w[3],
+                                           double L, uint64_t& count)
+{
+    if constexpr (kGridLds) {
+        return walk_sum<Real, true>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, count);
+    } else {
+        const unsigned char* g = reinterpret_cast<const unsigned char*>(gd);
+        return walk_sum<Real, true, kWalkLoads, false, (int)sizeof(Real)>(
+            s, [&](uint32_t off) { return *reinterpret_cast<const Real*>(g + off); }, p0, w, L, count);
+    }
+}
+
 // Prefix weights, one wavefront per task (batch, b) with the field
 // beta_t - beta_ref cached in LDS when it fits (persistent workgroups): a lane
 // holds one path of the batch at its scatter b <= brender and stores
@@ -88,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) render_prefix_kernel(TraceArgs a, Vert
         double w[3];
         const double L = seg_dir(p0, p1, w);
         // free-flight segment b-1: transmittance ratio exp(-(tau_t - tau_ref))
-        const Real dt = walk_sum<Real, true, kGridLds ? 1 : kWalkLoads>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, nseg);
+        const Real dt = delta_walk<Real, kGridLds>(s, gd, p0, w, L, nseg);
         double q = exp(-(double)dt * s.vk);
         if (b == 1) {
             q *= s.w0;
@@ -1501,7 +1517,7 @@ __global__ void __launch_bounds__(kBlock) reweight_kernel(TraceArgs a)
             const Vtx p1 = load_vtx(V, k + 1);
             double w[3];
             const double L = seg_dir(p0, p1, w);
-            lr -= (double)walk_sum<Real, true, kGridLds ? 1 : kWalkLoads>(s, [&](uint32_t v) { return gd[v]; }, p0, w, L, cnt) * s.vk;
+            lr -= (double)delta_walk<Real, kGridLds>(s, gd, p0, w, L, cnt) * s.vk;
             if (k >= 1) {
                 // scatter k (it has the successor k+1): extinction ratio and
                 // direction-pdf ratio f_s,t bs_ref / (f_s,ref bs_t)
