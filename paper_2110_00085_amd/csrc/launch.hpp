@@ -178,9 +178,10 @@ hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu
 // Stable sort of the paths by (size B, spatial key): perm[sorted position] =
 // path id, B[position] = size, nv[position] = tnv[path id] for positions < n
 // and 0 up to n_slots, and (when inv is given) inv[path id] = sorted position.
-// hist: sort_scratch_words(n, nbins) words; tmp_perm: n entries.
+// hist: sort_scratch_words(n, nbins) words; tmp_perm and carry: n entries.
 hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint8_t* tnv, const uint16_t* cell,
-                             int64_t n, int64_t n_slots, int nbins, uint32_t* hist, int32_t* tmp_perm, int32_t* perm,
+                             int64_t n, int64_t n_slots, int nbins, uint32_t* hist, int32_t* tmp_perm,
+                             uint16_t* carry, int32_t* perm,
                              uint8_t* B, uint8_t* nv, int32_t* inv);
 int64_t sort_scratch_words(int64_t n, int nbins);
 // scratch: the sort's scratch (sort_scratch_words(64 * nb, ...) words) may be reused.

@@ -515,12 +515,14 @@ int layout_store(prt_ctx c, prt_paths p, const uint8_t* tB, const uint8_t* tnv, 
     int rc;
     if ((rc = reserve_paths(p, n))) return rc;
     if ((rc = ensure_scratch(&c->s_hist, &c->s_hist_bytes, sort_scratch_words(n, nbins) * sizeof(uint32_t)))) return rc;
-    if ((rc = ensure_scratch(&c->s_perm, &c->s_perm_bytes, (size_t)n * (inv ? 2 : 1) * sizeof(int32_t)))) return rc;
+    const int64_t n_i32 = n * (inv ? 2 : 1);
+    if ((rc = ensure_scratch(&c->s_perm, &c->s_perm_bytes, (size_t)n_i32 * sizeof(int32_t) + (size_t)n * 2))) return rc;
     if (inv) *inv = (int32_t*)c->s_perm + n;
+    uint16_t* carry = (uint16_t*)((int32_t*)c->s_perm + n_i32);
     {
         TimedScope ts(c, K_SORT);
         HIPCHK(launch_sort_paths(c->stream, tB, tnv, tC, n, p->n_slots, nbins, (uint32_t*)c->s_hist,
-                                 (int32_t*)c->s_perm, p->perm, p->B, p->nv, inv ? *inv : nullptr));
+                                 (int32_t*)c->s_perm, carry, p->perm, p->B, p->nv, inv ? *inv : nullptr));
         HIPCHK(launch_batch_offsets(c->stream, p->nv, p->nb, p->batch_off, c->s_hist));
         HIPCHK(launch_store_meta(c->stream, p->B, n, p->batch_off, p->nb, c->dmeta));
     }

@@ -351,18 +351,31 @@ hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu
 constexpr int kSortTile = 1024;
 
 // Optional outputs of a scatter pass: key_out[dst] = key of the element,
-// aux_out[dst] = aux_in[element] for every sorted position dst, and zeros in
-// [n, n_pad).
+// aux_out[dst] = its aux byte for every sorted position dst, and zeros in
+// [n, n_pad); carry_out[dst] = carry_lo[i] | carry_hi[i] << 8 carries two
+// bytes of every element into the pass's output order.
 struct SortExtra {
-    const uint8_t* aux_in = nullptr;
     uint8_t* key_out = nullptr;
     uint8_t* aux_out = nullptr;
     int32_t* inv_out = nullptr;  // inv_out[element] = dst
     int64_t n_pad = 0;
+    const uint8_t* carry_lo = nullptr;
+    const uint8_t* carry_hi = nullptr;
+    uint16_t* carry_out = nullptr;
 };
+
+// A key read: kPacked keys are the carried uint16 of position i (key in the
+// low byte, aux in the high byte), so a pass over an earlier pass's output
+// reads them in order instead of gathering key[in[i]].
+template <typename K, bool kPacked>
+__device__ __forceinline__ uint32_t sort_key_raw(const K* __restrict__ key, const int32_t* __restrict__ in, int64_t i)
+{
+    if constexpr (kPacked) return key[i];
+    else return key[in ? in[i] : i];
+}
 constexpr int kMaxBins = kCells > kMaxOrder + 1 ? kCells : kMaxOrder + 1;
 
-template <typename K>
+template <typename K, bool kPacked>
 __global__ void __launch_bounds__(256) sort_hist_kernel(const K* __restrict__ key, const int32_t* __restrict__ in,
                                                         int64_t n, int nbins, int64_t n_tiles,
                                                         uint32_t* __restrict__ hist)
@@ -373,7 +386,10 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const K* __restrict__ ke
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int j = threadIdx.x; j < kSortTile; j += blockDim.x) {
         const int64_t i = base + j;
-        if (i < n) atomicAdd(&h[min((int)key[in ? in[i] : i], nbins - 1)], 1u);
+        if (i < n) {
+            const uint32_t kr = sort_key_raw<K, kPacked>(key, in, i);
+            atomicAdd(&h[min((int)(kPacked ? kr & 0xffu : kr), nbins - 1)], 1u);
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nbins; k += blockDim.x) hist[(int64_t)k * n_tiles + blockIdx.x] = h[k];
@@ -452,7 +468,7 @@ static hipError_t scan_exclusive(hipStream_t st, T* a, int64_t n, T* scratch)
 // key bit), counts those below it, so equal keys keep their order, and the
 // last lane of each key advances that key's running output position in LDS.
 // Writes out[pos] = in[i] (or i).
-template <typename K>
+template <typename K, bool kPacked>
 __global__ void __launch_bounds__(kWave) sort_scatter_kernel(const K* __restrict__ key,
                                                              const int32_t* __restrict__ in, int64_t n, int nbins,
                                                              int64_t n_tiles, const uint32_t* __restrict__ off,
@@ -474,7 +490,8 @@ __global__ void __launch_bounds__(kWave) sort_scatter_kernel(const K* __restrict
     for (int r = 0; r < kSortTile / kWave; ++r) {
         const int64_t i = t0 + r * kWave + lane;
         const bool valid = i < n;
-        const int k = valid ? min((int)key[in ? in[i] : i], nbins - 1) : 0;
+        const uint32_t kr = valid ? sort_key_raw<K, kPacked>(key, in, i) : 0u;
+        const int k = min((int)(kPacked ? kr & 0xffu : kr), nbins - 1);
         uint64_t same = __ballot(valid);
         for (int bit = 0; bit < nbits; ++bit) {
             const bool set = (k >> bit) & 1;
@@ -487,10 +504,11 @@ __global__ void __launch_bounds__(kWave) sort_scatter_kernel(const K* __restrict
             const uint32_t dst = base[k] + below;
             out[dst] = id;
             if (x.key_out) {
-                x.key_out[dst] = (uint8_t)key[id];
-                x.aux_out[dst] = x.aux_in[id];
+                x.key_out[dst] = (uint8_t)kr;
+                x.aux_out[dst] = (uint8_t)(kr >> 8);
             }
             if (x.inv_out) x.inv_out[id] = (int32_t)dst;
+            if (x.carry_out) x.carry_out[dst] = (uint16_t)(x.carry_lo[i] | (uint32_t)x.carry_hi[i] << 8);
             if (below == total - 1) base[k] += total;
         }
         __syncthreads();
@@ -509,18 +527,18 @@ hipError_t launch_scan_u32(hipStream_t st, uint32_t* a, int64_t n, uint32_t* scr
     return scan_exclusive<uint32_t>(st, a, n, scratch);
 }
 
-template <typename K>
+template <typename K, bool kPacked = false>
 static hipError_t counting_sort(hipStream_t st, const K* key, const int32_t* in, int64_t n, int nbins,
                                 uint32_t* hist, int32_t* out, SortExtra x = SortExtra{})
 {
     const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
-    sort_hist_kernel<K><<<dim3((unsigned)n_tiles), dim3(256), 0, st>>>(key, in, n, nbins, n_tiles, hist);
+    sort_hist_kernel<K, kPacked><<<dim3((unsigned)n_tiles), dim3(256), 0, st>>>(key, in, n, nbins, n_tiles, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t m = n_tiles * nbins;
     if ((e = scan_exclusive<uint32_t>(st, hist, m, hist + m)) != hipSuccess) return e;
-    sort_scatter_kernel<K><<<dim3((unsigned)n_tiles), dim3(kWave), 0, st>>>(key, in, n, nbins, n_tiles, hist, out,
-                                                                            x);
+    sort_scatter_kernel<K, kPacked><<<dim3((unsigned)n_tiles), dim3(kWave), 0, st>>>(key, in, n, nbins, n_tiles,
+                                                                                     hist, out, x);
     return hipGetLastError();
 }
 
@@ -536,20 +554,25 @@ int64_t sort_scratch_words(int64_t n, int nbins)
 }
 
 hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint8_t* tnv, const uint16_t* cell,
-                             int64_t n, int64_t n_slots, int nbins, uint32_t* hist, int32_t* tmp_perm, int32_t* perm,
-                             uint8_t* B, uint8_t* nv, int32_t* inv)
+                             int64_t n, int64_t n_slots, int nbins, uint32_t* hist, int32_t* tmp_perm,
+                             uint16_t* carry, int32_t* perm, uint8_t* B, uint8_t* nv, int32_t* inv)
 {
     if (n <= 0) return hipSuccess;
-    hipError_t e = counting_sort<uint16_t>(st, cell, nullptr, n, kCells, hist, tmp_perm);
+    // the cell pass carries every path's size key and vertex count along,
+    // so the size pass reads them in order
+    SortExtra c;
+    c.carry_lo = size_key;
+    c.carry_hi = tnv;
+    c.carry_out = carry;
+    hipError_t e = counting_sort<uint16_t>(st, cell, nullptr, n, kCells, hist, tmp_perm, c);
     if (e != hipSuccess) return e;
     // the size pass also writes every slot's B and vertex count (zero past n)
     SortExtra x;
-    x.aux_in = tnv;
     x.key_out = B;
     x.aux_out = nv;
     x.inv_out = inv;
     x.n_pad = n_slots;
-    return counting_sort<uint8_t>(st, size_key, tmp_perm, n, nbins, hist, perm, x);
+    return counting_sort<uint16_t, true>(st, carry, tmp_perm, n, nbins, hist, perm, x);
 }
 
 // --------------------------------------------------------------- packing
