@@ -348,7 +348,7 @@ hipError_t launch_sample(hipStream_t st, int fp64, const SampleArgs& a, int n_cu
 // is key[in[i]] (or key[i] without an input permutation).  Tile t's count of
 // key k lives at hist[k * n_tiles + t], so an exclusive scan of hist in that
 // order gives every (key, tile) its first output position.
-constexpr int kSortTile = 1024;
+constexpr int kSortTile = 4096;
 
 // Optional outputs of a scatter pass: key_out[dst] = key of the element,
 // aux_out[dst] = its aux byte for every sorted position dst, and zeros in
