@@ -352,16 +352,12 @@ constexpr int kSortTile = 4096;
 
 // Optional outputs of a scatter pass: key_out[dst] = key of the element,
 // aux_out[dst] = its aux byte for every sorted position dst, and zeros in
-// [n, n_pad); carry_out[dst] = carry_lo[i] | carry_hi[i] << 8 carries two
-// bytes of every element into the pass's output order.
+// [n, n_pad).
 struct SortExtra {
     uint8_t* key_out = nullptr;
     uint8_t* aux_out = nullptr;
     int32_t* inv_out = nullptr;  // inv_out[element] = dst
     int64_t n_pad = 0;
-    const uint8_t* carry_lo = nullptr;
-    const uint8_t* carry_hi = nullptr;
-    uint16_t* carry_out = nullptr;
 };
 
 // A key read: kPacked keys are the carried uint16 of position i (key in the
@@ -508,10 +504,88 @@ __global__ void __launch_bounds__(kWave) sort_scatter_kernel(const K* __restrict
                 x.aux_out[dst] = (uint8_t)(kr >> 8);
             }
             if (x.inv_out) x.inv_out[id] = (int32_t)dst;
-            if (x.carry_out) x.carry_out[dst] = (uint16_t)(x.carry_lo[i] | (uint32_t)x.carry_hi[i] << 8);
             if (below == total - 1) base[k] += total;
         }
         __syncthreads();
+    }
+}
+
+// The cell pass, staged through LDS.  The wavefront loads its tile's keys
+// and carried bytes into LDS, ranks every key within the tile with the same
+// ballots as sort_scatter_kernel (equal keys keep their order), records
+// which element lands at each local position, and then writes the tile out in
+// local order: consecutive lanes write consecutive positions of one key's run
+// (4096 keys over 512 cells, runs of 8 on average) instead of one line per
+// lane.  Writes out[dst] = i and carry_out[dst] = carry_lo[i] |
+// carry_hi[i] << 8, which carries two bytes of every element into cell order.
+__global__ void __launch_bounds__(kWave) sort_scatter_cells_kernel(
+    const uint16_t* __restrict__ key, int64_t n, int64_t n_tiles, const uint32_t* __restrict__ off,
+    int32_t* __restrict__ out, const uint8_t* __restrict__ carry_lo, const uint8_t* __restrict__ carry_hi,
+    uint16_t* __restrict__ carry_out)
+{
+    constexpr int kPer = kCells / kWave;
+    static_assert(kPer * kWave == kCells && kSortTile <= 65536, "cell pass layout");
+    __shared__ uint32_t gbase[kCells];   // first output position of key k for this tile
+    __shared__ uint32_t lstart[kCells];  // first local position of key k
+    __shared__ uint32_t lrun[kCells];    // next free local position of key k
+    __shared__ uint16_t kin[kSortTile];  // the tile's keys
+    __shared__ uint16_t cin[kSortTile];  // the tile's carried bytes
+    __shared__ uint16_t src[kSortTile];  // tile offset of the element at each local position
+    const int lane = threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * kSortTile;
+    const int cnt = (int)min<int64_t>(kSortTile, n - t0);
+    for (int j = lane; j < cnt; j += kWave) {
+        kin[j] = (uint16_t)min((int)key[t0 + j], kCells - 1);
+        cin[j] = (uint16_t)(carry_lo[t0 + j] | (uint32_t)carry_hi[t0 + j] << 8);
+    }
+    // this tile's count of key k: the entry after (k, tile) in scan order is
+    // (k, tile + 1), or (k + 1, 0) for the last tile; n follows the last entry
+    const int64_t m = (int64_t)kCells * n_tiles;
+    uint32_t c[kPer], tot = 0;
+    for (int q = 0; q < kPer; ++q) {
+        const int k = lane * kPer + q;
+        const int64_t idx = (int64_t)k * n_tiles + blockIdx.x;
+        const uint32_t g = off[idx];
+        c[q] = (idx + 1 < m ? off[idx + 1] : (uint32_t)n) - g;
+        gbase[k] = g;
+        tot += c[q];
+    }
+    uint32_t incl = tot;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    uint32_t run = incl - tot;
+    for (int q = 0; q < kPer; ++q) {
+        lstart[lane * kPer + q] = run;
+        lrun[lane * kPer + q] = run;
+        run += c[q];
+    }
+    __syncthreads();
+    const uint64_t below_mask = lane ? (~0ull >> (kWave - lane)) : 0ull;
+    for (int r = 0; r * kWave < cnt; ++r) {
+        const int j = r * kWave + lane;
+        const bool valid = j < cnt;
+        const int k = valid ? (int)kin[j] : 0;
+        uint64_t same = __ballot(valid);
+        for (int bit = 0; bit < 3 * kCellBits; ++bit) {
+            const bool set = (k >> bit) & 1;
+            const uint64_t bb = __ballot(set);
+            same &= set ? bb : ~bb;
+        }
+        if (valid) {
+            const int below = __popcll(same & below_mask), total = __popcll(same);
+            src[lrun[k] + below] = (uint16_t)j;
+            if (below == total - 1) lrun[k] += total;
+        }
+        __syncthreads();
+    }
+    for (int j = lane; j < cnt; j += kWave) {
+        const int e = src[j];
+        const int k = kin[e];
+        const uint32_t dst = gbase[k] + (uint32_t)(j - (int)lstart[k]);
+        out[dst] = (int32_t)(t0 + e);
+        carry_out[dst] = cin[e];
     }
 }
 
@@ -560,12 +634,15 @@ hipError_t launch_sort_paths(hipStream_t st, const uint8_t* size_key, const uint
     if (n <= 0) return hipSuccess;
     // the cell pass carries every path's size key and vertex count along,
     // so the size pass reads them in order
-    SortExtra c;
-    c.carry_lo = size_key;
-    c.carry_hi = tnv;
-    c.carry_out = carry;
-    hipError_t e = counting_sort<uint16_t>(st, cell, nullptr, n, kCells, hist, tmp_perm, c);
+    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    sort_hist_kernel<uint16_t, false><<<dim3((unsigned)n_tiles), dim3(256), 0, st>>>(cell, nullptr, n, kCells,
+                                                                                     n_tiles, hist);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((e = scan_exclusive<uint32_t>(st, hist, n_tiles * kCells, hist + n_tiles * kCells)) != hipSuccess) return e;
+    sort_scatter_cells_kernel<<<dim3((unsigned)n_tiles), dim3(kWave), 0, st>>>(cell, n, n_tiles, hist, tmp_perm,
+                                                                               size_key, tnv, carry);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     // the size pass also writes every slot's B and vertex count (zero past n)
     SortExtra x;
     x.key_out = B;
