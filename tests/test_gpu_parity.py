@@ -305,6 +305,24 @@ def test_sample_fp32_close_to_oracle(env, name):
     _check_sort(P.prt_paths_permutation(ctx.handle, st.handle), scene, off, vox, B)
 
 
+def test_sort_over_many_tiles(env):
+    """The store order over many sort tiles with a ragged tail: 300 001 paths
+    of cloud32 (74 tiles of 4096 keys; most paths leave without scattering,
+    so a few cells hold most keys) are in the exact stable order by (B, cell,
+    id), drawn and imported again in id order."""
+    torch, P, api = env
+    scene, n, seed = inputs.cloud32(), 300_001, 1234
+    say(f"sort over many tiles: cloud32 n={n}")
+    ctx = api.Context(0, P.PRT_TRAVERSAL_FP32)
+    bt = _dev(torch, scene.beta_cloud)
+    st = api.PathStore.sample(ctx, scene, bt, seed, n)
+    off, xyz, vox, B, br = st.export()
+    perm = P.prt_paths_permutation(ctx.handle, st.handle)
+    _check_sort(perm, scene, off, vox, B)
+    imp = api.PathStore.from_host(ctx, scene, bt, off, xyz, vox, B, br, seed)
+    assert np.array_equal(P.prt_paths_permutation(ctx.handle, imp.handle), perm)
+
+
 # ---------------------------------------------- render / grad / reweight
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
