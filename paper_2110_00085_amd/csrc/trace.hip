@@ -554,7 +554,7 @@ __device__ __forceinline__ void slab_tally_end(const SlabTally<kLds>& t, double*
 // matches beta_t (FP32 traversal mode): the per-camera phase functions are
 // evaluated in FP32, like the stored weights.
 
-constexpr int kGwCams = 8;
+constexpr int kGwCams = 5;
 // cameras per camera group: at most 3 groups of the kMaxCams cameras
 constexpr int kGroupCams = (kMaxCams + 2) / 3;
 constexpr int kGwBlock = 256;
